@@ -1,0 +1,138 @@
+/*
+ * C ABI of the MI355X environment-recycled imaginary-time TEBD library.
+ *
+ * Method: Phien, McCulloch and Vidal, "Faster convergence of imaginary time
+ * evolution tensor network algorithms by recycling the environment"
+ * (arXiv:1411.0391).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All tensors are float64, C-contiguous (row-major), real.
+ * - Tensor arguments are DEVICE pointers owned by the caller (e.g. a torch
+ *   tensor's data_ptr()); the library never frees or keeps them past the
+ *   call.  Small descriptors (unit cells) and scalar outputs are HOST
+ *   pointers, as marked.
+ * - Every call is ordered on the context's HIP stream and returns after its
+ *   host scalar outputs are valid (the call synchronises that stream).
+ * - Return codes: TN_OK (0); TN_NOT_CONVERGED (1): outputs hold the last
+ *   iterate, the tolerance was not met; negative codes: outputs unspecified,
+ *   tn_last_error() has the message.
+ * - One context per host thread; calls on one context must not overlap.
+ * - iPEPS site tensors A[s][l][r][d][u] (physical, left, right, down, up).
+ * - Unit cell: Lx x Ly positions, position p = y*Lx + x (x right, y down,
+ *   periodic); cell[p] is the index of the site tensor at p.
+ * - CTM environment per position: corners C[p][k][chi][chi] and edges
+ *   T[p][k][chi][D][D][chi], k = 0..3 for C1..C4 (top-left, top-right,
+ *   bottom-right, bottom-left) and T1..T4 (top, right, bottom, left); the
+ *   two boundary legs of each tensor are ordered clockwise around the ring
+ *   C1 T1 C2 T2 C3 T3 C4 T4, an edge's middle legs are (ket, bra).
+ */
+#ifndef ITEBD_H
+#define ITEBD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_ctx tn_ctx;
+
+enum {
+  TN_OK = 0,
+  TN_NOT_CONVERGED = 1,
+  TN_EINVAL = -1,
+  TN_EHIP = -2,
+  TN_ENUMERIC = -3,
+  TN_ENOMEM = -4
+};
+
+/* Bulk-contraction precision of ctmrg_iterate (factorisations stay FP64). */
+enum { TN_FP64 = 0, TN_FP32 = 1, TN_BF16 = 2 };
+
+/* Create a context on the current HIP device.  hip_stream may be NULL (the
+ * null stream) or a hipStream_t owned by the caller.  Errors: TN_EHIP. */
+int tn_create(tn_ctx** ctx, void* hip_stream);
+
+/* Release the context and everything it allocated. */
+int tn_destroy(tn_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none).  The
+ * string stays valid until the next call on the context. */
+const char* tn_last_error(const tn_ctx* ctx);
+
+/* Library version string. */
+const char* tn_version(void);
+
+/*
+ * ctmrg_iterate -- corner transfer matrix environment of an iPEPS (Sec. VI B,
+ * Fig. 21(a) of the paper).
+ *
+ * Directional CTMRG on an Lx x Ly cell: one iteration is a left, up, right
+ * and down move, each absorbing every column (row) of the cell in turn; a
+ * move computes, for each row cut, the projector pair from the truncated SVD
+ * of the product of the two halves of the 2x2 block of enlarged corners,
+ * P = R_d V S^-1/2 and Pt = S^-1/2 W^T R_u^T with R_u^T R_d = W S V^T, and
+ * renormalises C1, T4, C4 of the next column.  New tensors are scaled to
+ * unit Frobenius norm.  Convergence: delta = max over corners of the l2
+ * change of the corner's singular values normalised to unit l2 norm, per
+ * iteration; stops when delta < tol or after max_iter iterations.
+ *
+ *   Lx, Ly        cell size (>= 1)
+ *   D, d          PEPS bond and physical dimension
+ *   nsite         number of distinct site tensors
+ *   sites         device [nsite][d][D][D][D][D]
+ *   cell          host  [Lx*Ly] site index per position, each < nsite
+ *   chi           environment bond dimension (chi <= chi*D*D)
+ *   C, T          device in/out, shapes above; the input is the start
+ *   max_iter      maximum iterations (>= 1)
+ *   tol           convergence tolerance on delta
+ *   precision     TN_FP64, TN_FP32 or TN_BF16 for the bulk contractions
+ *                 (enlarged corners, renormalisation); SVDs stay FP64
+ *   n_polish_fp64 with a reduced precision, the number of final iterations
+ *                 run in FP64 (the reduced-precision phase stops at
+ *                 delta < 1e-6 for FP32, 1e-3 for BF16)
+ *   iters, delta  host out: iterations done and the last delta
+ * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL (bad sizes or pointers),
+ * TN_ENUMERIC (non-finite values or a failed factorisation), TN_EHIP.
+ */
+int ctmrg_iterate(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                  const int* cell, int chi, double* C, double* T, int max_iter, double tol,
+                  int precision, int n_polish_fp64, int* iters, double* delta);
+
+/*
+ * ctmrg_moves -- run exactly n_moves directional moves (no convergence test),
+ * starting with direction first_dir (0 left, 1 up, 2 right, 3 down) and
+ * column 0, in the order ctmrg_iterate uses.  For measurement and parity
+ * checks of single moves.  Arguments as ctmrg_iterate.
+ */
+int ctmrg_moves(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                const int* cell, int chi, double* C, double* T, int n_moves, int first_dir,
+                int precision);
+
+/*
+ * ipeps_rdms -- reduced density matrices from a CTM environment (used for
+ * the TFIM energy and magnetisation, Sec. VI D).
+ *   rho1 device out [Lx*Ly][d][d]          one-site, at each position
+ *   rhoh device out [Lx*Ly][d*d][d*d]      position with its right neighbour
+ *   rhov device out [Lx*Ly][d*d][d*d]      position (top) with the one below
+ * Each matrix has trace 1; two-site matrices are indexed (s1 s2),(s1' s2').
+ */
+int ipeps_rdms(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+               const int* cell, int chi, const double* C, const double* T, double* rho1,
+               double* rhoh, double* rhov);
+
+/*
+ * tn_gemm -- the library's contraction engine on a plain matrix product, for
+ * testing and measurement: C = alpha op(A) op(B) + beta C with row-major
+ * storage, op(X) = X or X^T (ta, tb nonzero), leading dimensions lda, ldb,
+ * ldc.  All matrices device, FP64.  precision must be TN_FP64 here.
+ */
+int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B,
+            int ldb, int tb, double* C, int ldc, double alpha, double beta, int precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITEBD_H */

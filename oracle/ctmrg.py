@@ -25,8 +25,8 @@ Conventions
   of the lattice rotated counter-clockwise by 90, 180, 270 degrees.
 * Every new corner and edge is scaled to unit Frobenius norm.
 * Singular values below 1e-14 times the largest are dropped when forming
-  S^{-1/2}; each kept left singular vector is sign-fixed so that its
-  largest-magnitude entry is positive.
+  S^{-1/2}; each kept left singular vector is sign-fixed so that its first
+  entry within a relative 1e-8 of the largest magnitude is positive.
 * Convergence: per corner the singular values normalised to unit l2 norm;
   delta = max over corners of the l2 change between iterations.
 """
@@ -77,9 +77,14 @@ def rotate_ccw(cell, tensors, C, T):
 
 
 def _svd_signfix(m):
+    """SVD with each left singular vector's sign fixed: the first entry whose
+    magnitude is within a relative 1e-8 of the largest is made positive (the
+    tolerance makes the rule independent of rounding when symmetric inputs
+    give vectors whose largest entries come in +- pairs)."""
     u, s, vt = np.linalg.svd(m)
     for i in range(u.shape[1]):
-        j = int(np.argmax(np.abs(u[:, i])))
+        a = np.abs(u[:, i])
+        j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
         if u[j, i] < 0:
             u[:, i] = -u[:, i]
             vt[i, :] = -vt[i, :]

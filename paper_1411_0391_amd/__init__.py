@@ -1,0 +1,178 @@
+"""Python binding of the MI355X environment-recycled iTEBD library.
+
+Argument marshalling only: every call forwards device pointers of torch
+tensors (PyTorch provides device memory and the stream) to the C ABI in
+``include/itebd.h``; all arithmetic runs in the HIP kernels of
+``libitebd.so``.  Importing this module on a machine without the built
+library raises immediately -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libitebd.so")
+
+TN_OK, TN_NOT_CONVERGED = 0, 1
+TN_FP64, TN_FP32, TN_BF16 = 0, 1, 2
+_PREC = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16}
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+# name -> (restype, argtypes); every symbol include/itebd.h declares
+SIGNATURES = {
+    "tn_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp]),
+    "tn_destroy": (ctypes.c_int, [_vp]),
+    "tn_last_error": (ctypes.c_char_p, [_vp]),
+    "tn_version": (ctypes.c_char_p, []),
+    "ctmrg_iterate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _vp, _c_int_p, ctypes.c_int, _vp, _vp,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     _c_int_p, _c_double_p]),
+    "ctmrg_moves": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, _vp, _c_int_p, ctypes.c_int, _vp, _vp,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ipeps_rdms": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, _vp, _c_int_p, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                  _vp]),
+    "tn_gemm": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                               ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libitebd.so and attach the C signatures; raise if it is absent."""
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} is not built; run paper_1411_0391_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class TNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libitebd error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a device (cuda/hip) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to torch's current HIP stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = lib().tn_create(ctypes.byref(h), ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise TNError(rc, "tn_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_nc=False):
+        if rc < 0 or (rc == TN_NOT_CONVERGED and not allow_nc):
+            raise TNError(rc, lib().tn_last_error(self._h).decode())
+        return rc
+
+    # -- 2D environment ----------------------------------------------------
+    @staticmethod
+    def _cell(cell):
+        arr = (ctypes.c_int * len(cell))(*[int(c) for c in cell])
+        return arr
+
+    def ctmrg_iterate(self, Lx, Ly, sites, cell, C, T, max_iter, tol, precision="fp64",
+                      n_polish=5):
+        nsite, d, D = sites.shape[0], sites.shape[1], sites.shape[2]
+        chi = C.shape[-1]
+        it = ctypes.c_int(0)
+        de = ctypes.c_double(0.0)
+        rc = lib().ctmrg_iterate(self._h, Lx, Ly, D, d, nsite, _ptr(sites), self._cell(cell), chi,
+                                 _ptr(C), _ptr(T), max_iter, tol, _PREC[precision], n_polish,
+                                 ctypes.byref(it), ctypes.byref(de))
+        self._check(rc, allow_nc=True)
+        return rc, it.value, de.value
+
+    def ctmrg_moves(self, Lx, Ly, sites, cell, C, T, n_moves, first_dir=0, precision="fp64"):
+        nsite, d, D = sites.shape[0], sites.shape[1], sites.shape[2]
+        chi = C.shape[-1]
+        rc = lib().ctmrg_moves(self._h, Lx, Ly, D, d, nsite, _ptr(sites), self._cell(cell), chi,
+                               _ptr(C), _ptr(T), n_moves, first_dir, _PREC[precision])
+        self._check(rc)
+
+    def ipeps_rdms(self, Lx, Ly, sites, cell, C, T):
+        import torch
+        nsite, d, D = sites.shape[0], sites.shape[1], sites.shape[2]
+        chi = C.shape[-1]
+        npos = Lx * Ly
+        dev = sites.device
+        r1 = torch.empty((npos, d, d), dtype=torch.float64, device=dev)
+        rh = torch.empty((npos, d * d, d * d), dtype=torch.float64, device=dev)
+        rv = torch.empty((npos, d * d, d * d), dtype=torch.float64, device=dev)
+        rc = lib().ipeps_rdms(self._h, Lx, Ly, D, d, nsite, _ptr(sites), self._cell(cell), chi,
+                              _ptr(C), _ptr(T), _ptr(r1), _ptr(rh), _ptr(rv))
+        self._check(rc)
+        return r1, rh, rv
+
+    def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0):
+        M = A.shape[1] if ta else A.shape[0]
+        K = A.shape[0] if ta else A.shape[1]
+        N = B.shape[0] if tb else B.shape[1]
+        rc = lib().tn_gemm(self._h, M, N, K, _ptr(A), A.shape[1], int(ta), _ptr(B), B.shape[1],
+                           int(tb), _ptr(C), C.shape[1], alpha, beta, TN_FP64)
+        self._check(rc)
+
+
+def tfim_energy_per_site(rho1, rhoh, rhov, J, h):
+    """Energy per site from RDMs (host arithmetic on 4x4 matrices is not on
+    the hot path; the RDMs themselves come from the kernels)."""
+    sz = np.diag([1.0, -1.0])
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    zz = np.kron(sz, sz)
+    r1, rh, rv = (x.detach().cpu().numpy() for x in (rho1, rhoh, rhov))
+    e = 0.0
+    for p in range(r1.shape[0]):
+        e += -J * np.trace(rh[p] @ zz) - J * np.trace(rv[p] @ zz) - h * np.trace(r1[p] @ sx)
+    return float(e / r1.shape[0])

@@ -1,0 +1,144 @@
+// C ABI entry points and context management.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                   const int* cell, int chi, double* C, double* T, int max_iter, double tol,
+                   int n_moves, int first_dir, int* iters, double* delta);
+int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                    const int* cell, int chi, const double* C, const double* T, double* rho1,
+                    double* rhoh, double* rhov);
+
+int ws_reserve(tn_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->arena_size) return TN_OK;
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->arena) TN_HIP(ctx, hipFree(ctx->arena));
+  ctx->arena = nullptr;
+  ctx->arena_size = 0;
+  const size_t want = bytes + bytes / 8;
+  if (hipMalloc(&ctx->arena, want) != hipSuccess) {
+    ctx->arena = nullptr;
+    (void)hipGetLastError();
+    TN_FAIL(ctx, TN_ENOMEM, "cannot allocate %zu bytes of workspace", want);
+  }
+  ctx->arena_size = want;
+  ctx->arena_off = 0;
+  return TN_OK;
+}
+
+void* ws_alloc_bytes(tn_ctx* ctx, size_t bytes) {
+  const size_t off = (ctx->arena_off + 255) & ~size_t(255);
+  if (off + bytes > ctx->arena_size) {
+    // sticky: every later request fails too, so checking the last pointer
+    // of a group of allocations is enough
+    ctx->err = "workspace arena exhausted";
+    ctx->arena_off = ctx->arena_size;
+    return nullptr;
+  }
+  ctx->arena_off = off + bytes;
+  return ctx->arena + off;
+}
+
+int keep_buffer(tn_ctx* ctx, const std::string& key, size_t bytes, void** ptr, bool* fresh) {
+  auto it = ctx->keep.find(key);
+  if (it != ctx->keep.end() && it->second.second == bytes) {
+    *ptr = it->second.first;
+    if (fresh) *fresh = false;
+    return TN_OK;
+  }
+  if (it != ctx->keep.end()) {
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    TN_HIP(ctx, hipFree(it->second.first));
+    ctx->keep.erase(it);
+  }
+  void* p = nullptr;
+  TN_HIP(ctx, hipMalloc(&p, bytes));
+  ctx->keep[key] = {p, bytes};
+  *ptr = p;
+  if (fresh) *fresh = true;
+  return TN_OK;
+}
+
+extern "C" {
+
+int tn_create(tn_ctx** out, void* hip_stream) {
+  if (!out) return TN_EINVAL;
+  tn_ctx* ctx = new tn_ctx();
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&ctx->device) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->host_scratch), 64 * sizeof(double)) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    *out = nullptr;
+    return TN_EHIP;
+  }
+  *out = ctx;
+  return TN_OK;
+}
+
+int tn_destroy(tn_ctx* ctx) {
+  if (!ctx) return TN_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
+  for (auto& kv : ctx->keep) (void)hipFree(kv.second.first);
+  if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
+  delete ctx;
+  return TN_OK;
+}
+
+const char* tn_last_error(const tn_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+const char* tn_version(void) { return "itebd-mi355x 0.1 (gfx950)"; }
+
+int ctmrg_iterate(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                  const int* cell, int chi, double* C, double* T, int max_iter, double tol,
+                  int precision, int n_polish_fp64, int* iters, double* delta) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
+  if (precision != TN_FP64 && precision != TN_FP32 && precision != TN_BF16)
+    TN_FAIL(ctx, TN_EINVAL, "unknown precision %d", precision);
+  if (precision != TN_FP64)
+    TN_FAIL(ctx, TN_EINVAL, "reduced-precision bulk contractions are not built in this library");
+  (void)n_polish_fp64;
+  return ctmrg_run_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, max_iter, tol, 0, 0,
+                        iters, delta);
+}
+
+int ctmrg_moves(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                const int* cell, int chi, double* C, double* T, int n_moves, int first_dir,
+                int precision) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  if (n_moves < 1) TN_FAIL(ctx, TN_EINVAL, "n_moves must be >= 1");
+  if (first_dir < 0 || first_dir > 3) TN_FAIL(ctx, TN_EINVAL, "first_dir must be 0..3");
+  if (precision != TN_FP64)
+    TN_FAIL(ctx, TN_EINVAL, "reduced-precision bulk contractions are not built in this library");
+  return ctmrg_run_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, 0, 0.0, n_moves,
+                        first_dir, nullptr, nullptr);
+}
+
+int ipeps_rdms(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+               const int* cell, int chi, const double* C, const double* T, double* rho1,
+               double* rhoh, double* rhov) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ipeps_rdms_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, rho1, rhoh, rhov);
+}
+
+int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B,
+            int ldb, int tb, double* C, int ldc, double alpha, double beta, int precision) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  if (M < 0 || N < 0 || K < 0 || !A || !B || !C) TN_FAIL(ctx, TN_EINVAL, "bad gemm arguments");
+  if (precision != TN_FP64) TN_FAIL(ctx, TN_EINVAL, "tn_gemm supports TN_FP64 only");
+  TN_TRY(gemm(ctx, M, N, K, A, lda, ta != 0, B, ldb, tb != 0, C, ldc, alpha, beta));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+}  // extern "C"

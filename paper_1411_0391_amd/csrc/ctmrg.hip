@@ -1,0 +1,954 @@
+// Directional CTMRG on the GPU (Sec. VI B of the paper, Fig. 21(a)) and the
+// reduced density matrices computed from its environment.
+//
+// Every move is the left move of the lattice rotated by 0, 90, 180 or 270
+// degrees counter-clockwise ("frame" f).  In frame f the corner and edge
+// slots k of a position are the lattice slots (k + f) mod 4 and the site
+// tensor is the lattice tensor rotated f times; positions map through the
+// composed rotation (x', y') = (y, -x).  All four enlarged corners of a 2x2
+// block are therefore one contraction, the upper-left one, evaluated in
+// frames f, f+1, f+2, f+3; the projector matrix R_u^T R_d of the row cut is
+// the transpose of the ring product K = E2 E3 E0 E1 of those corners.
+//
+// Projectors come from the top-chi singular triplets of K, computed without
+// forming K (four n x n x k products per application, n = chi D^2): block
+// subspace iteration on K K^T with k = chi + oversampling columns,
+// orthonormalised by shifted Cholesky-QR (three passes), Rayleigh-Ritz by a
+// one-sided Jacobi SVD of the k x k factor, stopped when the residual
+// |K w_i - s_i v_i| of every kept triplet is below tol * s_1.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+// one counter-clockwise rotation of a site tensor: new (l,r,d,u) = old (u,d,l,r)
+__global__ void rotate_site_kernel(const double* __restrict__ A, double* __restrict__ B, int d,
+                                   int D) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)d * D * D * D * D;
+  if (t >= tot) return;
+  long long r = t;
+  const int u2 = r % D; r /= D;
+  const int d2 = r % D; r /= D;
+  const int r2 = r % D; r /= D;
+  const int l2 = r % D; r /= D;
+  const int s = (int)r;
+  // new[s][l2][r2][d2][u2] = old[s][l=d2][r=u2][d=r2][u=l2]
+  const long long src = ((((long long)s * D + d2) * D + u2) * D + r2) * D + l2;
+  B[t] = A[src];
+}
+
+__global__ void copy_cols_kernel(int n, int kin, int kout, const double* __restrict__ X,
+                                 double* __restrict__ Y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * kout) return;
+  const int i = (int)(t / kout), j = (int)(t % kout);
+  Y[t] = X[(long long)i * kin + j];
+}
+
+// per kept column i < chi: |Y[:,i] - S[i] V[:,i]|; out = max_i (.) / S[0]
+__global__ __launch_bounds__(256) void resid_kernel(int n, int k, int chi,
+                                                    const double* __restrict__ Y,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ S,
+                                                    double* __restrict__ colres) {
+  const int j = blockIdx.x;
+  __shared__ double part[4];
+  double a = 0.0;
+  const double s = S[j];
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double r = Y[(long long)i * k + j] - s * V[(long long)i * k + j];
+    a += r * r;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) colres[j] = sqrt(part[0] + part[1] + part[2] + part[3]);
+  (void)chi;
+}
+
+__global__ void max_over_kernel(const double* __restrict__ x, int n, const double* __restrict__ ref,
+                                double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m = fmax(m, x[i]);
+  *out = (ref[0] > 0.0) ? m / ref[0] : m;
+}
+
+// sign convention on the kept left singular vectors of M (= W): the first
+// entry within a relative 1e-8 of the largest magnitude is made positive; the
+// matching columns of V flip with them
+__global__ __launch_bounds__(256) void signfix_kernel(int n, int ldw, double* __restrict__ W,
+                                                      int ldv, double* __restrict__ V) {
+  const int j = blockIdx.x;
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  double best = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) best = fmax(best, fabs(W[(long long)i * ldw + j]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double thr = (1.0 - 1e-8) * mx;
+  int idx = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += 256)
+    if (fabs(W[(long long)i * ldw + j]) >= thr) {
+      idx = i;
+      break;
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) idx = min(idx, __shfl_xor(idx, o, 64));
+  if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = idx;
+  __syncthreads();
+  const int first = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  const double sg = (first < n && W[(long long)first * ldw + j] < 0.0) ? -1.0 : 1.0;
+  if (sg < 0.0)
+    for (int i = threadIdx.x; i < n; i += 256) {
+      W[(long long)i * ldw + j] = -W[(long long)i * ldw + j];
+      V[(long long)i * ldv + j] = -V[(long long)i * ldv + j];
+    }
+}
+
+// spectra: normalise each row of S to unit l2 norm, compare with prev,
+// out = max over rows of the l2 difference; prev <- normalised S
+__global__ void spectra_delta_kernel(const double* __restrict__ S, double* __restrict__ prev,
+                                     int rows, int chi, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double dmax = 0.0;
+  for (int r = 0; r < rows; ++r) {
+    double nrm = 0.0;
+    for (int i = 0; i < chi; ++i) nrm += S[r * chi + i] * S[r * chi + i];
+    nrm = sqrt(nrm);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    double dd = 0.0;
+    for (int i = 0; i < chi; ++i) {
+      const double v = S[r * chi + i] * inv;
+      const double e = v - prev[r * chi + i];
+      dd += e * e;
+      prev[r * chi + i] = v;
+    }
+    dmax = fmax(dmax, sqrt(dd));
+  }
+  *out = dmax;
+}
+
+__global__ void trace_normalize_kernel(double* __restrict__ R, int dim, long long stride) {
+  double* r = R + (long long)blockIdx.x * stride;
+  __shared__ double tr;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < dim; ++i) t += r[i * dim + i];
+    tr = t;
+  }
+  __syncthreads();
+  const double inv = 1.0 / tr;
+  for (int i = threadIdx.x; i < dim * dim; i += blockDim.x) r[i] *= inv;
+}
+
+__global__ void finite_check_kernel(const double* __restrict__ x, long long n, int* flag) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+struct Frames {
+  int Lx[4], Ly[4];
+  std::vector<int> pos[4];  // pos[f][y*Lx_f + x] = lattice position
+  int at(int f, int x, int y) const {
+    const int lx = Lx[f], ly = Ly[f];
+    x = ((x % lx) + lx) % lx;
+    y = ((y % ly) + ly) % ly;
+    return pos[f][y * lx + x];
+  }
+};
+
+Frames make_frames(int Lx, int Ly) {
+  Frames F;
+  F.Lx[0] = Lx;
+  F.Ly[0] = Ly;
+  F.pos[0].resize(Lx * Ly);
+  for (int p = 0; p < Lx * Ly; ++p) F.pos[0][p] = p;
+  for (int f = 1; f < 4; ++f) {
+    const int ox = F.Lx[f - 1], oy = F.Ly[f - 1];
+    F.Lx[f] = oy;
+    F.Ly[f] = ox;
+    F.pos[f].resize(Lx * Ly);
+    for (int yn = 0; yn < ox; ++yn)
+      for (int xn = 0; xn < oy; ++xn) {
+        const int x = ((-yn) % ox + ox) % ox, y = xn;
+        F.pos[f][yn * oy + xn] = F.pos[f - 1][y * ox + x];
+      }
+  }
+  return F;
+}
+
+struct Geo {
+  int Lx, Ly, D, d, nsite, chi, npos, n;
+  std::vector<int> cell;
+  Frames F;
+  const double* arot[4];  // rotated site tensors [nsite][d][D^4]
+  double* C;
+  double* T;
+  long long csz() const { return (long long)chi * chi; }
+  long long tsz() const { return (long long)chi * D * D * chi; }
+  double* Cp(int p, int k) const { return C + ((long long)p * 4 + (k & 3)) * csz(); }
+  double* Tp(int p, int k) const { return T + ((long long)p * 4 + (k & 3)) * tsz(); }
+  const double* site(int f, int p) const {
+    return arot[f & 3] + (long long)cell[p] * d * D * D * D * D;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// contractions
+// ---------------------------------------------------------------------------
+
+// Upper-left enlarged corner
+// E[(a, dk, db), (b, rk, rb)] = sum C[g,h] T1[h,uk,ub,b] T4[a,lk,lb,g] A[s,lk,rk,dk,uk] A[s,lb,rb,db,ub]
+// scratch: X1 chi*D2*chi, X2 chi*D2*D2*chi, X3 chi*chi*d*D2*D2.
+int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, const double* T4,
+              const double* A, double* E, double* X1, double* X2, double* X3) {
+  const long long chi = g.chi, D = g.D, d = g.d, D2 = D * D, D4 = D2 * D2, n = g.n;
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T4, (int)chi, false, Cc, (int)chi, false,
+              X1, (int)chi, 1.0, 0.0));
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
+              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
+  Contraction c3;
+  c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
+  c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
+  c3.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
+  c3.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
+  c3.cm = grp({{(int)chi, chi * d * D4}, {(int)D, D}, {(int)D, 1}, {(int)chi, d * D4}});
+  c3.cn = grp({{(int)d, D2}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
+  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
+  Contraction c4;
+  c4.am = grp({{(int)chi, chi * d * D4}, {(int)chi, d * D4}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
+  c4.ak = grp({{(int)d, D2}, {(int)D, D}, {(int)D, 1}});
+  c4.bk = grp({{(int)d, D4}, {(int)D, D2 * D}, {(int)D, 1}});
+  c4.bn = grp({{(int)D, D2}, {(int)D, D}});
+  c4.cm = grp({{(int)chi, D2 * n}, {(int)chi, D2}, {(int)D, D}, {(int)D, D * n}});
+  c4.cn = grp({{(int)D, 1}, {(int)D, n}});
+  TN_TRY(tc_run(ctx, c4, X3, A, E, 1.0, 0.0));
+  return TN_OK;
+}
+
+// corner j of the block in frame f: frame-(f+j) upper-left corner at lattice position p
+int corner_of(tn_ctx* ctx, const Geo& g, int fj, int p, double* E, double* X1, double* X2,
+              double* X3) {
+  return corner_ul(ctx, g, g.Cp(p, fj), g.Tp(p, fj), g.Tp(p, fj + 3), g.site(fj, p), E, X1, X2, X3);
+}
+
+struct TopK {
+  int n, k, chi;
+  const double* E[4];
+  double *t1, *t2;
+};
+
+// Y = K X with K = E2 E3 E0 E1
+int applyK(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
+  const int n = t.n, k = t.k;
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, false, X, k, false, t.t1, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, false, t.t1, k, false, t.t2, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, false, t.t2, k, false, t.t1, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, false, t.t1, k, false, Y, k, 1.0, 0.0));
+  return TN_OK;
+}
+
+// Y = K^T X
+int applyKT(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
+  const int n = t.n, k = t.k;
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, true, X, k, false, t.t1, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, true, t.t1, k, false, t.t2, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, true, t.t2, k, false, t.t1, k, 1.0, 0.0));
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, true, t.t1, k, false, Y, k, 1.0, 0.0));
+  return TN_OK;
+}
+
+// Column scaling by 1 / max(s_j, floor * s_0) (floor keeps columns below the
+// FP64 resolution of the block at unit scale instead of blowing them up).
+__global__ void inv_scale_cols_kernel(int n, int k, double* X, const double* s, double floor_rel,
+                                      double* sc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < k) sc[t] = fmax(s[t], floor_rel * s[0]);
+  if (t >= (long long)n * k) return;
+  const int j = (int)(t % k);
+  X[t] /= fmax(s[j], floor_rel * s[0]);
+}
+
+// R <- R diag(sc)
+__global__ void right_scale_kernel(int k, double* R, const double* sc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * k) return;
+  R[t] *= sc[t % k];
+}
+
+// Orthonormalise the columns of X (n x k) in place: Cholesky-QR passes, the
+// first `nshift` of them shifted (shifted Cholesky-QR, Fukaya et al., SIAM J.
+// Sci. Comput. 2020), `npass` in total.  R (k x k, optional) with
+// X_in = Q R.  info[0..npass) receives the Cholesky status of each pass.
+int cholqr_passes(tn_ctx* ctx, int n, int k, double* X, double* Rout, double* tmp, int* info,
+                  int npass, int nshift) {
+  // scratch is reused by the next call: later kernels on the same stream
+  // run after these, so releasing the arena slice here is safe
+  const size_t mark = ctx->arena_off;
+  double* G = ws_alloc<double>(ctx, (size_t)k * k);
+  double* R = ws_alloc<double>(ctx, (size_t)k * k * npass);
+  double* Ri = ws_alloc<double>(ctx, (size_t)k * k);
+  double* Racc = ws_alloc<double>(ctx, (size_t)k * k);
+  if (!Racc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in cholqr");
+  const double u = 1.1102230246251565e-16;
+  double* src = X;
+  double* dst = tmp;
+  for (int pass = 0; pass < npass; ++pass) {
+    TN_TRY(gemm(ctx, k, k, n, src, k, true, src, k, false, G, k, 1.0, 0.0));
+    const double shift = pass < nshift ? 11.0 * ((double)n * k + (double)k * (k + 1)) * u : 0.0;
+    TN_TRY(cholesky_inv(ctx, k, G, shift, R + (size_t)pass * k * k, Ri, info + pass));
+    TN_TRY(gemm(ctx, n, k, k, src, k, false, Ri, k, false, dst, k, 1.0, 0.0));
+    std::swap(src, dst);
+  }
+  if (src != X)
+    TN_HIP(ctx, hipMemcpyAsync(X, src, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  if (Rout) {
+    // R = R_last ... R_1
+    TN_HIP(ctx, hipMemcpyAsync(Rout, R + (size_t)(npass - 1) * k * k, (size_t)k * k * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    for (int pass = npass - 2; pass >= 0; --pass) {
+      TN_TRY(gemm(ctx, k, k, k, Rout, k, false, R + (size_t)pass * k * k, k, false, Racc, k, 1.0,
+                  0.0));
+      TN_HIP(ctx, hipMemcpyAsync(Rout, Racc, (size_t)k * k * 8, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+    }
+  }
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
+// Robust orthonormalisation: optional column pre-scaling by `scale` (the
+// current Ritz values, which makes a Ritz-ordered block nearly orthonormal),
+// then shifted Cholesky-QR3; if a pass breaks down, the original block is
+// redone with two shifted passes followed by two plain ones.
+int orth_robust(tn_ctx* ctx, int n, int k, double* X, const double* scale, double* Rout,
+                double* tmp, double* save, int* info) {
+  const size_t mark = ctx->arena_off;
+  double* sc = ws_alloc<double>(ctx, (size_t)k);
+  if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in orth_robust");
+  const long long tot = (long long)n * k;
+  if (scale) {
+    hipLaunchKernelGGL(inv_scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       ctx->stream, n, k, X, scale, 1e-15, sc);
+    TN_HIP(ctx, hipGetLastError());
+  }
+  TN_HIP(ctx, hipMemcpyAsync(save, X, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TN_HIP(ctx, hipMemsetAsync(info, 0, 8 * sizeof(int), ctx->stream));
+  TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 3, 1));
+  int h[8];
+  TN_HIP(ctx, hipMemcpyAsync(h, info, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h[0] || h[1] || h[2]) {
+    TN_HIP(ctx, hipMemcpyAsync(X, save, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemsetAsync(info, 0, 8 * sizeof(int), ctx->stream));
+    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 4, 2));
+    TN_HIP(ctx, hipMemcpyAsync(h, info, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[0] || h[1] || h[2] || h[3])
+      TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
+  }
+  if (scale && Rout) {
+    hipLaunchKernelGGL(right_scale_kernel, dim3((unsigned)((k * k + 255) / 256)), dim3(256), 0,
+                       ctx->stream, k, Rout, sc);
+    TN_HIP(ctx, hipGetLastError());
+  }
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
+struct SvdStats {
+  long long iters = 0, calls = 0, unconverged = 0, explicit_calls = 0;
+};
+
+// Top-chi singular triplets of K = V S W^T (V: left, W: right), n x chi.
+// warm: optional start basis [n][k] followed by its k Ritz values (in/out).
+int topk_svd(tn_ctx* ctx, TopK& t, double* warm, bool warm_valid, double* Vout, double* Sout,
+             double* Wout, double tol, int maxit, unsigned long long seed, SvdStats* st) {
+  const int n = t.n, k = t.k, chi = t.chi;
+  const size_t nk = (size_t)n * k;
+  const long long tot = (long long)n * chi;
+  if (n <= 256) {
+    // small problems: form K and take its full one-sided Jacobi SVD
+    double* Km = ws_alloc<double>(ctx, (size_t)n * n);
+    double* K2 = ws_alloc<double>(ctx, (size_t)n * n);
+    double* Uf = ws_alloc<double>(ctx, (size_t)n * n);
+    double* Vf = ws_alloc<double>(ctx, (size_t)n * n);
+    double* Sf = ws_alloc<double>(ctx, (size_t)n);
+    if (!Sf) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
+    TN_TRY(gemm(ctx, n, n, n, t.E[0], n, false, t.E[1], n, false, Km, n, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, n, n, t.E[3], n, false, Km, n, false, K2, n, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, n, n, t.E[2], n, false, K2, n, false, Km, n, 1.0, 0.0));
+    TN_TRY(jacobi_svd(ctx, 1, n, n, Km, n, 0, Uf, n, 0, Sf, 0, Vf, n, 0));
+    hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       ctx->stream, n, n, chi, Uf, Vout);
+    hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       ctx->stream, n, n, chi, Vf, Wout);
+    TN_HIP(ctx, hipMemcpyAsync(Sout, Sf, chi * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi, Wout, chi,
+                       Vout);
+    TN_HIP(ctx, hipGetLastError());
+    if (st) st->explicit_calls += 1;
+    return TN_OK;
+  }
+  double* Q = ws_alloc<double>(ctx, nk);
+  double* B = ws_alloc<double>(ctx, nk);
+  double* Y = ws_alloc<double>(ctx, nk);
+  double* Wb = ws_alloc<double>(ctx, nk);
+  double* Vr = ws_alloc<double>(ctx, nk);
+  double* tmp = ws_alloc<double>(ctx, nk);
+  double* save = ws_alloc<double>(ctx, nk);
+  double* R = ws_alloc<double>(ctx, (size_t)k * k);
+  double* UR = ws_alloc<double>(ctx, (size_t)k * k);
+  double* VR = ws_alloc<double>(ctx, (size_t)k * k);
+  double* S = ws_alloc<double>(ctx, (size_t)k);
+  double* Sprev = ws_alloc<double>(ctx, (size_t)k);
+  double* colres = ws_alloc<double>(ctx, (size_t)k);
+  double* res = ws_alloc<double>(ctx, 1);
+  int* info = ws_alloc<int>(ctx, 8);
+  if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
+  bool have_s = false;
+  if (warm && warm_valid) {
+    TN_HIP(ctx, hipMemcpyAsync(Q, warm, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(Sprev, warm + nk, k * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    have_s = true;
+  } else {
+    TN_TRY(fill_random(ctx, Q, (long long)nk, seed));
+  }
+  TN_TRY(orth_robust(ctx, n, k, Q, nullptr, nullptr, tmp, save, info));
+  int it = 0;
+  double hres = 1.0;
+  for (it = 1; it <= maxit; ++it) {
+    TN_TRY(applyKT(ctx, t, Q, B));
+    TN_TRY(orth_robust(ctx, n, k, B, have_s ? Sprev : nullptr, R, tmp, save, info));
+    TN_TRY(jacobi_svd(ctx, 1, k, k, R, k, 0, UR, k, 0, S, 0, VR, k, 0));
+    TN_TRY(gemm(ctx, n, k, k, B, k, false, UR, k, false, Wb, k, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0));
+    TN_TRY(applyK(ctx, t, Wb, Y));
+    hipLaunchKernelGGL(resid_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, k, chi, Y, Vr, S,
+                       colres);
+    hipLaunchKernelGGL(max_over_kernel, dim3(1), dim3(1), 0, ctx->stream, colres, chi, S, res);
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, res, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    hres = ctx->host_scratch[0];
+    if (!std::isfinite(hres)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite residual in the projector SVD");
+    if (hres <= tol || it == maxit) break;
+    TN_HIP(ctx, hipMemcpyAsync(Q, Y, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    TN_TRY(orth_robust(ctx, n, k, Q, S, nullptr, tmp, save, info));
+    TN_HIP(ctx, hipMemcpyAsync(Sprev, S, k * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    have_s = true;
+  }
+  if (st) {
+    st->iters += it;
+    st->calls += 1;
+    if (hres > tol) st->unconverged += 1;
+  }
+  if (warm) {
+    TN_HIP(ctx, hipMemcpyAsync(warm, Vr, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(warm + nk, S, k * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  }
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, n, k, chi, Vr, Vout);
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, n, k, chi, Wb, Wout);
+  TN_HIP(ctx, hipMemcpyAsync(Sout, S, chi * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi, Wout, chi, Vout);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
+struct MoveBufs {
+  double* E[4];
+  double *X1, *X2, *X3;
+  double *P, *PtT;        // [Ly][n][chi]
+  double *V, *W, *S;      // n x chi, n x chi, chi
+  double *G1;             // n x chi
+  double *t1, *t2;        // n x k
+  double *Cn1, *Tn4, *Cn4;  // new tensors [Ly][...]
+  double* CT;             // chi*D2*chi
+  double* warm;           // [4][Lx][Ly][n][k] or null
+  int k;
+};
+
+// left move in frame f at frame column x
+int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st, bool* warm_ok) {
+  const Frames& F = g.F;
+  const int Lyf = F.Ly[f], Lxf = F.Lx[f];
+  const int n = g.n, chi = g.chi, D = g.D, d = g.d;
+  const long long D2 = (long long)D * D;
+  const long long nchi = (long long)n * chi;
+  for (int y = 0; y < Lyf; ++y) {
+    const int ptl = F.at(f, x, y), ptr = F.at(f, x + 1, y);
+    const int pbr = F.at(f, x + 1, y + 1), pbl = F.at(f, x, y + 1);
+    TN_TRY(corner_of(ctx, g, f + 0, ptl, b.E[0], b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 1, ptr, b.E[1], b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 2, pbr, b.E[2], b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 3, pbl, b.E[3], b.X1, b.X2, b.X3));
+    TopK t;
+    t.n = n;
+    t.k = b.k;
+    t.chi = chi;
+    for (int j = 0; j < 4; ++j) t.E[j] = b.E[j];
+    t.t1 = b.t1;
+    t.t2 = b.t2;
+    const size_t slot = ((size_t)f * (Lxf * Lyf) + (size_t)y * Lxf + x);
+    double* warm = b.warm ? b.warm + slot * ((size_t)n * b.k + b.k) : nullptr;
+    const bool wv = warm && warm_ok[slot];
+    const size_t mark = ctx->arena_off;
+    TN_TRY(topk_svd(ctx, t, warm, wv, b.V, b.S, b.W, 1e-13, 40,
+                    0x5DEECE66DULL * (slot + 1), st));
+    ctx->arena_off = mark;
+    if (warm) warm_ok[slot] = true;
+    // P = E3^T (E2^T V) S^-1/2 ; Pt^T = E0 (E1 W) S^-1/2
+    double* P = b.P + (size_t)y * nchi;
+    double* PtT = b.PtT + (size_t)y * nchi;
+    TN_TRY(gemm(ctx, n, chi, n, b.E[2], n, true, b.V, chi, false, b.G1, chi, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, chi, n, b.E[3], n, true, b.G1, chi, false, P, chi, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, chi, n, b.E[1], n, false, b.W, chi, false, b.G1, chi, 1.0, 0.0));
+    TN_TRY(gemm(ctx, n, chi, n, b.E[0], n, false, b.G1, chi, false, PtT, chi, 1.0, 0.0));
+    TN_TRY(scale_columns(ctx, n, chi, P, chi, b.S, 1));
+    TN_TRY(scale_columns(ctx, n, chi, PtT, chi, b.S, 1));
+  }
+  const long long csz = (long long)chi * chi, tsz = (long long)chi * D2 * chi;
+  const long long dD4 = (long long)d * D2 * D2;
+  for (int y = 0; y < Lyf; ++y) {
+    const int src = F.at(f, x, y), s1 = F.at(f, x, y + 1);
+    const double* P = b.P + (size_t)y * nchi;
+    const double* PtTy = b.PtT + (size_t)y * nchi;
+    const double* PtTm = b.PtT + (size_t)((y - 1 + Lyf) % Lyf) * nchi;
+    // C1 of (x+1, y+1) = P_y^T (C1 T1)(x, y+1)
+    TN_TRY(gemm(ctx, chi, (int)(D2 * chi), chi, g.Cp(s1, f), chi, false, g.Tp(s1, f),
+                (int)(D2 * chi), false, b.CT, (int)(D2 * chi), 1.0, 0.0));
+    TN_TRY(gemm(ctx, chi, chi, n, P, chi, true, b.CT, chi, false, b.Cn1 + y * csz, chi, 1.0, 0.0));
+    // C4 of (x+1, y) = [T3 C4](x, y) Pt_y^T, Z[a3, (b4, k, b)]
+    {
+      Contraction c;
+      c.am = grp({{chi, D2 * chi}, {D, (long long)D * chi}, {D, chi}});
+      c.ak = grp({{chi, 1}});
+      c.bk = grp({{chi, chi}});
+      c.bn = grp({{chi, 1}});
+      c.cm = grp({{chi, (long long)n}, {D, D}, {D, 1}});
+      c.cn = grp({{chi, D2}});
+      TN_TRY(tc_run(ctx, c, g.Tp(src, f + 2), g.Cp(src, f + 3), b.CT, 1.0, 0.0));
+      TN_TRY(gemm(ctx, chi, chi, n, b.CT, n, false, PtTy, chi, false, b.Cn4 + y * csz, chi, 1.0,
+                  0.0));
+    }
+    // T4 of (x+1, y) = Pt_{y-1} (T4 a a)(x, y) P_y
+    {
+      const double* T4 = g.Tp(src, f + 3);
+      const double* A = g.site(f, src);
+      const long long nn = n;
+      double* Y1 = b.X2;  // chi * D2 * n
+      double* Y2 = b.X3;  // chi * d * D4 * chi
+      double* Y3 = b.X2;  // chi * D2 * n (Y1 is dead by then)
+      Contraction a;  // Y1[c, uk, ub, a, lk, lb] = sum_b PtT[(b,uk,ub), c] T4[a, lk, lb, b]
+      a.am = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}});
+      a.ak = grp({{chi, D2 * chi}});
+      a.bk = grp({{chi, 1}});
+      a.bn = grp({{chi, D2 * chi}, {D, (long long)D * chi}, {D, chi}});
+      a.cm = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
+      a.cn = grp({{chi, D2}, {D, D}, {D, 1}});
+      TN_TRY(tc_run(ctx, a, PtTm, T4, Y1, 1.0, 0.0));
+      Contraction bk;  // Y2[c, a, rk, dk, s, lb, ub] = sum_{lk,uk} Y1[...] A[s,lk,rk,dk,uk]
+      bk.am = grp({{chi, D2 * nn}, {D, nn}, {chi, D2}, {D, 1}});
+      bk.ak = grp({{D, D}, {D, (long long)D * nn}});
+      bk.bk = grp({{D, D2 * D}, {D, 1}});
+      bk.bn = grp({{d, D2 * D2}, {D, D2}, {D, D}});
+      bk.cm = grp({{chi, chi * dD4}, {D, 1}, {chi, dD4}, {D, D}});
+      bk.cn = grp({{d, D2}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
+      TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0));
+      Contraction cb;  // Y3[c, rk, rb, a, dk, db] = sum_{s,lb,ub} Y2[...] A[s,lb,rb,db,ub]
+      cb.am = grp({{chi, chi * dD4}, {chi, dD4}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
+      cb.ak = grp({{d, D2}, {D, D}, {D, 1}});
+      cb.bk = grp({{d, D2 * D2}, {D, D2 * D}, {D, 1}});
+      cb.bn = grp({{D, D2}, {D, D}});
+      cb.cm = grp({{chi, D2 * nn}, {chi, D2}, {D, (long long)D * nn}, {D, D}});
+      cb.cn = grp({{D, nn}, {D, 1}});
+      TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0));
+      Contraction dp;  // T4new[e, rk, rb, c] = sum_i Y3[c, rk, rb, i] P[i, e]
+      dp.am = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
+      dp.ak = grp({{(int)nn, 1}});
+      dp.bk = grp({{(int)nn, chi}});
+      dp.bn = grp({{chi, 1}});
+      dp.cm = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}});
+      dp.cn = grp({{chi, D2 * chi}});
+      TN_TRY(tc_run(ctx, dp, Y3, P, b.Tn4 + y * tsz, 1.0, 0.0));
+    }
+  }
+  // write back and normalise
+  for (int y = 0; y < Lyf; ++y) {
+    const int dst = F.at(f, x + 1, y), d1 = F.at(f, x + 1, y + 1);
+    TN_HIP(ctx, hipMemcpyAsync(g.Cp(d1, f), b.Cn1 + y * csz, csz * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(g.Tp(dst, f + 3), b.Tn4 + y * tsz, tsz * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(g.Cp(dst, f + 3), b.Cn4 + y * csz, csz * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_TRY(frob_normalize(ctx, g.Cp(d1, f), csz, nullptr));
+    TN_TRY(frob_normalize(ctx, g.Tp(dst, f + 3), tsz, nullptr));
+    TN_TRY(frob_normalize(ctx, g.Cp(dst, f + 3), csz, nullptr));
+  }
+  return TN_OK;
+}
+
+int check_geometry(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                   const int* cell, int chi, const void* C, const void* T) {
+  if (!ctx) return TN_EINVAL;
+  if (Lx < 1 || Ly < 1 || D < 1 || d < 1 || nsite < 1 || chi < 1)
+    TN_FAIL(ctx, TN_EINVAL, "sizes must be positive (Lx=%d Ly=%d D=%d d=%d nsite=%d chi=%d)",
+            Lx, Ly, D, d, nsite, chi);
+  if (Lx * Ly > 64) TN_FAIL(ctx, TN_EINVAL, "cell larger than 64 positions");
+  if (!sites || !cell || !C || !T) TN_FAIL(ctx, TN_EINVAL, "null pointer argument");
+  for (int p = 0; p < Lx * Ly; ++p)
+    if (cell[p] < 0 || cell[p] >= nsite)
+      TN_FAIL(ctx, TN_EINVAL, "cell[%d] = %d out of range [0, %d)", p, cell[p], nsite);
+  const long long n = (long long)chi * D * D;
+  if (n > 32768) TN_FAIL(ctx, TN_EINVAL, "chi*D*D = %lld too large", n);
+  return TN_OK;
+}
+
+int setup_geo(tn_ctx* ctx, Geo& g, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+              const int* cell, int chi, double* C, double* T) {
+  g.Lx = Lx;
+  g.Ly = Ly;
+  g.D = D;
+  g.d = d;
+  g.nsite = nsite;
+  g.chi = chi;
+  g.npos = Lx * Ly;
+  g.n = chi * D * D;
+  g.cell.assign(cell, cell + Lx * Ly);
+  g.F = make_frames(Lx, Ly);
+  g.C = C;
+  g.T = T;
+  const long long asz = (long long)nsite * d * D * D * D * D;
+  g.arot[0] = sites;
+  const double* prev = sites;
+  for (int f = 1; f < 4; ++f) {
+    double* r = ws_alloc<double>(ctx, asz);
+    if (!r) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (rotated sites)");
+    for (int s = 0; s < nsite; ++s) {
+      const long long one = (long long)d * D * D * D * D;
+      hipLaunchKernelGGL(rotate_site_kernel, dim3((unsigned)((one + 255) / 256)), dim3(256), 0,
+                         ctx->stream, prev + s * one, r + s * one, d, D);
+    }
+    TN_HIP(ctx, hipGetLastError());
+    g.arot[f] = r;
+    prev = r;
+  }
+  return TN_OK;
+}
+
+size_t move_bytes(const Geo& g, int k, bool warm) {
+  const size_t chi = g.chi, D = g.D, d = g.d, D2 = D * D, n = g.n;
+  const int Lm = std::max(g.Lx, g.Ly);
+  size_t b = 0;
+  auto add = [&](size_t cnt) { b += ((cnt * 8 + 255) / 256) * 256; };
+  for (int j = 0; j < 4; ++j) add(n * n);
+  add(chi * D2 * chi);
+  add(std::max(chi * D2 * D2 * chi, chi * D2 * n));
+  add(chi * chi * d * D2 * D2);
+  add(Lm * n * chi);
+  add(Lm * n * chi);
+  add(n * chi);
+  add(n * chi);
+  add(chi);
+  add(n * chi);
+  add(n * k);
+  add(n * k);
+  add(Lm * chi * chi);
+  add(Lm * chi * D2 * chi);
+  add(Lm * chi * chi);
+  add(chi * D2 * chi);
+  if (warm) add((size_t)4 * g.npos * (n * k + k));
+  // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
+  add(std::max((size_t)7 * n * k, 4 * n * n + n));
+  add(3 * k * k);
+  add(3 * k + 64);
+  add(8 * k * k + k);        // Cholesky-QR passes (one alive at a time)
+  add(2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k);  // jacobi work
+  // rotated sites
+  add(3 * (size_t)g.nsite * d * D2 * D2);
+  // spectra
+  add(8 * (size_t)g.npos * chi * chi);
+  return b + (1 << 20);
+}
+
+int alloc_move_bufs(tn_ctx* ctx, const Geo& g, MoveBufs& b, bool warm) {
+  const size_t chi = g.chi, D = g.D, d = g.d, D2 = D * D, n = g.n;
+  const int Lm = std::max(g.Lx, g.Ly);
+  for (int j = 0; j < 4; ++j) b.E[j] = ws_alloc<double>(ctx, n * n);
+  b.X1 = ws_alloc<double>(ctx, chi * D2 * chi);
+  b.X2 = ws_alloc<double>(ctx, std::max(chi * D2 * D2 * chi, chi * D2 * n));
+  b.X3 = ws_alloc<double>(ctx, chi * chi * d * D2 * D2);
+  b.P = ws_alloc<double>(ctx, Lm * n * chi);
+  b.PtT = ws_alloc<double>(ctx, Lm * n * chi);
+  b.V = ws_alloc<double>(ctx, n * chi);
+  b.W = ws_alloc<double>(ctx, n * chi);
+  b.S = ws_alloc<double>(ctx, chi);
+  b.G1 = ws_alloc<double>(ctx, n * chi);
+  b.t1 = ws_alloc<double>(ctx, n * b.k);
+  b.t2 = ws_alloc<double>(ctx, n * b.k);
+  b.Cn1 = ws_alloc<double>(ctx, Lm * chi * chi);
+  b.Tn4 = ws_alloc<double>(ctx, Lm * chi * D2 * chi);
+  b.Cn4 = ws_alloc<double>(ctx, Lm * chi * chi);
+  b.CT = ws_alloc<double>(ctx, chi * D2 * chi);
+  b.warm = warm ? ws_alloc<double>(ctx, (size_t)4 * g.npos * (n * b.k + b.k)) : nullptr;
+  if (!b.CT || (warm && !b.warm)) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (move buffers)");
+  return TN_OK;
+}
+
+int pick_k(int n, int chi) {
+  int k = chi + std::max(16, chi / 4);
+  k = (k + 15) / 16 * 16;
+  return std::min(k, n);
+}
+
+int finite_or_fail(tn_ctx* ctx, const double* x, long long n, const char* what) {
+  int* flag = ws_alloc<int>(ctx, 1);
+  if (!flag) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  TN_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+  hipLaunchKernelGGL(finite_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     ctx->stream, x, n, flag);
+  int h = 0;
+  TN_HIP(ctx, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h) TN_FAIL(ctx, TN_ENUMERIC, "non-finite values in %s", what);
+  return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reduced density matrices
+// ---------------------------------------------------------------------------
+
+// Left half of the horizontal two-site network in frame f at lattice
+// position p: L[t, s, s', rk, rb, b] (t = T1.b, b = T3.a in frame f).
+int half_left(tn_ctx* ctx, const Geo& g, int f, int p, double* L, double* X1, double* X2,
+              double* X3, double* X4, double* Y) {
+  const long long chi = g.chi, D = g.D, d = g.d, D2 = D * D, D4 = D2 * D2, n = g.n;
+  const double* C1 = g.Cp(p, f);
+  const double* T1 = g.Tp(p, f);
+  const double* T4 = g.Tp(p, f + 3);
+  const double* C4 = g.Cp(p, f + 3);
+  const double* T3 = g.Tp(p, f + 2);
+  const double* A = g.site(f, p);
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T4, (int)chi, false, C1, (int)chi, false,
+              X1, (int)chi, 1.0, 0.0));
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
+              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
+  Contraction c3;  // as the corner: X3[e][t][rk][dk][s][lb][ub]
+  c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
+  c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
+  c3.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
+  c3.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
+  c3.cm = grp({{(int)chi, chi * d * D4}, {(int)D, D}, {(int)D, 1}, {(int)chi, d * D4}});
+  c3.cn = grp({{(int)d, D2}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
+  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
+  // X4[t][s][s'][rk][rb][e][dk][db] = sum_{lb,ub} X3[e,t,rk,dk,s,lb,ub] A[s',lb,rb,db,ub]
+  Contraction c4;
+  c4.am = grp({{(int)chi, chi * d * D4}, {(int)chi, d * D4}, {(int)D, d * D2 * D},
+               {(int)D, d * D2}, {(int)d, D2}});
+  c4.ak = grp({{(int)D, D}, {(int)D, 1}});
+  c4.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
+  c4.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
+  c4.cm = grp({{(int)chi, D2}, {(int)chi, d * d * D2 * n}, {(int)D, D * n}, {(int)D, D},
+               {(int)d, d * D2 * n}});
+  c4.cn = grp({{(int)d, D2 * n}, {(int)D, n}, {(int)D, 1}});
+  TN_TRY(tc_run(ctx, c4, X3, A, X4, 1.0, 0.0));
+  // Y[(b, dk, db), e] = T3[(b,dk,db), f] C4[f, e]
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T3, (int)chi, false, C4, (int)chi, false,
+              Y, (int)chi, 1.0, 0.0));
+  // L[(t,s,s',rk,rb), b] = sum_{e,dk,db} X4[..., e, dk, db] Y[b, dk, db, e]
+  Contraction c6;
+  c6.am = grp({{(int)(chi * d * d * D2), n}});
+  c6.ak = grp({{(int)chi, D2}, {(int)D, D}, {(int)D, 1}});
+  c6.bk = grp({{(int)chi, 1}, {(int)D, D * chi}, {(int)D, chi}});
+  c6.bn = grp({{(int)chi, D2 * chi}});
+  c6.cm = grp({{(int)(chi * d * d * D2), chi}});
+  c6.cn = grp({{(int)chi, 1}});
+  TN_TRY(tc_run(ctx, c6, X4, Y, L, 1.0, 0.0));
+  return TN_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public entry points (C ABI wrappers live in abi.hip)
+// ---------------------------------------------------------------------------
+
+int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                   const int* cell, int chi, double* C, double* T, int max_iter, double tol,
+                   int n_moves, int first_dir, int* iters, double* delta) {
+  TN_TRY(check_geometry(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T));
+  Geo g;
+  const int n = chi * D * D;
+  const int k = pick_k(n, chi);
+  {
+    Geo tmp;
+    tmp.Lx = Lx;
+    tmp.Ly = Ly;
+    tmp.D = D;
+    tmp.d = d;
+    tmp.nsite = nsite;
+    tmp.chi = chi;
+    tmp.npos = Lx * Ly;
+    tmp.n = n;
+    TN_TRY(ws_reserve(ctx, move_bytes(tmp, k, true)));
+  }
+  ws_reset(ctx);
+  TN_TRY(setup_geo(ctx, g, Lx, Ly, D, d, nsite, sites, cell, chi, C, T));
+  MoveBufs b;
+  b.k = k;
+  TN_TRY(alloc_move_bufs(ctx, g, b, true));
+  std::vector<char> warm_ok((size_t)4 * g.npos, 0);
+  bool* wok = reinterpret_cast<bool*>(warm_ok.data());
+  SvdStats st;
+  const size_t base = ctx->arena_off;
+  if (n_moves > 0) {
+    // exact move count, in iteration order starting at first_dir
+    int done = 0, f = first_dir & 3;
+    while (done < n_moves) {
+      for (int x = 0; x < g.F.Lx[f] && done < n_moves; ++x, ++done) {
+        ctx->arena_off = base;
+        TN_TRY(left_move(ctx, g, f, x, b, &st, wok));
+      }
+      f = (f + 1) & 3;
+    }
+    TN_TRY(finite_or_fail(ctx, C, (long long)g.npos * 4 * g.csz(), "corners"));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return TN_OK;
+  }
+  // iterate to convergence
+  const int rows = g.npos * 4;
+  double* Sprev = ws_alloc<double>(ctx, (size_t)rows * chi);
+  double* Sc = ws_alloc<double>(ctx, (size_t)rows * chi);
+  double* dd = ws_alloc<double>(ctx, 1);
+  if (!dd) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (spectra)");
+  const size_t base2 = ctx->arena_off;
+  // spectra of the starting corners
+  TN_TRY(jacobi_svd(ctx, rows, chi, chi, C, chi, g.csz(), nullptr, 0, 0, Sc, chi, nullptr, 0, 0));
+  hipLaunchKernelGGL(spectra_delta_kernel, dim3(1), dim3(1), 0, ctx->stream, Sc, Sprev, rows, chi,
+                     dd);
+  int it = 0;
+  double hd = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    for (int f = 0; f < 4; ++f)
+      for (int x = 0; x < g.F.Lx[f]; ++x) {
+        ctx->arena_off = base2;
+        TN_TRY(left_move(ctx, g, f, x, b, &st, wok));
+      }
+    ctx->arena_off = base2;
+    TN_TRY(jacobi_svd(ctx, rows, chi, chi, C, chi, g.csz(), nullptr, 0, 0, Sc, chi, nullptr, 0, 0));
+    hipLaunchKernelGGL(spectra_delta_kernel, dim3(1), dim3(1), 0, ctx->stream, Sc, Sprev, rows,
+                       chi, dd);
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dd, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    hd = ctx->host_scratch[0];
+    if (!std::isfinite(hd)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite corner spectra");
+    if (hd < tol) break;
+  }
+  if (iters) *iters = std::min(it, max_iter);
+  if (delta) *delta = hd;
+  return (hd < tol) ? TN_OK : TN_NOT_CONVERGED;
+}
+
+int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                    const int* cell, int chi, const double* C, const double* T, double* rho1,
+                    double* rhoh, double* rhov) {
+  TN_TRY(check_geometry(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T));
+  if (!rho1 || !rhoh || !rhov) TN_FAIL(ctx, TN_EINVAL, "null output pointer");
+  const size_t chi_ = chi, D_ = D, d_ = d, D2 = D_ * D_, n = chi_ * D2;
+  size_t need = 0;
+  auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
+  add(chi_ * D2 * chi_);
+  add(chi_ * D2 * D2 * chi_);
+  add(chi_ * chi_ * d_ * D2 * D2);
+  add(chi_ * chi_ * d_ * d_ * D2 * D2);
+  add(chi_ * D2 * chi_);
+  add(2 * chi_ * d_ * d_ * D2 * chi_);
+  add(chi_ * D2 * chi_);
+  add(3 * nsite * d_ * D2 * D2);
+  TN_TRY(ws_reserve(ctx, need + (1 << 20)));
+  ws_reset(ctx);
+  Geo g;
+  TN_TRY(setup_geo(ctx, g, Lx, Ly, D, d, nsite, sites, cell, chi, const_cast<double*>(C),
+                   const_cast<double*>(T)));
+  double* X1 = ws_alloc<double>(ctx, chi_ * D2 * chi_);
+  double* X2 = ws_alloc<double>(ctx, chi_ * D2 * D2 * chi_);
+  double* X3 = ws_alloc<double>(ctx, chi_ * chi_ * d_ * D2 * D2);
+  double* X4 = ws_alloc<double>(ctx, chi_ * chi_ * d_ * d_ * D2 * D2);
+  double* Y = ws_alloc<double>(ctx, chi_ * D2 * chi_);
+  double* L1 = ws_alloc<double>(ctx, 2 * chi_ * d_ * d_ * D2 * chi_);
+  double* L2 = L1 + chi_ * d_ * d_ * D2 * chi_;
+  double* Rc = ws_alloc<double>(ctx, chi_ * D2 * chi_);
+  if (!Rc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (rdms)");
+  const long long cD = (long long)chi * D * D;
+  const long long dd = d;
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) {
+      const int p = g.F.at(0, x, y);
+      // one-site: L(0, p) closed by C2 T2 C3
+      TN_TRY(half_left(ctx, g, 0, p, L1, X1, X2, X3, X4, Y));
+      TN_TRY(gemm(ctx, chi, (int)(D2 * chi_), chi, g.Cp(p, 1), chi, false, g.Tp(p, 1),
+                  (int)(D2 * chi_), false, X1, (int)(D2 * chi_), 1.0, 0.0));
+      TN_TRY(gemm(ctx, (int)(chi_ * D2), chi, chi, X1, chi, false, g.Cp(p, 2), chi, false, Rc, chi,
+                  1.0, 0.0));
+      Contraction c1;
+      c1.am = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
+      c1.ak = grp({{chi, dd * dd * D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
+      c1.bk = grp({{chi, (long long)D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
+      c1.bn = grp({{1, 0}});
+      c1.cm = grp({{d, dd}, {d, 1}});
+      c1.cn = grp({{1, 0}});
+      TN_TRY(tc_run(ctx, c1, L1, Rc, rho1 + (long long)p * d * d, 1.0, 0.0));
+      // horizontal pair (x, y)-(x+1, y): L(0, p) with L(2, q)
+      const int q = g.F.at(0, x + 1, y);
+      TN_TRY(half_left(ctx, g, 2, q, L2, X1, X2, X3, X4, Y));
+      Contraction c2;
+      c2.am = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
+      c2.ak = grp({{chi, dd * dd * D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
+      c2.bk = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}, {chi, dd * dd * D2 * chi}});
+      c2.bn = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
+      c2.cm = grp({{d, dd * dd * dd}, {d, dd}});
+      c2.cn = grp({{d, dd * dd}, {d, 1}});
+      TN_TRY(tc_run(ctx, c2, L1, L2, rhoh + (long long)p * d * d * d * d, 1.0, 0.0));
+      // vertical pair: frame 1 (top site on the left) with frame 3 (bottom site)
+      const int pb = g.F.at(0, x, y + 1);
+      TN_TRY(half_left(ctx, g, 1, p, L1, X1, X2, X3, X4, Y));
+      TN_TRY(half_left(ctx, g, 3, pb, L2, X1, X2, X3, X4, Y));
+      TN_TRY(tc_run(ctx, c2, L1, L2, rhov + (long long)p * d * d * d * d, 1.0, 0.0));
+    }
+  (void)cD;
+  const int npos = Lx * Ly;
+  hipLaunchKernelGGL(trace_normalize_kernel, dim3(npos), dim3(64), 0, ctx->stream, rho1, d,
+                     (long long)d * d);
+  hipLaunchKernelGGL(trace_normalize_kernel, dim3(npos), dim3(64), 0, ctx->stream, rhoh, d * d,
+                     (long long)d * d * d * d);
+  hipLaunchKernelGGL(trace_normalize_kernel, dim3(npos), dim3(64), 0, ctx->stream, rhov, d * d,
+                     (long long)d * d * d * d);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}

@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every symbol include/itebd.h declares
+(CPU: no compute calls)."""
+import os
+import re
+
+import pytest
+
+import paper_1411_0391_amd as tn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "itebd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tn.LIB_PATH):
+        from paper_1411_0391_amd import build
+        build.build()
+    return tn.load_library()
+
+
+def test_header_declares_the_calls():
+    names = declared_functions()
+    for n in ("tn_create", "tn_destroy", "ctmrg_iterate", "ipeps_rdms"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) == set(tn.SIGNATURES)
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.tn_version()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(tn.LibraryMissing):
+        tn.load_library(str(tmp_path / "nope.so"))
