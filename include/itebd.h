@@ -131,6 +131,20 @@ int ipeps_rdms(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const doubl
 int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B,
             int ldb, int tb, double* C, int ldc, double alpha, double beta, int precision);
 
+/*
+ * Measurement support.  tn_prof_enable(ctx, 1) starts timing every launch of
+ * the contraction kernel with HIP events on the context stream (and resets
+ * the counters); tn_prof_read returns, since the last enable/read: total
+ * kernel milliseconds, total algorithmic flops (2 M N K per product), the
+ * launch count, and counters[5] = {CTMRG moves, projector SVDs, subspace
+ * iterations, SVDs stopped at the iteration cap, SVDs done by the explicit
+ * small-n path}.  Reading resets everything.  Host pointers; any may be
+ * NULL.
+ */
+int tn_prof_enable(tn_ctx* ctx, int on);
+int tn_prof_read(tn_ctx* ctx, double* gemm_ms, double* gemm_flops, long long* gemm_launches,
+                 long long* counters);
+
 #ifdef __cplusplus
 }
 #endif

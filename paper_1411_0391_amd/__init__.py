@@ -43,6 +43,10 @@ SIGNATURES = {
     "tn_gemm": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "tn_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "tn_prof_read": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
+                                    ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_longlong)]),
 }
 
 
@@ -155,6 +159,19 @@ class Context:
                               _ptr(C), _ptr(T), _ptr(r1), _ptr(rh), _ptr(rv))
         self._check(rc)
         return r1, rh, rv
+
+    def prof_enable(self, on=True):
+        self._check(lib().tn_prof_enable(self._h, int(on)))
+
+    def prof_read(self):
+        ms, fl = ctypes.c_double(0), ctypes.c_double(0)
+        nl = ctypes.c_longlong(0)
+        cnt = (ctypes.c_longlong * 5)()
+        self._check(lib().tn_prof_read(self._h, ctypes.byref(ms), ctypes.byref(fl),
+                                       ctypes.byref(nl), cnt))
+        return dict(gemm_ms=ms.value, gemm_flops=fl.value, gemm_launches=nl.value,
+                    moves=cnt[0], svd_calls=cnt[1], svd_iters=cnt[2], svd_unconverged=cnt[3],
+                    svd_explicit=cnt[4])
 
     def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0):
         M = A.shape[1] if ta else A.shape[0]

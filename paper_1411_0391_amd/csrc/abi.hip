@@ -85,6 +85,7 @@ int tn_destroy(tn_ctx* ctx) {
   if (ctx->arena) (void)hipFree(ctx->arena);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   for (auto& kv : ctx->keep) (void)hipFree(kv.second.first);
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
   delete ctx;
   return TN_OK;
@@ -138,6 +139,43 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
   if (precision != TN_FP64) TN_FAIL(ctx, TN_EINVAL, "tn_gemm supports TN_FP64 only");
   TN_TRY(gemm(ctx, M, N, K, A, lda, ta != 0, B, ldb, tb != 0, C, ldc, alpha, beta));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int tn_prof_enable(tn_ctx* ctx, int on) {
+  if (!ctx) return TN_EINVAL;
+  ctx->prof = on != 0;
+  ctx->ev_used = 0;
+  ctx->prof_flops.clear();
+  ctx->svd_iters = ctx->svd_calls = ctx->svd_unconverged = ctx->svd_explicit = ctx->moves = 0;
+  return TN_OK;
+}
+
+int tn_prof_read(tn_ctx* ctx, double* gemm_ms, double* gemm_flops, long long* gemm_launches,
+                 long long* counters) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double ms = 0.0, fl = 0.0;
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float t = 0.f;
+    TN_HIP(ctx, hipEventElapsedTime(&t, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
+    ms += t;
+  }
+  for (double f : ctx->prof_flops) fl += f;
+  if (gemm_ms) *gemm_ms = ms;
+  if (gemm_flops) *gemm_flops = fl;
+  if (gemm_launches) *gemm_launches = (long long)ctx->prof_flops.size();
+  if (counters) {
+    counters[0] = ctx->moves;
+    counters[1] = ctx->svd_calls;
+    counters[2] = ctx->svd_iters;
+    counters[3] = ctx->svd_unconverged;
+    counters[4] = ctx->svd_explicit;
+  }
+  ctx->ev_used = 0;
+  ctx->prof_flops.clear();
+  ctx->svd_iters = ctx->svd_calls = ctx->svd_unconverged = ctx->svd_explicit = ctx->moves = 0;
   return TN_OK;
 }
 

@@ -26,6 +26,14 @@ struct tn_ctx {
   std::map<std::string, std::pair<void*, size_t>> keep;
   // pinned host staging for small scalar read-backs
   double* host_scratch = nullptr;
+  // optional per-launch timing of the contraction kernel (HIP events on the
+  // context stream) and the algorithmic flops of each timed launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<double> prof_flops;
+  // solver counters since the last read
+  long long svd_iters = 0, svd_calls = 0, svd_unconverged = 0, svd_explicit = 0, moves = 0;
 };
 
 #define TN_FAIL(ctx, code, ...)                                   \

@@ -837,6 +837,11 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
     }
     TN_TRY(finite_or_fail(ctx, C, (long long)g.npos * 4 * g.csz(), "corners"));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->moves += n_moves;
+    ctx->svd_calls += st.calls;
+    ctx->svd_iters += st.iters;
+    ctx->svd_unconverged += st.unconverged;
+    ctx->svd_explicit += st.explicit_calls;
     return TN_OK;
   }
   // iterate to convergence
@@ -871,6 +876,11 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
   }
   if (iters) *iters = std::min(it, max_iter);
   if (delta) *delta = hd;
+  ctx->moves += (long long)std::min(it, max_iter) * (2 * (g.F.Lx[0] + g.F.Lx[1]));
+  ctx->svd_calls += st.calls;
+  ctx->svd_iters += st.iters;
+  ctx->svd_unconverged += st.unconverged;
+  ctx->svd_explicit += st.explicit_calls;
   return (hd < tol) ? TN_OK : TN_NOT_CONVERGED;
 }
 

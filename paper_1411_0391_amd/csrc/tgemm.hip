@@ -201,8 +201,22 @@ int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, 
     // C = beta * C: run with a zero-length k loop
   }
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)c.batch);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->prof) {
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+      hipEvent_t e;
+      TN_HIP(ctx, hipEventCreate(&e));
+      ctx->ev_pool.push_back(e);
+    }
+    e0 = ctx->ev_pool[ctx->ev_used];
+    e1 = ctx->ev_pool[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    ctx->prof_flops.push_back(2.0 * (double)M * (double)N * (double)K * (double)c.batch);
+    TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  }
   hipLaunchKernelGGL(tgemm_f64_kernel, grid, dim3(256), 0, ctx->stream, A, B, C, d, alpha, beta);
   TN_HIP(ctx, hipGetLastError());
+  if (ctx->prof) TN_HIP(ctx, hipEventRecord(e1, ctx->stream));
   return TN_OK;
 }
 

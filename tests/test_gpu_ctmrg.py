@@ -138,3 +138,24 @@ def test_invalid_arguments_are_rejected(ctx):
         ctx.ctmrg_moves(1, 1, sites, [3], C, T, 1)          # site index out of range
     with pytest.raises(tn.TNError):
         ctx.ctmrg_iterate(1, 1, sites, [0], C, T, 0, 1e-8)  # max_iter < 1
+
+
+@pytest.mark.parametrize("cellspec,D,chi", [(tninputs.CHECKERBOARD, 3, 32),
+                                            (tninputs.SINGLE_SITE, 4, 20)])
+def test_subspace_projector_path_parity(ctx, cellspec, D, chi):
+    # n = chi D^2 > 256 takes the subspace-iteration projector SVD; after one
+    # warm-up iteration the environment has a decaying spectrum as in use
+    Lx, Ly, cell, sites, C, T = _setup(cellspec, D, chi, seed=7)
+    ocell = octm.Cell(Lx, Ly, cell)
+    C, T = octm.iteration(ocell, sites, C, T, chi)
+    Cr, Tr, spectra = octm.left_move(ocell, sites, C, T, 0, chi)
+    gap = min(s[chi - 1] / s[chi] for s in spectra)
+    assert gap > 1 + 1e-6
+    Cg, Tg = dev(C), dev(T)
+    ctx.prof_enable(True)
+    ctx.ctmrg_moves(Lx, Ly, dev(np.stack(sites)), cell, Cg, Tg, 1, 0)
+    st = ctx.prof_read()
+    ctx.prof_enable(False)
+    assert st["svd_explicit"] == 0 and st["svd_calls"] == Ly
+    np.testing.assert_allclose(host(Cg), Cr, atol=1e-9)
+    np.testing.assert_allclose(host(Tg), Tr, atol=1e-9)
