@@ -119,6 +119,8 @@ def main():
                      "flops_per_launch": flops_per_launch},
         "step_mfma_tflops": round(prof["gemm_flops"] / elapsed / 1e12, 3),
         "svd_iters_per_projector": round(prof["svd_iters"] / max(1, prof["svd_calls"]), 3),
+        "svd_at_cap": prof["svd_unconverged"],
+        "jacobi_sweeps": prof["jacobi_sweeps"],
     }
     if not args.no_cpu:
         ncores = os.cpu_count() or 1

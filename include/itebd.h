@@ -132,13 +132,35 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
             int ldb, int tb, double* C, int ldc, double alpha, double beta, int precision);
 
 /*
+ * tn_svd -- the library's small dense FP64 SVD (one-sided Jacobi, one
+ * workgroup per matrix), used for the Rayleigh-Ritz step of the projector
+ * SVD, the corner spectra, the canonical-form and gauge-fixing
+ * factorisations.  A = U diag(S) V^T for `batch` row-major m x n matrices
+ * (m >= n, n <= 512) stored back to back; U [batch][m][n], S [batch][n]
+ * (descending), V [batch][n][n]; each column of U sign-fixed so that its
+ * first entry within 1e-8 of its largest magnitude is positive.  A is not
+ * modified.  U and V may be NULL.  Device pointers.
+ */
+int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, double* S,
+           double* V);
+
+/*
+ * tn_clear_cache -- drop the state the context keeps between calls: the
+ * start bases of the projector SVDs of ctmrg_iterate / ctmrg_moves (kept per
+ * cell geometry so that a converging CTMRG restarts its subspace iterations
+ * from the previous projectors).  Results never depend on this state beyond
+ * the SVD tolerance; clearing it makes a call independent of earlier calls.
+ */
+int tn_clear_cache(tn_ctx* ctx);
+
+/*
  * Measurement support.  tn_prof_enable(ctx, 1) starts timing every launch of
  * the contraction kernel with HIP events on the context stream (and resets
  * the counters); tn_prof_read returns, since the last enable/read: total
  * kernel milliseconds, total algorithmic flops (2 M N K per product), the
- * launch count, and counters[5] = {CTMRG moves, projector SVDs, subspace
+ * launch count, and counters[6] = {CTMRG moves, projector SVDs, subspace
  * iterations, SVDs stopped at the iteration cap, SVDs done by the explicit
- * small-n path}.  Reading resets everything.  Host pointers; any may be
+ * small-n path, Jacobi sweeps of the small dense SVDs}.  Reading resets everything.  Host pointers; any may be
  * NULL.
  */
 int tn_prof_enable(tn_ctx* ctx, int on);

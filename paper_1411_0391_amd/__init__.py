@@ -43,6 +43,8 @@ SIGNATURES = {
     "tn_gemm": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "tn_clear_cache": (ctypes.c_int, [_vp]),
+    "tn_svd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tn_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tn_prof_read": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
                                     ctypes.POINTER(ctypes.c_longlong),
@@ -160,18 +162,31 @@ class Context:
         self._check(rc)
         return r1, rh, rv
 
+    def svd(self, A):
+        """Batched small SVD of device matrices A [batch][m][n] -> U, S, V."""
+        import torch
+        b, m, n = A.shape
+        U = torch.empty((b, m, n), dtype=torch.float64, device=A.device)
+        S = torch.empty((b, n), dtype=torch.float64, device=A.device)
+        V = torch.empty((b, n, n), dtype=torch.float64, device=A.device)
+        self._check(lib().tn_svd(self._h, b, m, n, _ptr(A), _ptr(U), _ptr(S), _ptr(V)))
+        return U, S, V
+
+    def clear_cache(self):
+        self._check(lib().tn_clear_cache(self._h))
+
     def prof_enable(self, on=True):
         self._check(lib().tn_prof_enable(self._h, int(on)))
 
     def prof_read(self):
         ms, fl = ctypes.c_double(0), ctypes.c_double(0)
         nl = ctypes.c_longlong(0)
-        cnt = (ctypes.c_longlong * 5)()
+        cnt = (ctypes.c_longlong * 6)()
         self._check(lib().tn_prof_read(self._h, ctypes.byref(ms), ctypes.byref(fl),
                                        ctypes.byref(nl), cnt))
         return dict(gemm_ms=ms.value, gemm_flops=fl.value, gemm_launches=nl.value,
                     moves=cnt[0], svd_calls=cnt[1], svd_iters=cnt[2], svd_unconverged=cnt[3],
-                    svd_explicit=cnt[4])
+                    svd_explicit=cnt[4], jacobi_sweeps=cnt[5])
 
     def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0):
         M = A.shape[1] if ta else A.shape[0]

@@ -11,6 +11,8 @@ int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const 
                     const int* cell, int chi, const double* C, const double* T, double* rho1,
                     double* rhoh, double* rhov);
 
+int jacobi_sweeps_read(tn_ctx* ctx, unsigned long long* out);
+
 int ws_reserve(tn_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_size) return TN_OK;
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -142,8 +144,34 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
   return TN_OK;
 }
 
+int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, double* S,
+           double* V) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  if (batch < 1 || m < 1 || n < 1 || m < n || n > 512 || !A || !S)
+    TN_FAIL(ctx, TN_EINVAL, "tn_svd needs batch >= 1, m >= n >= 1, n <= 512 (m=%d n=%d)", m, n);
+  TN_TRY(ws_reserve(ctx, (size_t)batch * (m * n + n * n) * sizeof(double) + (1 << 20)));
+  ws_reset(ctx);
+  TN_TRY(jacobi_svd(ctx, batch, m, n, const_cast<double*>(A), n, (long long)m * n, U, n,
+                    (long long)m * n, S, n, V, n, (long long)n * n));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int tn_clear_cache(tn_ctx* ctx) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& kv : ctx->keep) TN_HIP(ctx, hipFree(kv.second.first));
+  ctx->keep.clear();
+  ctx->keep_flags.clear();
+  return TN_OK;
+}
+
 int tn_prof_enable(tn_ctx* ctx, int on) {
   if (!ctx) return TN_EINVAL;
+  unsigned long long sw = 0;
+  TN_TRY(jacobi_sweeps_read(ctx, &sw));  // restart the sweep counter too
   ctx->prof = on != 0;
   ctx->ev_used = 0;
   ctx->prof_flops.clear();
@@ -166,7 +194,10 @@ int tn_prof_read(tn_ctx* ctx, double* gemm_ms, double* gemm_flops, long long* ge
   if (gemm_ms) *gemm_ms = ms;
   if (gemm_flops) *gemm_flops = fl;
   if (gemm_launches) *gemm_launches = (long long)ctx->prof_flops.size();
+  unsigned long long sw = 0;
+  TN_TRY(jacobi_sweeps_read(ctx, &sw));
   if (counters) {
+    counters[5] = (long long)sw;
     counters[0] = ctx->moves;
     counters[1] = ctx->svd_calls;
     counters[2] = ctx->svd_iters;

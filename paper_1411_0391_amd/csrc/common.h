@@ -24,6 +24,7 @@ struct tn_ctx {
   std::map<std::string, int*> tables;
   // persistent per-key device buffers (warm starts of iterative solvers)
   std::map<std::string, std::pair<void*, size_t>> keep;
+  std::map<std::string, std::vector<char>> keep_flags;  // host validity flags per buffer slot
   // pinned host staging for small scalar read-backs
   double* host_scratch = nullptr;
   // optional per-launch timing of the contraction kernel (HIP events on the

@@ -352,7 +352,12 @@ int orth_robust(tn_ctx* ctx, int n, int k, double* X, const double* scale, doubl
   }
   TN_HIP(ctx, hipMemcpyAsync(save, X, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
   TN_HIP(ctx, hipMemsetAsync(info, 0, 8 * sizeof(int), ctx->stream));
-  TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 3, 1));
+  // a pre-scaled block is close to orthonormal: two plain passes give
+  // orthogonality to rounding; otherwise shifted Cholesky-QR3
+  if (scale)
+    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 2, 0));
+  else
+    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 3, 1));
   int h[8];
   TN_HIP(ctx, hipMemcpyAsync(h, info, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -681,7 +686,8 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
   add(Lm * chi * D2 * chi);
   add(Lm * chi * chi);
   add(chi * D2 * chi);
-  if (warm) add((size_t)4 * g.npos * (n * k + k));
+  (void)warm;
+  add(16 * n * k + 64 * (size_t)k * k);  // split-K partials of the n x n x k products
   // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
   add(std::max((size_t)7 * n * k, 4 * n * n + n));
   add(3 * k * k);
@@ -820,9 +826,20 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
   TN_TRY(setup_geo(ctx, g, Lx, Ly, D, d, nsite, sites, cell, chi, C, T));
   MoveBufs b;
   b.k = k;
-  TN_TRY(alloc_move_bufs(ctx, g, b, true));
-  std::vector<char> warm_ok((size_t)4 * g.npos, 0);
-  bool* wok = reinterpret_cast<bool*>(warm_ok.data());
+  TN_TRY(alloc_move_bufs(ctx, g, b, false));
+  // projector start bases persist in the context across calls with the same
+  // geometry (a converging CTMRG changes them little between iterations)
+  char key[160];
+  snprintf(key, sizeof(key), "ctm-warm:%d:%d:%d:%d:%d:%d", Lx, Ly, D, d, chi, k);
+  for (int p = 0; p < Lx * Ly; ++p) snprintf(key + strlen(key), sizeof(key) - strlen(key), ":%d", cell[p]);
+  void* wptr = nullptr;
+  bool fresh = false;
+  TN_TRY(keep_buffer(ctx, key, (size_t)4 * g.npos * ((size_t)n * k + k) * sizeof(double), &wptr,
+                     &fresh));
+  b.warm = static_cast<double*>(wptr);
+  std::vector<char>& flags = ctx->keep_flags[key];
+  if (fresh || flags.size() != (size_t)4 * g.npos) flags.assign((size_t)4 * g.npos, 0);
+  bool* wok = reinterpret_cast<bool*>(flags.data());
   SvdStats st;
   const size_t base = ctx->arena_off;
   if (n_moves > 0) {

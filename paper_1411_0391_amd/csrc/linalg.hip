@@ -28,19 +28,22 @@ __device__ inline double wave_max(double v) {
 // z = (b - a) / (2 g), c = 1/sqrt(1 + t^2), s = c t; it makes the pair
 // orthogonal.  Sweeps stop when every |g| <= tol sqrt(a b).
 // ---------------------------------------------------------------------------
-constexpr int SVD_THREADS = 512;
+constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
 
+// work == nullptr: the m x n work matrix and the n x n rotation accumulator
+// live in dynamic LDS; otherwise in the global buffer `work`.
 __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     const double* __restrict__ Ain, int lda, long long sA, double* __restrict__ U, int ldu,
     long long sU, double* __restrict__ S, long long sS, double* __restrict__ V, int ldv,
-    long long sV, int m, int n, double* __restrict__ work, int max_sweeps, double tol) {
+    long long sV, int m, int n, double* __restrict__ work, int max_sweeps, double tol,
+    unsigned long long* __restrict__ sweep_count) {
+  extern __shared__ double lds[];
   const long long b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* A = Ain + b * sA;
-  double* X = work + b * (long long)(m * n + n * n);  // X[j*m + i]
-  double* W = X + (long long)m * n;                    // W[j*n + i] (V columns)
-  __shared__ double off_w[SVD_WAVES];
+  double* X = work ? work + b * (long long)(m * n + n * n) : lds;  // X[j*m + i]
+  double* W = X + (long long)m * n;                                 // W[j*n + i] (V columns)
   __shared__ double colnorm[512];
   __shared__ int perm[512];
   __shared__ int done;
@@ -56,11 +59,15 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
   if (tid == 0) done = 0;
   __syncthreads();
 
+  // 16-lane groups: one column pair per group per round (64 groups)
+  const int grp = tid >> 4, gl = tid & 15;
+  constexpr int NGRP = SVD_THREADS / 16;
+  __shared__ double off_g[NGRP];
   const int N = (n + 1) & ~1;  // players incl. a dummy when n is odd
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
     double offmax = 0.0;
     for (int r = 0; r < N - 1; ++r) {
-      for (int q = wave; q < N / 2; q += SVD_WAVES) {
+      for (int q = grp; q < N / 2; q += NGRP) {
         const int p0 = (q == 0) ? 0 : 1 + ((q - 1 + r) % (N - 1));
         const int p1 = 1 + ((N - 2 - q + r) % (N - 1));
         if (p0 >= n || p1 >= n) continue;
@@ -68,29 +75,32 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
         double* xp = X + (long long)p * m;
         double* xq = X + (long long)qq * m;
         double a = 0.0, bb = 0.0, g = 0.0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += 16) {
           const double u = xp[i], v = xq[i];
           a += u * u;
           bb += v * v;
           g += u * v;
         }
-        a = wave_sum(a);
-        bb = wave_sum(bb);
-        g = wave_sum(g);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, 16);
+          bb += __shfl_xor(bb, o, 16);
+          g += __shfl_xor(g, o, 16);
+        }
         const double scale = sqrt(a * bb);
         if (scale == 0.0 || fabs(g) <= tol * scale) continue;
         offmax = fmax(offmax, fabs(g) / scale);
         const double z = (bb - a) / (2.0 * g);
         const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += 16) {
           const double u = xp[i], v = xq[i];
           xp[i] = c * u - s * v;
           xq[i] = s * u + c * v;
         }
         double* wp = W + (long long)p * n;
         double* wq = W + (long long)qq * n;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = gl; i < n; i += 16) {
           const double u = wp[i], v = wq[i];
           wp[i] = c * u - s * v;
           wq[i] = s * u + c * v;
@@ -98,14 +108,15 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
       }
       __syncthreads();
     }
-    if (lane == 0) off_w[wave] = offmax;
+    if (gl == 0) off_g[grp] = offmax;
     __syncthreads();
     if (tid == 0) {
       double mx = 0.0;
-      for (int w = 0; w < SVD_WAVES; ++w) mx = fmax(mx, off_w[w]);
+      for (int w = 0; w < NGRP; ++w) mx = fmax(mx, off_g[w]);
       done = (mx <= tol) ? 1 : 0;
     }
     __syncthreads();
+    if (tid == 0 && sweep_count) atomicAdd(sweep_count, 1ULL);
     if (done) break;
   }
   // column norms = singular values
@@ -132,25 +143,18 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     const int j = perm[r];
     const double sj = colnorm[j];
     const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-    // argmax |x| over the column (first occurrence)
-    double best = -1.0;
+    // sign: the first entry within a relative 1e-8 of the largest magnitude
+    double best = 0.0;
+    for (int i = lane; i < m; i += 64) best = fmax(best, fabs(X[(long long)j * m + i]));
+    best = wave_max(best);
     int bi = 0x7fffffff;
-    for (int i = lane; i < m; i += 64) {
-      const double v = fabs(X[(long long)j * m + i]);
-      if (v > best) {
-        best = v;
+    for (int i = lane; i < m; i += 64)
+      if (fabs(X[(long long)j * m + i]) >= (1.0 - 1e-8) * best) {
         bi = i;
+        break;
       }
-    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
+    for (int o = 32; o > 0; o >>= 1) bi = min(bi, __shfl_xor(bi, o, 64));
     const double sg = (bi < m && X[(long long)j * m + bi] < 0.0) ? -1.0 : 1.0;
     if (U)
       for (int i = lane; i < m; i += 64)
@@ -163,65 +167,72 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky of G + shift I (right-looking, k steps) and the inverse of the
-// upper factor by back substitution, one column per thread.
+// Cholesky of G + shift I and the inverse of its upper factor.  The trailing
+// matrix lives in LDS; step j reads the unscaled row j, writes row j of R
+// (divided by sqrt of the pivot) and updates the trailing block with
+// W[r][c] -= W[j][r] W[j][c] / W[j][j] -- one barrier per step.  The inverse
+// is back substitution, one column per thread, reading R from LDS when it
+// fits there too.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cholesky_inv_kernel(const double* __restrict__ G, int k,
-                                                           double shift_rel,
-                                                           double* __restrict__ R,
-                                                           double* __restrict__ Rinv,
-                                                           double* __restrict__ Wk,
-                                                           int* __restrict__ info) {
-  const int tid = threadIdx.x;
+constexpr int CHOL_THREADS = 1024;
+
+__global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
+    const double* __restrict__ G, int k, double shift_rel, double* __restrict__ R,
+    double* __restrict__ Rinv, int* __restrict__ info, int r_in_lds) {
+  extern __shared__ double lds[];
+  double* Wk = lds;                        // k x k trailing matrix, later R^-1
+  double* Rl = r_in_lds ? lds + k * k : R;  // R rows as they are produced
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   __shared__ double shift;
-  __shared__ int fail;
-  if (tid == 0) {
+  if (tid < 64) {
     double tr = 0.0;
-    for (int i = 0; i < k; ++i) tr += G[i * k + i];
-    shift = shift_rel * tr;
-    fail = 0;
+    for (int i = tid; i < k; i += 64) tr += G[i * k + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    if (tid == 0) shift = shift_rel * tr;
   }
   __syncthreads();
-  for (int t = tid; t < k * k; t += 256) {
+  for (int t = tid; t < k * k; t += CHOL_THREADS) {
     const int i = t / k, j = t % k;
     Wk[t] = G[t] + ((i == j) ? shift : 0.0);
-    R[t] = 0.0;
+    Rl[t] = 0.0;
   }
   __syncthreads();
+  int fail = 0;
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double dj = Wk[j * k + j];
-      if (!(dj > 0.0)) {
-        fail = j + 1;
-      } else {
-        R[j * k + j] = sqrt(dj);
-      }
+    const double dj = Wk[j * k + j];
+    if (!(dj > 0.0)) {  // every thread sees the same pivot
+      fail = j + 1;
+      break;
     }
-    __syncthreads();
-    if (fail) break;
-    const double rjj = R[j * k + j];
-    for (int c = j + 1 + tid; c < k; c += 256) R[j * k + c] = Wk[j * k + c] / rjj;
-    __syncthreads();
-    const int w = k - j - 1;
-    for (int t = tid; t < w * w; t += 256) {
-      const int r = j + 1 + t / w, c = j + 1 + t % w;
-      if (r <= c) Wk[r * k + c] -= R[j * k + r] * R[j * k + c];
+    const double inv_d = 1.0 / dj, inv_r = 1.0 / sqrt(dj);
+    for (int c = j + tid; c < k; c += CHOL_THREADS) Rl[j * k + c] = Wk[j * k + c] * inv_r;
+    // trailing update of the upper triangle, rows over ty, columns over tx
+    for (int r = j + 1 + ty; r < k; r += 32) {
+      const double wr = Wk[j * k + r] * inv_d;
+      for (int c = r + tx; c < k; c += 32) Wk[r * k + c] -= wr * Wk[j * k + c];
     }
     __syncthreads();
   }
   if (tid == 0) *info = fail;
   if (fail) return;
-  // Rinv column c: solve R x = e_c from the bottom
-  for (int c = tid; c < k; c += 256) {
-    for (int i = k - 1; i >= 0; --i) {
-      if (i > c) {
-        Rinv[i * k + c] = 0.0;
-        continue;
-      }
+  // R^-1 by back substitution in LDS (Wk is free), rows in lockstep from the
+  // bottom so that R[i][l] is a broadcast and the R^-1 column reads of the
+  // lanes (one column each) are consecutive; entries below the diagonal are
+  // zero, so every lane can run the full l range without divergence
+  for (int t = tid; t < k * k; t += CHOL_THREADS) Wk[t] = 0.0;
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    for (int c = i + tid; c < k; c += CHOL_THREADS) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= c; ++l) s -= R[i * k + l] * Rinv[l * k + c];
-      Rinv[i * k + c] = s / R[i * k + i];
+      for (int l = i + 1; l < k; ++l) s -= Rl[i * k + l] * Wk[l * k + c];
+      Wk[i * k + c] = s / Rl[i * k + i];
     }
+    __syncthreads();
+  }
+  for (int t = tid; t < k * k; t += CHOL_THREADS) {
+    Rinv[t] = Wk[t];
+    if (r_in_lds) R[t] = Rl[t];
   }
 }
 
@@ -267,19 +278,43 @@ __global__ void fill_random_kernel(double* x, long long n, unsigned long long se
   x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+constexpr size_t LDS_LIMIT = 150 * 1024;
+
 }  // namespace
+
+// device-side sweep counter for diagnostics (read by tn_prof_read)
+__device__ unsigned long long g_sweep_counter = 0;
+static unsigned long long* g_sweeps = nullptr;
+
+int jacobi_sweeps_read(tn_ctx* ctx, unsigned long long* out) {
+  if (!g_sweeps) TN_HIP(ctx, hipGetSymbolAddress((void**)&g_sweeps, HIP_SYMBOL(g_sweep_counter)));
+  TN_HIP(ctx, hipMemcpy(out, g_sweeps, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  const unsigned long long zero = 0;
+  TN_HIP(ctx, hipMemcpy(g_sweeps, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  return TN_OK;
+}
 
 int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long long sA, double* U,
                int ldu, long long sU, double* S, long long sS, double* V, int ldv, long long sV) {
   if (m < n) TN_FAIL(ctx, TN_EINVAL, "jacobi_svd needs m >= n (m=%d n=%d)", m, n);
   if (n > 512) TN_FAIL(ctx, TN_EINVAL, "jacobi_svd supports n <= 512 (n=%d)", n);
   if (batch <= 0 || n <= 0) return TN_OK;
+  if (!g_sweeps) TN_HIP(ctx, hipGetSymbolAddress((void**)&g_sweeps, HIP_SYMBOL(g_sweep_counter)));
   const size_t mark = ctx->arena_off;  // stream order makes the slice reusable afterwards
-  double* work = ws_alloc<double>(ctx, (size_t)batch * (m * n + n * n));
-  if (!work) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in jacobi_svd");
-  const double tol = 2.220446049250313e-16 * sqrt((double)m);
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(batch), dim3(SVD_THREADS), 0, ctx->stream, A, lda,
-                     sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol);
+  const size_t lds_bytes = (size_t)(m * n + n * n) * sizeof(double);
+  double* work = nullptr;
+  size_t dyn = 0;
+  if (lds_bytes <= LDS_LIMIT) {
+    dyn = lds_bytes;
+  } else {
+    work = ws_alloc<double>(ctx, (size_t)batch * (m * n + n * n));
+    if (!work) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in jacobi_svd");
+  }
+  // rotations stop once every column pair is orthogonal to the rounding
+  // level of its dot product (about m ulp), or the sweeps would never end
+  const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream, A, lda,
+                     sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
   TN_HIP(ctx, hipGetLastError());
   ctx->arena_off = mark;
   return TN_OK;
@@ -287,13 +322,12 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
 
 int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* R, double* Rinv,
                  int* info) {
-  const size_t mark = ctx->arena_off;
-  double* wk = ws_alloc<double>(ctx, (size_t)k * k);
-  if (!wk) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in cholesky_inv");
-  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(1), dim3(256), 0, ctx->stream, G, k, shift_rel, R,
-                     Rinv, wk, info);
+  const size_t one = (size_t)k * k * sizeof(double);
+  if (one > LDS_LIMIT) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports k <= 137 (k=%d)", k);
+  const int r_in_lds = 2 * one <= LDS_LIMIT;
+  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(1), dim3(CHOL_THREADS), (r_in_lds ? 2 : 1) * one,
+                     ctx->stream, G, k, shift_rel, R, Rinv, info, r_in_lds);
   TN_HIP(ctx, hipGetLastError());
-  ctx->arena_off = mark;
   return TN_OK;
 }
 

@@ -18,41 +18,59 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct TDesc {
   int M, N, K;
+  // table mode: offset tables; strided mode: element strides
   const int* am;
   const int* ak;
   const int* bk;
   const int* bn;
   const int* cm;
   const int* cn;
-  long long sa, sb, sc;
+  long long sam, sak, sbk, sbn, scm, scn;
+  long long sa, sb, sc;  // batch strides
   int a_mfast, b_nfast;
+  int ksplit, kchunk;    // split-K: chunk length (multiple of BK)
+  double* part;          // split-K partials [batch*ksplit][M][N]
 };
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
 
+template <bool TABLE>
+__device__ inline long long offA(const TDesc& d, int m, int k) {
+  if (TABLE) return (long long)d.am[m] + d.ak[k];
+  return (long long)m * d.sam + (long long)k * d.sak;
+}
+template <bool TABLE>
+__device__ inline long long offB(const TDesc& d, int k, int n) {
+  if (TABLE) return (long long)d.bk[k] + d.bn[n];
+  return (long long)k * d.sbk + (long long)n * d.sbn;
+}
+template <bool TABLE>
+__device__ inline long long offC(const TDesc& d, int m, int n) {
+  if (TABLE) return (long long)d.cm[m] + d.cn[n];
+  return (long long)m * d.scm + (long long)n * d.scn;
+}
+
 // 256 threads = 4 waves; each wave owns a 32x32 quarter of the 64x64 tile as
-// 2x2 MFMA blocks.  Operand tiles are staged through LDS; the table entries
-// of the tile's rows, columns and k-slice are staged too.
+// 2x2 MFMA blocks.  Operand tiles are staged through two LDS buffers: the
+// next k-slice is fetched into registers while the MFMAs consume the current
+// one.  With split-K each z-slice of the grid sums one chunk of k into a
+// partial tile; a second kernel reduces the partials in a fixed order.
+template <bool TABLE>
 __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict__ A,
                                                         const double* __restrict__ B,
                                                         double* __restrict__ C, TDesc d,
                                                         double alpha, double beta) {
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
-  __shared__ int sam[BM], sbn[BN], sak[BK], sbk[BK];
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const long long bz = blockIdx.z;
+  const int split = blockIdx.z % d.ksplit;
+  const long long bz = blockIdx.z / d.ksplit;
   A += bz * d.sa;
   B += bz * d.sb;
-  C += bz * d.sc;
-  if (tid < BM) {
-    sam[tid] = (m0 + tid < d.M) ? d.am[m0 + tid] : 0;
-  } else if (tid < BM + BN) {
-    const int j = tid - BM;
-    sbn[j] = (n0 + j < d.N) ? d.bn[n0 + j] : 0;
-  }
+  const int kbeg = split * d.kchunk;
+  const int kend = min(d.K, kbeg + d.kchunk);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   d4 acc[2][2];
 #pragma unroll
@@ -60,75 +78,118 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
-    __syncthreads();
-    if (tid < BK) {
-      sak[tid] = (k0 + tid < d.K) ? d.ak[k0 + tid] : 0;
-    } else if (tid >= 64 && tid < 64 + BK) {
-      const int j = tid - 64;
-      sbk[j] = (k0 + j < d.K) ? d.bk[k0 + j] : 0;
+  // per-thread coordinates of its 4 A and 4 B tile elements
+  int am_[4], ak_[4], bk_[4], bn_[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (d.a_mfast) {
+      am_[i] = tid & 63;
+      ak_[i] = (tid >> 6) + 4 * i;
+    } else {
+      ak_[i] = tid & 15;
+      am_[i] = (tid >> 4) + 16 * i;
     }
-    __syncthreads();
+    if (d.b_nfast) {
+      bn_[i] = tid & 63;
+      bk_[i] = (tid >> 6) + 4 * i;
+    } else {
+      bk_[i] = tid & 15;
+      bn_[i] = (tid >> 4) + 16 * i;
+    }
+  }
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      int m, k;
-      if (d.a_mfast) {
-        m = tid & 63;
-        k = (tid >> 6) + 4 * i;
-      } else {
-        k = tid & 15;
-        m = (tid >> 4) + 16 * i;
-      }
-      double v = 0.0;
-      if (m0 + m < d.M && k0 + k < d.K) v = A[(long long)sam[m] + sak[k]];
-      As[k][m] = v;
+      const int m = m0 + am_[i], k = k0 + ak_[i];
+      ra[i] = (m < d.M && k < kend) ? A[offA<TABLE>(d, m, k)] : 0.0;
+      const int n = n0 + bn_[i], kb = k0 + bk_[i];
+      rb[i] = (n < d.N && kb < kend) ? B[offB<TABLE>(d, kb, n)] : 0.0;
     }
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      int n, k;
-      if (d.b_nfast) {
-        n = tid & 63;
-        k = (tid >> 6) + 4 * i;
-      } else {
-        k = tid & 15;
-        n = (tid >> 4) + 16 * i;
-      }
-      double v = 0.0;
-      if (n0 + n < d.N && k0 + k < d.K) v = B[(long long)sbk[k] + sbn[n]];
-      Bs[k][n] = v;
+      As[buf][ak_[i]][am_[i]] = ra[i];
+      Bs[buf][bk_[i]][bn_[i]] = rb[i];
     }
-    __syncthreads();
+  };
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   // D layout of the 16x16 FP64 block (measured on gfx950): lane l, register r
   // holds row l/16 + 4 r, column l%16
+  if (d.ksplit == 1) {
+    C += bz * d.sc;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + wn + j * 16 + (lane & 15);
-        if (row < d.M && col < d.N) {
-          const long long off = (long long)d.cm[row] + d.cn[col];
-          double v = alpha * acc[i][j][r];
-          if (beta != 0.0) v += beta * C[off];
-          C[off] = v;
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < d.M && col < d.N) {
+            const long long off = offC<TABLE>(d, row, col);
+            double v = alpha * acc[i][j][r];
+            if (beta != 0.0) v += beta * C[off];
+            C[off] = v;
+          }
         }
-      }
+  } else {
+    double* P = d.part + (long long)blockIdx.z * d.M * d.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < d.M && col < d.N) P[(long long)row * d.N + col] = acc[i][j][r];
+        }
+  }
+}
+
+// C = alpha * sum_s part[s] + beta * C, partial order fixed (deterministic)
+template <bool TABLE>
+__global__ void splitk_reduce_kernel(double* __restrict__ C, TDesc d, double alpha, double beta,
+                                     int batch) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long mn = (long long)d.M * d.N;
+  if (t >= mn * batch) return;
+  const long long bz = t / mn, e = t % mn;
+  const int row = (int)(e / d.N), col = (int)(e % d.N);
+  double s = 0.0;
+  for (int p = 0; p < d.ksplit; ++p) s += d.part[(bz * d.ksplit + p) * mn + e];
+  double* Cb = C + bz * d.sc;
+  const long long off = offC<TABLE>(d, row, col);
+  double v = alpha * s;
+  if (beta != 0.0) v += beta * Cb[off];
+  Cb[off] = v;
 }
 
 std::string key_of(const IdxGroup& g) {
@@ -172,6 +233,73 @@ bool unit_fast(const IdxGroup& g) { return !g.str.empty() && g.str.back() == 1; 
 
 }  // namespace
 
+namespace {
+
+// Launch with either tables (TABLE) or strides; picks split-K so that the
+// grid has enough workgroups to occupy the 256 compute units.
+int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const double* B,
+           double* C, double alpha, double beta) {
+  const long long tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  const long long tiles = tm * tn * batch;
+  int ksplit = 1;
+  const int ktiles = (d.K + BK - 1) / BK;
+  if (tiles < 512 && ktiles >= 8) {
+    ksplit = (int)std::min<long long>((1024 + tiles - 1) / tiles, ktiles / 4);
+    ksplit = std::max(1, std::min(ksplit, 64));
+  }
+  d.ksplit = ksplit;
+  d.kchunk = ((ktiles + ksplit - 1) / ksplit) * BK;
+  d.part = nullptr;
+  const size_t mark = ctx->arena_off;
+  if (ksplit > 1) {
+    d.part = ws_alloc<double>(ctx, (size_t)ksplit * batch * d.M * d.N);
+    if (!d.part) {  // no room for partials: run unsplit
+      ctx->err.clear();
+      ctx->arena_off = mark;
+      d.ksplit = 1;
+      d.kchunk = ktiles * BK;
+    }
+  }
+  if (d.M > 0 && d.N > 0 && (long long)batch * d.ksplit > 65535)
+    TN_FAIL(ctx, TN_EINVAL, "contraction batch too large for one launch");
+  dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)(batch * d.ksplit));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->prof) {
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+      hipEvent_t e;
+      TN_HIP(ctx, hipEventCreate(&e));
+      ctx->ev_pool.push_back(e);
+    }
+    e0 = ctx->ev_pool[ctx->ev_used];
+    e1 = ctx->ev_pool[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    ctx->prof_flops.push_back(2.0 * (double)d.M * (double)d.N * (double)d.K * (double)batch);
+    TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  }
+  if (table)
+    hipLaunchKernelGGL(tgemm_f64_kernel<true>, grid, dim3(256), 0, ctx->stream, A, B, C, d, alpha,
+                       beta);
+  else
+    hipLaunchKernelGGL(tgemm_f64_kernel<false>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
+                       alpha, beta);
+  TN_HIP(ctx, hipGetLastError());
+  if (d.ksplit > 1) {
+    const long long tot = (long long)d.M * d.N * batch;
+    if (table)
+      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)((tot + 255) / 256)),
+                         dim3(256), 0, ctx->stream, C, d, alpha, beta, batch);
+    else
+      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)((tot + 255) / 256)),
+                         dim3(256), 0, ctx->stream, C, d, alpha, beta, batch);
+    TN_HIP(ctx, hipGetLastError());
+  }
+  if (ctx->prof) TN_HIP(ctx, hipEventRecord(e1, ctx->stream));
+  ctx->arena_off = mark;  // partials are consumed in stream order
+  return TN_OK;
+}
+
+}  // namespace
+
 int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, double* C,
            double alpha, double beta, int prec) {
   const long long M = c.am.size(), N = c.bn.size(), K = c.ak.size();
@@ -183,41 +311,34 @@ int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, 
     TN_FAIL(ctx, TN_EINVAL, "contraction too large for one launch");
   (void)prec;
   TDesc d;
+  std::memset(&d, 0, sizeof(d));
   d.M = (int)M;
   d.N = (int)N;
   d.K = (int)K;
-  TN_TRY(table_of(ctx, c.am, &d.am));
-  TN_TRY(table_of(ctx, c.ak, &d.ak));
-  TN_TRY(table_of(ctx, c.bk, &d.bk));
-  TN_TRY(table_of(ctx, c.bn, &d.bn));
-  TN_TRY(table_of(ctx, c.cm, &d.cm));
-  TN_TRY(table_of(ctx, c.cn, &d.cn));
+  // single-index groups run in strided mode, the rest through offset tables
+  const bool strided = c.am.ext.size() == 1 && c.ak.ext.size() == 1 && c.bk.ext.size() == 1 &&
+                       c.bn.ext.size() == 1 && c.cm.ext.size() == 1 && c.cn.ext.size() == 1;
+  if (strided) {
+    d.sam = c.am.str[0];
+    d.sak = c.ak.str[0];
+    d.sbk = c.bk.str[0];
+    d.sbn = c.bn.str[0];
+    d.scm = c.cm.str[0];
+    d.scn = c.cn.str[0];
+  } else {
+    TN_TRY(table_of(ctx, c.am, &d.am));
+    TN_TRY(table_of(ctx, c.ak, &d.ak));
+    TN_TRY(table_of(ctx, c.bk, &d.bk));
+    TN_TRY(table_of(ctx, c.bn, &d.bn));
+    TN_TRY(table_of(ctx, c.cm, &d.cm));
+    TN_TRY(table_of(ctx, c.cn, &d.cn));
+  }
   d.sa = c.sa;
   d.sb = c.sb;
   d.sc = c.sc;
   d.a_mfast = unit_fast(c.am) || !unit_fast(c.ak);
   d.b_nfast = unit_fast(c.bn) || !unit_fast(c.bk);
-  if (K == 0) {
-    // C = beta * C: run with a zero-length k loop
-  }
-  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)c.batch);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->prof) {
-    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
-      hipEvent_t e;
-      TN_HIP(ctx, hipEventCreate(&e));
-      ctx->ev_pool.push_back(e);
-    }
-    e0 = ctx->ev_pool[ctx->ev_used];
-    e1 = ctx->ev_pool[ctx->ev_used + 1];
-    ctx->ev_used += 2;
-    ctx->prof_flops.push_back(2.0 * (double)M * (double)N * (double)K * (double)c.batch);
-    TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
-  }
-  hipLaunchKernelGGL(tgemm_f64_kernel, grid, dim3(256), 0, ctx->stream, A, B, C, d, alpha, beta);
-  TN_HIP(ctx, hipGetLastError());
-  if (ctx->prof) TN_HIP(ctx, hipEventRecord(e1, ctx->stream));
-  return TN_OK;
+  return launch(ctx, !strided, d, c.batch, A, B, C, alpha, beta);
 }
 
 int gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, bool ta, const double* B,
