@@ -123,6 +123,57 @@ int ipeps_rdms(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const doubl
                double* rhoh, double* rhov);
 
 /*
+ * tm_fixed_point -- the 1D environment: dominant left and right eigenvectors
+ * of the unit-cell transfer matrix of an iMPS (Sec. III A; with different ket
+ * and bra tensors the mixed transfer matrix of Eq. (iMPSDM1)).
+ *   n_sites, chi, d  cell length, bond and physical dimension
+ *   ket, bra         device [n_sites][chi][d][chi] (lambda absorbed, A form)
+ *   vl, vr           device out [chi][chi], indexed (ket, bra):
+ *                    eta vl = sum_s K^T vl B over the cell,
+ *                    eta vr = sum_s K vr B^T over the cell (last site first);
+ *                    |vl|_F = 1, Tr(vl) > 0, sum(vl * vr) = 1
+ *   eta              host out: dominant eigenvalue
+ *   tol, max_iter    power-iteration stop: iterate moves by < tol (2-norm)
+ *   iters            host out: iterations used
+ *   flags            bit 0: start from the vl, vr passed in
+ * Returns TN_OK, TN_NOT_CONVERGED (e.g. a complex dominant pair of the mixed
+ * transfer matrix), TN_EINVAL, TN_ENUMERIC, TN_EHIP.
+ */
+int tm_fixed_point(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket, const double* bra,
+                   double* vl, double* vr, double* eta, double tol, int max_iter, int* iters,
+                   int flags);
+
+/* Size in doubles of the env1d workspace of itebd_step for bond chi. */
+size_t tn_env1d_size(int chi, int d);
+
+/* itebd_step modes */
+enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2 };
+
+/*
+ * itebd_step -- one imaginary-time step of the transverse-field Ising chain
+ * H = -J sum sz sz - h sum sx on a two-site iMPS (Sec. V).  The state is in
+ * the symmetric A form (sqrt(lambda) Gamma sqrt(lambda)).
+ *   A          device in/out [2][chi][d][chi] (d = 2); site 0 then site 1
+ *   dt         time step; the iMPO of Eq. (iMPO1) (second-order Trotter)
+ *   mode       TN_PLAIN: Theta = g A, environment = transfer-matrix fixed
+ *              points of the Theta chain, truncation A = Q Theta P
+ *              (Eq. (EqCanoPQ1)) on both bonds
+ *   env1d      device workspace of tn_env1d_size(chi, d) doubles, owned by
+ *              the caller, zero-filled before the first step; carries warm
+ *              starts between steps
+ *   lambda_out device out [2][chi] (may be NULL): kept spectra of bonds 0
+ *              (after site 0) and 1, unit l2 norm
+ *   tol        fixed-point tolerance
+ *   trunc_err  host out: discarded weight summed over the two bonds
+ *   energy_or_null host out (may be NULL): energy per site of the new state
+ * Returns TN_OK, TN_NOT_CONVERGED (a fixed point hit its iteration cap),
+ * TN_EINVAL, TN_ENUMERIC, TN_EHIP.
+ */
+int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
+               double* env1d, double* lambda_out, double tol, double* trunc_err,
+               double* energy_or_null);
+
+/*
  * tn_gemm -- the library's contraction engine on a plain matrix product, for
  * testing and measurement: C = alpha op(A) op(B) + beta C with row-major
  * storage, op(X) = X or X^T (ta, tb nonzero), leading dimensions lda, ldb,

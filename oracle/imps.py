@@ -107,6 +107,12 @@ def _sym_sqrt_factors(v):
     s, w = np.linalg.eigh(v)
     if s[-1] < 0:               # fixed point came out negative definite
         s, w = -s[::-1], w[:, ::-1]
+    # eigenvector signs: first entry within 1e-8 of the largest magnitude positive
+    for i in range(w.shape[1]):
+        a = np.abs(w[:, i])
+        j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
+        if w[j, i] < 0:
+            w[:, i] = -w[:, i]
     keep = s > CUT * s.max()
     sq = np.where(keep, np.sqrt(np.abs(s)), 0.0)
     isq = np.where(keep, 1.0 / np.where(keep, sq, 1.0), 0.0)
@@ -130,6 +136,14 @@ def truncation_pq(vl, vr, chi):
     X, Xinv = _sym_sqrt_factors(vr)          # vr = X X^T
     Y, Yinv = Yt.T, Ytinv.T
     u, s, vt = np.linalg.svd(Y @ X)
+    # sign of each singular pair: first entry of u within 1e-8 of its largest
+    # magnitude positive (fixes the gauge of the new bond index)
+    for i in range(u.shape[1]):
+        a = np.abs(u[:, i])
+        j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
+        if u[j, i] < 0:
+            u[:, i] = -u[:, i]
+            vt[i, :] = -vt[i, :]
     sq = np.sqrt(s[:chi])
     P = Yinv @ (u[:, :chi] * sq)
     Q = (sq[:, None] * vt[:chi]) @ Xinv

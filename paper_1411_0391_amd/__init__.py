@@ -44,6 +44,13 @@ SIGNATURES = {
                                ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int]),
     "tn_clear_cache": (ctypes.c_int, [_vp]),
+    "tn_env1d_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "tm_fixed_point": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                      _vp, _vp, _c_double_p, ctypes.c_double, ctypes.c_int,
+                                      _c_int_p, ctypes.c_int]),
+    "itebd_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp,
+                                  ctypes.c_double, _c_double_p, _c_double_p]),
     "tn_svd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tn_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tn_prof_read": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
@@ -161,6 +168,36 @@ class Context:
                               _ptr(C), _ptr(T), _ptr(r1), _ptr(rh), _ptr(rv))
         self._check(rc)
         return r1, rh, rv
+
+    # -- 1D ------------------------------------------------------------------
+    def tm_fixed_point(self, kets, bras, tol=1e-14, max_iter=200000, vl=None, vr=None):
+        import torch
+        ns, chi, d, _ = kets.shape
+        warm = vl is not None
+        if vl is None:
+            vl = torch.empty((chi, chi), dtype=torch.float64, device=kets.device)
+            vr = torch.empty((chi, chi), dtype=torch.float64, device=kets.device)
+        eta = ctypes.c_double(0)
+        it = ctypes.c_int(0)
+        rc = lib().tm_fixed_point(self._h, ns, chi, d, _ptr(kets), _ptr(bras), _ptr(vl), _ptr(vr),
+                                  ctypes.byref(eta), tol, max_iter, ctypes.byref(it), int(warm))
+        self._check(rc, allow_nc=True)
+        return vl, vr, eta.value, it.value, rc
+
+    def env1d(self, chi, d=2):
+        import torch
+        n = lib().tn_env1d_size(chi, d)
+        return torch.zeros(n, dtype=torch.float64, device="cuda")
+
+    def itebd_step(self, A, J, h, dt, env, mode=0, tol=1e-13, energy=False, lam=None):
+        chi, d = A.shape[1], A.shape[2]
+        err = ctypes.c_double(0)
+        e = ctypes.c_double(0)
+        rc = lib().itebd_step(self._h, chi, d, _ptr(A), J, h, dt, mode, _ptr(env),
+                              _ptr(lam) if lam is not None else None, tol, ctypes.byref(err),
+                              ctypes.byref(e) if energy else None)
+        self._check(rc, allow_nc=True)
+        return err.value, (e.value if energy else None), rc
 
     def svd(self, A):
         """Batched small SVD of device matrices A [batch][m][n] -> U, S, V."""

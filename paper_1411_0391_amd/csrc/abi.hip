@@ -12,6 +12,13 @@ int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const 
                     double* rhoh, double* rhov);
 
 int jacobi_sweeps_read(tn_ctx* ctx, unsigned long long* out);
+size_t env1d_doubles(int chi, int d);
+int tm_fixed_point_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                        const double* bra, double* vl, double* vr, double* eta, double tol,
+                        int max_iter, int* iters, int flags);
+int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
+                    double* env1d, double* lambda_out, double tol, double* trunc_err,
+                    double* energy_or_null);
 
 int ws_reserve(tn_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_size) return TN_OK;
@@ -142,6 +149,26 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
   TN_TRY(gemm(ctx, M, N, K, A, lda, ta != 0, B, ldb, tb != 0, C, ldc, alpha, beta));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
+}
+
+size_t tn_env1d_size(int chi, int d) { return env1d_doubles(chi, d); }
+
+int tm_fixed_point(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket, const double* bra,
+                   double* vl, double* vr, double* eta, double tol, int max_iter, int* iters,
+                   int flags) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return tm_fixed_point_impl(ctx, n_sites, chi, d, ket, bra, vl, vr, eta, tol, max_iter, iters,
+                             flags);
+}
+
+int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
+               double* env1d, double* lambda_out, double tol, double* trunc_err,
+               double* energy_or_null) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return itebd_step_impl(ctx, chi, d, A, J, h, dt, mode, env1d, lambda_out, tol, trunc_err,
+                         energy_or_null);
 }
 
 int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, double* S,

@@ -1,0 +1,508 @@
+// 1D iMPS environment and the iTEBD step (Sec. III and V of the paper).
+//
+// The environment of a bond of an infinite MPS is the pair of dominant
+// eigenvectors of the unit-cell transfer matrix: the Gram matrices of the
+// half-infinite chains on either side of the bond.  They are found by power
+// iteration in one persistent workgroup per direction, with the cell tensors,
+// the iterate and the intermediate held in LDS (chi <= 36 for a two-site cell
+// with d = 2; larger cells use a global scratch buffer).  The truncation
+// factors the fixed points (vl = Y^T Y, vr = X X^T) with the small Jacobi
+// SVD, takes the SVD of Y X and keeps chi singular pairs (Eq. (EqCanoPQ1)).
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+constexpr int TM_THREADS = 1024;
+
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < TM_THREADS / 64; ++i) s += red[i];
+  return s;
+}
+
+// v <- one application of the cell transfer matrix (left: v -> sum K^T v B
+// site by site in cell order; right: v -> sum K v B^T, last site first)
+__device__ void tm_apply(const double* K, const double* B, int nsite, int chi, int d, int left,
+                         double* v, double* x) {
+  const int tid = threadIdx.x;
+  const int cdc = chi * d * chi;
+  for (int q = 0; q < nsite; ++q) {
+    const int site = left ? q : nsite - 1 - q;
+    const double* k = K + (long long)site * cdc;
+    const double* bb = B + (long long)site * cdc;
+    if (left) {
+      // x[b][s][c] = sum_a v[a][b] k[a][s][c]
+      for (int t = tid; t < cdc; t += TM_THREADS) {
+        const int b = t / (d * chi), sc = t % (d * chi);
+        double acc = 0.0;
+        for (int a = 0; a < chi; ++a) acc += v[a * chi + b] * k[a * d * chi + sc];
+        x[t] = acc;
+      }
+      __syncthreads();
+      // v[c][e] = sum_{b,s} x[b][s][c] bb[b][s][e]
+      for (int t = tid; t < chi * chi; t += TM_THREADS) {
+        const int c = t / chi, e = t % chi;
+        double acc = 0.0;
+        for (int bs = 0; bs < chi * d; ++bs) acc += x[bs * chi + c] * bb[bs * chi + e];
+        v[t] = acc;
+      }
+    } else {
+      // x[a][s][e] = sum_c k[a][s][c] v[c][e]
+      for (int t = tid; t < cdc; t += TM_THREADS) {
+        const int as = t / chi, e = t % chi;
+        double acc = 0.0;
+        for (int c = 0; c < chi; ++c) acc += k[as * chi + c] * v[c * chi + e];
+        x[t] = acc;
+      }
+      __syncthreads();
+      // v[a][b] = sum_{s,e} x[a][s][e] bb[b][s][e]
+      for (int t = tid; t < chi * chi; t += TM_THREADS) {
+        const int a = t / chi, b = t % chi;
+        double acc = 0.0;
+        for (int se = 0; se < d * chi; ++se) acc += x[a * d * chi + se] * bb[b * d * chi + se];
+        v[t] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Power iteration: block 0 left, block 1 right.  The iterate is kept at unit
+// Frobenius norm with positive trace; stops when it moves by less than tol.
+__global__ __launch_bounds__(TM_THREADS) void tm_power_kernel(
+    const double* __restrict__ kets, const double* __restrict__ bras, int nsite, int chi, int d,
+    double* __restrict__ vout, double* __restrict__ eta, int* __restrict__ iters, double tol,
+    int max_iter, int warm, double* __restrict__ gwork) {
+  extern __shared__ double lds[];
+  __shared__ double red[TM_THREADS / 64];
+  const int left = blockIdx.x == 0 ? 1 : 0;
+  const int tid = threadIdx.x;
+  const int cdc = chi * d * chi, cc = chi * chi;
+  const long long per = 2LL * nsite * cdc + 2LL * cc + cdc;
+  double* base = gwork ? gwork + blockIdx.x * per : lds;
+  double* K = base;
+  double* B = K + (long long)nsite * cdc;
+  double* v = B + (long long)nsite * cdc;
+  double* w = v + cc;
+  double* x = w + cc;
+  for (long long t = tid; t < (long long)nsite * cdc; t += TM_THREADS) {
+    K[t] = kets[t];
+    B[t] = bras[t];
+  }
+  double* vo = vout + blockIdx.x * cc;
+  for (int t = tid; t < cc; t += TM_THREADS)
+    v[t] = warm ? vo[t] : ((t / chi == t % chi) ? 1.0 : 0.0);
+  __syncthreads();
+  // normalise the start
+  {
+    double a = 0.0;
+    for (int t = tid; t < cc; t += TM_THREADS) a += v[t] * v[t];
+    const double nrm = sqrt(block_sum(a, red));
+    double tr = 0.0;
+    for (int i = tid; i < chi; i += TM_THREADS) tr += v[i * chi + i];
+    tr = block_sum(tr, red);
+    const double f = (tr < 0.0 ? -1.0 : 1.0) / (nrm > 0.0 ? nrm : 1.0);
+    for (int t = tid; t < cc; t += TM_THREADS) v[t] *= f;
+    __syncthreads();
+  }
+  int it = 0;
+  double ev = 0.0;
+  for (it = 1; it <= max_iter; ++it) {
+    for (int t = tid; t < cc; t += TM_THREADS) w[t] = v[t];
+    __syncthreads();
+    tm_apply(K, B, nsite, chi, d, left, w, x);
+    double a = 0.0, ip = 0.0, tr = 0.0;
+    for (int t = tid; t < cc; t += TM_THREADS) {
+      a += w[t] * w[t];
+      ip += w[t] * v[t];
+    }
+    for (int i = tid; i < chi; i += TM_THREADS) tr += w[i * chi + i];
+    const double nrm = sqrt(block_sum(a, red));
+    ev = block_sum(ip, red);
+    tr = block_sum(tr, red);
+    const double f = (tr < 0.0 ? -1.0 : 1.0) / (nrm > 0.0 ? nrm : 1.0);
+    double dd = 0.0;
+    for (int t = tid; t < cc; t += TM_THREADS) {
+      const double nv = w[t] * f;
+      dd += (nv - v[t]) * (nv - v[t]);
+      v[t] = nv;
+    }
+    const double diff = sqrt(block_sum(dd, red));
+    if (!(diff >= tol)) break;  // also stops on NaN
+  }
+  for (int t = tid; t < cc; t += TM_THREADS) vo[t] = v[t];
+  if (tid == 0) {
+    eta[blockIdx.x] = ev;
+    iters[blockIdx.x] = it;
+  }
+}
+
+// vr <- vr / sum(vl * vr)
+__global__ void pair_normalize_kernel(const double* __restrict__ vl, double* __restrict__ vr,
+                                      int cc) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int t = threadIdx.x; t < cc; t += 256) a += vl[t] * vr[t];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const double s = red[0] + red[1] + red[2] + red[3];
+  const double inv = s != 0.0 ? 1.0 / s : 0.0;
+  for (int t = threadIdx.x; t < cc; t += 256) vr[t] *= inv;
+}
+
+// Theta[(i,a)][s][(j,b)] = sum_t g[a][b][s][t] A[i][t][j]
+__global__ void impo_apply_kernel(const double* __restrict__ g, const double* __restrict__ A,
+                                  double* __restrict__ Th, int chi, int d, int kap) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)chi * kap * d * chi * kap;
+  if (t >= tot) return;
+  long long r = t;
+  const int b = r % kap; r /= kap;
+  const int j = r % chi; r /= chi;
+  const int s = r % d; r /= d;
+  const int a = r % kap; r /= kap;
+  const int i = (int)r;
+  double acc = 0.0;
+  for (int tt = 0; tt < d; ++tt)
+    acc += g[((a * kap + b) * d + s) * d + tt] * A[((long long)i * d + tt) * chi + j];
+  Th[t] = acc;
+}
+
+// Square-root factors of a symmetric positive semi-definite v = W S W^T
+// given its SVD (U = W, S): F = W sqrt(S) and Finv = (W / sqrt(S))^T,
+// dropping S < 1e-14 S_max (F, Finv n x n).
+__global__ void sqrt_factors_kernel(const double* __restrict__ U, const double* __restrict__ S,
+                                    int n, double* __restrict__ F, double* __restrict__ Finv) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int i = t / n, j = t % n;
+  const double sj = S[j];
+  const bool keep = sj > 1e-14 * S[0];
+  const double sq = keep ? sqrt(sj) : 0.0;
+  F[i * n + j] = U[i * n + j] * sq;
+  Finv[j * n + i] = keep ? U[i * n + j] / sq : 0.0;
+}
+
+// P = Yinv[:, :] U[:, :chi] sqrt(S) with Yinv = W / sqrt(s) (columns),
+// computed by the host as a product; here: scale the chi kept columns of a
+// matrix by sqrt(S) (cols) or its rows (rows = 1).
+__global__ void scale_sqrt_kernel(double* __restrict__ X, int rows, int cols, int ld,
+                                  const double* __restrict__ S, int by_rows) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int i = t / cols, j = t % cols;
+  X[i * ld + j] *= sqrt(fmax(S[by_rows ? i : j], 0.0));
+}
+
+// kept spectrum (normalised) and discarded weight of one bond
+__global__ void spectrum_kernel(const double* __restrict__ S, int n, int chi,
+                                double* __restrict__ lam, double* __restrict__ err) {
+  if (threadIdx.x != 0) return;
+  double kept = 0.0, tot = 0.0;
+  for (int i = 0; i < n; ++i) {
+    tot += S[i] * S[i];
+    if (i < chi) kept += S[i] * S[i];
+  }
+  const double inv = kept > 0.0 ? 1.0 / sqrt(kept) : 0.0;
+  for (int i = 0; i < chi; ++i) lam[i] = (i < n) ? S[i] * inv : 0.0;
+  *err += tot > 0.0 ? (tot - kept) / tot : 0.0;
+}
+
+// TFIM energy per site from the two bond RDMs (4x4, (s1 s2),(s1' s2'))
+__global__ void tfim1d_energy_kernel(const double* __restrict__ r0, const double* __restrict__ r1,
+                                     double J, double h, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const double zz[4] = {1.0, -1.0, -1.0, 1.0};
+  double tr0 = 0.0, tr1 = 0.0, z0 = 0.0, z1 = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    tr0 += r0[i * 4 + i];
+    tr1 += r1[i * 4 + i];
+    z0 += zz[i] * r0[i * 4 + i];
+    z1 += zz[i] * r1[i * 4 + i];
+  }
+  // <sx (x) 1> and <1 (x) sx> on the first bond: index (s1 s2) = 2 s1 + s2
+  double x1 = 0.0, x2 = 0.0;
+  for (int s2 = 0; s2 < 2; ++s2) {
+    x1 += r0[(0 * 2 + s2) * 4 + (1 * 2 + s2)] + r0[(1 * 2 + s2) * 4 + (0 * 2 + s2)];
+  }
+  for (int s1 = 0; s1 < 2; ++s1) {
+    x2 += r0[(s1 * 2 + 0) * 4 + (s1 * 2 + 1)] + r0[(s1 * 2 + 1) * 4 + (s1 * 2 + 0)];
+  }
+  *out = -J * 0.5 * (z0 / tr0 + z1 / tr1) - h * 0.5 * (x1 + x2) / tr0;
+}
+
+int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const double* bras,
+            double* v2 /*[2][chi][chi]*/, double* eta_d, int* it_d, double tol, int max_iter,
+            int warm) {
+  const size_t per = 2ULL * nsite * chi * d * chi + 2ULL * chi * chi + (size_t)chi * d * chi;
+  double* gwork = nullptr;
+  size_t dyn = per * sizeof(double);
+  if (dyn > 150 * 1024) {
+    gwork = ws_alloc<double>(ctx, 2 * per);
+    if (!gwork) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (transfer matrix)");
+    dyn = 0;
+  }
+  hipLaunchKernelGGL(tm_power_kernel, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets, bras,
+                     nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
+  TN_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(pair_normalize_kernel, dim3(1), dim3(256), 0, ctx->stream, v2,
+                     v2 + (size_t)chi * chi, chi * chi);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
+// Host-side iMPO g[a][b][s][t] of the TFIM (Eq. (iMPO1)): g = gF R_a L_b gF,
+// gF = exp(dt h sx / 2), exp(dt J sz sz) = sum_k L_k (x) R_k with
+// L = {sqrt(cosh) 1, sqrt|sinh| sz}, R = {sqrt(cosh) 1, sign(sinh) sqrt|sinh| sz}.
+void tfim_impo(double J, double h, double dt, double g[2][2][2][2]) {
+  const double c = cosh(0.5 * dt * h), s = sinh(0.5 * dt * h);
+  const double gf[2][2] = {{c, s}, {s, c}};
+  const double ch = cosh(dt * J), sh = sinh(dt * J);
+  const double l[2] = {sqrt(ch), sqrt(fabs(sh))};
+  const double r[2] = {sqrt(ch), (sh < 0 ? -1.0 : 1.0) * sqrt(fabs(sh))};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      // diagonal middle factor: R_a L_b, sz powers add
+      double mid[2];
+      for (int q = 0; q < 2; ++q) {
+        const double za = (a == 1) ? (q == 0 ? 1.0 : -1.0) : 1.0;
+        const double zb = (b == 1) ? (q == 0 ? 1.0 : -1.0) : 1.0;
+        mid[q] = r[a] * za * l[b] * zb;
+      }
+      for (int s1 = 0; s1 < 2; ++s1)
+        for (int t1 = 0; t1 < 2; ++t1) {
+          double acc = 0.0;
+          for (int q = 0; q < 2; ++q) acc += gf[s1][q] * mid[q] * gf[q][t1];
+          g[a][b][s1][t1] = acc;
+        }
+    }
+}
+
+}  // namespace
+
+// Workspace layout of env1d (doubles): [0, 4 n^2) warm fixed points
+// (bond 0: vl, vr; bond 1: vl, vr) with n = kappa chi; then the recycling
+// factors Lf[2][chi][n] and Rf[2][n][chi]; then 16 flags/scalars.
+size_t env1d_doubles(int chi, int d) {
+  (void)d;
+  const size_t n = 2 * (size_t)chi;
+  return 4 * n * n + 4 * (size_t)chi * n + 16;
+}
+
+int tm_fixed_point_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                        const double* bra, double* vl, double* vr, double* eta, double tol,
+                        int max_iter, int* iters, int flags) {
+  if (n_sites < 1 || chi < 1 || d < 1 || !ket || !bra || !vl || !vr || max_iter < 1)
+    TN_FAIL(ctx, TN_EINVAL, "bad tm_fixed_point arguments");
+  TN_TRY(ws_reserve(ctx, 2 * (2ULL * n_sites * chi * d * chi + 3ULL * chi * chi + chi * d * chi) *
+                             8 + (4 << 20)));
+  ws_reset(ctx);
+  double* v2 = ws_alloc<double>(ctx, 2 * (size_t)chi * chi);
+  double* ed = ws_alloc<double>(ctx, 2);
+  int* itd = ws_alloc<int>(ctx, 2);
+  if (!itd) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  const size_t cc = (size_t)chi * chi;
+  if (flags & 1) {
+    TN_HIP(ctx, hipMemcpyAsync(v2, vl, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(v2 + cc, vr, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  TN_TRY(tm_pair(ctx, n_sites, chi, d, ket, bra, v2, ed, itd, tol, max_iter, flags & 1));
+  TN_HIP(ctx, hipMemcpyAsync(vl, v2, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(vr, v2 + cc, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  double he[2];
+  int hi[2];
+  TN_HIP(ctx, hipMemcpyAsync(he, ed, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (eta) *eta = he[0];
+  if (iters) *iters = hi[0] > hi[1] ? hi[0] : hi[1];
+  if (!std::isfinite(he[0]) || !std::isfinite(he[1]))
+    TN_FAIL(ctx, TN_ENUMERIC, "non-finite transfer-matrix eigenvalue");
+  return (hi[0] >= max_iter || hi[1] >= max_iter) ? TN_NOT_CONVERGED : TN_OK;
+}
+
+namespace {
+
+// Truncation of bond b of the two-site Theta chain (bond 0 after site 0):
+// fixed points of the cell ending with the left site, factors, SVD of Y X,
+// P (n x chi) and Q (chi x n).
+int bond_truncation(tn_ctx* ctx, int n, int chi, int d, const double* th /*[2][n][d][n]*/, int b,
+                    double* vwarm /*[2][n][n] in/out*/, int warm, double tol, double* P, double* Q,
+                    double* lam, double* err, int* tm_iters) {
+  const size_t nn = (size_t)n * n, ndn = (size_t)n * d * n;
+  double* cell = ws_alloc<double>(ctx, 2 * ndn);
+  double* ed = ws_alloc<double>(ctx, 2);
+  int* itd = ws_alloc<int>(ctx, 2);
+  double* U = ws_alloc<double>(ctx, nn);
+  double* S = ws_alloc<double>(ctx, n);
+  double* Yt = ws_alloc<double>(ctx, nn);
+  double* Ytinv = ws_alloc<double>(ctx, nn);
+  double* X = ws_alloc<double>(ctx, nn);
+  double* Xinv = ws_alloc<double>(ctx, nn);
+  double* M = ws_alloc<double>(ctx, nn);
+  double* Um = ws_alloc<double>(ctx, nn);
+  double* Vm = ws_alloc<double>(ctx, nn);
+  double* Sm = ws_alloc<double>(ctx, n);
+  if (!Sm) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (truncation)");
+  // cell [other, b]: its left fixed point ends with site b, its right one
+  // starts with the other site
+  const int a = b, o = 1 - b;
+  TN_HIP(ctx, hipMemcpyAsync(cell, th + o * ndn, ndn * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(cell + ndn, th + a * ndn, ndn * 8, hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  TN_TRY(tm_pair(ctx, 2, n, d, cell, cell, vwarm, ed, itd, tol, 100000, warm));
+  int hi[2];
+  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  // vl = Yt Yt^T (Y = Yt^T), vr = X X^T
+  TN_TRY(jacobi_svd(ctx, 1, n, n, vwarm, n, 0, U, n, 0, S, 0, nullptr, 0, 0));
+  hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, U,
+                     S, n, Yt, Ytinv);
+  TN_TRY(jacobi_svd(ctx, 1, n, n, vwarm + nn, n, 0, U, n, 0, S, 0, nullptr, 0, 0));
+  hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, U,
+                     S, n, X, Xinv);
+  TN_HIP(ctx, hipGetLastError());
+  // M = Y X = Yt^T X ; SVD M = Um Sm Vm^T (sign-fixed)
+  TN_TRY(gemm(ctx, n, n, n, Yt, n, true, X, n, false, M, n, 1.0, 0.0));
+  TN_TRY(jacobi_svd(ctx, 1, n, n, M, n, 0, Um, n, 0, Sm, 0, Vm, n, 0));
+  // P = Y^+ Um[:, :chi] sqrt(S) with Y^+ = Ytinv^T ; Q = sqrt(S) Vm[:, :chi]^T X^+
+  TN_TRY(gemm(ctx, n, chi, n, Ytinv, n, true, Um, n, false, P, chi, 1.0, 0.0));
+  hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream, P,
+                     n, chi, chi, Sm, 0);
+  TN_TRY(gemm(ctx, chi, n, n, Vm, n, true, Xinv, n, false, Q, n, 1.0, 0.0));
+  hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream, Q,
+                     chi, n, n, Sm, 1);
+  hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1), 0, ctx->stream, Sm, n, chi, lam, err);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *tm_iters = hi[0] > hi[1] ? hi[0] : hi[1];
+  return TN_OK;
+}
+
+// out[i][s][j] = sum Q[i][a] th[a][s][b] P[b][j]   (chi x d x chi)
+int sandwich(tn_ctx* ctx, int n, int chi, int d, const double* Q, const double* th, const double* P,
+             double* tmp, double* out) {
+  TN_TRY(gemm(ctx, chi, d * n, n, Q, n, false, th, d * n, false, tmp, d * n, 1.0, 0.0));
+  TN_TRY(gemm(ctx, chi * d, chi, n, tmp, n, false, P, chi, false, out, chi, 1.0, 0.0));
+  return TN_OK;
+}
+
+// two-site RDMs of the A-form chain and the TFIM energy per site
+int energy_1d(tn_ctx* ctx, int chi, int d, const double* A /*[2][chi][d][chi]*/, double J,
+              double h, double* e_dev) {
+  const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
+  double* cell = ws_alloc<double>(ctx, 2 * cdc);
+  double* v2 = ws_alloc<double>(ctx, 2 * cc);
+  double* ed = ws_alloc<double>(ctx, 2);
+  int* itd = ws_alloc<int>(ctx, 2);
+  double* Mt = ws_alloc<double>(ctx, (size_t)chi * d * d * chi);
+  double* W1 = ws_alloc<double>(ctx, (size_t)chi * d * d * chi);
+  double* W2 = ws_alloc<double>(ctx, (size_t)chi * d * d * chi);
+  double* rho = ws_alloc<double>(ctx, 2 * 16);
+  if (!rho) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (energy)");
+  if (d != 2) TN_FAIL(ctx, TN_EINVAL, "the TFIM energy needs d = 2");
+  for (int b = 0; b < 2; ++b) {
+    const double* a = A + b * cdc;
+    const double* c = A + (1 - b) * cdc;
+    // cell [a, c]: left environment just before a, right one just after c
+    TN_HIP(ctx, hipMemcpyAsync(cell, a, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(cell + cdc, c, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_TRY(tm_pair(ctx, 2, chi, d, cell, cell, v2, ed, itd, 1e-14, 200000, 0));
+    // M[x][s][t][c] = sum_b a[x][s][b] c[b][t][c]
+    TN_TRY(gemm(ctx, chi * d, d * chi, chi, a, chi, false, c, d * chi, false, Mt, d * chi, 1.0,
+                0.0));
+    // W1[y][(s t c)] = sum_x vl[x][y] M[x][(s t c)]
+    TN_TRY(gemm(ctx, chi, d * d * chi, chi, v2, chi, true, Mt, d * d * chi, false, W1,
+                d * d * chi, 1.0, 0.0));
+    // W2[(y s t)][e] = sum_c W1[(y s t)][c] vr[c][e]
+    TN_TRY(gemm(ctx, chi * d * d, chi, chi, W1, chi, false, v2 + cc, chi, false, W2, chi, 1.0, 0.0));
+    // rho[(s t)][(u v)] = sum_{y,e} W2[y][(s t)][e] M[y][(u v)][e]
+    Contraction k;
+    k.am = grp({{d * d, chi}});
+    k.ak = grp({{chi, (long long)d * d * chi}, {chi, 1}});
+    k.bk = grp({{chi, (long long)d * d * chi}, {chi, 1}});
+    k.bn = grp({{d * d, chi}});
+    k.cm = grp({{d * d, d * d}});
+    k.cn = grp({{d * d, 1}});
+    TN_TRY(tc_run(ctx, k, W2, Mt, rho + 16 * b, 1.0, 0.0));
+  }
+  hipLaunchKernelGGL(tfim1d_energy_kernel, dim3(1), dim3(1), 0, ctx->stream, rho, rho + 16, J, h,
+                     e_dev);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
+}  // namespace
+
+int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*/, double J,
+                    double h, double dt, int mode, double* env1d, double* lambda_out,
+                    double tol, double* trunc_err, double* energy_or_null) {
+  if (chi < 1 || d != 2 || !A || !env1d) TN_FAIL(ctx, TN_EINVAL, "bad itebd_step arguments");
+  if (mode != 0) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
+  const int kap = 2, n = kap * chi;
+  const size_t nn = (size_t)n * n, ndn = (size_t)n * d * n, cdc = (size_t)chi * d * chi;
+  TN_TRY(ws_reserve(ctx, (40 * nn + 8 * ndn + 16 * cdc) * 8 + (8 << 20)));
+  ws_reset(ctx);
+  double hg[2][2][2][2];
+  tfim_impo(J, h, dt, hg);
+  double* g = ws_alloc<double>(ctx, 16);
+  double* th = ws_alloc<double>(ctx, 2 * ndn);
+  double* P = ws_alloc<double>(ctx, 2 * (size_t)n * chi);
+  double* Q = ws_alloc<double>(ctx, 2 * (size_t)n * chi);
+  double* lam = ws_alloc<double>(ctx, 2 * (size_t)chi);
+  double* errd = ws_alloc<double>(ctx, 1);
+  double* edev = ws_alloc<double>(ctx, 1);
+  double* tmp = ws_alloc<double>(ctx, (size_t)chi * d * n);
+  if (!tmp) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (itebd)");
+  TN_HIP(ctx, hipMemcpyAsync(g, hg, 16 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  TN_HIP(ctx, hipMemsetAsync(errd, 0, sizeof(double), ctx->stream));
+  for (int s = 0; s < 2; ++s)
+    hipLaunchKernelGGL(impo_apply_kernel, dim3((unsigned)((ndn + 255) / 256)), dim3(256), 0,
+                       ctx->stream, g, A + s * cdc, th + s * ndn, chi, d, kap);
+  TN_HIP(ctx, hipGetLastError());
+  // warm starts of the fixed points live in env1d; flag slot 0 marks them valid
+  double* flagp = env1d + env1d_doubles(chi, d) - 16;
+  double hflag = 0.0;
+  TN_HIP(ctx, hipMemcpyAsync(&hflag, flagp, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int warm = hflag == 1.0 ? 1 : 0;
+  int tmi = 0;
+  for (int b = 0; b < 2; ++b) {
+    const size_t mark = ctx->arena_off;
+    int it = 0;
+    TN_TRY(bond_truncation(ctx, n, chi, d, th, b, env1d + 2 * b * nn, warm, tol, P + b * n * chi,
+                           Q + b * n * chi, lam + b * chi, errd, &it));
+    tmi = it > tmi ? it : tmi;
+    ctx->arena_off = mark;
+  }
+  const double one = 1.0;
+  TN_HIP(ctx, hipMemcpyAsync(flagp, &one, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  // site 0 sits between bond 1 (left) and bond 0 (right), site 1 the reverse
+  TN_TRY(sandwich(ctx, n, chi, d, Q + 1 * n * chi, th, P, tmp, A));
+  TN_TRY(sandwich(ctx, n, chi, d, Q, th + ndn, P + 1 * n * chi, tmp, A + cdc));
+  TN_TRY(frob_normalize(ctx, A, cdc, nullptr));
+  TN_TRY(frob_normalize(ctx, A + cdc, cdc, nullptr));
+  if (lambda_out)
+    TN_HIP(ctx, hipMemcpyAsync(lambda_out, lam, 2 * chi * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  if (energy_or_null) TN_TRY(energy_1d(ctx, chi, d, A, J, h, edev));
+  double he = 0.0, herr = 0.0;
+  TN_HIP(ctx, hipMemcpyAsync(&herr, errd, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (energy_or_null)
+    TN_HIP(ctx, hipMemcpyAsync(&he, edev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (trunc_err) *trunc_err = herr;
+  if (energy_or_null) *energy_or_null = he;
+  if (!std::isfinite(herr)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite truncation");
+  return tmi >= 100000 ? TN_NOT_CONVERGED : TN_OK;
+}

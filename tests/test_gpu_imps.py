@@ -1,0 +1,125 @@
+"""GPU parity of the 1D path (transfer-matrix fixed points, iTEBD step)."""
+import numpy as np
+import pytest
+
+import tninputs
+from oracle import gates, imps
+from tests import pins
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1411_0391_amd as tn  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tn.Context()
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _state(seed, chi, steps=30, h=1.0):
+    ga, _, gb, _ = tninputs.imps_two_site(seed, chi)
+    sites, _ = imps.run_itebd([ga, gb], 1.0, h, 0.05, chi, steps)
+    return sites
+
+
+@pytest.mark.parametrize("chi", [4, 16, 32])
+def test_tm_fixed_point_parity(ctx, chi):
+    sites = _state(0, min(chi, 16))
+    if chi > 16:  # a kappa*chi Theta chain, as inside a step
+        g = gates.impo(1.0, 1.0, 0.01)
+        sites = [gates.apply_impo(g, s) for s in sites]
+    kets = [sites[1], sites[0]]
+    vl, vr, eta = imps.tm_fixed_point(kets, kets)
+    K = dev(np.stack(kets))
+    gvl, gvr, geta, it, rc = ctx.tm_fixed_point(K, K, tol=1e-14)
+    assert rc == tn.TN_OK
+    assert abs(geta - eta) < 1e-12 * abs(eta)
+    np.testing.assert_allclose(host(gvl), vl, atol=1e-11)
+    np.testing.assert_allclose(host(gvr), vr, atol=1e-11 * np.abs(vr).max())
+
+
+def _mixed_case():
+    # random kets and nearby bras; this seed has a real leading eigenvalue of
+    # the mixed transfer matrix separated from the next by a factor ~0.56
+    rng = np.random.default_rng(0)
+    kets = [rng.standard_normal((5, 2, 5)) for _ in range(2)]
+    bras = [k + 0.1 * rng.standard_normal(k.shape) for k in kets]
+    return kets, bras
+
+
+def _dense_mixed(kets, bras):
+    n = kets[0].shape[0]
+    E = np.eye(n * n)
+    for k, b in zip(kets, bras):
+        E = E @ np.einsum("asc,bsd->abcd", k, b).reshape(n * n, n * n)
+    return E
+
+
+def test_tm_fixed_point_mixed_brute_force(ctx):
+    kets, bras = _mixed_case()
+    E = _dense_mixed(kets, bras)
+    w = np.linalg.eigvals(E)
+    lead = w[np.argmax(np.abs(w))]
+    assert abs(lead.imag) < 1e-12
+    vl, vr, geta, it, rc = ctx.tm_fixed_point(dev(np.stack(kets)), dev(np.stack(bras)))
+    assert rc == tn.TN_OK
+    assert abs(geta - lead.real) < 1e-11 * abs(lead)
+    x = host(vl).ravel()
+    np.testing.assert_allclose(x @ E, geta * x, atol=1e-10 * abs(geta))
+    y = host(vr).ravel()
+    np.testing.assert_allclose(E @ y, geta * y, atol=1e-10 * abs(geta) * np.abs(y).max())
+
+
+@pytest.mark.parametrize("chi,h", [(8, 1.0), (16, 1.0), (12, 0.5)])
+def test_itebd_plain_step_parity(ctx, chi, h):
+    sites = _state(2, chi, h=h)
+    g = gates.impo(1.0, h, 0.01)
+    new, P, Q, spec, err = imps.itebd_plain_step(sites, g, chi)
+    e_ref = imps.energy_per_site(new, 1.0, h)
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    lam = torch.empty((2, chi), dtype=torch.float64, device="cuda")
+    gerr, ge, rc = ctx.itebd_step(A, 1.0, h, 0.01, env, energy=True, lam=lam)
+    assert rc == tn.TN_OK
+    np.testing.assert_allclose(host(lam), np.stack(spec), atol=1e-10)
+    assert abs(gerr - err) < 1e-10 * max(err, 1e-30) + 1e-15
+    assert abs(ge - e_ref) < 1e-10 * abs(e_ref)
+    np.testing.assert_allclose(host(A), np.stack(new), atol=1e-8)
+
+
+def test_itebd_trajectory_parity(ctx):
+    chi, h, dt = 8, 1.0, 0.02
+    ga, _, gb, _ = tninputs.imps_two_site(4, chi)
+    sites = [ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)]
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    g = gates.impo(1.0, h, dt)
+    for step in range(40):
+        sites, _, _, _, _ = imps.itebd_plain_step(sites, g, chi)
+        _, ge, _ = ctx.itebd_step(A, 1.0, h, dt, env, energy=(step % 10 == 9))
+        if step % 10 == 9:
+            er = imps.energy_per_site(sites, 1.0, h)
+            assert abs(ge - er) < 1e-9 * abs(er), (step, ge, er)
+
+
+def test_critical_chain_full_config(ctx):
+    # two-site iMPS, chi = 16, dt = 0.01, h = 1, 2000 plain steps: -4/pi
+    chi = 16
+    ga, _, gb, _ = tninputs.imps_two_site(0, chi)
+    A = dev(np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)]))
+    env = ctx.env1d(chi)
+    for step in range(2000):
+        _, e, rc = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, energy=(step == 1999))
+        assert rc >= 0
+    assert abs(e + 4 / np.pi) < 2e-4
