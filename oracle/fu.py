@@ -18,7 +18,7 @@ Readings taken where the paper is silent or describes a one-site cell:
   R[(i c),(i' c')] = sum_{j j'} Q[c,j] N[i,j,i',j'] Q[c',j'] and
   S[(i c)] = sum_{j i'} Q[c,j] N[i,j,i',i']; then Q likewise; after each
   pair the pair is balanced through the SVD of P Q; solves use
-  R + 1e-14 ||R|| I; one pass over the links in cell order (r, d, l, u for
+  R + 1e-14 tr(R) I; one pass over the links in cell order (r, d, l, u for
   the checkerboard), each link iterated until |df|/f_0 < tol;
 * energies are measured at environment steps, for the pre-truncated state
   the environment was computed for.
@@ -134,9 +134,24 @@ def cost(N, P, Q):
 
 
 def _solve(R, S):
+    """Solve (R + 1e-14 tr(R) I) x = S; R is the positive semi-definite
+    quadratic form of Eq. (var1), its trace the scale of the regulariser."""
     n = R.shape[0]
-    reg = 1e-14 * np.linalg.norm(R)
+    reg = 1e-14 * np.trace(R)
     return np.linalg.solve(R + reg * np.eye(n), S)
+
+
+def _svd_signfix(m):
+    """SVD with each left singular vector's first entry within 1e-8 of its
+    largest magnitude made positive (the right vector flips with it)."""
+    u, s, vt = np.linalg.svd(m)
+    for i in range(u.shape[1]):
+        a = np.abs(u[:, i])
+        j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
+        if u[j, i] < 0:
+            u[:, i] = -u[:, i]
+            vt[i, :] = -vt[i, :]
+    return u, s, vt
 
 
 def als(N, P, Q, tol=1e-12, max_sweeps=50):
@@ -157,7 +172,7 @@ def als(N, P, Q, tol=1e-12, max_sweeps=50):
         S = np.einsum("ic,ij->cj", P, trace_b).reshape(D * n)
         Q = _solve(0.5 * (R + R.T), S).reshape(D, n)
         # balance the pair
-        u, s, vt = np.linalg.svd(P @ Q)
+        u, s, vt = _svd_signfix(P @ Q)
         sq = np.sqrt(s[:D])
         P, Q = u[:, :D] * sq[None, :], sq[:, None] * vt[:D]
         fn, _ = cost(N, P, Q)

@@ -189,10 +189,24 @@ def _gram(t, leg):
     return m @ m.T
 
 
+def _signfix_cols(u, vt=None):
+    """Make the first entry within 1e-8 of each column's largest magnitude
+    positive (flipping the matching row of vt)."""
+    for i in range(u.shape[1]):
+        a = np.abs(u[:, i])
+        j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
+        if u[j, i] < 0:
+            u[:, i] = -u[:, i]
+            if vt is not None:
+                vt[i, :] = -vt[i, :]
+    return u, vt
+
+
 def _sqrt_factor(v):
     """v = F F^T with F = W sqrt(S); returns (F, pinv(F))."""
     v = 0.5 * (v + v.T)
     s, w = np.linalg.eigh(v)
+    w, _ = _signfix_cols(w)
     keep = s > CUT * s.max()
     sq = np.where(keep, np.sqrt(np.abs(s)), 0.0)
     isq = np.where(keep, 1.0 / np.where(keep, sq, 1.0), 0.0)
@@ -222,6 +236,7 @@ def canonicalize(cell, gammas, lams=None, tol=1e-14, max_iter=1000):
             Yt, Ytinv = _sqrt_factor(v1)
             X, Xinv = _sqrt_factor(v2)
             u, s, vt = np.linalg.svd(Yt.T @ np.diag(lams[b]) @ X)
+            u, vt = _signfix_cols(u, vt)
             upd.append((Ytinv.T @ u, vt @ Xinv))
             newl.append(s / np.linalg.norm(s))
         for b, (s1, l1, s2, l2) in enumerate(links):
