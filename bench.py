@@ -25,6 +25,43 @@ import time
 METRIC = ("CTMRG moves/s + MFMA TFLOP/s at D=6 χ=72; time-to-1e-6 energy, "
           "recycled vs plain")
 FP64_PEAK_TFLOPS = 78.6
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "tgemm_f64_kernel_ctmrg_D6_chi72_traffic.txt")
+KERNEL_SRC = os.path.join(HERE, "paper_1411_0391_amd", "csrc", "tgemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per contraction-kernel launch from the committed rocprofv3
+    counter summary, or None when the kernel source has changed since the
+    counters were taken (or no summary exists)."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, run under the HBM byte
+    counters to scale them."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}),
+          flush=True)
 
 
 def cpu_baseline(sites, C, T, chi, cell, moves):
@@ -48,11 +85,17 @@ def main():
     ap.add_argument("--chi", type=int, default=72)
     ap.add_argument("--cpu-moves", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the method's environment "
               "computation is single-device here); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibrate:
+        copy_calibration(args.copy_calibrate)
+        return
 
     import numpy as np
     import torch
@@ -114,7 +157,7 @@ def main():
                    "moves_per_step": moves_per_step},
         "roofline": {"bound": "mfma", "kernel": "tgemm_f64_kernel",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "avg_launch_ms": round(avg_ms, 5), "launches": prof["gemm_launches"],
                      "flops_per_launch": flops_per_launch},
         "step_mfma_tflops": round(prof["gemm_flops"] / elapsed / 1e12, 3),
@@ -123,7 +166,11 @@ def main():
         "jacobi_sweeps": prof["jacobi_sweeps"],
     }
     if not args.no_cpu:
-        ncores = os.cpu_count() or 1
+        try:
+            from threadpoolctl import threadpool_info
+            ncores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) or 1
+        except Exception:  # no BLAS pool reported: count the host cores
+            ncores = os.cpu_count() or 1
         rate, dt = cpu_baseline(sites_h, C_bench, T_bench, chi, cell, args.cpu_moves)
         out["cpu_baseline"] = {"value": round(rate, 5), "unit": "moves/s", "cores": ncores,
                                "kind": "oracle",

@@ -206,7 +206,6 @@ def _sqrt_factor(v):
     """v = F F^T with F = W sqrt(S); returns (F, pinv(F))."""
     v = 0.5 * (v + v.T)
     s, w = np.linalg.eigh(v)
-    w, _ = _signfix_cols(w)
     keep = s > CUT * s.max()
     sq = np.where(keep, np.sqrt(np.abs(s)), 0.0)
     isq = np.where(keep, 1.0 / np.where(keep, sq, 1.0), 0.0)
@@ -236,8 +235,10 @@ def canonicalize(cell, gammas, lams=None, tol=1e-14, max_iter=1000):
             Yt, Ytinv = _sqrt_factor(v1)
             X, Xinv = _sqrt_factor(v2)
             u, s, vt = np.linalg.svd(Yt.T @ np.diag(lams[b]) @ X)
-            u, vt = _signfix_cols(u, vt)
-            upd.append((Ytinv.T @ u, vt @ Xinv))
+            # the sign rule acts on the transform itself, which does not
+            # depend on the eigenbases chosen for V_1 and V_2
+            r, l = _signfix_cols(Ytinv.T @ u, vt @ Xinv)
+            upd.append((r, l))
             newl.append(s / np.linalg.norm(s))
         for b, (s1, l1, s2, l2) in enumerate(links):
             r, l = upd[b]
