@@ -174,6 +174,163 @@ int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, doubl
                double* energy_or_null);
 
 /*
+ * ---------------------------------------------------------------------------
+ * Full update of an iPEPS (Sec. VI B, VI C), canonical form (Sec. IV A) and
+ * gauge fixing (Sec. IV B).
+ *
+ * Links of a unit cell: enumerated in first-seen order over the positions
+ * p = 0, 1, ..., the right link of a position before its down link; link b
+ * joins leg l1 (r or d) of site s1 with leg l2 (l or u) of site s2 (legs
+ * numbered 1 l, 2 r, 3 d, 4 u as tensor axes).  Per-link matrices: the first
+ * end carries P[b] (n_old x n_new, applied as new = P^T old on that leg), the
+ * second end Q[b] (n_new x n_old, new = Q old): A~ = Q Theta P.
+ * ---------------------------------------------------------------------------
+ */
+
+/* ipeps_cell_links -- the link enumeration above, for the caller's
+ * bookkeeping.  nlink host out; links host out [64][4] = (s1, l1, s2, l2).
+ * Host-only: ctx may be NULL.  Errors: TN_EINVAL for a cell that puts two
+ * links on one leg or leaves a site out. */
+int ipeps_cell_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
+                     int* links);
+
+/*
+ * ipeps_gate -- Theta = g A (Sec. VI A, Fig. 20): the TFIM iPEPO of one
+ * second-order Trotter step (half field steps exp(dt h sx / 2) on both sides
+ * of the four bond factors of exp(dt J sz sz), split by operator SVD into
+ * kappa = 2 terms) applied to every site tensor.
+ *   A      device [nsite][d][D][D][D][D], d = 2
+ *   Theta  device out [nsite][d][2D][2D][2D][2D]; each bond index is
+ *          (D index, kappa index) with the kappa index fastest
+ */
+int ipeps_gate(tn_ctx* ctx, int nsite, int D, int d, double J, double h, double dt,
+               const double* A, double* Theta);
+
+/*
+ * ipeps_truncate -- A~ = Q Theta P on every link (Sec. VI B), each site then
+ * scaled to unit Frobenius norm.  Also applies the renormalized gate's
+ * factors (Sec. VI C) when called with Rf, Lf as P, Q.
+ *   Theta  device [nsite][d][D_in]^4;  P device [nlink][D_in][D_out];
+ *   Q      device [nlink][D_out][D_in]; A_out device out [nsite][d][D_out]^4
+ */
+int ipeps_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D_in,
+                   int D_out, const double* Theta, const double* P, const double* Q,
+                   double* A_out);
+
+/*
+ * ipeps_canonicalize -- canonical form of an iPEPS (Sec. IV A, Eqs. (17)-(20))
+ * by the paper's iteration on every link at once: per link the Gram matrices
+ * V1, V2 of the two ends (lambda on the other three legs) give V1 = Y^T Y,
+ * V2 = X X^T, the SVD Y lambda X = U S V^T gives the transforms Y^+ U and
+ * V^T X^+ and the new spectrum S / |S|; starting from flat spectra, until
+ * the spectra move by less than tol (max norm).  Pseudo-inverse square roots
+ * drop eigenvalues below 1e-14 of the largest; the columns of each transform
+ * Y^+ U are sign-fixed (first entry within 1e-8 of the largest magnitude
+ * positive).
+ *   A        device [nsite][d][D]^4, the state in A form
+ *   A_out    device out (may be NULL; needs D_keep = D): the canonical A form
+ *            A1 = Qc A Pc, unit norm per site
+ *   lambdas  device out (may be NULL) [nlink][D]: spectra, unit l2 norm
+ *   P, Q     device out [nlink][D][D_keep], [nlink][D_keep][D]: the first
+ *            D_keep columns of Pc = TR sqrt(lambda) and rows of
+ *            Qc = sqrt(lambda) TL, TR and TL the accumulated transforms of
+ *            the two ends.  With D_keep < D this is the simple-update style
+ *            pre-truncation of a gated state Theta (keep the D_keep largest
+ *            Schmidt values of every link)
+ *   tol, max_iter, iters (host out)
+ * Returns TN_OK or TN_NOT_CONVERGED (outputs from the last iterate).
+ */
+int ipeps_canonicalize(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                       int D_keep, const double* A, double* A_out, double* lambdas, double* P,
+                       double* Q, double tol, int max_iter, int* iters);
+
+/*
+ * gauge_fix -- orthogonal U_b per link with a_new ~ U(a_ref) (U_b applied as
+ * new = U_b old on both legs of link b), maximising the fidelity of Eq. (25),
+ * F = sum_s <a_new_s | U(a_ref_s)> / sum_s |a_ref_s| |a_new_s|, by alternating
+ * Procrustes steps (Sec. IV B): each link in turn, the other factors fixed,
+ * U_b = W V^T from the SVD of the linear coefficient W S V^T.  Stops when F
+ * changes by less than tol in a pass over the links.
+ *   a_ref, a_new  device [nsite][d][D]^4 (nsite <= 30)
+ *   U             device in/out [nlink][D][D]: start, then result
+ *   fidelity, iters  host out
+ * Returns TN_OK or TN_NOT_CONVERGED.
+ */
+int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+              const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
+              double* fidelity, int* iters);
+
+/*
+ * bond_env_truncate -- full-update truncation of every link (Sec. VI B,
+ * Eqs. (var), (var1)), links in enumeration order.  For link b the bond
+ * environment N[i][j][i'][j'] is the CTM network (C, T of the truncated
+ * state, bond D) around the link's two sites, each carrying Theta-hat:
+ * Theta with its other three legs truncated by the current P, Q (earlier
+ * links already updated); i, j are the ket link legs of the first and second
+ * site, i', j' the bra legs; N is symmetrised in ket <-> bra.  Then
+ * alternating least squares on f = <(I - PQ)|N|(I - PQ)>: P = R^-1 S with Q
+ * fixed, then Q with P fixed, each solve on R + 1e-14 tr(R) I (Cholesky),
+ * after each pair the pair is balanced through the SVD of PQ; stops when
+ * |df| < tol <I|N|I> or after max_sweeps.
+ *   Theta        device [nsite][d][Dk]^4, Dk = kappa D
+ *   C, T         device, the environment of the truncated state (bond D)
+ *   P, Q         device in/out [nlink][Dk][D], [nlink][D][Dk]
+ *   cost         host out (may be NULL) [nlink]: final f per link
+ *   sweeps       host out (may be NULL): sweeps summed over links
+ * Returns TN_OK, TN_EINVAL, TN_ENUMERIC (a normal matrix that is not
+ * positive definite, non-finite values), TN_EHIP.
+ */
+int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                      int Dk, const double* Theta, int chi, const double* C, const double* T,
+                      double* P, double* Q, int max_sweeps, double tol, double* cost,
+                      int* sweeps);
+
+/*
+ * bond_environment -- the symmetrised bond environment N of one link, as
+ * bond_env_truncate computes it before its ALS (same arguments; P, Q are
+ * read only).  N device out [Dk][Dk][Dk][Dk] indexed [i][j][i'][j'].
+ */
+int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                     int Dk, const double* Theta, int chi, const double* C, const double* T,
+                     const double* P, const double* Q, int link, double* N);
+
+/*
+ * fu_gauge_start -- start of the gauge fix inside the recycling step
+ * (Sec. VI C): for a small time step the renormalized gate is close to the
+ * identity, so the kappa = 0 block of the composite truncation maps the old
+ * bond basis onto the new one.  Per link, with (P Pc) [Dk][D] and (Qc Q)
+ * [D][Dk] and the bond index (i, k) (k the kappa index, fastest):
+ * K = B1 / |B1|_F + B2 / |B2|_F, B1[j][i] = (P Pc)[(i, 0)][j],
+ * B2[j][i] = (Qc Q)[j][(i, 0)], and U0 = W V^T from K = W S V^T.
+ *   P [nlink][Dk][D], Q [nlink][D][Dk], Pc, Qc [nlink][D][D] device;
+ *   U0 device out [nlink][D][D]; Dk = kappa D
+ */
+int fu_gauge_start(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
+                   const double* Q, const double* Pc, const double* Qc, double* U0);
+
+/*
+ * fu_renormalized_gate -- the per-link factors of the renormalized gate of
+ * Sec. VI C, G = U^T (Qc Q) g (P Pc) U: Rf[b] = P[b] Pc[b] U[b] on the first
+ * end, Lf[b] = U[b]^T Qc[b] Q[b] on the second end; recycled steps are then
+ * ipeps_gate followed by ipeps_truncate with (Rf, Lf).
+ *   P [nlink][Dk][D], Q [nlink][D][Dk], Pc, Qc, U [nlink][D][D] (device);
+ *   Rf device out [nlink][Dk][D], Lf device out [nlink][D][Dk]
+ */
+int fu_renormalized_gate(tn_ctx* ctx, int nlink, int Dk, int D, const double* P, const double* Q,
+                         const double* Pc, const double* Qc, const double* U, double* Rf,
+                         double* Lf);
+
+/*
+ * ipeps_energy -- TFIM energy per site from a CTM environment (Sec. VI A,
+ * VI D): mean over positions of -J <sz sz> on the position's right and down
+ * bonds and -h <sx> on the position, from the reduced density matrices of
+ * ipeps_rdms.  d must be 2.  energy host out.
+ */
+int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                 const int* cell, int chi, const double* C, const double* T, double J, double h,
+                 double* energy);
+
+/*
  * tn_gemm -- the library's contraction engine on a plain matrix product, for
  * testing and measurement: C = alpha op(A) op(B) + beta C with row-major
  * storage, op(X) = X or X^T (ta, tb nonzero), leading dimensions lda, ldb,

@@ -209,6 +209,20 @@ def fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol=1e-10, ctm_max=100, J=1.0,
                 ctm_iters=iters, ctm_delta=delta, costs=costs)
 
 
+def gauge_start(P, Q, Pc, Qc, kappa):
+    """Start of the gauge fix inside the recycling step (Sec. VI C): for a
+    small time step the renormalized gate is close to the identity, so the
+    kappa = 0 block of the composite truncation maps the old bond basis onto
+    the new one; both ends' blocks, each normalised, are added and the
+    orthogonal polar factor is taken."""
+    U0 = []
+    for b in range(len(P)):
+        b1 = (P[b] @ Pc[b])[0::kappa, :].T
+        b2 = (Qc[b] @ Q[b])[:, 0::kappa]
+        U0.append(polar_orthogonal(b1 / np.linalg.norm(b1) + b2 / np.linalg.norm(b2)))
+    return U0
+
+
 def renormalized_gate(P, Q, Pc, Qc, U):
     """Per-link factors of G (Sec. VI C step (iii), read as
     G = U^T (Qc Q) g (P Pc) U per link): Rf = P Pc U on the first leg,
@@ -245,12 +259,7 @@ def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=No
             step += 1
             continue
         a1, _, Pc, Qc, _ = canonicalize_a_form(cell, out["sites"])
-        kappa = g.shape[0]
-        U0 = [polar_orthogonal((out["P"][b] @ Pc[b])[0::kappa, :].T
-                               / np.linalg.norm((out["P"][b] @ Pc[b])[0::kappa, :])
-                               + (Qc[b] @ out["Q"][b])[:, 0::kappa]
-                               / np.linalg.norm((Qc[b] @ out["Q"][b])[:, 0::kappa]))
-              for b in range(len(links))]
+        U0 = gauge_start(out["P"], out["Q"], Pc, Qc, g.shape[0])
         U, _, _ = gauge_fix(cell, sites, a1, U0=U0)
         Rf, Lf = renormalized_gate(out["P"], out["Q"], Pc, Qc, U)
         a0 = sites

@@ -51,6 +51,33 @@ SIGNATURES = {
     "itebd_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                   ctypes.c_double, _c_double_p, _c_double_p]),
+    "ipeps_cell_links": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                        _c_int_p, _c_int_p]),
+    "ipeps_gate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "ipeps_truncate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                      _vp]),
+    "ipeps_canonicalize": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                          _vp, _vp, ctypes.c_double, ctypes.c_int, _c_int_p]),
+    "gauge_fix": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                 ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
+                                 ctypes.c_int, _c_double_p, _c_int_p]),
+    "bond_env_truncate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                         ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                         ctypes.c_double, _c_double_p, _c_int_p]),
+    "bond_environment": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                        ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "fu_gauge_start": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "fu_renormalized_gate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                            _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ipeps_energy": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, _vp, _c_int_p, ctypes.c_int, _vp, _vp,
+                                    ctypes.c_double, ctypes.c_double, _c_double_p]),
     "tn_svd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tn_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tn_prof_read": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
@@ -169,6 +196,107 @@ class Context:
         self._check(rc)
         return r1, rh, rv
 
+    def ipeps_energy(self, Lx, Ly, sites, cell, C, T, J, h):
+        nsite, d, D = sites.shape[0], sites.shape[1], sites.shape[2]
+        chi = C.shape[-1]
+        e = ctypes.c_double(0.0)
+        rc = lib().ipeps_energy(self._h, Lx, Ly, D, d, nsite, _ptr(sites), self._cell(cell), chi,
+                                _ptr(C), _ptr(T), J, h, ctypes.byref(e))
+        self._check(rc)
+        return e.value
+
+    # -- full update -----------------------------------------------------------
+    def cell_links(self, Lx, Ly, nsite, cell):
+        return cell_links(Lx, Ly, nsite, cell)
+
+    def ipeps_gate(self, A, J, h, dt):
+        import torch
+        nsite, d, D = A.shape[0], A.shape[1], A.shape[2]
+        Th = torch.empty((nsite, d) + (2 * D,) * 4, dtype=torch.float64, device=A.device)
+        self._check(lib().ipeps_gate(self._h, nsite, D, d, J, h, dt, _ptr(A), _ptr(Th)))
+        return Th
+
+    def ipeps_truncate(self, Lx, Ly, cell, Theta, P, Q):
+        import torch
+        nsite, d, Din = Theta.shape[0], Theta.shape[1], Theta.shape[2]
+        Dout = P.shape[2]
+        out = torch.empty((nsite, d) + (Dout,) * 4, dtype=torch.float64, device=Theta.device)
+        self._check(lib().ipeps_truncate(self._h, Lx, Ly, nsite, self._cell(cell), d, Din, Dout,
+                                         _ptr(Theta), _ptr(P), _ptr(Q), _ptr(out)))
+        return out
+
+    def ipeps_canonicalize(self, Lx, Ly, cell, A, D_keep=None, tol=1e-14, max_iter=1000,
+                           a_out=True):
+        """Returns (A1 or None, lambdas, P, Q, iters, rc)."""
+        import torch
+        nsite, d, D = A.shape[0], A.shape[1], A.shape[2]
+        Dk = D if D_keep is None else D_keep
+        nl = len(self.cell_links(Lx, Ly, nsite, cell))
+        dev = A.device
+        A1 = torch.empty_like(A) if (a_out and Dk == D) else None
+        lam = torch.empty((nl, D), dtype=torch.float64, device=dev)
+        P = torch.empty((nl, D, Dk), dtype=torch.float64, device=dev)
+        Q = torch.empty((nl, Dk, D), dtype=torch.float64, device=dev)
+        it = ctypes.c_int(0)
+        rc = lib().ipeps_canonicalize(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk, _ptr(A),
+                                      _ptr(A1) if A1 is not None else None, _ptr(lam), _ptr(P),
+                                      _ptr(Q), tol, max_iter, ctypes.byref(it))
+        self._check(rc, allow_nc=True)
+        return A1, lam, P, Q, it.value, rc
+
+    def gauge_fix(self, Lx, Ly, cell, a_ref, a_new, U, tol=1e-12, max_iter=1000):
+        """U (device [nlink][D][D]) is updated in place; returns (F, iters, rc)."""
+        nsite, d, D = a_ref.shape[0], a_ref.shape[1], a_ref.shape[2]
+        F = ctypes.c_double(0)
+        it = ctypes.c_int(0)
+        rc = lib().gauge_fix(self._h, Lx, Ly, nsite, self._cell(cell), d, D, _ptr(a_ref),
+                             _ptr(a_new), _ptr(U), tol, max_iter, ctypes.byref(F),
+                             ctypes.byref(it))
+        self._check(rc, allow_nc=True)
+        return F.value, it.value, rc
+
+    def bond_env_truncate(self, Lx, Ly, cell, Theta, C, T, P, Q, max_sweeps=50, tol=1e-12):
+        """P, Q (device) are updated in place; returns (costs, sweeps)."""
+        nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
+        D = P.shape[2]
+        chi = C.shape[-1]
+        nl = P.shape[0]
+        cost = (ctypes.c_double * nl)()
+        sw = ctypes.c_int(0)
+        rc = lib().bond_env_truncate(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
+                                     _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(P), _ptr(Q),
+                                     max_sweeps, tol, cost, ctypes.byref(sw))
+        self._check(rc)
+        return list(cost), sw.value
+
+    def bond_environment(self, Lx, Ly, cell, Theta, C, T, P, Q, link):
+        import torch
+        nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
+        D = P.shape[2]
+        chi = C.shape[-1]
+        N = torch.empty((Dk,) * 4, dtype=torch.float64, device=Theta.device)
+        self._check(lib().bond_environment(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
+                                           _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(P), _ptr(Q),
+                                           link, _ptr(N)))
+        return N
+
+    def fu_gauge_start(self, P, Q, Pc, Qc, kappa=2):
+        import torch
+        nl, Dk, D = P.shape
+        U0 = torch.empty((nl, D, D), dtype=torch.float64, device=P.device)
+        self._check(lib().fu_gauge_start(self._h, nl, Dk, D, kappa, _ptr(P), _ptr(Q), _ptr(Pc),
+                                         _ptr(Qc), _ptr(U0)))
+        return U0
+
+    def fu_renormalized_gate(self, P, Q, Pc, Qc, U):
+        import torch
+        nl, Dk, D = P.shape
+        Rf = torch.empty_like(P)
+        Lf = torch.empty_like(Q)
+        self._check(lib().fu_renormalized_gate(self._h, nl, Dk, D, _ptr(P), _ptr(Q), _ptr(Pc),
+                                               _ptr(Qc), _ptr(U), _ptr(Rf), _ptr(Lf)))
+        return Rf, Lf
+
     # -- 1D ------------------------------------------------------------------
     def tm_fixed_point(self, kets, bras, tol=1e-14, max_iter=200000, vl=None, vr=None):
         import torch
@@ -234,14 +362,13 @@ class Context:
         self._check(rc)
 
 
-def tfim_energy_per_site(rho1, rhoh, rhov, J, h):
-    """Energy per site from RDMs (host arithmetic on 4x4 matrices is not on
-    the hot path; the RDMs themselves come from the kernels)."""
-    sz = np.diag([1.0, -1.0])
-    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
-    zz = np.kron(sz, sz)
-    r1, rh, rv = (x.detach().cpu().numpy() for x in (rho1, rhoh, rhov))
-    e = 0.0
-    for p in range(r1.shape[0]):
-        e += -J * np.trace(rh[p] @ zz) - J * np.trace(rv[p] @ zz) - h * np.trace(r1[p] @ sx)
-    return float(e / r1.shape[0])
+def cell_links(Lx, Ly, nsite, cell):
+    """Link enumeration of a unit cell (host-only call into the library):
+    list of (site1, leg1, site2, leg2), legs numbered 1 l, 2 r, 3 d, 4 u."""
+    nl = ctypes.c_int(0)
+    buf = (ctypes.c_int * 256)()
+    arr = (ctypes.c_int * len(cell))(*[int(c) for c in cell])
+    rc = lib().ipeps_cell_links(None, Lx, Ly, nsite, arr, ctypes.byref(nl), buf)
+    if rc != 0:
+        raise TNError(rc, "invalid unit cell")
+    return [tuple(buf[4 * b:4 * b + 4]) for b in range(nl.value)]

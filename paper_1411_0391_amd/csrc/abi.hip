@@ -20,6 +20,35 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A, double J, double h, 
                     double* env1d, double* lambda_out, double tol, double* trunc_err,
                     double* energy_or_null);
 
+int cell_links_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
+                    int* links);
+int ipeps_gate_impl(tn_ctx* ctx, int nsite, int D, int d, double J, double h, double dt,
+                    const double* A, double* Theta);
+int ipeps_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int Din,
+                        int Dout, const double* Theta, const double* P, const double* Q,
+                        double* Aout);
+int ipeps_canonicalize_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                            int Dkeep, const double* A, double* Aout, double* lams, double* P,
+                            double* Q, double tol, int max_iter, int* iters);
+int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                   const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
+                   double* fidelity, int* iters);
+int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                           int Dk, const double* Theta, int chi, const double* C, const double* T,
+                           double* P, double* Q, int max_sweeps, double tol, double* cost,
+                           int* sweeps);
+int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                          int Dk, const double* Theta, int chi, const double* C, const double* T,
+                          const double* P, const double* Q, int link, double* N_out);
+int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
+                        const double* Q, const double* Pc, const double* Qc, double* U0);
+int fu_renormalized_gate_impl(tn_ctx* ctx, int nlink, int Dk, int D, const double* P,
+                              const double* Q, const double* Pc, const double* Qc, const double* U,
+                              double* Rf, double* Lf);
+int ipeps_energy_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                      const int* cell, int chi, const double* C, const double* T, double J,
+                      double h, double* energy);
+
 int ws_reserve(tn_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_size) return TN_OK;
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -169,6 +198,91 @@ int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, doubl
   ctx->err.clear();
   return itebd_step_impl(ctx, chi, d, A, J, h, dt, mode, env1d, lambda_out, tol, trunc_err,
                          energy_or_null);
+}
+
+int ipeps_cell_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
+                     int* links) {
+  if (!ctx) {  // host-only: usable without a context (errors give the code only)
+    tn_ctx tmp;
+    return cell_links_impl(&tmp, Lx, Ly, nsite, cell, nlink, links);
+  }
+  ctx->err.clear();
+  return cell_links_impl(ctx, Lx, Ly, nsite, cell, nlink, links);
+}
+
+int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                     int Dk, const double* Theta, int chi, const double* C, const double* T,
+                     const double* P, const double* Q, int link, double* N) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return bond_environment_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, P, Q, link,
+                               N);
+}
+
+int fu_gauge_start(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
+                   const double* Q, const double* Pc, const double* Qc, double* U0) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return fu_gauge_start_impl(ctx, nlink, Dk, D, kappa, P, Q, Pc, Qc, U0);
+}
+
+int ipeps_gate(tn_ctx* ctx, int nsite, int D, int d, double J, double h, double dt,
+               const double* A, double* Theta) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ipeps_gate_impl(ctx, nsite, D, d, J, h, dt, A, Theta);
+}
+
+int ipeps_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D_in,
+                   int D_out, const double* Theta, const double* P, const double* Q,
+                   double* A_out) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ipeps_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D_in, D_out, Theta, P, Q, A_out);
+}
+
+int ipeps_canonicalize(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                       int D_keep, const double* A, double* A_out, double* lambdas, double* P,
+                       double* Q, double tol, int max_iter, int* iters) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ipeps_canonicalize_impl(ctx, Lx, Ly, nsite, cell, d, D, D_keep, A, A_out, lambdas, P, Q,
+                                 tol, max_iter, iters);
+}
+
+int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+              const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
+              double* fidelity, int* iters) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return gauge_fix_impl(ctx, Lx, Ly, nsite, cell, d, D, a_ref, a_new, U, tol, max_iter, fidelity,
+                        iters);
+}
+
+int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                      int Dk, const double* Theta, int chi, const double* C, const double* T,
+                      double* P, double* Q, int max_sweeps, double tol, double* cost,
+                      int* sweeps) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return bond_env_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, P, Q,
+                                max_sweeps, tol, cost, sweeps);
+}
+
+int fu_renormalized_gate(tn_ctx* ctx, int nlink, int Dk, int D, const double* P, const double* Q,
+                         const double* Pc, const double* Qc, const double* U, double* Rf,
+                         double* Lf) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return fu_renormalized_gate_impl(ctx, nlink, Dk, D, P, Q, Pc, Qc, U, Rf, Lf);
+}
+
+int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                 const int* cell, int chi, const double* C, const double* T, double J, double h,
+                 double* energy) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ipeps_energy_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, J, h, energy);
 }
 
 int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, double* S,

@@ -171,8 +171,8 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
 // matrix lives in LDS; step j reads the unscaled row j, writes row j of R
 // (divided by sqrt of the pivot) and updates the trailing block with
 // W[r][c] -= W[j][r] W[j][c] / W[j][j] -- one barrier per step.  The inverse
-// is back substitution, one column per thread, reading R from LDS when it
-// fits there too.
+// is a column-oriented back substitution over all columns at once, also one
+// barrier per step, reading R from LDS when it fits there too.
 // ---------------------------------------------------------------------------
 constexpr int CHOL_THREADS = 1024;
 
@@ -216,22 +216,25 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
   }
   if (tid == 0) *info = fail;
   if (fail) return;
-  // R^-1 by back substitution in LDS (Wk is free), rows in lockstep from the
-  // bottom so that R[i][l] is a broadcast and the R^-1 column reads of the
-  // lanes (one column each) are consecutive; entries below the diagonal are
-  // zero, so every lane can run the full l range without divergence
-  for (int t = tid; t < k * k; t += CHOL_THREADS) Wk[t] = 0.0;
+  // R^-1 by column-oriented back substitution on all columns at once (Wk is
+  // free): B = I; for j = k-1 .. 0, with row j of B final,
+  // B[i][c] -= R[i][j] B[j][c] / R[j][j] for i < j <= c; finally row j of
+  // R^-1 is B[j][:] / R[j][j].  One barrier per step; the work of a step is
+  // spread over all threads.
+  for (int t = tid; t < k * k; t += CHOL_THREADS) Wk[t] = (t / k == t % k) ? 1.0 : 0.0;
   __syncthreads();
-  for (int i = k - 1; i >= 0; --i) {
-    for (int c = i + tid; c < k; c += CHOL_THREADS) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int l = i + 1; l < k; ++l) s -= Rl[i * k + l] * Wk[l * k + c];
-      Wk[i * k + c] = s / Rl[i * k + i];
+  for (int j = k - 1; j > 0; --j) {
+    const double inv_jj = 1.0 / Rl[j * k + j];
+    const int w = k - j;
+    for (int t = tid; t < j * w; t += CHOL_THREADS) {
+      const int i = t / w, c = j + t % w;
+      Wk[i * k + c] -= Rl[i * k + j] * (Wk[j * k + c] * inv_jj);
     }
     __syncthreads();
   }
   for (int t = tid; t < k * k; t += CHOL_THREADS) {
-    Rinv[t] = Wk[t];
+    const int i = t / k;
+    Rinv[t] = Wk[t] / Rl[i * k + i];
     if (r_in_lds) R[t] = Rl[t];
   }
 }

@@ -1,0 +1,1543 @@
+// Full update of an iPEPS with environment recycling (Sec. VI B, VI C of the
+// paper), the canonical form of an iPEPS (Sec. IV A) and gauge fixing
+// (Sec. IV B, Eq. (25)) on the GPU.
+//
+// Site tensors here are small (d (kappa D)^4 entries), so the elementwise and
+// per-leg kernels are plain one-pass kernels over L2-resident data and the
+// small factorisations run one workgroup per matrix.  The bond environment N
+// of a link -- the CTM network around the link's two sites with the link's
+// ket and bra legs open -- is the one sizeable contraction and runs on the
+// table-driven MFMA contraction engine, as two half networks joined over
+// their boundary legs.
+//
+// Links of a unit cell are enumerated in first-seen order over the positions
+// (p = y Lx + x), the right link of a position before its down link; link b
+// joins leg l1 (r or d) of site s1 to leg l2 (l or u) of site s2.  On a link
+// the first site carries P (new = P^T old on that leg) and the second Q
+// (new = Q old), as in A~ = Q Theta P.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                    const int* cell, int chi, const double* C, const double* T, double* rho1,
+                    double* rhoh, double* rhov);
+
+namespace {
+
+constexpr int MAXL = 64;        // links of a cell
+constexpr int MAXN = 32;        // largest bond handled by the small per-leg kernels
+constexpr double CUT = 1e-14;   // relative cutoff of pseudo-inverse square roots
+enum { AX_S = 0, AX_L = 1, AX_R = 2, AX_D = 3, AX_U = 4 };
+
+// ---------------------------------------------------------------------------
+// cell links
+// ---------------------------------------------------------------------------
+
+struct CellLinks {
+  int nl = 0;
+  int s1[MAXL], l1[MAXL], s2[MAXL], l2[MAXL];
+  int x[MAXL], y[MAXL];  // position of the first site where the link is first met
+  std::vector<std::array<int, 5>> leg_link;  // [site][axis] -> link
+};
+
+int build_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, CellLinks& L) {
+  if (Lx < 1 || Ly < 1 || nsite < 1 || !cell) TN_FAIL(ctx, TN_EINVAL, "bad unit cell");
+  if (Lx * Ly > 64) TN_FAIL(ctx, TN_EINVAL, "cell larger than 64 positions");
+  for (int p = 0; p < Lx * Ly; ++p)
+    if (cell[p] < 0 || cell[p] >= nsite)
+      TN_FAIL(ctx, TN_EINVAL, "cell[%d] = %d out of range [0, %d)", p, cell[p], nsite);
+  L.nl = 0;
+  L.leg_link.assign(nsite, {-1, -1, -1, -1, -1});
+  auto pos = [&](int x, int y) { return (((y % Ly) + Ly) % Ly) * Lx + (((x % Lx) + Lx) % Lx); };
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) {
+      const int s = cell[pos(x, y)];
+      const int legs[2][4] = {{AX_R, AX_L, 1, 0}, {AX_D, AX_U, 0, 1}};
+      for (auto& lg : legs) {
+        const int t = cell[pos(x + lg[2], y + lg[3])];
+        int b = -1;
+        for (int k = 0; k < L.nl; ++k)
+          if (L.s1[k] == s && L.l1[k] == lg[0] && L.s2[k] == t) b = k;
+        if (b < 0) {
+          if (L.nl == MAXL) TN_FAIL(ctx, TN_EINVAL, "too many links");
+          b = L.nl++;
+          L.s1[b] = s;
+          L.l1[b] = lg[0];
+          L.s2[b] = t;
+          L.l2[b] = lg[1];
+          L.x[b] = x;
+          L.y[b] = y;
+        }
+        const int ends[2][2] = {{s, lg[0]}, {t, lg[1]}};
+        for (auto& e : ends) {
+          int& slot = L.leg_link[e[0]][e[1]];
+          if (slot >= 0 && slot != b)
+            TN_FAIL(ctx, TN_EINVAL, "the cell assigns two links to leg %d of site %d", e[1], e[0]);
+          slot = b;
+        }
+      }
+    }
+  for (int s = 0; s < nsite; ++s)
+    if (L.leg_link[s][AX_L] < 0) TN_FAIL(ctx, TN_EINVAL, "site %d does not occur in the cell", s);
+  return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tensor shapes and per-leg kernels
+// ---------------------------------------------------------------------------
+
+struct TDims {
+  int n[5];
+};
+
+__host__ __device__ inline long long tsize(const TDims& t) {
+  return (long long)t.n[0] * t.n[1] * t.n[2] * t.n[3] * t.n[4];
+}
+
+TDims dims5(int d, int a, int b, int c, int e) { return TDims{{d, a, b, c, e}}; }
+
+// out = m applied on axis ax of in: out[.., i, ..] = sum_a m_eff[i][a] in[.., a, ..],
+// m_eff = m (nnew x nold) or, with trans, m^T for m stored nold x nnew
+__global__ void apply_leg_kernel(const double* __restrict__ in, double* __restrict__ out, TDims din,
+                                 int ax, const double* __restrict__ m, int trans, int nnew) {
+  TDims dout = din;
+  dout.n[ax] = nnew;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tsize(dout)) return;
+  int idx[5];
+  long long r = t;
+  for (int k = 4; k >= 0; --k) {
+    idx[k] = (int)(r % dout.n[k]);
+    r /= dout.n[k];
+  }
+  long long st[5];
+  st[4] = 1;
+  for (int k = 3; k >= 0; --k) st[k] = st[k + 1] * din.n[k + 1];
+  long long base = 0;
+  for (int k = 0; k < 5; ++k)
+    if (k != ax) base += idx[k] * st[k];
+  const int i = idx[ax], nold = din.n[ax];
+  double acc = 0.0;
+  for (int a = 0; a < nold; ++a) {
+    const double mv = trans ? m[(long long)a * nnew + i] : m[(long long)i * nold + a];
+    acc += mv * in[base + a * st[ax]];
+  }
+  out[t] = acc;
+}
+
+int apply_leg(tn_ctx* ctx, const double* in, double* out, TDims din, int ax, const double* m,
+              int trans, int nnew) {
+  TDims dout = din;
+  dout.n[ax] = nnew;
+  const long long tot = tsize(dout);
+  hipLaunchKernelGGL(apply_leg_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, in, out, din, ax, m, trans, nnew);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
+// One matrix per bond axis (null: leave the axis alone), applied in axis
+// order; `out` receives the result, t1/t2 are scratch of the largest
+// intermediate size.  Returns the output shape in *dout.
+struct LegMats {
+  const double* m[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int trans[5] = {0, 0, 0, 0, 0};
+  int nnew[5] = {0, 0, 0, 0, 0};
+};
+
+int apply_legs(tn_ctx* ctx, const double* in, double* out, TDims din, const LegMats& lm,
+               double* t1, double* t2, TDims* dout) {
+  int todo[4], nt = 0;
+  for (int ax = 1; ax <= 4; ++ax)
+    if (lm.m[ax]) todo[nt++] = ax;
+  TDims cur = din;
+  const double* src = in;
+  for (int k = 0; k < nt; ++k) {
+    const int ax = todo[k];
+    double* dst = (k == nt - 1) ? out : ((k & 1) ? t2 : t1);
+    TN_TRY(apply_leg(ctx, src, dst, cur, ax, lm.m[ax], lm.trans[ax], lm.nnew[ax]));
+    cur.n[ax] = lm.nnew[ax];
+    src = dst;
+  }
+  if (nt == 0)
+    TN_HIP(ctx, hipMemcpyAsync(out, in, tsize(din) * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  if (dout) *dout = cur;
+  return TN_OK;
+}
+
+// one counter-clockwise rotation: new (l, r, d, u) = old (u, d, l, r)
+__global__ void rotate_kernel(const double* __restrict__ in, double* __restrict__ out, TDims din) {
+  const TDims dout{{din.n[0], din.n[4], din.n[3], din.n[1], din.n[2]}};
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tsize(dout)) return;
+  long long r = t;
+  const int e = (int)(r % dout.n[4]); r /= dout.n[4];
+  const int c = (int)(r % dout.n[3]); r /= dout.n[3];
+  const int b = (int)(r % dout.n[2]); r /= dout.n[2];
+  const int a = (int)(r % dout.n[1]); r /= dout.n[1];
+  const int s = (int)r;
+  // new[s][a][b][c][e] = old[s][l=c][r=e][d=b][u=a]
+  const long long src =
+      ((((long long)s * din.n[1] + c) * din.n[2] + e) * din.n[3] + b) * din.n[4] + a;
+  out[t] = in[src];
+}
+
+int rotate_times(tn_ctx* ctx, const double* in, double* out, double* tmp, TDims din, int times,
+                 TDims* dout) {
+  TDims cur = din;
+  const double* src = in;
+  if (times == 0) {
+    TN_HIP(ctx, hipMemcpyAsync(out, in, tsize(din) * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  }
+  for (int k = 0; k < times; ++k) {
+    // alternate so that the last rotation lands in out
+    double* dst = ((times - 1 - k) & 1) ? tmp : out;
+    const long long tot = tsize(cur);
+    hipLaunchKernelGGL(rotate_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       ctx->stream, src, dst, cur);
+    TN_HIP(ctx, hipGetLastError());
+    cur = TDims{{cur.n[0], cur.n[4], cur.n[3], cur.n[1], cur.n[2]}};
+    src = dst;
+  }
+  if (dout) *dout = cur;
+  return TN_OK;
+}
+
+// Gram-type products over every index but one bond axis:
+// out[i][i'] = sum_terms sum_rest A_t[.., i, ..] w(rest) B_t[.., i', ..] w(rest)
+// with the open index on axis ax[t] of term t, w(rest) = product of
+// lam_k[index on axis k] over the weighted axes k (null: weight 1).
+struct GramJob {
+  const double* A[2];
+  const double* B[2];
+  int ax[2];
+  int nterm;
+  TDims dims;
+  const double* lam[5];
+  double* out;
+};
+constexpr int GRAM_JOBS = 16;
+struct GramBatch {
+  GramJob job[GRAM_JOBS];
+};
+
+constexpr int GRAM_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void leg_gram_kernel(GramBatch batch) {
+  const GramJob& J = batch.job[blockIdx.x];
+  const int n = J.dims.n[J.ax[0]];
+  __shared__ double ta[MAXN][GRAM_CHUNK + 1], tb[MAXN][GRAM_CHUNK + 1];
+  long long st[5];
+  st[4] = 1;
+  for (int k = 3; k >= 0; --k) st[k] = st[k + 1] * J.dims.n[k + 1];
+  const long long rest = tsize(J.dims) / n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int tid = threadIdx.x;
+  for (int term = 0; term < J.nterm; ++term) {
+    const double* A = J.A[term];
+    const double* B = J.B[term];
+    const int ax = J.ax[term];
+    int other[4], no = 0;
+    for (int k = 0; k < 5; ++k)
+      if (k != ax) other[no++] = k;
+    for (long long c0 = 0; c0 < rest; c0 += GRAM_CHUNK) {
+      for (int e = tid; e < n * GRAM_CHUNK; e += 256) {
+        const int i = e / GRAM_CHUNK, c = e % GRAM_CHUNK;
+        const long long col = c0 + c;
+        double va = 0.0, vb = 0.0;
+        if (col < rest) {
+          long long r = col, off = 0;
+          double w = 1.0;
+          for (int q = 3; q >= 0; --q) {
+            const int k = other[q];
+            const int ik = (int)(r % J.dims.n[k]);
+            r /= J.dims.n[k];
+            off += ik * st[k];
+            if (J.lam[k]) w *= J.lam[k][ik];
+          }
+          off += (long long)i * st[ax];
+          va = A[off] * w;
+          vb = B[off] * w;
+        }
+        ta[i][c] = va;
+        tb[i][c] = vb;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + q * 256;
+        if (e < n * n) {
+          const int i = e / n, j = e % n;
+          double s = 0.0;
+          for (int c = 0; c < GRAM_CHUNK; ++c) s += ta[i][c] * tb[j][c];
+          acc[q] += s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * 256;
+    if (e < n * n) J.out[e] = acc[q];
+  }
+}
+
+int run_grams(tn_ctx* ctx, const std::vector<GramJob>& jobs) {
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += GRAM_JOBS) {
+    GramBatch b;
+    std::memset(&b, 0, sizeof(b));
+    const int nj = (int)std::min<size_t>(GRAM_JOBS, jobs.size() - j0);
+    for (int j = 0; j < nj; ++j) b.job[j] = jobs[j0 + j];
+    hipLaunchKernelGGL(leg_gram_kernel, dim3(nj), dim3(256), 0, ctx->stream, b);
+    TN_HIP(ctx, hipGetLastError());
+  }
+  return TN_OK;
+}
+
+__device__ inline double block_sum256(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ inline double block_max256(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// sign rule on column j of an n x n matrix in LDS: the first entry within a
+// relative 1e-8 of the column's largest magnitude is made positive; returns
+// the factor (+1 or -1), identical in every thread
+__device__ double column_sign(const double* X, int n, int j, double* red) {
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, fabs(X[i * n + j]));
+  mx = block_max256(mx, red);
+  // the first qualifying row: smallest index, as a max over -index
+  double first = -1e30;
+  for (int i = threadIdx.x; i < n; i += 256)
+    if (fabs(X[i * n + j]) >= (1.0 - 1e-8) * mx) first = fmax(first, -(double)i);
+  first = block_max256(first, red);
+  const int fi = (int)(-first);
+  return (fi >= 0 && fi < n && X[fi * n + j] < 0.0) ? -1.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// canonical form (Sec. IV A)
+// ---------------------------------------------------------------------------
+
+// M_b = F1^T diag(lam_b) F2 with F = W sqrt(s) (s below CUT * s_max dropped);
+// W, S hold the factorisations of V1 (jobs 0..nl-1) and V2 (nl..2nl-1)
+__global__ __launch_bounds__(256) void canon_m_kernel(int nl, int n, const double* __restrict__ W,
+                                                      const double* __restrict__ S,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ M) {
+  const int b = blockIdx.x;
+  const double* W1 = W + (long long)b * n * n;
+  const double* W2 = W + (long long)(nl + b) * n * n;
+  const double* S1 = S + (long long)b * n;
+  const double* S2 = S + (long long)(nl + b) * n;
+  const double* lb = lam + (long long)b * n;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int k = e / n, m = e % n;
+    const double s1 = S1[k] > CUT * S1[0] ? sqrt(S1[k]) : 0.0;
+    const double s2 = S2[m] > CUT * S2[0] ? sqrt(S2[m]) : 0.0;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += W1[i * n + k] * lb[i] * W2[i * n + m];
+    M[(long long)b * n * n + e] = acc * s1 * s2;
+  }
+}
+
+// Per link: r = W1 S1^-1/2 U, l = V^T S2^-1/2 W2^T (sign rule on the columns
+// of r, rows of l flipping with them); lam <- s / |s|; TR <- TR r, TL <- l TL,
+// each rescaled to unit Frobenius norm; dl[b] = max |lam_new - lam_old|.
+__global__ __launch_bounds__(256) void canon_update_kernel(
+    int nl, int n, const double* __restrict__ W, const double* __restrict__ S,
+    const double* __restrict__ Um, const double* __restrict__ Sm, const double* __restrict__ Vm,
+    double* __restrict__ lam, double* __restrict__ TR, double* __restrict__ TL,
+    double* __restrict__ Rout, double* __restrict__ Lout, double* __restrict__ dl) {
+  const int b = blockIdx.x;
+  __shared__ double r[MAXN * MAXN], l[MAXN * MAXN], red[4];
+  const double* W1 = W + (long long)b * n * n;
+  const double* W2 = W + (long long)(nl + b) * n * n;
+  const double* S1 = S + (long long)b * n;
+  const double* S2 = S + (long long)(nl + b) * n;
+  const double* U = Um + (long long)b * n * n;
+  const double* V = Vm + (long long)b * n * n;
+  const long long nn = (long long)n * n;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double i1 = S1[k] > CUT * S1[0] ? 1.0 / sqrt(S1[k]) : 0.0;
+      const double i2 = S2[k] > CUT * S2[0] ? 1.0 / sqrt(S2[k]) : 0.0;
+      a += W1[i * n + k] * i1 * U[k * n + j];
+      // l[i][j] = sum_k V[k][i] i2_k W2[j][k]
+      c += V[k * n + i] * i2 * W2[j * n + k];
+    }
+    r[e] = a;
+    l[e] = c;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double sg = column_sign(r, n, j, red);
+    if (sg < 0.0) {
+      for (int i = threadIdx.x; i < n; i += 256) {
+        r[i * n + j] = -r[i * n + j];
+        l[j * n + i] = -l[j * n + i];
+      }
+    }
+    __syncthreads();
+  }
+  // spectrum
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) ss += Sm[(long long)b * n + i] * Sm[(long long)b * n + i];
+  const double snorm = sqrt(block_sum256(ss, red));
+  double dmax = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = Sm[(long long)b * n + i] / snorm;
+    dmax = fmax(dmax, fabs(v - lam[(long long)b * n + i]));
+    lam[(long long)b * n + i] = v;
+  }
+  dmax = block_max256(dmax, red);
+  if (threadIdx.x == 0) dl[b] = dmax;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    Rout[b * nn + e] = r[e];
+    Lout[b * nn + e] = l[e];
+  }
+  // TR <- TR r, TL <- l TL (in registers: each thread owns up to 4 entries)
+  double nr[4], nlv[4];
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
+    nr[q] = nlv[q] = 0.0;
+    if (e < n * n) {
+      const int i = e / n, j = e % n;
+      double a = 0.0, c = 0.0;
+      for (int k = 0; k < n; ++k) {
+        a += TR[b * nn + i * n + k] * r[k * n + j];
+        c += l[i * n + k] * TL[b * nn + k * n + j];
+      }
+      nr[q] = a;
+      nlv[q] = c;
+      s1 += a * a;
+      s2 += c * c;
+    }
+  }
+  const double n1 = sqrt(block_sum256(s1, red));
+  const double n2 = sqrt(block_sum256(s2, red));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < n * n) {
+      TR[b * nn + e] = nr[q] / n1;
+      TL[b * nn + e] = nlv[q] / n2;
+    }
+  }
+}
+
+__global__ void max_of_kernel(const double* __restrict__ x, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m = fmax(m, x[i]);
+  *out = m;
+}
+
+__global__ void eye_kernel(double* __restrict__ X, int batch, int n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)batch * n * n) return;
+  const int e = (int)(t % ((long long)n * n));
+  X[t] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+__global__ void fill_kernel(double* __restrict__ X, long long n, double v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) X[t] = v;
+}
+
+// Pc = TR diag(sqrt lam), Qc = diag(sqrt lam) TL (per link, n x n)
+__global__ void canon_pq_kernel(int nl, int n, const double* __restrict__ TR,
+                                const double* __restrict__ TL, const double* __restrict__ lam,
+                                double* __restrict__ Pc, double* __restrict__ Qc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nl * n * n) return;
+  const int b = (int)(t / ((long long)n * n));
+  const int e = (int)(t % ((long long)n * n));
+  const int i = e / n, j = e % n;
+  Pc[t] = TR[t] * sqrt(lam[(long long)b * n + j]);
+  Qc[t] = sqrt(lam[(long long)b * n + i]) * TL[t];
+}
+
+// ---------------------------------------------------------------------------
+// gauge fixing (Sec. IV B)
+// ---------------------------------------------------------------------------
+
+// U = W V^T per matrix (the orthogonal polar factor of K = W S V^T)
+__global__ void polar_kernel(int n, const double* __restrict__ W, const double* __restrict__ V,
+                             double* __restrict__ U) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e / n, j = e % n;
+  double a = 0.0;
+  for (int k = 0; k < n; ++k) a += W[i * n + k] * V[j * n + k];
+  U[e] = a;
+}
+
+__global__ __launch_bounds__(1024) void dot_kernel(const double* __restrict__ a,
+                                                   const double* __restrict__ b, long long n,
+                                                   double* __restrict__ out) {
+  __shared__ double part[16];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 1024) s += a[i] * b[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += part[w];
+    *out = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gates (Sec. VI A, Fig. 20)
+// ---------------------------------------------------------------------------
+
+// iPEPO of the TFIM, g[l][r][d][u][s][s'] = g_F (R_l L_r L_d R_u) g_F with the
+// interaction exp(dt J sz sz) = sum_k L_k (x) R_k, L = {sqrt(cosh) I,
+// sqrt|sinh| sz}, R = {sqrt(cosh) I, sign(sinh) sqrt|sinh| sz}, and the half
+// field step g_F = exp(dt h sx / 2); the left (top) site of a bond takes L on
+// its r (d) leg, the right (bottom) site R on its l (u) leg.
+void tfim_ipepo(double J, double h, double dt, double* g) {
+  const double c = cosh(0.5 * dt * h), s = sinh(0.5 * dt * h);
+  const double gf[2][2] = {{c, s}, {s, c}};
+  const double ch = cosh(dt * J), sh = sinh(dt * J);
+  const double lw[2] = {sqrt(ch), sqrt(fabs(sh))};
+  const double rw[2] = {sqrt(ch), (sh < 0 ? -1.0 : 1.0) * sqrt(fabs(sh))};
+  for (int l = 0; l < 2; ++l)
+    for (int r = 0; r < 2; ++r)
+      for (int d = 0; d < 2; ++d)
+        for (int u = 0; u < 2; ++u) {
+          double mid[2];
+          for (int q = 0; q < 2; ++q) {
+            const double z = q == 0 ? 1.0 : -1.0;
+            const int zp = l + r + d + u;  // total power of sz on this diagonal
+            double w = rw[l] * lw[r] * lw[d] * rw[u];
+            mid[q] = w * ((zp & 1) ? z : 1.0);
+          }
+          for (int s1 = 0; s1 < 2; ++s1)
+            for (int t1 = 0; t1 < 2; ++t1) {
+              double acc = 0.0;
+              for (int q = 0; q < 2; ++q) acc += gf[s1][q] * mid[q] * gf[q][t1];
+              g[((((l * 2 + r) * 2 + d) * 2 + u) * 2 + s1) * 2 + t1] = acc;
+            }
+        }
+}
+
+// Theta[s][(l,a)][(r,b)][(d,c)][(u,e)] = sum_t g[a][b][c][e][s][t] A[t][l][r][d][u]
+__global__ void ipepo_apply_kernel(const double* __restrict__ g, const double* __restrict__ A,
+                                   double* __restrict__ Th, int d, int D) {
+  const int K = 2, DK = D * K;
+  const long long tot = (long long)d * DK * DK * DK * DK;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  long long r = t;
+  const int ue = (int)(r % DK); r /= DK;
+  const int dc = (int)(r % DK); r /= DK;
+  const int rb = (int)(r % DK); r /= DK;
+  const int la = (int)(r % DK); r /= DK;
+  const int s = (int)r;
+  const int l = la / K, a = la % K, rr = rb / K, b = rb % K, dd = dc / K, c = dc % K, u = ue / K,
+            e = ue % K;
+  const long long D4 = (long long)D * D * D * D;
+  const long long off = (((long long)l * D + rr) * D + dd) * D + u;
+  double acc = 0.0;
+  for (int tt = 0; tt < d; ++tt)
+    acc += g[((((a * K + b) * K + c) * K + e) * d + s) * d + tt] * A[tt * D4 + off];
+  Th[t] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// bond environment (Sec. VI B) and ALS (Eqs. (var), (var1))
+// ---------------------------------------------------------------------------
+
+struct Env {
+  int chi, D;
+  const double* C;
+  const double* T;
+  const double* Cp(int p, int k) const { return C + ((long long)p * 4 + (k & 3)) * chi * chi; }
+  const double* Tp(int p, int k) const {
+    return T + ((long long)p * 4 + (k & 3)) * (long long)chi * D * D * chi;
+  }
+};
+
+// Left half of the link network in frame f at position p, with the site
+// tensor A (dims d, D, nr, D, D: its r leg is the open link leg) as ket and
+// bra: L[t, rk, rb, b] (t = T1 boundary leg, b = T3 boundary leg).
+int half_open(tn_ctx* ctx, const Env& env, int f, int p, const double* A, int d, int nr,
+              double* L, double* X1, double* X2, double* X3, double* X4, double* Y) {
+  const long long chi = env.chi, D = env.D, D2 = D * D, dd = d, n = nr;
+  const double* C1 = env.Cp(p, f);
+  const double* T1 = env.Tp(p, f);
+  const double* T4 = env.Tp(p, f + 3);
+  const double* C4 = env.Cp(p, f + 3);
+  const double* T3 = env.Tp(p, f + 2);
+  // site strides (s, l, r, d, u)
+  const long long su = 1, sd = D, sr = D2, sl = n * D2, ss = D * n * D2;
+  // X1[(e,lk,lb), h] = T4 C1;  X2[(e,lk,lb),(uk,ub,t)] = X1 T1
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T4, (int)chi, false, C1, (int)chi, false,
+              X1, (int)chi, 1.0, 0.0));
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
+              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
+  // X3[e][t][rk][dk][s][lb][ub] = sum_{lk,uk} X2[e,lk,lb,uk,ub,t] A[s,lk,rk,dk,uk]
+  const long long x3_ub = 1, x3_lb = D, x3_s = D2, x3_dk = dd * D2, x3_rk = D * dd * D2,
+                  x3_t = n * x3_rk, x3_e = chi * x3_t;
+  Contraction c3;
+  c3.am = grp({{(int)chi, D2 * D2 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
+  c3.ak = grp({{(int)D, D * D2 * chi}, {(int)D, D * chi}});
+  c3.bk = grp({{(int)D, sl}, {(int)D, su}});
+  c3.bn = grp({{(int)d, ss}, {(int)n, sr}, {(int)D, sd}});
+  c3.cm = grp({{(int)chi, x3_e}, {(int)D, x3_lb}, {(int)D, x3_ub}, {(int)chi, x3_t}});
+  c3.cn = grp({{(int)d, x3_s}, {(int)n, x3_rk}, {(int)D, x3_dk}});
+  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
+  // X4[t][rk][rb][e][dk][db] = sum_{s,lb,ub} X3[e,t,rk,dk,s,lb,ub] A[s,lb,rb,db,ub]
+  const long long x4_db = 1, x4_dk = D, x4_e = D2, x4_rb = chi * D2, x4_rk = n * x4_rb,
+                  x4_t = n * x4_rk;
+  Contraction c4;
+  c4.am = grp({{(int)chi, x3_t}, {(int)n, x3_rk}, {(int)chi, x3_e}, {(int)D, x3_dk}});
+  c4.ak = grp({{(int)d, x3_s}, {(int)D, x3_lb}, {(int)D, x3_ub}});
+  c4.bk = grp({{(int)d, ss}, {(int)D, sl}, {(int)D, su}});
+  c4.bn = grp({{(int)n, sr}, {(int)D, sd}});
+  c4.cm = grp({{(int)chi, x4_t}, {(int)n, x4_rk}, {(int)chi, x4_e}, {(int)D, x4_dk}});
+  c4.cn = grp({{(int)n, x4_rb}, {(int)D, x4_db}});
+  TN_TRY(tc_run(ctx, c4, X3, A, X4, 1.0, 0.0));
+  // Y[(b,dk,db), e] = T3 C4
+  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T3, (int)chi, false, C4, (int)chi, false,
+              Y, (int)chi, 1.0, 0.0));
+  // L[(t,rk,rb), b] = sum_{e,dk,db} X4[(t,rk,rb),(e,dk,db)] Y[b,dk,db,e]
+  Contraction c6;
+  c6.am = grp({{(int)(chi * n * n), chi * D2}});
+  c6.ak = grp({{(int)chi, D2}, {(int)D, D}, {(int)D, 1}});
+  c6.bk = grp({{(int)chi, 1}, {(int)D, D * chi}, {(int)D, chi}});
+  c6.bn = grp({{(int)chi, D2 * chi}});
+  c6.cm = grp({{(int)(chi * n * n), chi}});
+  c6.cn = grp({{(int)chi, 1}});
+  TN_TRY(tc_run(ctx, c6, X4, Y, L, 1.0, 0.0));
+  return TN_OK;
+}
+
+// Ns = (N + N^T) / 2 for N an m x m matrix
+__global__ void symmetrize_kernel(const double* __restrict__ N, double* __restrict__ Ns, int m) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m * m) return;
+  const int i = (int)(t / m), j = (int)(t % m);
+  Ns[t] = 0.5 * (N[t] + N[(long long)j * m + i]);
+}
+
+// tb[i][j] = sum_a N[i][j][a][a]; t = <I|N|I> = sum_{i,a} N[i][i][a][a]
+__global__ __launch_bounds__(256) void als_traces_kernel(const double* __restrict__ N, int n,
+                                                         double* __restrict__ tb,
+                                                         double* __restrict__ tconst) {
+  __shared__ double red[4];
+  const long long n2 = (long long)n * n;
+  double t = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    double a = 0.0;
+    for (int q = 0; q < n; ++q) a += N[(long long)e * n2 + q * n + q];
+    tb[e] = a;
+    if (e / n == e % n) t += a;
+  }
+  t = block_sum256(t, red);
+  if (threadIdx.x == 0) *tconst = t;
+}
+
+// Normal equations of one ALS half step (Eq. (var1)), symmetrised:
+// mode 0 (P given Q):  R[(i c),(i' c')] = sum_{j j'} Q[c,j] N[i,j,i',j'] Q[c',j'],
+//                      S[(i c)] = sum_j Q[c,j] tb[i,j]
+// mode 1 (Q given P):  R[(c j),(c' j')] = sum_{i i'} P[i,c] N[i,j,i',j'] P[i',c'],
+//                      S[(c j)] = sum_i P[i,c] tb[i,j]
+// F is Q (D x n) for mode 0 and P (n x D) for mode 1.
+__global__ void als_normal_kernel(int mode, const double* __restrict__ N,
+                                  const double* __restrict__ tb, const double* __restrict__ F,
+                                  int n, int D, double* __restrict__ R, double* __restrict__ S) {
+  const int k = n * D;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)k * k + k) return;
+  const long long n2 = (long long)n * n, n3 = n2 * n;
+  if (t >= (long long)k * k) {
+    const int row = (int)(t - (long long)k * k);
+    double a = 0.0;
+    if (mode == 0) {
+      const int i = row / D, c = row % D;
+      for (int j = 0; j < n; ++j) a += F[c * n + j] * tb[i * n + j];
+    } else {
+      const int c = row / n, j = row % n;
+      for (int i = 0; i < n; ++i) a += F[i * D + c] * tb[i * n + j];
+    }
+    S[row] = a;
+    return;
+  }
+  const int r1 = (int)(t / k), r2 = (int)(t % k);
+  double a = 0.0, b = 0.0;
+  if (mode == 0) {
+    const int i = r1 / D, c = r1 % D, ip = r2 / D, cp = r2 % D;
+    for (int j = 0; j < n; ++j)
+      for (int jp = 0; jp < n; ++jp) {
+        const double q = F[c * n + j] * F[cp * n + jp];
+        a += q * N[i * n3 + j * n2 + ip * n + jp];
+        b += q * N[ip * n3 + jp * n2 + i * n + j];
+      }
+  } else {
+    const int c = r1 / n, j = r1 % n, cp = r2 / n, jp = r2 % n;
+    for (int i = 0; i < n; ++i)
+      for (int ip = 0; ip < n; ++ip) {
+        const double q = F[i * D + c] * F[ip * D + cp];
+        a += q * N[i * n3 + j * n2 + ip * n + jp];
+        b += q * N[ip * n3 + jp * n2 + i * n + j];
+      }
+  }
+  R[t] = 0.5 * (a + b);
+}
+
+// x = Rinv Rinv^T S (the solution of (R + shift) x = S from the Cholesky
+// factor's inverse); one workgroup
+__global__ __launch_bounds__(1024) void chol_solve_kernel(int k, const double* __restrict__ Rinv,
+                                                          const double* __restrict__ S,
+                                                          double* __restrict__ x) {
+  extern __shared__ double y[];
+  for (int i = threadIdx.x; i < k; i += 1024) {
+    double a = 0.0;
+    for (int j = 0; j <= i; ++j) a += Rinv[(long long)j * k + i] * S[j];
+    y[i] = a;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += 1024) {
+    double a = 0.0;
+    for (int j = i; j < k; ++j) a += Rinv[(long long)i * k + j] * y[j];
+    x[i] = a;
+  }
+}
+
+// O = P Q (n x n)
+__global__ void pq_kernel(int n, int D, const double* __restrict__ P, const double* __restrict__ Q,
+                          double* __restrict__ O) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e / n, j = e % n;
+  double a = 0.0;
+  for (int c = 0; c < D; ++c) a += P[i * D + c] * Q[c * n + j];
+  O[e] = a;
+}
+
+// balance: P = u[:, :D] sqrt(s), Q = sqrt(s) V[:, :D]^T
+__global__ void als_balance_kernel(int n, int D, const double* __restrict__ u,
+                                   const double* __restrict__ s, const double* __restrict__ V,
+                                   double* __restrict__ P, double* __restrict__ Q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * D) return;
+  const int i = e / D, c = e % D;
+  const double sq = sqrt(s[c]);
+  P[i * D + c] = u[i * n + c] * sq;
+  Q[c * n + i] = sq * V[i * n + c];
+}
+
+// f = t - 2 <PQ|N|I> + <PQ|N|PQ> (Eq. (var), real case); out[0] = f
+__global__ __launch_bounds__(256) void als_cost_kernel(int n, int D, const double* __restrict__ N,
+                                                       const double* __restrict__ tb,
+                                                       const double* __restrict__ tconst,
+                                                       const double* __restrict__ P,
+                                                       const double* __restrict__ Q,
+                                                       double* __restrict__ out) {
+  __shared__ double O[MAXN * MAXN], red[4];
+  const int n2 = n * n;
+  for (int e = threadIdx.x; e < n2; e += 256) {
+    const int i = e / n, j = e % n;
+    double a = 0.0;
+    for (int c = 0; c < D; ++c) a += P[i * D + c] * Q[c * n + j];
+    O[e] = a;
+  }
+  __syncthreads();
+  double c = 0.0, q = 0.0;
+  for (int e = threadIdx.x; e < n2; e += 256) {
+    c += O[e] * tb[e];
+    double row = 0.0;
+    for (int f = 0; f < n2; ++f) row += N[(long long)e * n2 + f] * O[f];
+    q += O[e] * row;
+  }
+  c = block_sum256(c, red);
+  q = block_sum256(q, red);
+  if (threadIdx.x == 0) out[0] = tconst[0] - 2.0 * c + q;
+}
+
+// Rf = P Pc U (Dk x D), Lf = U^T Qc Q (D x Dk), one link per block row
+__global__ void renorm_gate_kernel(int nl, int Dk, int D, const double* __restrict__ P,
+                                   const double* __restrict__ Q, const double* __restrict__ Pc,
+                                   const double* __restrict__ Qc, const double* __restrict__ U,
+                                   double* __restrict__ Rf, double* __restrict__ Lf) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)Dk * D;
+  if (t >= 2 * nl * per) return;
+  const int which = (int)(t / (nl * per));
+  const long long r = t % (nl * per);
+  const int b = (int)(r / per);
+  const int e = (int)(r % per);
+  const double* Pb = P + b * per;
+  const double* Qb = Q + b * per;
+  const double* Pcb = Pc + (long long)b * D * D;
+  const double* Qcb = Qc + (long long)b * D * D;
+  const double* Ub = U + (long long)b * D * D;
+  if (which == 0) {
+    // Rf[i][j] = sum_{a,c} P[i][a] Pc[a][c] U[c][j]
+    const int i = e / D, j = e % D;
+    double acc = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double pu = 0.0;
+      for (int c = 0; c < D; ++c) pu += Pcb[a * D + c] * Ub[c * D + j];
+      acc += Pb[i * D + a] * pu;
+    }
+    Rf[b * per + e] = acc;
+  } else {
+    // Lf[j][i] = sum_{a,c} U[a][j] Qc[a][c] Q[c][i]
+    const int j = e / Dk, i = e % Dk;
+    double acc = 0.0;
+    for (int c = 0; c < D; ++c) {
+      double uq = 0.0;
+      for (int a = 0; a < D; ++a) uq += Ub[a * D + j] * Qcb[a * D + c];
+      acc += uq * Qb[c * Dk + i];
+    }
+    Lf[b * per + e] = acc;
+  }
+}
+
+// E = mean over positions of -J <zz>_h - J <zz>_v - h <x> (Sec. VI A)
+__global__ void tfim2d_energy_kernel(int npos, const double* __restrict__ rho1,
+                                     const double* __restrict__ rhoh,
+                                     const double* __restrict__ rhov, double J, double h,
+                                     double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double zz[4] = {1.0, -1.0, -1.0, 1.0};
+  double e = 0.0;
+  for (int p = 0; p < npos; ++p) {
+    double ch = 0.0, cv = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      ch += zz[k] * rhoh[p * 16 + k * 4 + k];
+      cv += zz[k] * rhov[p * 16 + k * 4 + k];
+    }
+    const double x = rho1[p * 4 + 1] + rho1[p * 4 + 2];
+    e += -J * ch - J * cv - h * x;
+  }
+  *out = e / npos;
+}
+
+inline unsigned nblk(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// canonicalisation driver
+// ---------------------------------------------------------------------------
+
+struct CanonOut {
+  double* lam;  // [nl][n]
+  double* TR;   // [nl][n][n]
+  double* TL;
+  int iters;
+};
+
+size_t canon_bytes(int nsite, int nl, int d, int n) {
+  const size_t tsz = (size_t)d * n * n * n * n;
+  size_t b = 0;
+  auto add = [&](size_t c) { b += ((c * 8 + 255) / 256) * 256; };
+  add(nsite * tsz);      // gammas
+  add(2 * tsz);          // ping-pong
+  add(3 * tsz);          // apply scratch
+  add(nl * n);           // lam
+  for (int k = 0; k < 4; ++k) add((size_t)nl * n * n);      // TR TL R L
+  add(2 * (size_t)nl * n * n);                            // grams
+  add(2 * (size_t)nl * n * n + 2 * (size_t)nl * n);       // W S
+  add(3 * (size_t)nl * n * n + (size_t)nl * n);           // M, Um, Vm, Sm
+  add(nl + 1);
+  add(4 * (size_t)nl * n * n);  // jacobi work
+  return b + (1 << 20);
+}
+
+// Iterates the canonical-form update on the gammas (initialised to `A`) until
+// the spectra move by less than tol (max norm), as in steps (i)-(iii) of
+// Sec. IV A applied to every link at once.
+int canonicalize_run(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n, const double* A,
+                     double tol, int max_iter, CanonOut& out) {
+  const int nl = L.nl;
+  const long long tsz = (long long)d * n * n * n * n;
+  const long long nn = (long long)n * n;
+  double* gam = ws_alloc<double>(ctx, nsite * tsz);
+  double* pp = ws_alloc<double>(ctx, 2 * tsz);
+  double* sc = ws_alloc<double>(ctx, 3 * tsz);
+  out.lam = ws_alloc<double>(ctx, nl * n);
+  out.TR = ws_alloc<double>(ctx, nl * nn);
+  out.TL = ws_alloc<double>(ctx, nl * nn);
+  double* Rm = ws_alloc<double>(ctx, nl * nn);
+  double* Lm = ws_alloc<double>(ctx, nl * nn);
+  double* G = ws_alloc<double>(ctx, 2 * nl * nn);
+  double* W = ws_alloc<double>(ctx, 2 * nl * nn);
+  double* S = ws_alloc<double>(ctx, 2 * nl * n);
+  double* M = ws_alloc<double>(ctx, nl * nn);
+  double* Um = ws_alloc<double>(ctx, nl * nn);
+  double* Vm = ws_alloc<double>(ctx, nl * nn);
+  double* Sm = ws_alloc<double>(ctx, nl * n);
+  double* dl = ws_alloc<double>(ctx, nl + 1);
+  if (!dl) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (canonical form)");
+  TN_HIP(ctx, hipMemcpyAsync(gam, A, nsite * tsz * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(nl * n)), dim3(256), 0, ctx->stream, out.lam,
+                     (long long)nl * n, 1.0 / sqrt((double)n));
+  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, out.TR, nl, n);
+  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, out.TL, nl, n);
+  TN_HIP(ctx, hipGetLastError());
+  const TDims dm = dims5(d, n, n, n, n);
+  int it = 0;
+  double delta = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    // Gram matrices of the weighted gammas on each end of each link
+    std::vector<GramJob> jobs;
+    for (int side = 0; side < 2; ++side)
+      for (int b = 0; b < nl; ++b) {
+        const int s = side ? L.s2[b] : L.s1[b];
+        const int ax = side ? L.l2[b] : L.l1[b];
+        GramJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.A[0] = j.B[0] = gam + s * tsz;
+        j.nterm = 1;
+        j.dims = dm;
+        j.ax[0] = ax;
+        for (int k = 1; k <= 4; ++k)
+          j.lam[k] = (k == ax) ? nullptr : out.lam + (long long)L.leg_link[s][k] * n;
+        j.out = G + (side * nl + b) * nn;
+        jobs.push_back(j);
+      }
+    TN_TRY(run_grams(ctx, jobs));
+    TN_TRY(jacobi_svd(ctx, 2 * nl, n, n, G, n, nn, W, n, nn, S, n, nullptr, 0, 0));
+    hipLaunchKernelGGL(canon_m_kernel, dim3(nl), dim3(256), 0, ctx->stream, nl, n, W, S, out.lam,
+                       M);
+    TN_TRY(jacobi_svd(ctx, nl, n, n, M, n, nn, Um, n, nn, Sm, n, Vm, n, nn));
+    hipLaunchKernelGGL(canon_update_kernel, dim3(nl), dim3(256), 0, ctx->stream, nl, n, W, S, Um,
+                       Sm, Vm, out.lam, out.TR, out.TL, Rm, Lm, dl);
+    TN_HIP(ctx, hipGetLastError());
+    // gammas: first end new = r^T old, second end new = l old
+    for (int s = 0; s < nsite; ++s) {
+      LegMats lm;
+      for (int ax = 1; ax <= 4; ++ax) {
+        const int b = L.leg_link[s][ax];
+        const bool first = (L.s1[b] == s && L.l1[b] == ax);
+        lm.m[ax] = (first ? Rm : Lm) + b * nn;
+        lm.trans[ax] = first ? 1 : 0;
+        lm.nnew[ax] = n;
+      }
+      TN_TRY(apply_legs(ctx, gam + s * tsz, pp, dm, lm, sc, sc + tsz, nullptr));
+      TN_HIP(ctx, hipMemcpyAsync(gam + s * tsz, pp, tsz * sizeof(double),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+      TN_TRY(frob_normalize(ctx, gam + s * tsz, tsz, nullptr));
+    }
+    hipLaunchKernelGGL(max_of_kernel, dim3(1), dim3(1), 0, ctx->stream, dl, nl, dl + nl);
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dl + nl, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    delta = ctx->host_scratch[0];
+    if (!std::isfinite(delta)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite canonical-form spectra");
+    if (delta < tol) break;
+  }
+  out.iters = std::min(it, max_iter);
+  return delta < tol ? TN_OK : TN_NOT_CONVERGED;
+}
+
+int check_bond(tn_ctx* ctx, int n, const char* what) {
+  if (n < 1 || n > MAXN) TN_FAIL(ctx, TN_EINVAL, "%s = %d outside [1, %d]", what, n, MAXN);
+  return TN_OK;
+}
+
+// A~ = legs of `in` (bond n_in) times P (first ends) and Q (second ends), then
+// unit Frobenius norm per site
+int truncate_sites(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n_in, int n_out,
+                   const double* in, const double* P, const double* Q, double* out, double* sc) {
+  const long long tin = (long long)d * n_in * n_in * n_in * n_in;
+  const long long tout = (long long)d * n_out * n_out * n_out * n_out;
+  const long long per = (long long)n_in * n_out;
+  for (int s = 0; s < nsite; ++s) {
+    LegMats lm;
+    for (int ax = 1; ax <= 4; ++ax) {
+      const int b = L.leg_link[s][ax];
+      const bool first = (L.s1[b] == s && L.l1[b] == ax);
+      lm.m[ax] = (first ? P : Q) + b * per;
+      lm.trans[ax] = first ? 1 : 0;
+      lm.nnew[ax] = n_out;
+    }
+    TN_TRY(apply_legs(ctx, in + s * tin, out + s * tout, dims5(d, n_in, n_in, n_in, n_in), lm, sc,
+                      sc + tin, nullptr));
+    TN_TRY(frob_normalize(ctx, out + s * tout, tout, nullptr));
+  }
+  return TN_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public entry points (C ABI wrappers live in abi.hip)
+// ---------------------------------------------------------------------------
+
+int cell_links_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
+                    int* links) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  if (nlink) *nlink = L.nl;
+  if (links)
+    for (int b = 0; b < L.nl; ++b) {
+      links[4 * b + 0] = L.s1[b];
+      links[4 * b + 1] = L.l1[b];
+      links[4 * b + 2] = L.s2[b];
+      links[4 * b + 3] = L.l2[b];
+    }
+  return TN_OK;
+}
+
+int ipeps_gate_impl(tn_ctx* ctx, int nsite, int D, int d, double J, double h, double dt,
+                    const double* A, double* Theta) {
+  if (nsite < 1 || D < 1 || d != 2 || !A || !Theta)
+    TN_FAIL(ctx, TN_EINVAL, "ipeps_gate needs nsite >= 1, D >= 1, d = 2 and device tensors");
+  TN_TRY(check_bond(ctx, 2 * D, "kappa*D"));
+  double hg[64];
+  tfim_ipepo(J, h, dt, hg);
+  TN_TRY(ws_reserve(ctx, 1 << 16));
+  ws_reset(ctx);
+  double* g = ws_alloc<double>(ctx, 64);
+  if (!g) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  TN_HIP(ctx, hipMemcpyAsync(g, hg, sizeof(hg), hipMemcpyHostToDevice, ctx->stream));
+  const long long ain = (long long)d * D * D * D * D;
+  const long long aout = ain * 16;
+  for (int s = 0; s < nsite; ++s)
+    hipLaunchKernelGGL(ipepo_apply_kernel, dim3(nblk(aout)), dim3(256), 0, ctx->stream, g,
+                       A + s * ain, Theta + s * aout, d, D);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int ipeps_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int Din,
+                        int Dout, const double* Theta, const double* P, const double* Q,
+                        double* Aout) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  TN_TRY(check_bond(ctx, Din, "input bond"));
+  TN_TRY(check_bond(ctx, Dout, "output bond"));
+  if (d < 1 || !Theta || !P || !Q || !Aout) TN_FAIL(ctx, TN_EINVAL, "null tensor argument");
+  const long long tin = (long long)d * Din * Din * Din * Din;
+  TN_TRY(ws_reserve(ctx, 2 * tin * sizeof(double) + (1 << 20)));
+  ws_reset(ctx);
+  double* sc = ws_alloc<double>(ctx, 2 * tin);
+  if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  TN_TRY(truncate_sites(ctx, L, nsite, d, Din, Dout, Theta, P, Q, Aout, sc));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int ipeps_canonicalize_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                            int Dkeep, const double* A, double* Aout, double* lams, double* P,
+                            double* Q, double tol, int max_iter, int* iters) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  TN_TRY(check_bond(ctx, D, "bond"));
+  if (Dkeep < 1 || Dkeep > D) TN_FAIL(ctx, TN_EINVAL, "kept bond %d outside [1, %d]", Dkeep, D);
+  if (d < 1 || !A || !P || !Q) TN_FAIL(ctx, TN_EINVAL, "null tensor argument");
+  if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
+  if (Aout && Dkeep != D) TN_FAIL(ctx, TN_EINVAL, "A_out needs the full bond (Dkeep = D)");
+  const int nl = L.nl;
+  const long long nn = (long long)D * D;
+  TN_TRY(ws_reserve(ctx, canon_bytes(nsite, nl, d, D) +
+                             (2 * nl * nn + 2LL * d * D * D * D * D) * sizeof(double)));
+  ws_reset(ctx);
+  CanonOut co;
+  const int rc = canonicalize_run(ctx, L, nsite, d, D, A, tol, max_iter, co);
+  if (rc < 0) return rc;
+  double* Pc = ws_alloc<double>(ctx, nl * nn);
+  double* Qc = ws_alloc<double>(ctx, nl * nn);
+  if (!Qc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  hipLaunchKernelGGL(canon_pq_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, nl, D,
+                     co.TR, co.TL, co.lam, Pc, Qc);
+  TN_HIP(ctx, hipGetLastError());
+  if (lams)
+    TN_HIP(ctx, hipMemcpyAsync(lams, co.lam, (size_t)nl * D * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  // kept columns of Pc and rows of Qc
+  TN_HIP(ctx, hipMemcpy2DAsync(P, Dkeep * sizeof(double), Pc, D * sizeof(double),
+                               Dkeep * sizeof(double), (size_t)nl * D, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  for (int b = 0; b < nl; ++b)
+    TN_HIP(ctx, hipMemcpyAsync(Q + (long long)b * Dkeep * D, Qc + b * nn,
+                               (size_t)Dkeep * D * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  if (Aout) {
+    const long long tsz = (long long)d * D * D * D * D;
+    double* sc = ws_alloc<double>(ctx, 2 * tsz);
+    if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+    TN_TRY(truncate_sites(ctx, L, nsite, d, D, D, A, Pc, Qc, Aout, sc));
+  }
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (iters) *iters = co.iters;
+  return rc;
+}
+
+int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                   const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
+                   double* fidelity, int* iters) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  TN_TRY(check_bond(ctx, D, "bond"));
+  if (d < 1 || !a_ref || !a_new || !U) TN_FAIL(ctx, TN_EINVAL, "null tensor argument");
+  if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
+  if (nsite > 30) TN_FAIL(ctx, TN_EINVAL, "gauge_fix handles at most 30 site tensors");
+  const int nl = L.nl;
+  const long long tsz = (long long)d * D * D * D * D, nn = (long long)D * D;
+  TN_TRY(ws_reserve(ctx, (6 * tsz + 4 * nn + 2 * nsite + 64 + 4 * nn) * sizeof(double) +
+                             (1 << 20)));
+  ws_reset(ctx);
+  double* rest = ws_alloc<double>(ctx, 2 * tsz);
+  double* sc = ws_alloc<double>(ctx, 2 * tsz);
+  double* full = ws_alloc<double>(ctx, 2 * tsz);
+  double* K = ws_alloc<double>(ctx, nn);
+  double* Wk = ws_alloc<double>(ctx, nn);
+  double* Vk = ws_alloc<double>(ctx, nn);
+  double* Sk = ws_alloc<double>(ctx, D);
+  double* dots = ws_alloc<double>(ctx, 2 * nsite + 2);
+  if (!dots) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (gauge fix)");
+  const TDims dm = dims5(d, D, D, D, D);
+  // norms of the references (fixed)
+  for (int s = 0; s < nsite; ++s) {
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_ref + s * tsz,
+                       a_ref + s * tsz, tsz, dots + nsite + s);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + s * tsz,
+                       a_new + s * tsz, tsz, dots + s);
+  }
+  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, 2 * nsite * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double den = 0.0;
+  for (int s = 0; s < nsite; ++s)
+    den += sqrt(ctx->host_scratch[s]) * sqrt(ctx->host_scratch[nsite + s]);
+  if (!(den > 0.0)) TN_FAIL(ctx, TN_EINVAL, "zero site tensor");
+  auto fid = [&](double* F) -> int {
+    for (int s = 0; s < nsite; ++s) {
+      LegMats lm;
+      for (int ax = 1; ax <= 4; ++ax) {
+        lm.m[ax] = U + L.leg_link[s][ax] * nn;
+        lm.nnew[ax] = D;
+      }
+      TN_TRY(apply_legs(ctx, a_ref + s * tsz, full, dm, lm, sc, sc + tsz, nullptr));
+      hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + s * tsz, full,
+                         tsz, dots + s);
+    }
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, nsite * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double num = 0.0;
+    for (int s = 0; s < nsite; ++s) num += ctx->host_scratch[s];
+    *F = num / den;
+    return TN_OK;
+  };
+  double F = 0.0;
+  TN_TRY(fid(&F));
+  int it = 0;
+  double dF = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    // one Procrustes step per link, the other links' factors held fixed
+    for (int b = 0; b < nl; ++b) {
+      GramJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.nterm = 2;
+      j.dims = dm;
+      j.out = K;
+      for (int side = 0; side < 2; ++side) {
+        const int s = side ? L.s2[b] : L.s1[b];
+        const int leg = side ? L.l2[b] : L.l1[b];
+        LegMats lm;
+        for (int ax = 1; ax <= 4; ++ax) {
+          if (ax == leg) continue;
+          lm.m[ax] = U + L.leg_link[s][ax] * nn;
+          lm.nnew[ax] = D;
+        }
+        TN_TRY(apply_legs(ctx, a_ref + s * tsz, rest + side * tsz, dm, lm, sc, sc + tsz,
+                          nullptr));
+        j.A[side] = a_new + s * tsz;
+        j.B[side] = rest + side * tsz;
+        j.ax[side] = leg;
+      }
+      TN_TRY(run_grams(ctx, {j}));
+      TN_TRY(jacobi_svd(ctx, 1, D, D, K, D, nn, Wk, D, nn, Sk, D, Vk, D, nn));
+      hipLaunchKernelGGL(polar_kernel, dim3(nblk(nn)), dim3(256), 0, ctx->stream, D, Wk, Vk,
+                         U + b * nn);
+      TN_HIP(ctx, hipGetLastError());
+    }
+    double Fn = 0.0;
+    TN_TRY(fid(&Fn));
+    if (!std::isfinite(Fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite fidelity");
+    dF = fabs(Fn - F);
+    F = Fn;
+    if (dF < tol) break;
+  }
+  if (fidelity) *fidelity = F;
+  if (iters) *iters = std::min(it, max_iter);
+  return dF < tol ? TN_OK : TN_NOT_CONVERGED;
+}
+
+namespace {
+
+// Buffers and steps of the bond environment of one link.
+struct BondEnv {
+  const CellLinks* L;
+  int Lx, Ly, d, D, n, chi;
+  size_t tsz;
+  const double* Theta;
+  Env env;
+  double *sc, *th, *thr, *rtmp, *X1, *X2, *X3, *X4, *Y, *L1, *L2, *N, *Ns;
+
+  static size_t bytes(int d, int D, int n, int chi) {
+    const size_t chi_ = chi, D_ = D, D2 = D_ * D_, n_ = n, d_ = d;
+    const size_t tsz = d_ * n_ * n_ * n_ * n_;
+    size_t need = 0;
+    auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
+    add(2 * tsz);
+    add(2 * tsz);
+    add(2 * tsz);
+    add(tsz);
+    add(chi_ * D2 * chi_);
+    add(chi_ * D2 * D2 * chi_);
+    add(chi_ * chi_ * n_ * D_ * d_ * D2);
+    add(chi_ * chi_ * n_ * n_ * D2);
+    add(chi_ * D2 * chi_);
+    add(2 * chi_ * n_ * n_ * chi_);
+    add(2 * n_ * n_ * n_ * n_);
+    return need;
+  }
+
+  int alloc(tn_ctx* ctx) {
+    const size_t chi_ = chi, D_ = D, D2 = D_ * D_, n_ = n, d_ = d;
+    tsz = d_ * n_ * n_ * n_ * n_;
+    sc = ws_alloc<double>(ctx, 2 * tsz);
+    th = ws_alloc<double>(ctx, 2 * tsz);
+    thr = ws_alloc<double>(ctx, 2 * tsz);
+    rtmp = ws_alloc<double>(ctx, tsz);
+    X1 = ws_alloc<double>(ctx, chi_ * D2 * chi_);
+    X2 = ws_alloc<double>(ctx, chi_ * D2 * D2 * chi_);
+    X3 = ws_alloc<double>(ctx, chi_ * chi_ * n_ * D_ * d_ * D2);
+    X4 = ws_alloc<double>(ctx, chi_ * chi_ * n_ * n_ * D2);
+    Y = ws_alloc<double>(ctx, chi_ * D2 * chi_);
+    L1 = ws_alloc<double>(ctx, 2 * chi_ * n_ * n_ * chi_);
+    L2 = L1 ? L1 + chi_ * n_ * n_ * chi_ : nullptr;
+    N = ws_alloc<double>(ctx, 2 * n_ * n_ * n_ * n_);
+    Ns = N ? N + n_ * n_ * n_ * n_ : nullptr;
+    if (!Ns) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (bond environment)");
+    return TN_OK;
+  }
+
+  // Ns of link b with the current P, Q
+  int compute(tn_ctx* ctx, int b, const double* P, const double* Q) {
+    const CellLinks& Lk = *L;
+    auto pos = [&](int x, int y) { return (((y % Ly) + Ly) % Ly) * Lx + (((x % Lx) + Lx) % Lx); };
+    const long long per = (long long)n * D;
+    const bool horiz = Lk.l1[b] == AX_R;
+    const int frames[2] = {horiz ? 0 : 1, horiz ? 2 : 3};
+    // Theta-hat of both ends (every leg but the link's truncated with the
+    // current P, Q), rotated so that the open leg is the r leg of its frame
+    for (int side = 0; side < 2; ++side) {
+      const int s = side ? Lk.s2[b] : Lk.s1[b];
+      const int open = side ? Lk.l2[b] : Lk.l1[b];
+      LegMats lm;
+      for (int ax = 1; ax <= 4; ++ax) {
+        if (ax == open) continue;
+        const int bb = Lk.leg_link[s][ax];
+        const bool first = (Lk.s1[bb] == s && Lk.l1[bb] == ax);
+        lm.m[ax] = (first ? P : Q) + bb * per;
+        lm.trans[ax] = first ? 1 : 0;
+        lm.nnew[ax] = D;
+      }
+      TDims dh;
+      TN_TRY(apply_legs(ctx, Theta + s * tsz, th + side * tsz, dims5(d, n, n, n, n), lm, sc,
+                        sc + tsz, &dh));
+      TDims dr;
+      TN_TRY(rotate_times(ctx, th + side * tsz, thr + side * tsz, rtmp, dh, frames[side], &dr));
+      if (dr.n[AX_R] != n || dr.n[AX_L] != D)
+        TN_FAIL(ctx, TN_EINVAL, "internal: open leg not on the r axis after rotation");
+    }
+    const int p = pos(Lk.x[b], Lk.y[b]);
+    const int q = horiz ? pos(Lk.x[b] + 1, Lk.y[b]) : pos(Lk.x[b], Lk.y[b] + 1);
+    TN_TRY(half_open(ctx, env, frames[0], p, thr, d, n, L1, X1, X2, X3, X4, Y));
+    TN_TRY(half_open(ctx, env, frames[1], q, thr + tsz, d, n, L2, X1, X2, X3, X4, Y));
+    // N[k][i][K][I] = sum_{t,b} L1[t,k,K,b] L2[b,i,I,t]
+    const long long cn = chi, nn_ = n;
+    Contraction cN;
+    cN.am = grp({{n, nn_ * cn}, {n, cn}});
+    cN.ak = grp({{chi, nn_ * nn_ * cn}, {chi, 1}});
+    cN.bk = grp({{chi, 1}, {chi, nn_ * nn_ * cn}});
+    cN.bn = grp({{n, nn_ * cn}, {n, cn}});
+    cN.cm = grp({{n, nn_ * nn_ * nn_}, {n, nn_}});
+    cN.cn = grp({{n, nn_ * nn_}, {n, 1}});
+    TN_TRY(tc_run(ctx, cN, L1, L2, N, 1.0, 0.0));
+    const long long n4 = nn_ * nn_ * nn_ * nn_;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(n4)), dim3(256), 0, ctx->stream, N, Ns, n * n);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+  }
+};
+
+int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int chi, const void* Theta, const void* C,
+                   const void* T, const void* P, const void* Q) {
+  TN_TRY(check_bond(ctx, Dk, "theta bond"));
+  if (D < 1 || D > Dk) TN_FAIL(ctx, TN_EINVAL, "truncated bond %d outside [1, %d]", D, Dk);
+  if (d < 1 || chi < 1 || !Theta || !C || !T || !P || !Q)
+    TN_FAIL(ctx, TN_EINVAL, "bad bond environment arguments");
+  const long long n = (long long)chi * D * D;
+  if (n > 32768) TN_FAIL(ctx, TN_EINVAL, "chi*D*D = %lld too large", n);
+  return TN_OK;
+}
+
+}  // namespace
+
+int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                          int Dk, const double* Theta, int chi, const double* C, const double* T,
+                          const double* P, const double* Q, int link, double* N_out) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, P, Q));
+  if (link < 0 || link >= L.nl) TN_FAIL(ctx, TN_EINVAL, "link %d outside [0, %d)", link, L.nl);
+  if (!N_out) TN_FAIL(ctx, TN_EINVAL, "null output");
+  TN_TRY(ws_reserve(ctx, BondEnv::bytes(d, D, Dk, chi) + (1 << 20)));
+  ws_reset(ctx);
+  BondEnv be{&L, Lx, Ly, d, D, Dk, chi, 0, Theta, Env{chi, D, C, T}};
+  TN_TRY(be.alloc(ctx));
+  TN_TRY(be.compute(ctx, link, P, Q));
+  const size_t n4 = (size_t)Dk * Dk * Dk * Dk;
+  TN_HIP(ctx, hipMemcpyAsync(N_out, be.Ns, n4 * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+                           int Dk, const double* Theta, int chi, const double* C, const double* T,
+                           double* P, double* Q, int max_sweeps, double tol, double* cost,
+                           int* sweeps) {
+  CellLinks L;
+  TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
+  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, P, Q));
+  if (max_sweeps < 1) TN_FAIL(ctx, TN_EINVAL, "max_sweeps must be >= 1");
+  const int nl = L.nl, n = Dk, k = Dk * D;
+  if (k > 512) TN_FAIL(ctx, TN_EINVAL, "kappa*D*D = %d too large for the ALS solve", k);
+  const size_t n_ = n;
+  size_t need = BondEnv::bytes(d, D, Dk, chi);
+  auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
+  add(n_ * n_ + 2);                     // tb, t
+  add(4 * (size_t)k * k + 2 * k);       // R, Rc, Rinv, S, x
+  add(4 * n_ * n_ + n_ + 8);            // O, u, V, s, f
+  TN_TRY(ws_reserve(ctx, need + (1 << 20)));
+  ws_reset(ctx);
+  BondEnv be{&L, Lx, Ly, d, D, Dk, chi, 0, Theta, Env{chi, D, C, T}};
+  TN_TRY(be.alloc(ctx));
+  double* tb = ws_alloc<double>(ctx, n_ * n_ + 2);
+  double* tconst = tb + n_ * n_;
+  double* R = ws_alloc<double>(ctx, 4 * (size_t)k * k + 2 * k);
+  double* Rc = R + (size_t)k * k;
+  double* Rinv = Rc + (size_t)k * k;
+  double* S = Rinv + 2 * (size_t)k * k;
+  double* O = ws_alloc<double>(ctx, 4 * n_ * n_ + n_ + 8);
+  double* uo = O + n_ * n_;
+  double* Vo = uo + n_ * n_;
+  double* so = Vo + n_ * n_;
+  double* fdev = so + n_;
+  int* info = ws_alloc<int>(ctx, 4);
+  if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (ALS)");
+  double* Ns = be.Ns;
+  const long long per = (long long)Dk * D;
+  int total_sweeps = 0;
+  for (int b = 0; b < nl; ++b) {
+    TN_TRY(be.compute(ctx, b, P, Q));
+    hipLaunchKernelGGL(als_traces_kernel, dim3(1), dim3(256), 0, ctx->stream, Ns, n, tb, tconst);
+    double* Pb = P + b * per;
+    double* Qb = Q + b * per;
+    hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb, tconst,
+                       Pb, Qb, fdev);
+    TN_HIP(ctx, hipGetLastError());
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 1, tconst, sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double f = ctx->host_scratch[0];
+    const double f0 = ctx->host_scratch[1];
+    if (!std::isfinite(f) || !std::isfinite(f0)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite bond environment");
+    for (int sw = 1; sw <= max_sweeps; ++sw) {
+      ++total_sweeps;
+      for (int mode = 0; mode < 2; ++mode) {
+        hipLaunchKernelGGL(als_normal_kernel, dim3(nblk((long long)k * k + k)), dim3(256), 0,
+                           ctx->stream, mode, Ns, tb, mode == 0 ? Qb : Pb, n, D, R, S);
+        TN_HIP(ctx, hipGetLastError());
+        TN_TRY(cholesky_inv(ctx, k, R, 1e-14, Rc, Rinv, info + mode));
+        hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), k * sizeof(double), ctx->stream,
+                           k, Rinv, S, mode == 0 ? Pb : Qb);
+        TN_HIP(ctx, hipGetLastError());
+      }
+      // balance the pair through the SVD of P Q
+      hipLaunchKernelGGL(pq_kernel, dim3(nblk((long long)n * n)), dim3(256), 0, ctx->stream, n, D,
+                         Pb, Qb, O);
+      TN_TRY(jacobi_svd(ctx, 1, n, n, O, n, (long long)n * n, uo, n, (long long)n * n, so, n, Vo,
+                        n, (long long)n * n));
+      hipLaunchKernelGGL(als_balance_kernel, dim3(nblk(per)), dim3(256), 0, ctx->stream, n, D, uo,
+                         so, Vo, Pb, Qb);
+      hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb,
+                         tconst, Pb, Qb, fdev);
+      TN_HIP(ctx, hipGetLastError());
+      TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+      TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 2, info, 2 * sizeof(int),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+      TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      const int* hinfo = reinterpret_cast<const int*>(ctx->host_scratch + 2);
+      if (hinfo[0] || hinfo[1])
+        TN_FAIL(ctx, TN_ENUMERIC,
+                "ALS normal matrix of link %d not positive definite (pivot %d/%d)", b,
+                hinfo[0], hinfo[1]);
+      const double fn = ctx->host_scratch[0];
+      if (!std::isfinite(fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite ALS cost");
+      const bool done = fabs(fn - f) < tol * fabs(f0);
+      f = fn;
+      if (done) break;
+    }
+    if (cost) cost[b] = f;
+  }
+  if (sweeps) *sweeps = total_sweeps;
+  return TN_OK;
+}
+
+int fu_renormalized_gate_impl(tn_ctx* ctx, int nlink, int Dk, int D, const double* P,
+                              const double* Q, const double* Pc, const double* Qc, const double* U,
+                              double* Rf, double* Lf) {
+  if (nlink < 1 || Dk < 1 || D < 1 || D > Dk || !P || !Q || !Pc || !Qc || !U || !Rf || !Lf)
+    TN_FAIL(ctx, TN_EINVAL, "bad fu_renormalized_gate arguments");
+  const long long tot = 2LL * nlink * Dk * D;
+  hipLaunchKernelGGL(renorm_gate_kernel, dim3(nblk(tot)), dim3(256), 0, ctx->stream, nlink, Dk, D,
+                     P, Q, Pc, Qc, U, Rf, Lf);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
+int ipeps_energy_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
+                      const int* cell, int chi, const double* C, const double* T, double J,
+                      double h, double* energy) {
+  if (d != 2) TN_FAIL(ctx, TN_EINVAL, "ipeps_energy is the TFIM energy: d must be 2");
+  if (!energy) TN_FAIL(ctx, TN_EINVAL, "null energy pointer");
+  if (Lx < 1 || Ly < 1 || Lx * Ly > 64) TN_FAIL(ctx, TN_EINVAL, "bad cell size");
+  const int npos = Lx * Ly;
+  void* buf = nullptr;
+  TN_TRY(keep_buffer(ctx, "energy-rdms", (size_t)(npos * (4 + 16 + 16) + 1) * sizeof(double), &buf,
+                     nullptr));
+  double* rho1 = static_cast<double*>(buf);
+  double* rhoh = rho1 + npos * 4;
+  double* rhov = rhoh + npos * 16;
+  double* e = rhov + npos * 16;
+  TN_TRY(ipeps_rdms_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, rho1, rhoh, rhov));
+  hipLaunchKernelGGL(tfim2d_energy_kernel, dim3(1), dim3(1), 0, ctx->stream, npos, rho1, rhoh,
+                     rhov, J, h, e);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, e, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *energy = ctx->host_scratch[0];
+  if (!std::isfinite(*energy)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite energy");
+  return TN_OK;
+}
+
+namespace {
+
+// Start of the gauge fix inside the recycling step: for a small time step
+// the renormalized gate is close to the identity, so the kappa = 0 block of
+// the composite truncation maps the old bond basis onto the new one;
+// K = (P Pc)[(i,0), :]^T / |.| + (Qc Q)[:, (i,0)] / |.|, U0 = polar(K).
+__global__ __launch_bounds__(256) void gauge_start_kernel(int Dk, int D, int kappa,
+                                                          const double* __restrict__ P,
+                                                          const double* __restrict__ Q,
+                                                          const double* __restrict__ Pc,
+                                                          const double* __restrict__ Qc,
+                                                          double* __restrict__ K) {
+  const int b = blockIdx.x;
+  __shared__ double red[4];
+  const long long per = (long long)Dk * D, dd = (long long)D * D;
+  const double* Pb = P + b * per;
+  const double* Qb = Q + b * per;
+  const double* Pcb = Pc + b * dd;
+  const double* Qcb = Qc + b * dd;
+  double a[4], c[4];
+  double na = 0.0, nc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
+    a[q] = c[q] = 0.0;
+    if (e < D * D) {
+      const int i = e / D, j = e % D;
+      // a = (P Pc)[(j, 0), i]  (transposed block), c = (Qc Q)[i, (j, 0)]
+      double x = 0.0, y = 0.0;
+      for (int m = 0; m < D; ++m) {
+        x += Pb[(long long)(j * kappa) * D + m] * Pcb[m * D + i];
+        y += Qcb[i * D + m] * Qb[(long long)m * Dk + j * kappa];
+      }
+      a[q] = x;
+      c[q] = y;
+      na += x * x;
+      nc += y * y;
+    }
+  }
+  na = sqrt(block_sum256(na, red));
+  nc = sqrt(block_sum256(nc, red));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < D * D) K[b * dd + e] = a[q] / na + c[q] / nc;
+  }
+}
+
+}  // namespace
+
+int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
+                        const double* Q, const double* Pc, const double* Qc, double* U0) {
+  if (nlink < 1 || D < 1 || kappa < 1 || Dk != kappa * D || !P || !Q || !Pc || !Qc || !U0)
+    TN_FAIL(ctx, TN_EINVAL, "bad fu_gauge_start arguments");
+  TN_TRY(check_bond(ctx, D, "bond"));
+  const long long dd = (long long)D * D;
+  TN_TRY(ws_reserve(ctx, (size_t)(4 * nlink * dd + nlink * D) * sizeof(double) + (1 << 20)));
+  ws_reset(ctx);
+  double* K = ws_alloc<double>(ctx, nlink * dd);
+  double* W = ws_alloc<double>(ctx, nlink * dd);
+  double* V = ws_alloc<double>(ctx, nlink * dd);
+  double* S = ws_alloc<double>(ctx, nlink * D);
+  if (!S) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  hipLaunchKernelGGL(gauge_start_kernel, dim3(nlink), dim3(256), 0, ctx->stream, Dk, D, kappa, P,
+                     Q, Pc, Qc, K);
+  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(jacobi_svd(ctx, nlink, D, D, K, D, dd, W, D, dd, S, D, V, D, dd));
+  for (int b = 0; b < nlink; ++b)
+    hipLaunchKernelGGL(polar_kernel, dim3(nblk(dd)), dim3(256), 0, ctx->stream, D, W + b * dd,
+                       V + b * dd, U0 + b * dd);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}

@@ -46,3 +46,26 @@ def test_version_string(lib):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(tn.LibraryMissing):
         tn.load_library(str(tmp_path / "nope.so"))
+
+
+@pytest.mark.parametrize("spec", [(2, 2, (0, 1, 1, 0)), (1, 1, (0,)), (3, 2, (0, 1, 2, 3, 4, 5))])
+def test_cell_links_match_oracle(spec):
+    """The library's link enumeration (host-only call) is the oracle's."""
+    import paper_1411_0391_amd as tn
+    from oracle import ctmrg as octm
+    from oracle import peps as opeps
+    Lx, Ly, cell = spec
+    legnum = {"l": 1, "r": 2, "d": 3, "u": 4}
+    ref = [(s1, legnum[l1], s2, legnum[l2])
+           for (s1, l1, s2, l2) in opeps.cell_links(octm.Cell(Lx, Ly, list(cell)))[0]]
+    assert tn.cell_links(Lx, Ly, max(cell) + 1, list(cell)) == ref
+
+
+def test_cell_links_rejects_bad_cells():
+    import paper_1411_0391_amd as tn
+    with pytest.raises(tn.TNError):
+        tn.cell_links(2, 2, 2, [0, 1, 2, 0])      # site index out of range
+    with pytest.raises(tn.TNError):
+        tn.cell_links(2, 1, 3, [0, 1])            # site 2 never occurs
+    with pytest.raises(tn.TNError):
+        tn.cell_links(3, 1, 2, [0, 0, 1])         # site 0's r leg on two links

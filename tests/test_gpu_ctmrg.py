@@ -125,8 +125,7 @@ def test_converged_energy_parity(ctx):
     Cg, Tg = dev(C), dev(T)
     sg = dev(np.stack(sites))
     rc, it, delta = ctx.ctmrg_iterate(Lx, Ly, sg, cell, Cg, Tg, 60, 1e-11)
-    r1, rh, rv = ctx.ipeps_rdms(Lx, Ly, sg, cell, Cg, Tg)
-    eg = tn.tfim_energy_per_site(r1, rh, rv, 1.0, 3.0)
+    eg = ctx.ipeps_energy(Lx, Ly, sg, cell, Cg, Tg, 1.0, 3.0)
     assert it == itr
     assert abs(eg - er) < 1e-10 * abs(er)
 

@@ -1,0 +1,236 @@
+"""GPU parity of the full-update rows against the CPU oracle, through the C ABI:
+gate application, truncation, canonical form / pre-truncation, bond
+environment, ALS, gauge fixing and the renormalized gate."""
+import numpy as np
+import pytest
+
+import tninputs
+from oracle import ctmrg as octm
+from oracle import fu as ofu
+from oracle import gates
+from oracle import peps as opeps
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1411_0391_amd as tn  # noqa: E402
+
+LEGNUM = {"l": 1, "r": 2, "d": 3, "u": 4}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tn.Context()
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64))).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _cell(spec):
+    Lx, Ly, cell = spec
+    return Lx, Ly, list(cell), octm.Cell(Lx, Ly, list(cell)), max(cell) + 1
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_gate_parity(ctx, D):
+    A = tninputs.ipeps_sites(3, 2, D)
+    ref = np.stack([gates.apply_ipepo(gates.ipepo(1.0, 3.0, 0.01), a) for a in A])
+    got = host(ctx.ipeps_gate(dev(np.stack(A)), 1.0, 3.0, 0.01))
+    assert got.shape == ref.shape
+    assert rel(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("spec,Din,Dout", [(tninputs.CHECKERBOARD, 4, 2),
+                                           (tninputs.SINGLE_SITE, 6, 3),
+                                           (tninputs.CHECKERBOARD, 7, 7)])
+def test_truncate_parity(ctx, spec, Din, Dout):
+    Lx, Ly, cell, oc, nsite = _cell(spec)
+    links, _ = opeps.cell_links(oc)
+    rng = np.random.default_rng(Din * 10 + Dout)
+    th = [rng.standard_normal((2,) + (Din,) * 4) for _ in range(nsite)]
+    P = [rng.standard_normal((Din, Dout)) for _ in links]
+    Q = [rng.standard_normal((Dout, Din)) for _ in links]
+    ref = np.stack(opeps.truncate(th, links, P, Q))
+    got = host(ctx.ipeps_truncate(Lx, Ly, cell, dev(np.stack(th)), dev(np.stack(P)),
+                                  dev(np.stack(Q))))
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("spec,D", [(tninputs.CHECKERBOARD, 3), (tninputs.SINGLE_SITE, 4),
+                                    (tninputs.CHECKERBOARD, 5)])
+def test_canonical_form_parity(ctx, spec, D):
+    Lx, Ly, cell, oc, nsite = _cell(spec)
+    A = tninputs.ipeps_sites(5, nsite, D)
+    a1, lams, Pc, Qc, it = opeps.canonicalize_a_form(oc, A, tol=1e-13)
+    g1, glam, gP, gQ, git, rc = ctx.ipeps_canonicalize(Lx, Ly, cell, dev(np.stack(A)), tol=1e-13)
+    assert rc == 0
+    assert abs(git - it) <= 1
+    assert rel(host(glam), np.stack(lams)) < 1e-10
+    assert rel(host(gP), np.stack(Pc)) < 1e-8
+    assert rel(host(gQ), np.stack(Qc)) < 1e-8
+    assert rel(host(g1), np.stack(a1)) < 1e-8
+    # the GPU result is canonical on its own terms (Eqs. (17)-(20))
+    links, leg_link = opeps.cell_links(oc)
+    glams = list(host(glam))
+    gam = []
+    for s, t in enumerate(host(g1)):
+        for leg, ax in opeps.LEGS.items():
+            w = 1.0 / np.sqrt(glams[leg_link[s][leg]])
+            shape = [1] * 5
+            shape[ax] = D
+            t = t * w.reshape(shape)
+        gam.append(t)
+    assert opeps.canonical_residual(oc, gam, glams) < 1e-9
+
+
+def test_su_pretruncation_parity(ctx):
+    Lx, Ly, cell, oc, nsite = _cell(tninputs.CHECKERBOARD)
+    D = 3
+    A = tninputs.ipeps_sites(7, nsite, D)
+    th = [gates.apply_ipepo(gates.ipepo(1.0, 3.0, 0.01), a) for a in A]
+    P, Q = ofu.su_truncation(oc, th, D, tol=1e-13)
+    Thg = ctx.ipeps_gate(dev(np.stack(A)), 1.0, 3.0, 0.01)
+    _, _, gP, gQ, _, rc = ctx.ipeps_canonicalize(Lx, Ly, cell, Thg, D_keep=D, tol=1e-13,
+                                                 a_out=False)
+    assert rc == 0
+    for b in range(len(P)):
+        assert rel(host(gP)[b] @ host(gQ)[b], P[b] @ Q[b]) < 1e-8
+    assert rel(host(gP), np.stack(P)) < 1e-7
+    assert rel(host(gQ), np.stack(Q)) < 1e-7
+
+
+def _fu_state(spec, D, chi, converged, seed=0):
+    """Theta of a gated random state, its simple-update (P, Q) and an
+    environment of the pre-truncated state (converged by the oracle CTMRG, or
+    the positive random start)."""
+    Lx, Ly, cell, oc, nsite = _cell(spec)
+    A = tninputs.ipeps_sites(seed, nsite, D)
+    th = [gates.apply_ipepo(gates.ipepo(1.0, 3.0, 0.01), a) for a in A]
+    P, Q = ofu.su_truncation(oc, th, D)
+    links, _ = opeps.cell_links(oc)
+    pre = opeps.truncate(th, links, P, Q)
+    C, T = tninputs.ctm_env(seed + 1, Lx * Ly, chi, D, positive=True)
+    if converged:
+        C, T, _, _ = octm.ctmrg(oc, pre, C, T, chi, 100, 1e-10)
+    return Lx, Ly, cell, oc, th, P, Q, C, T
+
+
+@pytest.mark.parametrize("spec,D,chi,conv", [(tninputs.CHECKERBOARD, 2, 6, False),
+                                             (tninputs.CHECKERBOARD, 3, 8, True),
+                                             (tninputs.SINGLE_SITE, 2, 7, True)])
+def test_bond_environment_parity(ctx, spec, D, chi, conv):
+    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(spec, D, chi, conv)
+    args = (dev(np.stack(th)), dev(C), dev(T), dev(np.stack(P)), dev(np.stack(Q)))
+    for b in range(len(P)):
+        ref = ofu.bond_environment(oc, th, P, Q, C, T, b)
+        got = host(ctx.bond_environment(Lx, Ly, cell, *args, b))
+        assert rel(got, ref) < 1e-11, b
+
+
+@pytest.mark.parametrize("spec,D,chi", [(tninputs.CHECKERBOARD, 2, 6),
+                                        (tninputs.CHECKERBOARD, 3, 8),
+                                        (tninputs.SINGLE_SITE, 3, 9)])
+def test_bond_env_truncate_parity(ctx, spec, D, chi):
+    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(spec, D, chi, True)
+    Pr, Qr, costs = list(P), list(Q), []
+    for b in range(len(P)):
+        N = ofu.bond_environment(oc, th, Pr, Qr, C, T, b)
+        Pr[b], Qr[b], f, _, _ = ofu.als(N, Pr[b], Qr[b], 1e-12, 50)
+        costs.append(f)
+    gP, gQ = dev(np.stack(P)), dev(np.stack(Q))
+    gcost, sweeps = ctx.bond_env_truncate(Lx, Ly, cell, dev(np.stack(th)), dev(C), dev(T), gP, gQ,
+                                          50, 1e-12)
+    assert sweeps >= len(P)
+    for b in range(len(P)):
+        # the truncation PQ is gauge free; the balanced pair is fixed by the sign rule
+        assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-7, b
+        # f = t - 2c + q cancels down from t = <I|N|I>: rounding is relative to t
+        t = ofu.cost(ofu.bond_environment(oc, th, Pr, Qr, C, T, b), Pr[b], Qr[b])[1]
+        assert abs(gcost[b] - costs[b]) <= 1e-6 * abs(costs[b]) + 1e-12 * abs(t), b
+    assert rel(host(gP), np.stack(Pr)) < 1e-6
+    assert rel(host(gQ), np.stack(Qr)) < 1e-6
+
+
+def _rot(rng, D, eps):
+    a = rng.standard_normal((D, D))
+    from scipy.linalg import expm
+    return expm(eps * (a - a.T))
+
+
+@pytest.mark.parametrize("spec,D", [(tninputs.CHECKERBOARD, 3), (tninputs.SINGLE_SITE, 4),
+                                    (tninputs.CHECKERBOARD, 5)])
+def test_gauge_fix_parity(ctx, spec, D):
+    Lx, Ly, cell, oc, nsite = _cell(spec)
+    links, leg_link = opeps.cell_links(oc)
+    rng = np.random.default_rng(D)
+    a_ref = tninputs.ipeps_sites(11, nsite, D)
+    Ut = [_rot(rng, D, 0.3) for _ in links]
+    a_new = []
+    for s, a in enumerate(a_ref):
+        t = opeps._apply_all(a, s, leg_link, Ut)
+        a_new.append(t + 1e-3 * rng.standard_normal(t.shape))
+    U0 = [np.eye(D) for _ in links]
+    Ur, Fr, itr = opeps.gauge_fix(oc, a_ref, a_new, tol=1e-13, U0=U0)
+    Ug = dev(np.stack(U0))
+    Fg, itg, rc = ctx.gauge_fix(Lx, Ly, cell, dev(np.stack(a_ref)), dev(np.stack(a_new)), Ug,
+                                tol=1e-13)
+    assert rc == 0
+    assert abs(Fg - Fr) < 1e-12
+    assert abs(itg - itr) <= 1
+    assert rel(host(Ug), np.stack(Ur)) < 1e-8
+    # it found the planted gauge
+    assert rel(host(Ug), np.stack(Ut)) < 1e-2
+
+
+def test_recycling_factors_parity(ctx):
+    rng = np.random.default_rng(4)
+    nl, D, k = 4, 3, 2
+    Dk = k * D
+    P = [rng.standard_normal((Dk, D)) for _ in range(nl)]
+    Q = [rng.standard_normal((D, Dk)) for _ in range(nl)]
+    Pc = [rng.standard_normal((D, D)) for _ in range(nl)]
+    Qc = [rng.standard_normal((D, D)) for _ in range(nl)]
+    U = [_rot(rng, D, 1.0) for _ in range(nl)]
+    Rf, Lf = ofu.renormalized_gate(P, Q, Pc, Qc, U)
+    gRf, gLf = ctx.fu_renormalized_gate(dev(np.stack(P)), dev(np.stack(Q)), dev(np.stack(Pc)),
+                                        dev(np.stack(Qc)), dev(np.stack(U)))
+    assert rel(host(gRf), np.stack(Rf)) < 1e-13
+    assert rel(host(gLf), np.stack(Lf)) < 1e-13
+    U0 = ofu.gauge_start(P, Q, Pc, Qc, k)
+    gU0 = ctx.fu_gauge_start(dev(np.stack(P)), dev(np.stack(Q)), dev(np.stack(Pc)),
+                             dev(np.stack(Qc)), k)
+    assert rel(host(gU0), np.stack(U0)) < 1e-10
+
+
+def test_energy_parity(ctx):
+    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(tninputs.CHECKERBOARD, 2, 6, True)
+    links, _ = opeps.cell_links(oc)
+    pre = opeps.truncate(th, links, P, Q)
+    ref = opeps.energy_per_site(oc, pre, C, T, 1.0, 3.0)
+    got = ctx.ipeps_energy(Lx, Ly, dev(np.stack(pre)), cell, dev(C), dev(T), 1.0, 3.0)
+    assert abs(got - ref) < 1e-12 * abs(ref)
+
+
+def test_full_update_rejects_bad_arguments(ctx):
+    th = dev(np.zeros((2, 2, 4, 4, 4, 4)))
+    P, Q = dev(np.zeros((4, 4, 2))), dev(np.zeros((4, 2, 4)))
+    C, T = dev(np.zeros((4, 4, 3, 3))), dev(np.zeros((4, 4, 3, 2, 2, 3)))
+    with pytest.raises(tn.TNError):
+        ctx.ipeps_truncate(2, 2, [0, 1, 2, 0], th, P, Q)      # site index out of range
+    with pytest.raises(tn.TNError):
+        ctx.bond_env_truncate(2, 2, [0, 1, 1, 0], th, C, T, P, Q, max_sweeps=0)
+    with pytest.raises(tn.TNError):
+        ctx.bond_environment(2, 2, [0, 1, 1, 0], th, C, T, P, Q, 7)   # no link 7
+    with pytest.raises(tn.TNError):
+        ctx.ipeps_gate(dev(np.zeros((1, 3, 2, 2, 2, 2))), 1.0, 3.0, 0.01)  # d must be 2
