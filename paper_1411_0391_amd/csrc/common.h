@@ -133,11 +133,11 @@ int gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, bool ta, co
 int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long long sA, double* U,
                int ldu, long long sU, double* S, long long sS, double* V, int ldv, long long sV);
 
-// Upper Cholesky factor of (G + shift*I) and its inverse, k x k row-major, one
-// matrix.  shift_rel scales the shift by the Frobenius norm squared of G's
-// source (passed as trace of G).
+// Upper Cholesky factor of (G + shift*I) and its inverse, k x k row-major, for
+// `batch` matrices stored back to back (info: one int per matrix, 0 or the
+// failing pivot + 1).  The shift is shift_rel times the trace of G.
 int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* R, double* Rinv,
-                 int* info);
+                 int* info, int batch = 1);
 
 // Misc kernels.
 int scale_columns(tn_ctx* ctx, int m, int n, double* X, int ldx, const double* s, int invsqrt);

@@ -53,16 +53,20 @@ __global__ void copy_cols_kernel(int n, int kin, int kout, const double* __restr
   Y[t] = X[(long long)i * kin + j];
 }
 
-// per kept column i < chi: |Y[:,i] - S[i] V[:,i]|; out = max_i (.) / S[0]
+// per problem b (blockIdx.y) and kept column i < chi: |Y[:,i] - S[i] V[:,i]|
+// (Y, V: [batch][n][k], S: [batch][k], colres: [batch][chi])
 __global__ __launch_bounds__(256) void resid_kernel(int n, int k, int chi,
                                                     const double* __restrict__ Y,
                                                     const double* __restrict__ V,
                                                     const double* __restrict__ S,
                                                     double* __restrict__ colres) {
   const int j = blockIdx.x;
+  const long long b = blockIdx.y;
+  Y += b * n * k;
+  V += b * n * k;
   __shared__ double part[4];
   double a = 0.0;
-  const double s = S[j];
+  const double s = S[b * k + j];
   for (int i = threadIdx.x; i < n; i += 256) {
     const double r = Y[(long long)i * k + j] - s * V[(long long)i * k + j];
     a += r * r;
@@ -71,16 +75,21 @@ __global__ __launch_bounds__(256) void resid_kernel(int n, int k, int chi,
   for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
   __syncthreads();
-  if (threadIdx.x == 0) colres[j] = sqrt(part[0] + part[1] + part[2] + part[3]);
-  (void)chi;
+  if (threadIdx.x == 0) colres[b * chi + j] = sqrt(part[0] + part[1] + part[2] + part[3]);
 }
 
-__global__ void max_over_kernel(const double* __restrict__ x, int n, const double* __restrict__ ref,
-                                double* __restrict__ out) {
+// out = max over problems of (max_i colres[b][i]) / S[b][0]
+__global__ void max_over_kernel(const double* __restrict__ colres, int chi, int batch,
+                                const double* __restrict__ S, int k, double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double m = 0.0;
-  for (int i = 0; i < n; ++i) m = fmax(m, x[i]);
-  *out = (ref[0] > 0.0) ? m / ref[0] : m;
+  double r = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    double m = 0.0;
+    for (int i = 0; i < chi; ++i) m = fmax(m, colres[b * chi + i]);
+    const double s0 = S[(long long)b * k];
+    r = fmax(r, s0 > 0.0 ? m / s0 : m);
+  }
+  *out = r;
 }
 
 // sign convention on the kept left singular vectors of M (= W): the first
@@ -249,85 +258,99 @@ int corner_of(tn_ctx* ctx, const Geo& g, int fj, int p, double* E, double* X1, d
   return corner_ul(ctx, g, g.Cp(p, fj), g.Tp(p, fj), g.Tp(p, fj + 3), g.site(fj, p), E, X1, X2, X3);
 }
 
+// `batch` independent projector problems (the row cuts of one move): the
+// corners of problem b are E[j] + b n^2; t1, t2 are [batch][n][k] scratch.
 struct TopK {
-  int n, k, chi;
+  int n, k, chi, batch;
   const double* E[4];
   double *t1, *t2;
 };
 
-// Y = K X with K = E2 E3 E0 E1
+// Y = K X with K = E2 E3 E0 E1, per problem
 int applyK(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
-  const int n = t.n, k = t.k;
-  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, false, X, k, false, t.t1, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, false, t.t1, k, false, t.t2, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, false, t.t2, k, false, t.t1, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, false, t.t1, k, false, Y, k, 1.0, 0.0));
+  const int n = t.n, k = t.k, B = t.batch;
+  const long long sE = (long long)n * n, sX = (long long)n * k;
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, false, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, false, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, false, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, false, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX));
   return TN_OK;
 }
 
-// Y = K^T X
+// Y = K^T X, per problem
 int applyKT(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
-  const int n = t.n, k = t.k;
-  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, true, X, k, false, t.t1, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, true, t.t1, k, false, t.t2, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, true, t.t2, k, false, t.t1, k, 1.0, 0.0));
-  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, true, t.t1, k, false, Y, k, 1.0, 0.0));
+  const int n = t.n, k = t.k, B = t.batch;
+  const long long sE = (long long)n * n, sX = (long long)n * k;
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, true, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, true, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, true, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, true, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX));
   return TN_OK;
 }
 
-// Column scaling by 1 / max(s_j, floor * s_0) (floor keeps columns below the
-// FP64 resolution of the block at unit scale instead of blowing them up).
-__global__ void inv_scale_cols_kernel(int n, int k, double* X, const double* s, double floor_rel,
-                                      double* sc) {
+// Column scaling by 1 / max(s_j, floor * s_0) per problem (floor keeps
+// columns below the FP64 resolution of the block at unit scale instead of
+// blowing them up); X [batch][n][k], s and sc [batch][k].
+__global__ void inv_scale_cols_kernel(int n, int k, int batch, double* X, const double* s,
+                                      double floor_rel, double* sc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < k) sc[t] = fmax(s[t], floor_rel * s[0]);
-  if (t >= (long long)n * k) return;
+  if (t < (long long)batch * k) {
+    const long long b = t / k;
+    sc[t] = fmax(s[t], floor_rel * s[b * k]);
+  }
+  if (t >= (long long)batch * n * k) return;
+  const long long b = t / ((long long)n * k);
   const int j = (int)(t % k);
-  X[t] /= fmax(s[j], floor_rel * s[0]);
+  const double* sb = s + b * k;
+  X[t] /= fmax(sb[j], floor_rel * sb[0]);
 }
 
-// R <- R diag(sc)
-__global__ void right_scale_kernel(int k, double* R, const double* sc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= k * k) return;
-  R[t] *= sc[t % k];
+// R <- R diag(sc) per problem (R [batch][k][k], sc [batch][k])
+__global__ void right_scale_kernel(int k, int batch, double* R, const double* sc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)batch * k * k) return;
+  const long long b = t / ((long long)k * k);
+  R[t] *= sc[b * k + t % k];
 }
 
-// Orthonormalise the columns of X (n x k) in place: Cholesky-QR passes, the
-// first `nshift` of them shifted (shifted Cholesky-QR, Fukaya et al., SIAM J.
-// Sci. Comput. 2020), `npass` in total.  R (k x k, optional) with
-// X_in = Q R.  info[0..npass) receives the Cholesky status of each pass.
-int cholqr_passes(tn_ctx* ctx, int n, int k, double* X, double* Rout, double* tmp, int* info,
-                  int npass, int nshift) {
+// Orthonormalise the columns of X ([batch] blocks of n x k) in place:
+// Cholesky-QR passes, the first `nshift` of them shifted (shifted
+// Cholesky-QR, Fukaya et al., SIAM J. Sci. Comput. 2020), `npass` in total.
+// R ([batch][k][k], optional) with X_in = Q R.  info[pass * batch + b]
+// receives the Cholesky status of each pass and problem.
+int cholqr_passes(tn_ctx* ctx, int n, int k, int batch, double* X, double* Rout, double* tmp,
+                  int* info, int npass, int nshift) {
   // scratch is reused by the next call: later kernels on the same stream
   // run after these, so releasing the arena slice here is safe
   const size_t mark = ctx->arena_off;
-  double* G = ws_alloc<double>(ctx, (size_t)k * k);
-  double* R = ws_alloc<double>(ctx, (size_t)k * k * npass);
-  double* Ri = ws_alloc<double>(ctx, (size_t)k * k);
-  double* Racc = ws_alloc<double>(ctx, (size_t)k * k);
+  const long long kk = (long long)k * k, nk = (long long)n * k;
+  double* G = ws_alloc<double>(ctx, (size_t)batch * kk);
+  double* R = ws_alloc<double>(ctx, (size_t)batch * kk * npass);
+  double* Ri = ws_alloc<double>(ctx, (size_t)batch * kk);
+  double* Racc = ws_alloc<double>(ctx, (size_t)batch * kk);
   if (!Racc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in cholqr");
   const double u = 1.1102230246251565e-16;
   double* src = X;
   double* dst = tmp;
   for (int pass = 0; pass < npass; ++pass) {
-    TN_TRY(gemm(ctx, k, k, n, src, k, true, src, k, false, G, k, 1.0, 0.0));
+    TN_TRY(gemm(ctx, k, k, n, src, k, true, src, k, false, G, k, 1.0, 0.0, batch, nk, nk, kk));
     const double shift = pass < nshift ? 11.0 * ((double)n * k + (double)k * (k + 1)) * u : 0.0;
-    TN_TRY(cholesky_inv(ctx, k, G, shift, R + (size_t)pass * k * k, Ri, info + pass));
-    TN_TRY(gemm(ctx, n, k, k, src, k, false, Ri, k, false, dst, k, 1.0, 0.0));
+    TN_TRY(cholesky_inv(ctx, k, G, shift, R + (size_t)pass * batch * kk, Ri, info + pass * batch,
+                        batch));
+    TN_TRY(gemm(ctx, n, k, k, src, k, false, Ri, k, false, dst, k, 1.0, 0.0, batch, nk, kk, nk));
     std::swap(src, dst);
   }
   if (src != X)
-    TN_HIP(ctx, hipMemcpyAsync(X, src, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice,
-                               ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(X, src, (size_t)batch * nk * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
   if (Rout) {
     // R = R_last ... R_1
-    TN_HIP(ctx, hipMemcpyAsync(Rout, R + (size_t)(npass - 1) * k * k, (size_t)k * k * 8,
-                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(Rout, R + (size_t)(npass - 1) * batch * kk,
+                               (size_t)batch * kk * 8, hipMemcpyDeviceToDevice, ctx->stream));
     for (int pass = npass - 2; pass >= 0; --pass) {
-      TN_TRY(gemm(ctx, k, k, k, Rout, k, false, R + (size_t)pass * k * k, k, false, Racc, k, 1.0,
-                  0.0));
-      TN_HIP(ctx, hipMemcpyAsync(Rout, Racc, (size_t)k * k * 8, hipMemcpyDeviceToDevice,
+      TN_TRY(gemm(ctx, k, k, k, Rout, k, false, R + (size_t)pass * batch * kk, k, false, Racc, k,
+                  1.0, 0.0, batch, kk, kk, kk));
+      TN_HIP(ctx, hipMemcpyAsync(Rout, Racc, (size_t)batch * kk * 8, hipMemcpyDeviceToDevice,
                                  ctx->stream));
     }
   }
@@ -335,44 +358,51 @@ int cholqr_passes(tn_ctx* ctx, int n, int k, double* X, double* Rout, double* tm
   return TN_OK;
 }
 
-// Robust orthonormalisation: optional column pre-scaling by `scale` (the
-// current Ritz values, which makes a Ritz-ordered block nearly orthonormal),
-// then shifted Cholesky-QR3; if a pass breaks down, the original block is
-// redone with two shifted passes followed by two plain ones.
-int orth_robust(tn_ctx* ctx, int n, int k, double* X, const double* scale, double* Rout,
-                double* tmp, double* save, int* info) {
+// Robust orthonormalisation of [batch] blocks: optional column pre-scaling by
+// `scale` (the current Ritz values, which makes a Ritz-ordered block nearly
+// orthonormal), then Cholesky-QR; if any pass of any problem breaks down,
+// the original blocks are redone with two shifted passes followed by two
+// plain ones.
+int orth_robust(tn_ctx* ctx, int n, int k, int batch, double* X, const double* scale,
+                double* Rout, double* tmp, double* save, int* info) {
   const size_t mark = ctx->arena_off;
-  double* sc = ws_alloc<double>(ctx, (size_t)k);
+  double* sc = ws_alloc<double>(ctx, (size_t)batch * k);
   if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in orth_robust");
-  const long long tot = (long long)n * k;
+  const long long tot = (long long)batch * n * k;
   if (scale) {
     hipLaunchKernelGGL(inv_scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       ctx->stream, n, k, X, scale, 1e-15, sc);
+                       ctx->stream, n, k, batch, X, scale, 1e-15, sc);
     TN_HIP(ctx, hipGetLastError());
   }
   TN_HIP(ctx, hipMemcpyAsync(save, X, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  TN_HIP(ctx, hipMemsetAsync(info, 0, 8 * sizeof(int), ctx->stream));
+  const int ninfo = 4 * batch;
+  TN_HIP(ctx, hipMemsetAsync(info, 0, ninfo * sizeof(int), ctx->stream));
   // a pre-scaled block is close to orthonormal: two plain passes give
   // orthogonality to rounding; otherwise shifted Cholesky-QR3
   if (scale)
-    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 2, 0));
+    TN_TRY(cholqr_passes(ctx, n, k, batch, X, Rout, tmp, info, 2, 0));
   else
-    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 3, 1));
-  int h[8];
-  TN_HIP(ctx, hipMemcpyAsync(h, info, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TN_TRY(cholqr_passes(ctx, n, k, batch, X, Rout, tmp, info, 3, 1));
+  std::vector<int> h(ninfo);
+  TN_HIP(ctx, hipMemcpyAsync(h.data(), info, ninfo * sizeof(int), hipMemcpyDeviceToHost,
+                             ctx->stream));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (h[0] || h[1] || h[2]) {
+  bool bad = false;
+  for (int v : h) bad = bad || v != 0;
+  if (bad) {
     TN_HIP(ctx, hipMemcpyAsync(X, save, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemsetAsync(info, 0, 8 * sizeof(int), ctx->stream));
-    TN_TRY(cholqr_passes(ctx, n, k, X, Rout, tmp, info, 4, 2));
-    TN_HIP(ctx, hipMemcpyAsync(h, info, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipMemsetAsync(info, 0, ninfo * sizeof(int), ctx->stream));
+    TN_TRY(cholqr_passes(ctx, n, k, batch, X, Rout, tmp, info, 4, 2));
+    TN_HIP(ctx, hipMemcpyAsync(h.data(), info, ninfo * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (h[0] || h[1] || h[2] || h[3])
-      TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
+    for (int v : h)
+      if (v) TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
   }
   if (scale && Rout) {
-    hipLaunchKernelGGL(right_scale_kernel, dim3((unsigned)((k * k + 255) / 256)), dim3(256), 0,
-                       ctx->stream, k, Rout, sc);
+    const long long tk = (long long)batch * k * k;
+    hipLaunchKernelGGL(right_scale_kernel, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0,
+                       ctx->stream, k, batch, Rout, sc);
     TN_HIP(ctx, hipGetLastError());
   }
   ctx->arena_off = mark;
@@ -383,13 +413,15 @@ struct SvdStats {
   long long iters = 0, calls = 0, unconverged = 0, explicit_calls = 0;
 };
 
-// Top-chi singular triplets of K = V S W^T (V: left, W: right), n x chi.
-// warm: optional start basis [n][k] followed by its k Ritz values (in/out).
-int topk_svd(tn_ctx* ctx, TopK& t, double* warm, bool warm_valid, double* Vout, double* Sout,
-             double* Wout, double tol, int maxit, unsigned long long seed, SvdStats* st) {
-  const int n = t.n, k = t.k, chi = t.chi;
+// Top-chi singular triplets of K_b = V_b S_b W_b^T for every problem b:
+// Vout, Wout [batch][n][chi], Sout [batch][chi].  warmQ [batch][n][k] and
+// warmS [batch][k]: optional start bases and their Ritz values (in/out).
+int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid, double* Vout,
+             double* Sout, double* Wout, double tol, int maxit, unsigned long long seed,
+             SvdStats* st) {
+  const int n = t.n, k = t.k, chi = t.chi, B = t.batch;
   const size_t nk = (size_t)n * k;
-  const long long tot = (long long)n * chi;
+  const long long nchi = (long long)n * chi;
   if (n <= 256) {
     // small problems: form K and take its full one-sided Jacobi SVD
     double* Km = ws_alloc<double>(ctx, (size_t)n * n);
@@ -398,101 +430,117 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warm, bool warm_valid, double* Vout, 
     double* Vf = ws_alloc<double>(ctx, (size_t)n * n);
     double* Sf = ws_alloc<double>(ctx, (size_t)n);
     if (!Sf) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
-    TN_TRY(gemm(ctx, n, n, n, t.E[0], n, false, t.E[1], n, false, Km, n, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, n, n, t.E[3], n, false, Km, n, false, K2, n, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, n, n, t.E[2], n, false, K2, n, false, Km, n, 1.0, 0.0));
-    TN_TRY(jacobi_svd(ctx, 1, n, n, Km, n, 0, Uf, n, 0, Sf, 0, Vf, n, 0));
-    hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       ctx->stream, n, n, chi, Uf, Vout);
-    hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       ctx->stream, n, n, chi, Vf, Wout);
-    TN_HIP(ctx, hipMemcpyAsync(Sout, Sf, chi * sizeof(double), hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi, Wout, chi,
-                       Vout);
-    TN_HIP(ctx, hipGetLastError());
-    if (st) st->explicit_calls += 1;
+    const long long sE = (long long)n * n;
+    for (int b = 0; b < B; ++b) {
+      TN_TRY(gemm(ctx, n, n, n, t.E[0] + b * sE, n, false, t.E[1] + b * sE, n, false, Km, n, 1.0,
+                  0.0));
+      TN_TRY(gemm(ctx, n, n, n, t.E[3] + b * sE, n, false, Km, n, false, K2, n, 1.0, 0.0));
+      TN_TRY(gemm(ctx, n, n, n, t.E[2] + b * sE, n, false, K2, n, false, Km, n, 1.0, 0.0));
+      TN_TRY(jacobi_svd(ctx, 1, n, n, Km, n, 0, Uf, n, 0, Sf, 0, Vf, n, 0));
+      hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((nchi + 255) / 256)), dim3(256), 0,
+                         ctx->stream, n, n, chi, Uf, Vout + b * nchi);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((nchi + 255) / 256)), dim3(256), 0,
+                         ctx->stream, n, n, chi, Vf, Wout + b * nchi);
+      TN_HIP(ctx, hipMemcpyAsync(Sout + b * chi, Sf, chi * sizeof(double),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+      hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi,
+                         Wout + b * nchi, chi, Vout + b * nchi);
+      TN_HIP(ctx, hipGetLastError());
+    }
+    if (st) st->explicit_calls += B;
     return TN_OK;
   }
-  double* Q = ws_alloc<double>(ctx, nk);
-  double* B = ws_alloc<double>(ctx, nk);
-  double* Y = ws_alloc<double>(ctx, nk);
-  double* Wb = ws_alloc<double>(ctx, nk);
-  double* Vr = ws_alloc<double>(ctx, nk);
-  double* tmp = ws_alloc<double>(ctx, nk);
-  double* save = ws_alloc<double>(ctx, nk);
-  double* R = ws_alloc<double>(ctx, (size_t)k * k);
-  double* UR = ws_alloc<double>(ctx, (size_t)k * k);
-  double* VR = ws_alloc<double>(ctx, (size_t)k * k);
-  double* S = ws_alloc<double>(ctx, (size_t)k);
-  double* Sprev = ws_alloc<double>(ctx, (size_t)k);
-  double* colres = ws_alloc<double>(ctx, (size_t)k);
+  const size_t bnk = (size_t)B * nk, bkk = (size_t)B * k * k;
+  double* Q = ws_alloc<double>(ctx, bnk);
+  double* Bm = ws_alloc<double>(ctx, bnk);
+  double* Y = ws_alloc<double>(ctx, bnk);
+  double* Wb = ws_alloc<double>(ctx, bnk);
+  double* Vr = ws_alloc<double>(ctx, bnk);
+  double* tmp = ws_alloc<double>(ctx, bnk);
+  double* save = ws_alloc<double>(ctx, bnk);
+  double* R = ws_alloc<double>(ctx, bkk);
+  double* UR = ws_alloc<double>(ctx, bkk);
+  double* VR = ws_alloc<double>(ctx, bkk);
+  double* S = ws_alloc<double>(ctx, (size_t)B * k);
+  double* Sprev = ws_alloc<double>(ctx, (size_t)B * k);
+  double* colres = ws_alloc<double>(ctx, (size_t)B * chi);
   double* res = ws_alloc<double>(ctx, 1);
-  int* info = ws_alloc<int>(ctx, 8);
+  int* info = ws_alloc<int>(ctx, 8 * B);
   if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
+  const long long kk = (long long)k * k, snk = (long long)nk;
   bool have_s = false;
-  if (warm && warm_valid) {
-    TN_HIP(ctx, hipMemcpyAsync(Q, warm, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(Sprev, warm + nk, k * sizeof(double), hipMemcpyDeviceToDevice,
+  if (warmQ && warm_valid) {
+    TN_HIP(ctx, hipMemcpyAsync(Q, warmQ, bnk * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(Sprev, warmS, (size_t)B * k * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
     have_s = true;
   } else {
-    TN_TRY(fill_random(ctx, Q, (long long)nk, seed));
+    TN_TRY(fill_random(ctx, Q, (long long)bnk, seed));
   }
-  TN_TRY(orth_robust(ctx, n, k, Q, nullptr, nullptr, tmp, save, info));
+  TN_TRY(orth_robust(ctx, n, k, B, Q, nullptr, nullptr, tmp, save, info));
   int it = 0;
   double hres = 1.0;
   for (it = 1; it <= maxit; ++it) {
-    TN_TRY(applyKT(ctx, t, Q, B));
-    TN_TRY(orth_robust(ctx, n, k, B, have_s ? Sprev : nullptr, R, tmp, save, info));
-    TN_TRY(jacobi_svd(ctx, 1, k, k, R, k, 0, UR, k, 0, S, 0, VR, k, 0));
-    TN_TRY(gemm(ctx, n, k, k, B, k, false, UR, k, false, Wb, k, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0));
+    TN_TRY(applyKT(ctx, t, Q, Bm));
+    TN_TRY(orth_robust(ctx, n, k, B, Bm, have_s ? Sprev : nullptr, R, tmp, save, info));
+    TN_TRY(jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk));
+    TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
+    TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
     TN_TRY(applyK(ctx, t, Wb, Y));
-    hipLaunchKernelGGL(resid_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, k, chi, Y, Vr, S,
+    hipLaunchKernelGGL(resid_kernel, dim3(chi, B), dim3(256), 0, ctx->stream, n, k, chi, Y, Vr, S,
                        colres);
-    hipLaunchKernelGGL(max_over_kernel, dim3(1), dim3(1), 0, ctx->stream, colres, chi, S, res);
+    hipLaunchKernelGGL(max_over_kernel, dim3(1), dim3(1), 0, ctx->stream, colres, chi, B, S, k,
+                       res);
     TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, res, sizeof(double), hipMemcpyDeviceToHost,
                                ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     hres = ctx->host_scratch[0];
     if (!std::isfinite(hres)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite residual in the projector SVD");
     if (hres <= tol || it == maxit) break;
-    TN_HIP(ctx, hipMemcpyAsync(Q, Y, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    TN_TRY(orth_robust(ctx, n, k, Q, S, nullptr, tmp, save, info));
-    TN_HIP(ctx, hipMemcpyAsync(Sprev, S, k * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(Q, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    TN_TRY(orth_robust(ctx, n, k, B, Q, S, nullptr, tmp, save, info));
+    TN_HIP(ctx, hipMemcpyAsync(Sprev, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
     have_s = true;
   }
   if (st) {
-    st->iters += it;
-    st->calls += 1;
-    if (hres > tol) st->unconverged += 1;
+    st->iters += (long long)it * B;
+    st->calls += B;
+    if (hres > tol) st->unconverged += B;
   }
-  if (warm) {
-    TN_HIP(ctx, hipMemcpyAsync(warm, Vr, nk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(warm + nk, S, k * sizeof(double), hipMemcpyDeviceToDevice,
+  if (warmQ) {
+    TN_HIP(ctx, hipMemcpyAsync(warmQ, Vr, bnk * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(warmS, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
   }
+  // the kept columns of every problem: rows of all problems at once
+  const long long tot = (long long)B * nchi;
   hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                     ctx->stream, n, k, chi, Vr, Vout);
+                     ctx->stream, B * n, k, chi, Vr, Vout);
   hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                     ctx->stream, n, k, chi, Wb, Wout);
-  TN_HIP(ctx, hipMemcpyAsync(Sout, S, chi * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi, Wout, chi, Vout);
+                     ctx->stream, B * n, k, chi, Wb, Wout);
+  for (int b = 0; b < B; ++b) {
+    TN_HIP(ctx, hipMemcpyAsync(Sout + b * chi, S + (size_t)b * k, chi * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    hipLaunchKernelGGL(signfix_kernel, dim3(chi), dim3(256), 0, ctx->stream, n, chi,
+                       Wout + b * nchi, chi, Vout + b * nchi);
+  }
   TN_HIP(ctx, hipGetLastError());
   return TN_OK;
 }
 
 struct MoveBufs {
-  double* E[4];
+  double* E[4];           // [Ly][n][n] each: corner j of every row cut
   double *X1, *X2, *X3;
   double *P, *PtT;        // [Ly][n][chi]
-  double *V, *W, *S;      // n x chi, n x chi, chi
-  double *G1;             // n x chi
-  double *t1, *t2;        // n x k
+  double *V, *W, *S;      // [Ly][n][chi], [Ly][n][chi], [Ly][chi]
+  double *G1;             // [Ly][n][chi]
+  double *t1, *t2;        // [Ly][n][k]
   double *Cn1, *Tn4, *Cn4;  // new tensors [Ly][...]
   double* CT;             // chi*D2*chi
-  double* warm;           // [4][Lx][Ly][n][k] or null
+  double* warm;           // per frame, column and row: start basis [n][k] and Ritz values [k]
   int k;
 };
 
@@ -502,38 +550,48 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
   const int Lyf = F.Ly[f], Lxf = F.Lx[f];
   const int n = g.n, chi = g.chi, D = g.D, d = g.d;
   const long long D2 = (long long)D * D;
-  const long long nchi = (long long)n * chi;
+  const long long nchi = (long long)n * chi, nn = (long long)n * n;
+  // the four enlarged corners of every row cut of column x
   for (int y = 0; y < Lyf; ++y) {
     const int ptl = F.at(f, x, y), ptr = F.at(f, x + 1, y);
     const int pbr = F.at(f, x + 1, y + 1), pbl = F.at(f, x, y + 1);
-    TN_TRY(corner_of(ctx, g, f + 0, ptl, b.E[0], b.X1, b.X2, b.X3));
-    TN_TRY(corner_of(ctx, g, f + 1, ptr, b.E[1], b.X1, b.X2, b.X3));
-    TN_TRY(corner_of(ctx, g, f + 2, pbr, b.E[2], b.X1, b.X2, b.X3));
-    TN_TRY(corner_of(ctx, g, f + 3, pbl, b.E[3], b.X1, b.X2, b.X3));
-    TopK t;
-    t.n = n;
-    t.k = b.k;
-    t.chi = chi;
-    for (int j = 0; j < 4; ++j) t.E[j] = b.E[j];
-    t.t1 = b.t1;
-    t.t2 = b.t2;
-    const size_t slot = ((size_t)f * (Lxf * Lyf) + (size_t)y * Lxf + x);
-    double* warm = b.warm ? b.warm + slot * ((size_t)n * b.k + b.k) : nullptr;
-    const bool wv = warm && warm_ok[slot];
-    const size_t mark = ctx->arena_off;
-    TN_TRY(topk_svd(ctx, t, warm, wv, b.V, b.S, b.W, 1e-13, 40,
-                    0x5DEECE66DULL * (slot + 1), st));
-    ctx->arena_off = mark;
-    if (warm) warm_ok[slot] = true;
-    // P = E3^T (E2^T V) S^-1/2 ; Pt^T = E0 (E1 W) S^-1/2
-    double* P = b.P + (size_t)y * nchi;
-    double* PtT = b.PtT + (size_t)y * nchi;
-    TN_TRY(gemm(ctx, n, chi, n, b.E[2], n, true, b.V, chi, false, b.G1, chi, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, chi, n, b.E[3], n, true, b.G1, chi, false, P, chi, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, chi, n, b.E[1], n, false, b.W, chi, false, b.G1, chi, 1.0, 0.0));
-    TN_TRY(gemm(ctx, n, chi, n, b.E[0], n, false, b.G1, chi, false, PtT, chi, 1.0, 0.0));
-    TN_TRY(scale_columns(ctx, n, chi, P, chi, b.S, 1));
-    TN_TRY(scale_columns(ctx, n, chi, PtT, chi, b.S, 1));
+    TN_TRY(corner_of(ctx, g, f + 0, ptl, b.E[0] + y * nn, b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 1, ptr, b.E[1] + y * nn, b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 2, pbr, b.E[2] + y * nn, b.X1, b.X2, b.X3));
+    TN_TRY(corner_of(ctx, g, f + 3, pbl, b.E[3] + y * nn, b.X1, b.X2, b.X3));
+  }
+  // one batched top-chi SVD for all row cuts
+  TopK t;
+  t.n = n;
+  t.k = b.k;
+  t.chi = chi;
+  t.batch = Lyf;
+  for (int j = 0; j < 4; ++j) t.E[j] = b.E[j];
+  t.t1 = b.t1;
+  t.t2 = b.t2;
+  // warm slots: frame-major, then column, then row (rows of a column adjacent)
+  const size_t slot0 = (size_t)f * (Lxf * Lyf) + (size_t)x * Lyf;
+  double* wQ = b.warm ? b.warm + slot0 * ((size_t)n * b.k + b.k) : nullptr;
+  double* wS = wQ ? wQ + (size_t)Lyf * n * b.k : nullptr;
+  bool wv = wQ != nullptr;
+  for (int y = 0; y < Lyf && wv; ++y) wv = warm_ok[slot0 + y];
+  const size_t mark = ctx->arena_off;
+  TN_TRY(topk_svd(ctx, t, wQ, wS, wv, b.V, b.S, b.W, 1e-13, 40, 0x5DEECE66DULL * (slot0 + 1), st));
+  ctx->arena_off = mark;
+  if (wQ)
+    for (int y = 0; y < Lyf; ++y) warm_ok[slot0 + y] = true;
+  // P = E3^T (E2^T V) S^-1/2 ; Pt^T = E0 (E1 W) S^-1/2, all rows at once
+  TN_TRY(gemm(ctx, n, chi, n, b.E[2], n, true, b.V, chi, false, b.G1, chi, 1.0, 0.0, Lyf, nn,
+              nchi, nchi));
+  TN_TRY(gemm(ctx, n, chi, n, b.E[3], n, true, b.G1, chi, false, b.P, chi, 1.0, 0.0, Lyf, nn,
+              nchi, nchi));
+  TN_TRY(gemm(ctx, n, chi, n, b.E[1], n, false, b.W, chi, false, b.G1, chi, 1.0, 0.0, Lyf, nn,
+              nchi, nchi));
+  TN_TRY(gemm(ctx, n, chi, n, b.E[0], n, false, b.G1, chi, false, b.PtT, chi, 1.0, 0.0, Lyf, nn,
+              nchi, nchi));
+  for (int y = 0; y < Lyf; ++y) {
+    TN_TRY(scale_columns(ctx, n, chi, b.P + y * nchi, chi, b.S + y * chi, 1));
+    TN_TRY(scale_columns(ctx, n, chi, b.PtT + y * nchi, chi, b.S + y * chi, 1));
   }
   const long long csz = (long long)chi * chi, tsz = (long long)chi * D2 * chi;
   const long long dD4 = (long long)d * D2 * D2;
@@ -667,33 +725,33 @@ int setup_geo(tn_ctx* ctx, Geo& g, int Lx, int Ly, int D, int d, int nsite, cons
 
 size_t move_bytes(const Geo& g, int k, bool warm) {
   const size_t chi = g.chi, D = g.D, d = g.d, D2 = D * D, n = g.n;
-  const int Lm = std::max(g.Lx, g.Ly);
+  const size_t Lm = std::max(g.Lx, g.Ly);
   size_t b = 0;
   auto add = [&](size_t cnt) { b += ((cnt * 8 + 255) / 256) * 256; };
-  for (int j = 0; j < 4; ++j) add(n * n);
+  for (int j = 0; j < 4; ++j) add(Lm * n * n);
   add(chi * D2 * chi);
   add(std::max(chi * D2 * D2 * chi, chi * D2 * n));
   add(chi * chi * d * D2 * D2);
-  add(Lm * n * chi);
-  add(Lm * n * chi);
-  add(n * chi);
-  add(n * chi);
-  add(chi);
-  add(n * chi);
-  add(n * k);
-  add(n * k);
+  add(Lm * n * chi);  // P
+  add(Lm * n * chi);  // PtT
+  add(Lm * n * chi);  // V
+  add(Lm * n * chi);  // W
+  add(Lm * chi);      // S
+  add(Lm * n * chi);  // G1
+  add(Lm * n * k);    // t1
+  add(Lm * n * k);    // t2
   add(Lm * chi * chi);
   add(Lm * chi * D2 * chi);
   add(Lm * chi * chi);
   add(chi * D2 * chi);
   (void)warm;
-  add(16 * n * k + 64 * (size_t)k * k);  // split-K partials of the n x n x k products
+  add(Lm * (16 * n * k + 64 * (size_t)k * k));  // split-K partials of the n x n x k products
   // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
-  add(std::max((size_t)7 * n * k, 4 * n * n + n));
-  add(3 * k * k);
-  add(3 * k + 64);
-  add(8 * k * k + k);        // Cholesky-QR passes (one alive at a time)
-  add(2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k);  // jacobi work
+  add(std::max(Lm * 7 * n * k, 4 * n * n + n));
+  add(Lm * 3 * k * k);
+  add(Lm * (3 * k + chi) + 64);
+  add(Lm * (8 * k * k + k) + 64);                 // Cholesky-QR passes (one alive at a time)
+  add(Lm * (2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k));  // jacobi work
   // rotated sites
   add(3 * (size_t)g.nsite * d * D2 * D2);
   // spectra
@@ -703,19 +761,19 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
 
 int alloc_move_bufs(tn_ctx* ctx, const Geo& g, MoveBufs& b, bool warm) {
   const size_t chi = g.chi, D = g.D, d = g.d, D2 = D * D, n = g.n;
-  const int Lm = std::max(g.Lx, g.Ly);
-  for (int j = 0; j < 4; ++j) b.E[j] = ws_alloc<double>(ctx, n * n);
+  const size_t Lm = std::max(g.Lx, g.Ly);
+  for (int j = 0; j < 4; ++j) b.E[j] = ws_alloc<double>(ctx, Lm * n * n);
   b.X1 = ws_alloc<double>(ctx, chi * D2 * chi);
   b.X2 = ws_alloc<double>(ctx, std::max(chi * D2 * D2 * chi, chi * D2 * n));
   b.X3 = ws_alloc<double>(ctx, chi * chi * d * D2 * D2);
   b.P = ws_alloc<double>(ctx, Lm * n * chi);
   b.PtT = ws_alloc<double>(ctx, Lm * n * chi);
-  b.V = ws_alloc<double>(ctx, n * chi);
-  b.W = ws_alloc<double>(ctx, n * chi);
-  b.S = ws_alloc<double>(ctx, chi);
-  b.G1 = ws_alloc<double>(ctx, n * chi);
-  b.t1 = ws_alloc<double>(ctx, n * b.k);
-  b.t2 = ws_alloc<double>(ctx, n * b.k);
+  b.V = ws_alloc<double>(ctx, Lm * n * chi);
+  b.W = ws_alloc<double>(ctx, Lm * n * chi);
+  b.S = ws_alloc<double>(ctx, Lm * chi);
+  b.G1 = ws_alloc<double>(ctx, Lm * n * chi);
+  b.t1 = ws_alloc<double>(ctx, Lm * n * b.k);
+  b.t2 = ws_alloc<double>(ctx, Lm * n * b.k);
   b.Cn1 = ws_alloc<double>(ctx, Lm * chi * chi);
   b.Tn4 = ws_alloc<double>(ctx, Lm * chi * D2 * chi);
   b.Cn4 = ws_alloc<double>(ctx, Lm * chi * chi);

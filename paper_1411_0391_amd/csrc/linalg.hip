@@ -180,6 +180,13 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
     const double* __restrict__ G, int k, double shift_rel, double* __restrict__ R,
     double* __restrict__ Rinv, int* __restrict__ info, int r_in_lds) {
   extern __shared__ double lds[];
+  {
+    const long long off = (long long)blockIdx.x * k * k;  // one matrix per workgroup
+    G += off;
+    R += off;
+    Rinv += off;
+    info += blockIdx.x;
+  }
   double* Wk = lds;                        // k x k trailing matrix, later R^-1
   double* Rl = r_in_lds ? lds + k * k : R;  // R rows as they are produced
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
@@ -324,11 +331,12 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
 }
 
 int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* R, double* Rinv,
-                 int* info) {
+                 int* info, int batch) {
   const size_t one = (size_t)k * k * sizeof(double);
   if (one > LDS_LIMIT) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports k <= 137 (k=%d)", k);
+  if (batch < 1) return TN_OK;
   const int r_in_lds = 2 * one <= LDS_LIMIT;
-  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(1), dim3(CHOL_THREADS), (r_in_lds ? 2 : 1) * one,
+  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(batch), dim3(CHOL_THREADS), (r_in_lds ? 2 : 1) * one,
                      ctx->stream, G, k, shift_rel, R, Rinv, info, r_in_lds);
   TN_HIP(ctx, hipGetLastError());
   return TN_OK;
