@@ -1,0 +1,64 @@
+"""Imaginary-time evolution drivers that compose the library's calls.
+
+Only control flow lives here: every arithmetic step is a call into
+``libitebd.so`` through :class:`paper_1411_0391_amd.Context`.
+
+Full update with environment recycling (Sec. VI B, VI C of the paper):
+each environment step applies the gate, pre-truncates the gated state by
+its canonical form, converges the CTM environment (warm-started from the
+previous one), measures the energy, truncates every link by ALS on its bond
+environment, and -- in the recycling phase -- canonicalises the result,
+fixes its gauge against the previous state and builds the renormalized gate
+G, which then replaces the environment for the next ``n_re - 1`` steps.
+"""
+from __future__ import annotations
+
+import time
+
+
+def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm=0,
+                ctm_tol=1e-10, ctm_max=100, als_tol=1e-12, als_max=50, canon_tol=1e-14,
+                canon_max=1000, gauge_tol=1e-12, gauge_max=1000, callback=None):
+    """Evolve the iPEPS ``sites`` (device [nsite][d][D]^4) for ``nsteps``
+    steps of size dt.  C, T (device) are the start environment and are
+    updated in place.  Returns (sites, log) with log entries
+    (step, energy_per_site, seconds since start) at environment steps; the
+    environment is recomputed every ``n_re`` steps after ``n_warm`` plain
+    steps."""
+    import torch
+    D = sites.shape[2]
+    kappa = 2
+    log = []
+    t0 = time.perf_counter()
+    step = 0
+    while step < nsteps:
+        warm = step < n_warm
+        Th = ctx.ipeps_gate(sites, J, h, dt)
+        _, _, P, Q, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
+                                                   max_iter=canon_max, a_out=False)
+        pre = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
+        ctx.ctmrg_iterate(Lx, Ly, pre, cell, C, T, ctm_max, ctm_tol)
+        E = ctx.ipeps_energy(Lx, Ly, pre, cell, C, T, J, h)
+        ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, P, Q, als_max, als_tol)
+        new = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
+        torch.cuda.current_stream().synchronize()
+        log.append((step + 1, E, time.perf_counter() - t0))
+        if callback:
+            callback(step, E)
+        if warm or n_re == 1:
+            sites = new
+            step += 1
+            continue
+        a1, _, Pc, Qc, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, new, tol=canon_tol,
+                                                      max_iter=canon_max)
+        U = ctx.fu_gauge_start(P, Q, Pc, Qc, kappa)
+        ctx.gauge_fix(Lx, Ly, cell, sites, a1, U, tol=gauge_tol, max_iter=gauge_max)
+        Rf, Lf = ctx.fu_renormalized_gate(P, Q, Pc, Qc, U)
+        sites = ctx.ipeps_truncate(Lx, Ly, cell, Th, Rf, Lf)
+        step += 1
+        for _ in range(n_re - 1):
+            if step >= nsteps:
+                break
+            sites = ctx.ipeps_truncate(Lx, Ly, cell, ctx.ipeps_gate(sites, J, h, dt), Rf, Lf)
+            step += 1
+    return sites, log

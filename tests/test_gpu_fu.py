@@ -234,3 +234,24 @@ def test_full_update_rejects_bad_arguments(ctx):
         ctx.bond_environment(2, 2, [0, 1, 1, 0], th, C, T, P, Q, 7)   # no link 7
     with pytest.raises(tn.TNError):
         ctx.ipeps_gate(dev(np.zeros((1, 3, 2, 2, 2, 2))), 1.0, 3.0, 0.01)  # d must be 2
+
+
+@pytest.mark.parametrize("n_re,n_warm,nsteps", [(1, 0, 3), (3, 1, 7)])
+def test_full_update_driver_parity(ctx, n_re, n_warm, nsteps):
+    """The GPU driver (library calls only) follows the oracle's full update
+    with recycling step by step: energies at every environment step and the
+    final tensors."""
+    from paper_1411_0391_amd import driver
+    Lx, Ly, cell, oc, nsite = _cell(tninputs.CHECKERBOARD)
+    D, chi = 2, 8
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_sites(2, nsite, D)]
+    C, T = tninputs.ctm_env(3, Lx * Ly, chi, D, positive=True)
+    ref_sites, ref_log = ofu.run_fu(oc, A, 1.0, 3.0, 0.01, D, chi, nsteps, n_re=n_re,
+                                    n_warm=n_warm, C=C, T=T)
+    Cg, Tg = dev(C), dev(T)
+    sites, log = driver.full_update(ctx, Lx, Ly, cell, dev(np.stack(A)), Cg, Tg, 1.0, 3.0, 0.01,
+                                    nsteps, n_re=n_re, n_warm=n_warm)
+    assert [s for s, _, _ in log] == [s for s, _ in ref_log]
+    for (_, e, _), (_, er) in zip(log, ref_log):
+        assert abs(e - er) < 1e-9 * abs(er)
+    assert rel(host(sites), np.stack(ref_sites)) < 1e-6
