@@ -323,6 +323,16 @@ def canonicalize_a_form(sites, lams=None):
     for b in (0, 1):
         Pc[b] = (il[b][:, None] * TR[b]) * np.sqrt(l1[b])[None, :]
         Qc[b] = (np.sqrt(l1[b])[:, None] * TL[b]) * il[b][None, :]
+    # the canonical gauge is unique up to the sign of each bond index: fix
+    # it on the columns of Pc (rows of Qc flip with them), independently of
+    # the path the iteration took
+    for b in (0, 1):
+        for i in range(Pc[b].shape[1]):
+            a = np.abs(Pc[b][:, i])
+            j = int(np.argmax(a >= (1.0 - 1e-8) * a.max()))
+            if Pc[b][j, i] < 0:
+                Pc[b][:, i] = -Pc[b][:, i]
+                Qc[b][i, :] = -Qc[b][i, :]
     raw = [np.einsum("ia,asb,bj->isj", Qc[1], sites[0], Pc[0]),
            np.einsum("ia,asb,bj->isj", Qc[0], sites[1], Pc[1])]
     a1 = [r / np.linalg.norm(r) for r in raw]

@@ -254,6 +254,15 @@ def canonicalize(cell, gammas, lams=None, tol=1e-14, max_iter=1000):
         gammas = [g / np.linalg.norm(g) for g in gammas]
         if delta < tol:
             break
+    # the canonical gauge is unique up to the sign of each bond index: fix it
+    # on the columns of the accumulated first-end transform (rows of the
+    # second-end one flip with them), independently of the iteration's path
+    for b, (s1, l1, s2, l2) in enumerate(links):
+        before = TR[b].copy()
+        TR[b], TL[b] = _signfix_cols(TR[b].copy(), TL[b].copy())
+        sg = np.where(np.sum(before * TR[b], axis=0) < 0, -1.0, 1.0)
+        gammas[s1] = apply_leg(gammas[s1], l1, np.diag(sg))
+        gammas[s2] = apply_leg(gammas[s2], l2, np.diag(sg))
     return gammas, lams, it, TR, TL
 
 
