@@ -13,7 +13,9 @@ Readings taken where the paper is silent or describes a one-site cell:
   of that link, with Theta^ (Theta with every other leg truncated by the
   current (P, Q)) on both sites and the link's ket and bra legs open:
   N[i, j, i', j'] with i, j the ket legs of the first and second site and
-  i', j' the bra legs; N is symmetrised in (ket <-> bra);
+  i', j' the bra legs; N is symmetrised in (ket <-> bra) and its overall
+  sign, which the normalised boundary leaves free, is taken with
+  <I|N|I> > 0;
 * ALS (Eqs. (var), (var1)): with Q fixed, P = R^{-1} S where
   R[(i c),(i' c')] = sum_{j j'} Q[c,j] N[i,j,i',j'] Q[c',j'] and
   S[(i c)] = sum_{j i'} Q[c,j] N[i,j,i',i']; then Q likewise; after each
@@ -30,8 +32,8 @@ import numpy as np
 from . import gates
 from .ctmrg import Cell, ctmrg, rotate_ccw
 from .imps import polar_orthogonal
-from .peps import (LEGS, PATH_HALF, apply_leg, canonicalize, canonicalize_a_form, cell_links,
-                   energy_per_site, gauge_fix, truncate)
+from .peps import (LEGS, PATH_HALF, apply_leg, canonical_pq, canonicalize, canonicalize_a_form,
+                   cell_links, energy_per_site, gauge_fix, truncate)
 
 
 # ---------------------------------------------------------------------------
@@ -39,17 +41,12 @@ from .peps import (LEGS, PATH_HALF, apply_leg, canonicalize, canonicalize_a_form
 # ---------------------------------------------------------------------------
 
 def su_truncation(cell, thetas, D, tol=1e-14, max_iter=1000):
-    """(P, Q) per link from the canonical form of Theta: with the canonical
-    transforms TR, TL and spectra lam (bond kappa*D), keep the D largest:
-    P = TR[:, :D] sqrt(lam_D), Q = sqrt(lam_D) TL[:D, :]."""
-    links, _ = cell_links(cell)
+    """(P, Q) per link from the canonical form of Theta: the first D columns
+    of Pc and rows of Qc (``canonical_pq``: bond kappa*D), i.e. the D
+    largest Schmidt values of every link are kept."""
     _, lams, _, TR, TL = canonicalize(cell, thetas, None, tol, max_iter)
-    P, Q = [], []
-    for b in range(len(links)):
-        sq = np.sqrt(lams[b][:D])
-        P.append(TR[b][:, :D] * sq[None, :])
-        Q.append(sq[:, None] * TL[b][:D, :])
-    return P, Q
+    Pc, Qc = canonical_pq(TR, TL, lams)
+    return [p[:, :D].copy() for p in Pc], [q[:D, :].copy() for q in Qc]
 
 
 # ---------------------------------------------------------------------------
@@ -115,7 +112,12 @@ def bond_environment(cell, thetas, P, Q, C, T, b):
         N = _n_horizontal(rc, rC, rT, y, -x, rt[0], rt[1])
     n = N.shape[0]
     N2 = N.reshape(n * n, n * n)
-    return (0.5 * (N2 + N2.T)).reshape(n, n, n, n)
+    N = (0.5 * (N2 + N2.T)).reshape(n, n, n, n)
+    # the boundary fixes N only up to an overall factor (its tensors are
+    # normalised, their sign is free): take the sign with <I|N|I> > 0
+    if np.einsum("iiaa->", N) < 0:
+        N = -N
+    return N
 
 
 # ---------------------------------------------------------------------------

@@ -333,6 +333,9 @@ def canonicalize_a_form(sites, lams=None):
             if Pc[b][j, i] < 0:
                 Pc[b][:, i] = -Pc[b][:, i]
                 Qc[b][i, :] = -Qc[b][i, :]
+        # the scale is free too (Pc -> c Pc, Qc -> Qc / c): fix |Pc| = |Qc|
+        r = np.sqrt(np.linalg.norm(Qc[b]) / np.linalg.norm(Pc[b]))
+        Pc[b], Qc[b] = Pc[b] * r, Qc[b] / r
     raw = [np.einsum("ia,asb,bj->isj", Qc[1], sites[0], Pc[0]),
            np.einsum("ia,asb,bj->isj", Qc[0], sites[1], Pc[1])]
     a1 = [r / np.linalg.norm(r) for r in raw]

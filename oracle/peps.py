@@ -294,14 +294,28 @@ def a_form(cell, gammas, lams):
     return out
 
 
+def canonical_pq(TR, TL, lams):
+    """Pc = TR sqrt(lambda), Qc = sqrt(lambda) TL per link, with the scale
+    left free by the canonical form (Pc -> c Pc, Qc -> Qc / c changes the
+    two tensors of a link by c and 1/c, which their normalisation removes)
+    fixed by |Pc|_F = |Qc|_F."""
+    Pc, Qc = [], []
+    for b in range(len(TR)):
+        p = TR[b] * np.sqrt(lams[b])[None, :]
+        q = np.sqrt(lams[b])[:, None] * TL[b]
+        r = np.sqrt(np.linalg.norm(q) / np.linalg.norm(p))
+        Pc.append(p * r)
+        Qc.append(q / r)
+    return Pc, Qc
+
+
 def canonicalize_a_form(cell, tensors, tol=1e-14, max_iter=1000):
     """Canonicalize A-form tensors (starting from flat lambdas) and return
     (A1, lams, Pc, Qc, iters) with A1 = Qc/Pc applied to ``tensors``: Pc[b]
     on link b's first leg (new = Pc^T old), Qc[b] on its second leg."""
     links, _ = cell_links(cell)
     g, lams, it, TR, TL = canonicalize(cell, tensors, None, tol, max_iter)
-    Pc = [TR[b] * np.sqrt(lams[b])[None, :] for b in range(len(links))]
-    Qc = [np.sqrt(lams[b])[:, None] * TL[b] for b in range(len(links))]
+    Pc, Qc = canonical_pq(TR, TL, lams)
     a1 = truncate(tensors, links, Pc, Qc)
     return a1, lams, Pc, Qc, it
 
