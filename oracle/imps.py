@@ -333,7 +333,11 @@ def canonicalize_a_form(sites, lams=None):
             if Pc[b][j, i] < 0:
                 Pc[b][:, i] = -Pc[b][:, i]
                 Qc[b][i, :] = -Qc[b][i, :]
-        # the scale is free too (Pc -> c Pc, Qc -> Qc / c): fix |Pc| = |Qc|
+        # the scale is free too: Pc and Qc are inverse up to a factor, and
+        # Pc -> c Pc, Qc -> Qc / c is removed by the site normalisation; fix
+        # Pc Qc = I and |Pc| = |Qc|
+        m = np.sqrt(Pc[b].shape[0] / np.trace(Pc[b] @ Qc[b]))
+        Pc[b], Qc[b] = Pc[b] * m, Qc[b] * m
         r = np.sqrt(np.linalg.norm(Qc[b]) / np.linalg.norm(Pc[b]))
         Pc[b], Qc[b] = Pc[b] * r, Qc[b] / r
     raw = [np.einsum("ia,asb,bj->isj", Qc[1], sites[0], Pc[0]),

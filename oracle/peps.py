@@ -295,14 +295,17 @@ def a_form(cell, gammas, lams):
 
 
 def canonical_pq(TR, TL, lams):
-    """Pc = TR sqrt(lambda), Qc = sqrt(lambda) TL per link, with the scale
-    left free by the canonical form (Pc -> c Pc, Qc -> Qc / c changes the
-    two tensors of a link by c and 1/c, which their normalisation removes)
-    fixed by |Pc|_F = |Qc|_F."""
+    """Pc = TR sqrt(lambda), Qc = sqrt(lambda) TL per link.  Without
+    truncation the two are inverse up to a factor (the iteration keeps
+    TR lambda TL proportional to the identity); the factor and the split of
+    scale between them, which the normalisation of the sites removes, are
+    fixed by Pc Qc = I and |Pc|_F = |Qc|_F."""
     Pc, Qc = [], []
     for b in range(len(TR)):
         p = TR[b] * np.sqrt(lams[b])[None, :]
         q = np.sqrt(lams[b])[:, None] * TL[b]
+        m = np.sqrt(p.shape[0] / np.trace(p @ q))
+        p, q = p * m, q * m
         r = np.sqrt(np.linalg.norm(q) / np.linalg.norm(p))
         Pc.append(p * r)
         Qc.append(q / r)
