@@ -157,12 +157,24 @@ enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2 };
  *   dt         time step; the iMPO of Eq. (iMPO1) (second-order Trotter)
  *   mode       TN_PLAIN: Theta = g A, environment = transfer-matrix fixed
  *              points of the Theta chain, truncation A = Q Theta P
- *              (Eq. (EqCanoPQ1)) on both bonds
+ *              (Eq. (EqCanoPQ1)) on both bonds.
+ *              TN_RECYCLE_BUILD: an environment step of the recycling scheme
+ *              (Sec. V B (i)-(iii)): A_0 is brought to canonical form, the
+ *              plain truncation of g A_0 is brought to canonical form
+ *              (Qc, Pc; sign rule on the columns of Pc), its gauge is fixed
+ *              against A_0 by the alternating Procrustes maximisation of the
+ *              fidelity (start: kappa = 0 blocks of P Pc and Qc Q), and the
+ *              renormalized gate G = U^T (Qc Q) g (P Pc) U is stored in
+ *              env1d; the new state is G A_0.  Needs chi <= 16.
+ *              TN_RECYCLE_APPLY: A <- G A with the stored G (no environment);
+ *              TN_EINVAL if no build step has stored one; lambda_out is not
+ *              written and trunc_err is 0
  *   env1d      device workspace of tn_env1d_size(chi, d) doubles, owned by
  *              the caller, zero-filled before the first step; carries warm
  *              starts between steps
  *   lambda_out device out [2][chi] (may be NULL): kept spectra of bonds 0
- *              (after site 0) and 1, unit l2 norm
+ *              (after site 0) and 1, unit l2 norm (after a build step: the
+ *              canonical spectra of the truncated state)
  *   tol        fixed-point tolerance
  *   trunc_err  host out: discarded weight summed over the two bonds
  *   energy_or_null host out (may be NULL): energy per site of the new state

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libitebd.so")
 
 TN_OK, TN_NOT_CONVERGED = 0, 1
 TN_FP64, TN_FP32, TN_BF16 = 0, 1, 2
+TN_PLAIN, TN_RECYCLE_BUILD, TN_RECYCLE_APPLY = 0, 1, 2
 _PREC = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "bondnet.h"
 #include "common.h"
 
 namespace {
@@ -448,10 +449,17 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
                     double h, double dt, int mode, double* env1d, double* lambda_out,
                     double tol, double* trunc_err, double* energy_or_null) {
   if (chi < 1 || d != 2 || !A || !env1d) TN_FAIL(ctx, TN_EINVAL, "bad itebd_step arguments");
-  if (mode != 0) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
+  if (mode < 0 || mode > 2) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
   const int kap = 2, n = kap * chi;
+  if (mode != 0 && n > 32)
+    TN_FAIL(ctx, TN_EINVAL, "recycling supports chi <= 16 (chi=%d)", chi);
   const size_t nn = (size_t)n * n, ndn = (size_t)n * d * n, cdc = (size_t)chi * d * chi;
-  TN_TRY(ws_reserve(ctx, (40 * nn + 8 * ndn + 16 * cdc) * 8 + (8 << 20)));
+  const size_t cc = (size_t)chi * chi;
+  const BondNet net = bondnet_chain2(d);
+  size_t extra = 0;
+  if (mode == 1)
+    extra = bondnet_canon_bytes(net, chi) + bondnet_gauge_bytes(net, chi) + (12 * cc + 4 * cdc) * 8;
+  TN_TRY(ws_reserve(ctx, (40 * nn + 8 * ndn + 16 * cdc) * 8 + extra + (8 << 20)));
   ws_reset(ctx);
   double hg[2][2][2][2];
   tfim_impo(J, h, dt, hg);
@@ -466,16 +474,72 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
   if (!tmp) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (itebd)");
   TN_HIP(ctx, hipMemcpyAsync(g, hg, 16 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   TN_HIP(ctx, hipMemsetAsync(errd, 0, sizeof(double), ctx->stream));
-  for (int s = 0; s < 2; ++s)
-    hipLaunchKernelGGL(impo_apply_kernel, dim3((unsigned)((ndn + 255) / 256)), dim3(256), 0,
-                       ctx->stream, g, A + s * cdc, th + s * ndn, chi, d, kap);
-  TN_HIP(ctx, hipGetLastError());
-  // warm starts of the fixed points live in env1d; flag slot 0 marks them valid
+  // env1d: warm fixed points [4 n^2], the renormalized gate's factors
+  // Lf [2][chi][n] and Rf [2][n][chi], then flags: slot 0 marks the fixed
+  // points valid, slot 1 the factors
+  double* Lf = env1d + 4 * nn;
+  double* Rf = Lf + 2 * (size_t)chi * n;
   double* flagp = env1d + env1d_doubles(chi, d) - 16;
-  double hflag = 0.0;
-  TN_HIP(ctx, hipMemcpyAsync(&hflag, flagp, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  double hflag[2] = {0.0, 0.0};
+  TN_HIP(ctx, hipMemcpyAsync(hflag, flagp, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  const int warm = hflag == 1.0 ? 1 : 0;
+  auto gate = [&](const double* src) -> int {
+    for (int s = 0; s < 2; ++s)
+      hipLaunchKernelGGL(impo_apply_kernel, dim3((unsigned)((ndn + 255) / 256)), dim3(256), 0,
+                         ctx->stream, g, src + s * cdc, th + s * ndn, chi, d, kap);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+  };
+  // site 0 sits between bond 1 (left) and bond 0 (right), site 1 the reverse:
+  // dst_0 = L[1] th_0 R[0], dst_1 = L[0] th_1 R[1], each of unit norm
+  auto truncate2 = [&](const double* Lm, const double* Rm, double* dst) -> int {
+    TN_TRY(sandwich(ctx, n, chi, d, Lm + 1 * n * chi, th, Rm, tmp, dst));
+    TN_TRY(sandwich(ctx, n, chi, d, Lm, th + ndn, Rm + 1 * n * chi, tmp, dst + cdc));
+    TN_TRY(frob_normalize(ctx, dst, cdc, nullptr));
+    TN_TRY(frob_normalize(ctx, dst + cdc, cdc, nullptr));
+    return TN_OK;
+  };
+  if (mode == 2) {
+    // recycled step: A <- G A with the stored factors (Sec. V B)
+    if (hflag[1] != 1.0)
+      TN_FAIL(ctx, TN_EINVAL, "no renormalized gate in env1d: run a TN_RECYCLE_BUILD step first");
+    TN_TRY(gate(A));
+    TN_TRY(truncate2(Lf, Rf, A));
+    if (energy_or_null) {
+      TN_TRY(energy_1d(ctx, chi, d, A, J, h, edev));
+      double he = 0.0;
+      TN_HIP(ctx, hipMemcpyAsync(&he, edev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      *energy_or_null = he;
+    } else {
+      TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (trunc_err) *trunc_err = 0.0;
+    return TN_OK;
+  }
+  double* a0 = A;  // the state the environment is computed for
+  double *a0c = nullptr, *tr = nullptr, *Pc = nullptr, *Qc = nullptr, *U = nullptr,
+         *l1 = nullptr, *a1 = nullptr;
+  if (mode == 1) {
+    a0c = ws_alloc<double>(ctx, 2 * cdc);
+    tr = ws_alloc<double>(ctx, 2 * cdc);
+    a1 = ws_alloc<double>(ctx, 2 * cdc);
+    Pc = ws_alloc<double>(ctx, 2 * cc);
+    Qc = ws_alloc<double>(ctx, 2 * cc);
+    U = ws_alloc<double>(ctx, 2 * cc);
+    l1 = ws_alloc<double>(ctx, 2 * (size_t)chi);
+    if (!l1) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (recycling)");
+    // the scheme starts from the canonical form of A_0 (Sec. V B (i))
+    const size_t mark = ctx->arena_off;
+    const int rc = bondnet_canonicalize(ctx, net, chi, A, 1e-14, 1000, nullptr, Pc, Qc, a0c,
+                                        nullptr);
+    if (rc < 0) return rc;
+    ctx->arena_off = mark;
+    a0 = a0c;
+  }
+  TN_TRY(gate(a0));
+  const int warm = hflag[0] == 1.0 ? 1 : 0;
   int tmi = 0;
   for (int b = 0; b < 2; ++b) {
     const size_t mark = ctx->arena_off;
@@ -487,14 +551,33 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
   }
   const double one = 1.0;
   TN_HIP(ctx, hipMemcpyAsync(flagp, &one, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  // site 0 sits between bond 1 (left) and bond 0 (right), site 1 the reverse
-  TN_TRY(sandwich(ctx, n, chi, d, Q + 1 * n * chi, th, P, tmp, A));
-  TN_TRY(sandwich(ctx, n, chi, d, Q, th + ndn, P + 1 * n * chi, tmp, A + cdc));
-  TN_TRY(frob_normalize(ctx, A, cdc, nullptr));
-  TN_TRY(frob_normalize(ctx, A + cdc, cdc, nullptr));
-  if (lambda_out)
-    TN_HIP(ctx, hipMemcpyAsync(lambda_out, lam, 2 * chi * sizeof(double), hipMemcpyDeviceToDevice,
+  if (mode == 0) {
+    TN_TRY(truncate2(Q, P, A));
+    if (lambda_out)
+      TN_HIP(ctx, hipMemcpyAsync(lambda_out, lam, 2 * chi * sizeof(double),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    // truncated state, its canonical form, gauge fix against A_0 and the
+    // renormalized gate G = U^T (Qc Q) g (P Pc) U (Sec. V B (i)-(iii))
+    TN_TRY(truncate2(Q, P, tr));
+    size_t mark = ctx->arena_off;
+    int rc = bondnet_canonicalize(ctx, net, chi, tr, 1e-14, 1000, l1, Pc, Qc, a1, nullptr);
+    if (rc < 0) return rc;
+    ctx->arena_off = mark;
+    TN_TRY(recycle_gauge_start(ctx, 2, n, chi, kap, P, Q, Pc, Qc, U));
+    double F = 0.0;
+    rc = bondnet_gauge_fix(ctx, net, chi, a0c, a1, U, 1e-12, 1000, &F, nullptr);
+    if (rc < 0) return rc;
+    ctx->arena_off = mark;
+    TN_TRY(recycle_factors(ctx, 2, n, chi, P, Q, Pc, Qc, U, Rf, Lf));
+    TN_HIP(ctx, hipMemcpyAsync(flagp + 1, &one, sizeof(double), hipMemcpyHostToDevice,
                                ctx->stream));
+    // the new state is G A_0
+    TN_TRY(truncate2(Lf, Rf, A));
+    if (lambda_out)
+      TN_HIP(ctx, hipMemcpyAsync(lambda_out, l1, 2 * chi * sizeof(double),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  }
   if (energy_or_null) TN_TRY(energy_1d(ctx, chi, d, A, J, h, edev));
   double he = 0.0, herr = 0.0;
   TN_HIP(ctx, hipMemcpyAsync(&herr, errd, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <vector>
 
+#include "bondnet.h"
 #include "common.h"
 
 int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
@@ -152,8 +153,8 @@ struct LegMats {
 
 int apply_legs(tn_ctx* ctx, const double* in, double* out, TDims din, const LegMats& lm,
                double* t1, double* t2, TDims* dout) {
-  int todo[4], nt = 0;
-  for (int ax = 1; ax <= 4; ++ax)
+  int todo[5], nt = 0;
+  for (int ax = 0; ax <= 4; ++ax)
     if (lm.m[ax]) todo[nt++] = ax;
   TDims cur = din;
   const double* src = in;
@@ -470,17 +471,53 @@ __global__ void fill_kernel(double* __restrict__ X, long long n, double v) {
   if (t < n) X[t] = v;
 }
 
-// Pc = TR diag(sqrt lam), Qc = diag(sqrt lam) TL (per link, n x n)
-__global__ void canon_pq_kernel(int nl, int n, const double* __restrict__ TR,
-                                const double* __restrict__ TL, const double* __restrict__ lam,
-                                double* __restrict__ Pc, double* __restrict__ Qc) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nl * n * n) return;
-  const int b = (int)(t / ((long long)n * n));
-  const int e = (int)(t % ((long long)n * n));
-  const int i = e / n, j = e % n;
-  Pc[t] = TR[t] * sqrt(lam[(long long)b * n + j]);
-  Qc[t] = sqrt(lam[(long long)b * n + i]) * TL[t];
+// Pc = TR diag(sqrt lam), Qc = diag(sqrt lam) TL per link (one block each),
+// then the sign rule on the columns of Pc with the rows of Qc flipping along
+// and the scale fixed by |Pc|_F = |Qc|_F: the canonical gauge is unique up
+// to these signs and scale, so this makes it independent of the path of the
+// iteration
+__global__ __launch_bounds__(256) void canon_pq_kernel(int n, const double* __restrict__ TR,
+                                                       const double* __restrict__ TL,
+                                                       const double* __restrict__ lam,
+                                                       double* __restrict__ Pc,
+                                                       double* __restrict__ Qc) {
+  const int b = blockIdx.x;
+  const long long nn = (long long)n * n;
+  __shared__ double p[MAXN * MAXN], red[4];
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    p[e] = TR[b * nn + e] * sqrt(lam[(long long)b * n + j]);
+    Qc[b * nn + e] = sqrt(lam[(long long)b * n + i]) * TL[b * nn + e];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double sg = column_sign(p, n, j, red);
+    if (sg < 0.0)
+      for (int i = threadIdx.x; i < n; i += 256) {
+        p[i * n + j] = -p[i * n + j];
+        Qc[b * nn + (long long)j * n + i] = -Qc[b * nn + (long long)j * n + i];
+      }
+    __syncthreads();
+  }
+  // the scale is free as well: Pc and Qc are inverse up to a factor, and
+  // Pc -> c Pc, Qc -> Qc / c is removed by the site normalisation; fix
+  // Pc Qc = I (through its trace) and |Pc|_F = |Qc|_F
+  double np2 = 0.0, nq2 = 0.0, tr = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    np2 += p[e] * p[e];
+    nq2 += Qc[b * nn + e] * Qc[b * nn + e];
+    tr += p[e] * Qc[b * nn + (long long)j * n + i];
+  }
+  np2 = block_sum256(np2, red);
+  nq2 = block_sum256(nq2, red);
+  tr = block_sum256(tr, red);
+  const double m = sqrt((double)n / tr);
+  const double r = sqrt(sqrt(nq2) / sqrt(np2));
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    Pc[b * nn + e] = p[e] * m * r;
+    Qc[b * nn + e] *= m / r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -648,6 +685,21 @@ __global__ void symmetrize_kernel(const double* __restrict__ N, double* __restri
   if (t >= (long long)m * m) return;
   const int i = (int)(t / m), j = (int)(t % m);
   Ns[t] = 0.5 * (N[t] + N[(long long)j * m + i]);
+}
+
+// The normalised boundary leaves the overall sign of N free: flip N so that
+// <I|N|I> = sum_{i,a} N[i][i][a][a] > 0 (one workgroup)
+__global__ __launch_bounds__(256) void n_sign_kernel(double* __restrict__ N, int n) {
+  __shared__ double red[4];
+  const long long n2 = (long long)n * n, n4 = n2 * n2;
+  double t = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, a = e % n;
+    t += N[(long long)(i * n + i) * n2 + a * n + a];
+  }
+  t = block_sum256(t, red);
+  if (t < 0.0)
+    for (long long e = threadIdx.x; e < n4; e += 256) N[e] = -N[e];
 }
 
 // tb[i][j] = sum_a N[i][j][a][a]; t = <I|N|I> = sum_{i,a} N[i][i][a][a]
@@ -847,48 +899,126 @@ __global__ void tfim2d_energy_kernel(int npos, const double* __restrict__ rho1,
 
 inline unsigned nblk(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-// ---------------------------------------------------------------------------
-// canonicalisation driver
-// ---------------------------------------------------------------------------
-
-struct CanonOut {
-  double* lam;  // [nl][n]
-  double* TR;   // [nl][n][n]
-  double* TL;
-  int iters;
-};
-
-size_t canon_bytes(int nsite, int nl, int d, int n) {
-  const size_t tsz = (size_t)d * n * n * n * n;
-  size_t b = 0;
-  auto add = [&](size_t c) { b += ((c * 8 + 255) / 256) * 256; };
-  add(nsite * tsz);      // gammas
-  add(2 * tsz);          // ping-pong
-  add(3 * tsz);          // apply scratch
-  add(nl * n);           // lam
-  for (int k = 0; k < 4; ++k) add((size_t)nl * n * n);      // TR TL R L
-  add(2 * (size_t)nl * n * n);                            // grams
-  add(2 * (size_t)nl * n * n + 2 * (size_t)nl * n);       // W S
-  add(3 * (size_t)nl * n * n + (size_t)nl * n);           // M, Um, Vm, Sm
-  add(nl + 1);
-  add(4 * (size_t)nl * n * n);  // jacobi work
-  return b + (1 << 20);
+int check_bond(tn_ctx* ctx, int n, const char* what) {
+  if (n < 1 || n > MAXN) TN_FAIL(ctx, TN_EINVAL, "%s = %d outside [1, %d]", what, n, MAXN);
+  return TN_OK;
 }
 
-// Iterates the canonical-form update on the gammas (initialised to `A`) until
-// the spectra move by less than tol (max norm), as in steps (i)-(iii) of
-// Sec. IV A applied to every link at once.
-int canonicalize_run(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n, const double* A,
-                     double tol, int max_iter, CanonOut& out) {
-  const int nl = L.nl;
-  const long long tsz = (long long)d * n * n * n * n;
+BondNet net_of_cell(const CellLinks& L, int nsite, int d) {
+  BondNet net;
+  net.nsite = nsite;
+  net.nl = L.nl;
+  net.link.assign(nsite, {-1, -1, -1, -1, -1});
+  net.ext.assign(nsite, {d, 0, 0, 0, 0});
+  for (int s = 0; s < nsite; ++s)
+    for (int ax = 1; ax <= 4; ++ax) net.link[s][ax] = L.leg_link[s][ax];
+  for (int b = 0; b < L.nl; ++b) {
+    net.s1.push_back(L.s1[b]);
+    net.a1.push_back(L.l1[b]);
+    net.s2.push_back(L.s2[b]);
+    net.a2.push_back(L.l2[b]);
+  }
+  return net;
+}
+
+TDims net_dims(const BondNet& net, int s, int n) {
+  TDims t;
+  for (int k = 0; k < 5; ++k) t.n[k] = net.link[s][k] >= 0 ? n : net.ext[s][k];
+  return t;
+}
+
+long long net_max_size(const BondNet& net, int n) {
+  long long m = 0;
+  for (int s = 0; s < net.nsite; ++s) m = std::max(m, net.size(s, n));
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// network-level canonical form, truncation and gauge fixing
+// ---------------------------------------------------------------------------
+
+BondNet bondnet_chain2(int d) {
+  BondNet net;
+  net.nsite = 2;
+  net.nl = 2;
+  net.link = {{1, -1, 0, -1, -1}, {0, -1, 1, -1, -1}};
+  net.ext = {{0, d, 0, 1, 1}, {0, d, 0, 1, 1}};
+  net.s1 = {0, 1};
+  net.a1 = {2, 2};
+  net.s2 = {1, 0};
+  net.a2 = {0, 0};
+  return net;
+}
+
+size_t bondnet_canon_bytes(const BondNet& net, int n) {
+  const size_t tsz = (size_t)net_max_size(net, n), nl = net.nl, nn = (size_t)n * n;
+  size_t b = 0;
+  auto add = [&](size_t c) { b += ((c * 8 + 255) / 256) * 256; };
+  add(net.nsite * tsz);  // gammas
+  add(tsz);              // ping-pong
+  add(2 * tsz);          // apply scratch
+  add(nl * n);           // lam
+  for (int k = 0; k < 4; ++k) add(nl * nn);  // TR TL R L
+  add(2 * nl * nn);                          // grams
+  add(2 * nl * nn + 2 * nl * n);             // W S
+  add(3 * nl * nn + nl * n);                 // M, Um, Vm, Sm
+  add(nl + 1);
+  return b + (1 << 16);
+}
+
+size_t bondnet_gauge_bytes(const BondNet& net, int n) {
+  const size_t tsz = (size_t)net_max_size(net, n), nn = (size_t)n * n;
+  size_t b = 0;
+  auto add = [&](size_t c) { b += ((c * 8 + 255) / 256) * 256; };
+  add(2 * tsz);
+  add(2 * tsz);
+  add(tsz);
+  for (int k = 0; k < 3; ++k) add(nn);
+  add(n);
+  add(2 * net.nsite + 2);
+  return b + (1 << 16);
+}
+
+int bondnet_truncate(tn_ctx* ctx, const BondNet& net, int n_in, int n_out, const double* in,
+                     const double* P, const double* Q, double* out, double* sc) {
+  const long long per = (long long)n_in * n_out;
+  long long oin = 0, oout = 0;
+  const long long tmax = net_max_size(net, n_in);
+  for (int s = 0; s < net.nsite; ++s) {
+    LegMats lm;
+    for (int ax = 0; ax <= 4; ++ax) {
+      const int b = net.link[s][ax];
+      if (b < 0) continue;
+      const bool first = net.first_end(s, ax);
+      lm.m[ax] = (first ? P : Q) + b * per;
+      lm.trans[ax] = first ? 1 : 0;
+      lm.nnew[ax] = n_out;
+    }
+    TN_TRY(apply_legs(ctx, in + oin, out + oout, net_dims(net, s, n_in), lm, sc, sc + tmax,
+                      nullptr));
+    TN_TRY(frob_normalize(ctx, out + oout, net.size(s, n_out), nullptr));
+    oin += net.size(s, n_in);
+    oout += net.size(s, n_out);
+  }
+  return TN_OK;
+}
+
+int bondnet_canonicalize(tn_ctx* ctx, const BondNet& net, int n, const double* A, double tol,
+                         int max_iter, double* lams, double* Pc, double* Qc, double* Aout,
+                         int* iters) {
+  const int nl = net.nl, nsite = net.nsite;
+  const long long tmax = net_max_size(net, n);
   const long long nn = (long long)n * n;
-  double* gam = ws_alloc<double>(ctx, nsite * tsz);
-  double* pp = ws_alloc<double>(ctx, 2 * tsz);
-  double* sc = ws_alloc<double>(ctx, 3 * tsz);
-  out.lam = ws_alloc<double>(ctx, nl * n);
-  out.TR = ws_alloc<double>(ctx, nl * nn);
-  out.TL = ws_alloc<double>(ctx, nl * nn);
+  std::vector<long long> off(nsite + 1, 0);
+  for (int s = 0; s < nsite; ++s) off[s + 1] = off[s] + net.size(s, n);
+  double* gam = ws_alloc<double>(ctx, off[nsite]);
+  double* pp = ws_alloc<double>(ctx, tmax);
+  double* sc = ws_alloc<double>(ctx, 2 * tmax);
+  double* lam = ws_alloc<double>(ctx, nl * n);
+  double* TR = ws_alloc<double>(ctx, nl * nn);
+  double* TL = ws_alloc<double>(ctx, nl * nn);
   double* Rm = ws_alloc<double>(ctx, nl * nn);
   double* Lm = ws_alloc<double>(ctx, nl * nn);
   double* G = ws_alloc<double>(ctx, 2 * nl * nn);
@@ -900,14 +1030,13 @@ int canonicalize_run(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n, c
   double* Sm = ws_alloc<double>(ctx, nl * n);
   double* dl = ws_alloc<double>(ctx, nl + 1);
   if (!dl) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (canonical form)");
-  TN_HIP(ctx, hipMemcpyAsync(gam, A, nsite * tsz * sizeof(double), hipMemcpyDeviceToDevice,
+  TN_HIP(ctx, hipMemcpyAsync(gam, A, off[nsite] * sizeof(double), hipMemcpyDeviceToDevice,
                              ctx->stream));
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(nl * n)), dim3(256), 0, ctx->stream, out.lam,
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(nl * n)), dim3(256), 0, ctx->stream, lam,
                      (long long)nl * n, 1.0 / sqrt((double)n));
-  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, out.TR, nl, n);
-  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, out.TL, nl, n);
+  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, TR, nl, n);
+  hipLaunchKernelGGL(eye_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, TL, nl, n);
   TN_HIP(ctx, hipGetLastError());
-  const TDims dm = dims5(d, n, n, n, n);
   int it = 0;
   double delta = INFINITY;
   for (it = 1; it <= max_iter; ++it) {
@@ -915,41 +1044,43 @@ int canonicalize_run(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n, c
     std::vector<GramJob> jobs;
     for (int side = 0; side < 2; ++side)
       for (int b = 0; b < nl; ++b) {
-        const int s = side ? L.s2[b] : L.s1[b];
-        const int ax = side ? L.l2[b] : L.l1[b];
+        const int s = side ? net.s2[b] : net.s1[b];
+        const int ax = side ? net.a2[b] : net.a1[b];
         GramJob j;
         std::memset(&j, 0, sizeof(j));
-        j.A[0] = j.B[0] = gam + s * tsz;
+        j.A[0] = j.B[0] = gam + off[s];
         j.nterm = 1;
-        j.dims = dm;
+        j.dims = net_dims(net, s, n);
         j.ax[0] = ax;
-        for (int k = 1; k <= 4; ++k)
-          j.lam[k] = (k == ax) ? nullptr : out.lam + (long long)L.leg_link[s][k] * n;
+        for (int k = 0; k < 5; ++k)
+          j.lam[k] = (k == ax || net.link[s][k] < 0) ? nullptr
+                                                       : lam + (long long)net.link[s][k] * n;
         j.out = G + (side * nl + b) * nn;
         jobs.push_back(j);
       }
     TN_TRY(run_grams(ctx, jobs));
     TN_TRY(jacobi_svd(ctx, 2 * nl, n, n, G, n, nn, W, n, nn, S, n, nullptr, 0, 0));
-    hipLaunchKernelGGL(canon_m_kernel, dim3(nl), dim3(256), 0, ctx->stream, nl, n, W, S, out.lam,
-                       M);
+    hipLaunchKernelGGL(canon_m_kernel, dim3(nl), dim3(256), 0, ctx->stream, nl, n, W, S, lam, M);
     TN_TRY(jacobi_svd(ctx, nl, n, n, M, n, nn, Um, n, nn, Sm, n, Vm, n, nn));
     hipLaunchKernelGGL(canon_update_kernel, dim3(nl), dim3(256), 0, ctx->stream, nl, n, W, S, Um,
-                       Sm, Vm, out.lam, out.TR, out.TL, Rm, Lm, dl);
+                       Sm, Vm, lam, TR, TL, Rm, Lm, dl);
     TN_HIP(ctx, hipGetLastError());
     // gammas: first end new = r^T old, second end new = l old
     for (int s = 0; s < nsite; ++s) {
       LegMats lm;
-      for (int ax = 1; ax <= 4; ++ax) {
-        const int b = L.leg_link[s][ax];
-        const bool first = (L.s1[b] == s && L.l1[b] == ax);
+      for (int ax = 0; ax <= 4; ++ax) {
+        const int b = net.link[s][ax];
+        if (b < 0) continue;
+        const bool first = net.first_end(s, ax);
         lm.m[ax] = (first ? Rm : Lm) + b * nn;
         lm.trans[ax] = first ? 1 : 0;
         lm.nnew[ax] = n;
       }
-      TN_TRY(apply_legs(ctx, gam + s * tsz, pp, dm, lm, sc, sc + tsz, nullptr));
-      TN_HIP(ctx, hipMemcpyAsync(gam + s * tsz, pp, tsz * sizeof(double),
-                                 hipMemcpyDeviceToDevice, ctx->stream));
-      TN_TRY(frob_normalize(ctx, gam + s * tsz, tsz, nullptr));
+      const long long ts = net.size(s, n);
+      TN_TRY(apply_legs(ctx, gam + off[s], pp, net_dims(net, s, n), lm, sc, sc + tmax, nullptr));
+      TN_HIP(ctx, hipMemcpyAsync(gam + off[s], pp, ts * sizeof(double), hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+      TN_TRY(frob_normalize(ctx, gam + off[s], ts, nullptr));
     }
     hipLaunchKernelGGL(max_of_kernel, dim3(1), dim3(1), 0, ctx->stream, dl, nl, dl + nl);
     TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dl + nl, sizeof(double), hipMemcpyDeviceToHost,
@@ -959,36 +1090,120 @@ int canonicalize_run(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n, c
     if (!std::isfinite(delta)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite canonical-form spectra");
     if (delta < tol) break;
   }
-  out.iters = std::min(it, max_iter);
+  hipLaunchKernelGGL(canon_pq_kernel, dim3(nl), dim3(256), 0, ctx->stream, n, TR, TL, lam, Pc, Qc);
+  TN_HIP(ctx, hipGetLastError());
+  if (lams)
+    TN_HIP(ctx, hipMemcpyAsync(lams, lam, (size_t)nl * n * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  if (Aout) TN_TRY(bondnet_truncate(ctx, net, n, n, A, Pc, Qc, Aout, sc));
+  if (iters) *iters = std::min(it, max_iter);
   return delta < tol ? TN_OK : TN_NOT_CONVERGED;
 }
 
-int check_bond(tn_ctx* ctx, int n, const char* what) {
-  if (n < 1 || n > MAXN) TN_FAIL(ctx, TN_EINVAL, "%s = %d outside [1, %d]", what, n, MAXN);
-  return TN_OK;
+int bondnet_gauge_fix(tn_ctx* ctx, const BondNet& net, int n, const double* a_ref,
+                      const double* a_new, double* U, double tol, int max_iter, double* fidelity,
+                      int* iters) {
+  const int nl = net.nl, nsite = net.nsite;
+  if (nsite > 30) TN_FAIL(ctx, TN_EINVAL, "gauge fixing handles at most 30 site tensors");
+  const long long tmax = net_max_size(net, n), nn = (long long)n * n;
+  std::vector<long long> off(nsite + 1, 0);
+  for (int s = 0; s < nsite; ++s) off[s + 1] = off[s] + net.size(s, n);
+  double* rest = ws_alloc<double>(ctx, 2 * tmax);
+  double* sc = ws_alloc<double>(ctx, 2 * tmax);
+  double* full = ws_alloc<double>(ctx, tmax);
+  double* K = ws_alloc<double>(ctx, nn);
+  double* Wk = ws_alloc<double>(ctx, nn);
+  double* Vk = ws_alloc<double>(ctx, nn);
+  double* Sk = ws_alloc<double>(ctx, n);
+  double* dots = ws_alloc<double>(ctx, 2 * nsite + 2);
+  if (!dots) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (gauge fix)");
+  // norms of both sets (fixed)
+  for (int s = 0; s < nsite; ++s) {
+    const long long ts = net.size(s, n);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_ref + off[s],
+                       a_ref + off[s], ts, dots + nsite + s);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + off[s],
+                       a_new + off[s], ts, dots + s);
+  }
+  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, 2 * nsite * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double den = 0.0;
+  for (int s = 0; s < nsite; ++s)
+    den += sqrt(ctx->host_scratch[s]) * sqrt(ctx->host_scratch[nsite + s]);
+  if (!(den > 0.0)) TN_FAIL(ctx, TN_EINVAL, "zero site tensor");
+  // U applied as new = U old on every link leg (optionally all but one)
+  auto legs_of = [&](int s, int skip) {
+    LegMats lm;
+    for (int ax = 0; ax <= 4; ++ax) {
+      const int b = net.link[s][ax];
+      if (b < 0 || ax == skip) continue;
+      lm.m[ax] = U + b * nn;
+      lm.nnew[ax] = n;
+    }
+    return lm;
+  };
+  auto fid = [&](double* F) -> int {
+    for (int s = 0; s < nsite; ++s) {
+      TN_TRY(apply_legs(ctx, a_ref + off[s], full, net_dims(net, s, n), legs_of(s, -1), sc,
+                        sc + tmax, nullptr));
+      hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + off[s], full,
+                         net.size(s, n), dots + s);
+    }
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, nsite * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double num = 0.0;
+    for (int s = 0; s < nsite; ++s) num += ctx->host_scratch[s];
+    *F = num / den;
+    return TN_OK;
+  };
+  double F = 0.0;
+  TN_TRY(fid(&F));
+  int it = 0;
+  double dF = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    // one Procrustes step per link, the other links' factors held fixed
+    for (int b = 0; b < nl; ++b) {
+      GramJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.nterm = 2;
+      j.out = K;
+      for (int side = 0; side < 2; ++side) {
+        const int s = side ? net.s2[b] : net.s1[b];
+        const int leg = side ? net.a2[b] : net.a1[b];
+        TN_TRY(apply_legs(ctx, a_ref + off[s], rest + side * tmax, net_dims(net, s, n),
+                          legs_of(s, leg), sc, sc + tmax, nullptr));
+        j.A[side] = a_new + off[s];
+        j.B[side] = rest + side * tmax;
+        j.ax[side] = leg;
+        j.dims = net_dims(net, s, n);
+      }
+      if (net.size(net.s1[b], n) != net.size(net.s2[b], n))
+        TN_FAIL(ctx, TN_EINVAL, "internal: link ends of different tensor sizes");
+      TN_TRY(run_grams(ctx, {j}));
+      TN_TRY(jacobi_svd(ctx, 1, n, n, K, n, nn, Wk, n, nn, Sk, n, Vk, n, nn));
+      hipLaunchKernelGGL(polar_kernel, dim3(nblk(nn)), dim3(256), 0, ctx->stream, n, Wk, Vk,
+                         U + b * nn);
+      TN_HIP(ctx, hipGetLastError());
+    }
+    double Fn = 0.0;
+    TN_TRY(fid(&Fn));
+    if (!std::isfinite(Fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite fidelity");
+    dF = fabs(Fn - F);
+    F = Fn;
+    if (dF < tol) break;
+  }
+  if (fidelity) *fidelity = F;
+  if (iters) *iters = std::min(it, max_iter);
+  return dF < tol ? TN_OK : TN_NOT_CONVERGED;
 }
 
-// A~ = legs of `in` (bond n_in) times P (first ends) and Q (second ends), then
-// unit Frobenius norm per site
+namespace {
+
 int truncate_sites(tn_ctx* ctx, const CellLinks& L, int nsite, int d, int n_in, int n_out,
                    const double* in, const double* P, const double* Q, double* out, double* sc) {
-  const long long tin = (long long)d * n_in * n_in * n_in * n_in;
-  const long long tout = (long long)d * n_out * n_out * n_out * n_out;
-  const long long per = (long long)n_in * n_out;
-  for (int s = 0; s < nsite; ++s) {
-    LegMats lm;
-    for (int ax = 1; ax <= 4; ++ax) {
-      const int b = L.leg_link[s][ax];
-      const bool first = (L.s1[b] == s && L.l1[b] == ax);
-      lm.m[ax] = (first ? P : Q) + b * per;
-      lm.trans[ax] = first ? 1 : 0;
-      lm.nnew[ax] = n_out;
-    }
-    TN_TRY(apply_legs(ctx, in + s * tin, out + s * tout, dims5(d, n_in, n_in, n_in, n_in), lm, sc,
-                      sc + tin, nullptr));
-    TN_TRY(frob_normalize(ctx, out + s * tout, tout, nullptr));
-  }
-  return TN_OK;
+  return bondnet_truncate(ctx, net_of_cell(L, nsite, d), n_in, n_out, in, P, Q, out, sc);
 }
 
 }  // namespace
@@ -1062,23 +1277,18 @@ int ipeps_canonicalize_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* c
   if (d < 1 || !A || !P || !Q) TN_FAIL(ctx, TN_EINVAL, "null tensor argument");
   if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
   if (Aout && Dkeep != D) TN_FAIL(ctx, TN_EINVAL, "A_out needs the full bond (Dkeep = D)");
+  const BondNet net = net_of_cell(L, nsite, d);
   const int nl = L.nl;
   const long long nn = (long long)D * D;
-  TN_TRY(ws_reserve(ctx, canon_bytes(nsite, nl, d, D) +
-                             (2 * nl * nn + 2LL * d * D * D * D * D) * sizeof(double)));
+  TN_TRY(ws_reserve(ctx, bondnet_canon_bytes(net, D) + 2 * nl * nn * sizeof(double) +
+                             (1 << 20)));
   ws_reset(ctx);
-  CanonOut co;
-  const int rc = canonicalize_run(ctx, L, nsite, d, D, A, tol, max_iter, co);
-  if (rc < 0) return rc;
   double* Pc = ws_alloc<double>(ctx, nl * nn);
   double* Qc = ws_alloc<double>(ctx, nl * nn);
   if (!Qc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
-  hipLaunchKernelGGL(canon_pq_kernel, dim3(nblk(nl * nn)), dim3(256), 0, ctx->stream, nl, D,
-                     co.TR, co.TL, co.lam, Pc, Qc);
-  TN_HIP(ctx, hipGetLastError());
-  if (lams)
-    TN_HIP(ctx, hipMemcpyAsync(lams, co.lam, (size_t)nl * D * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
+  int it = 0;
+  const int rc = bondnet_canonicalize(ctx, net, D, A, tol, max_iter, lams, Pc, Qc, Aout, &it);
+  if (rc < 0) return rc;
   // kept columns of Pc and rows of Qc
   TN_HIP(ctx, hipMemcpy2DAsync(P, Dkeep * sizeof(double), Pc, D * sizeof(double),
                                Dkeep * sizeof(double), (size_t)nl * D, hipMemcpyDeviceToDevice,
@@ -1087,14 +1297,8 @@ int ipeps_canonicalize_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* c
     TN_HIP(ctx, hipMemcpyAsync(Q + (long long)b * Dkeep * D, Qc + b * nn,
                                (size_t)Dkeep * D * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
-  if (Aout) {
-    const long long tsz = (long long)d * D * D * D * D;
-    double* sc = ws_alloc<double>(ctx, 2 * tsz);
-    if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
-    TN_TRY(truncate_sites(ctx, L, nsite, d, D, D, A, Pc, Qc, Aout, sc));
-  }
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (iters) *iters = co.iters;
+  if (iters) *iters = it;
   return rc;
 }
 
@@ -1106,98 +1310,10 @@ int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int 
   TN_TRY(check_bond(ctx, D, "bond"));
   if (d < 1 || !a_ref || !a_new || !U) TN_FAIL(ctx, TN_EINVAL, "null tensor argument");
   if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
-  if (nsite > 30) TN_FAIL(ctx, TN_EINVAL, "gauge_fix handles at most 30 site tensors");
-  const int nl = L.nl;
-  const long long tsz = (long long)d * D * D * D * D, nn = (long long)D * D;
-  TN_TRY(ws_reserve(ctx, (6 * tsz + 4 * nn + 2 * nsite + 64 + 4 * nn) * sizeof(double) +
-                             (1 << 20)));
+  const BondNet net = net_of_cell(L, nsite, d);
+  TN_TRY(ws_reserve(ctx, bondnet_gauge_bytes(net, D) + (1 << 20)));
   ws_reset(ctx);
-  double* rest = ws_alloc<double>(ctx, 2 * tsz);
-  double* sc = ws_alloc<double>(ctx, 2 * tsz);
-  double* full = ws_alloc<double>(ctx, 2 * tsz);
-  double* K = ws_alloc<double>(ctx, nn);
-  double* Wk = ws_alloc<double>(ctx, nn);
-  double* Vk = ws_alloc<double>(ctx, nn);
-  double* Sk = ws_alloc<double>(ctx, D);
-  double* dots = ws_alloc<double>(ctx, 2 * nsite + 2);
-  if (!dots) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (gauge fix)");
-  const TDims dm = dims5(d, D, D, D, D);
-  // norms of the references (fixed)
-  for (int s = 0; s < nsite; ++s) {
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_ref + s * tsz,
-                       a_ref + s * tsz, tsz, dots + nsite + s);
-    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + s * tsz,
-                       a_new + s * tsz, tsz, dots + s);
-  }
-  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, 2 * nsite * sizeof(double),
-                             hipMemcpyDeviceToHost, ctx->stream));
-  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  double den = 0.0;
-  for (int s = 0; s < nsite; ++s)
-    den += sqrt(ctx->host_scratch[s]) * sqrt(ctx->host_scratch[nsite + s]);
-  if (!(den > 0.0)) TN_FAIL(ctx, TN_EINVAL, "zero site tensor");
-  auto fid = [&](double* F) -> int {
-    for (int s = 0; s < nsite; ++s) {
-      LegMats lm;
-      for (int ax = 1; ax <= 4; ++ax) {
-        lm.m[ax] = U + L.leg_link[s][ax] * nn;
-        lm.nnew[ax] = D;
-      }
-      TN_TRY(apply_legs(ctx, a_ref + s * tsz, full, dm, lm, sc, sc + tsz, nullptr));
-      hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, ctx->stream, a_new + s * tsz, full,
-                         tsz, dots + s);
-    }
-    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, dots, nsite * sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    double num = 0.0;
-    for (int s = 0; s < nsite; ++s) num += ctx->host_scratch[s];
-    *F = num / den;
-    return TN_OK;
-  };
-  double F = 0.0;
-  TN_TRY(fid(&F));
-  int it = 0;
-  double dF = INFINITY;
-  for (it = 1; it <= max_iter; ++it) {
-    // one Procrustes step per link, the other links' factors held fixed
-    for (int b = 0; b < nl; ++b) {
-      GramJob j;
-      std::memset(&j, 0, sizeof(j));
-      j.nterm = 2;
-      j.dims = dm;
-      j.out = K;
-      for (int side = 0; side < 2; ++side) {
-        const int s = side ? L.s2[b] : L.s1[b];
-        const int leg = side ? L.l2[b] : L.l1[b];
-        LegMats lm;
-        for (int ax = 1; ax <= 4; ++ax) {
-          if (ax == leg) continue;
-          lm.m[ax] = U + L.leg_link[s][ax] * nn;
-          lm.nnew[ax] = D;
-        }
-        TN_TRY(apply_legs(ctx, a_ref + s * tsz, rest + side * tsz, dm, lm, sc, sc + tsz,
-                          nullptr));
-        j.A[side] = a_new + s * tsz;
-        j.B[side] = rest + side * tsz;
-        j.ax[side] = leg;
-      }
-      TN_TRY(run_grams(ctx, {j}));
-      TN_TRY(jacobi_svd(ctx, 1, D, D, K, D, nn, Wk, D, nn, Sk, D, Vk, D, nn));
-      hipLaunchKernelGGL(polar_kernel, dim3(nblk(nn)), dim3(256), 0, ctx->stream, D, Wk, Vk,
-                         U + b * nn);
-      TN_HIP(ctx, hipGetLastError());
-    }
-    double Fn = 0.0;
-    TN_TRY(fid(&Fn));
-    if (!std::isfinite(Fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite fidelity");
-    dF = fabs(Fn - F);
-    F = Fn;
-    if (dF < tol) break;
-  }
-  if (fidelity) *fidelity = F;
-  if (iters) *iters = std::min(it, max_iter);
-  return dF < tol ? TN_OK : TN_NOT_CONVERGED;
+  return bondnet_gauge_fix(ctx, net, D, a_ref, a_new, U, tol, max_iter, fidelity, iters);
 }
 
 namespace {
@@ -1295,6 +1411,7 @@ struct BondEnv {
     TN_TRY(tc_run(ctx, cN, L1, L2, N, 1.0, 0.0));
     const long long n4 = nn_ * nn_ * nn_ * nn_;
     hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(n4)), dim3(256), 0, ctx->stream, N, Ns, n * n);
+    hipLaunchKernelGGL(n_sign_kernel, dim3(1), dim3(256), 0, ctx->stream, Ns, n);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
   }
@@ -1433,10 +1550,7 @@ int fu_renormalized_gate_impl(tn_ctx* ctx, int nlink, int Dk, int D, const doubl
                               double* Rf, double* Lf) {
   if (nlink < 1 || Dk < 1 || D < 1 || D > Dk || !P || !Q || !Pc || !Qc || !U || !Rf || !Lf)
     TN_FAIL(ctx, TN_EINVAL, "bad fu_renormalized_gate arguments");
-  const long long tot = 2LL * nlink * Dk * D;
-  hipLaunchKernelGGL(renorm_gate_kernel, dim3(nblk(tot)), dim3(256), 0, ctx->stream, nlink, Dk, D,
-                     P, Q, Pc, Qc, U, Rf, Lf);
-  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(recycle_factors(ctx, nlink, Dk, D, P, Q, Pc, Qc, U, Rf, Lf));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
 }
@@ -1517,6 +1631,36 @@ __global__ __launch_bounds__(256) void gauge_start_kernel(int Dk, int D, int kap
 
 }  // namespace
 
+int recycle_gauge_start(tn_ctx* ctx, int nl, int Dk, int D, int kappa, const double* P,
+                        const double* Q, const double* Pc, const double* Qc, double* U0) {
+  const long long dd = (long long)D * D;
+  const size_t mark = ctx->arena_off;
+  double* K = ws_alloc<double>(ctx, nl * dd);
+  double* W = ws_alloc<double>(ctx, nl * dd);
+  double* V = ws_alloc<double>(ctx, nl * dd);
+  double* S = ws_alloc<double>(ctx, nl * D);
+  if (!S) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (gauge start)");
+  hipLaunchKernelGGL(gauge_start_kernel, dim3(nl), dim3(256), 0, ctx->stream, Dk, D, kappa, P, Q,
+                     Pc, Qc, K);
+  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(jacobi_svd(ctx, nl, D, D, K, D, dd, W, D, dd, S, D, V, D, dd));
+  for (int b = 0; b < nl; ++b)
+    hipLaunchKernelGGL(polar_kernel, dim3(nblk(dd)), dim3(256), 0, ctx->stream, D, W + b * dd,
+                       V + b * dd, U0 + b * dd);
+  TN_HIP(ctx, hipGetLastError());
+  ctx->arena_off = mark;  // stream order makes the slice reusable
+  return TN_OK;
+}
+
+int recycle_factors(tn_ctx* ctx, int nl, int Dk, int D, const double* P, const double* Q,
+                    const double* Pc, const double* Qc, const double* U, double* Rf, double* Lf) {
+  const long long tot = 2LL * nl * Dk * D;
+  hipLaunchKernelGGL(renorm_gate_kernel, dim3(nblk(tot)), dim3(256), 0, ctx->stream, nl, Dk, D, P,
+                     Q, Pc, Qc, U, Rf, Lf);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
 int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
                         const double* Q, const double* Pc, const double* Qc, double* U0) {
   if (nlink < 1 || D < 1 || kappa < 1 || Dk != kappa * D || !P || !Q || !Pc || !Qc || !U0)
@@ -1525,19 +1669,7 @@ int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const 
   const long long dd = (long long)D * D;
   TN_TRY(ws_reserve(ctx, (size_t)(4 * nlink * dd + nlink * D) * sizeof(double) + (1 << 20)));
   ws_reset(ctx);
-  double* K = ws_alloc<double>(ctx, nlink * dd);
-  double* W = ws_alloc<double>(ctx, nlink * dd);
-  double* V = ws_alloc<double>(ctx, nlink * dd);
-  double* S = ws_alloc<double>(ctx, nlink * D);
-  if (!S) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
-  hipLaunchKernelGGL(gauge_start_kernel, dim3(nlink), dim3(256), 0, ctx->stream, Dk, D, kappa, P,
-                     Q, Pc, Qc, K);
-  TN_HIP(ctx, hipGetLastError());
-  TN_TRY(jacobi_svd(ctx, nlink, D, D, K, D, dd, W, D, dd, S, D, V, D, dd));
-  for (int b = 0; b < nlink; ++b)
-    hipLaunchKernelGGL(polar_kernel, dim3(nblk(dd)), dim3(256), 0, ctx->stream, D, W + b * dd,
-                       V + b * dd, U0 + b * dd);
-  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(recycle_gauge_start(ctx, nlink, Dk, D, kappa, P, Q, Pc, Qc, U0));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
 }

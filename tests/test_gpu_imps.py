@@ -123,3 +123,66 @@ def test_critical_chain_full_config(ctx):
         _, e, rc = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, energy=(step == 1999))
         assert rc >= 0
     assert abs(e + 4 / np.pi) < 2e-4
+
+
+@pytest.mark.parametrize("chi,h", [(8, 1.0), (16, 1.2)])
+def test_recycle_build_and_apply_parity(ctx, chi, h):
+    """An environment step of the recycling scheme (canonical A_0, truncation,
+    canonical form, gauge fix, renormalized gate) and one recycled step.
+    (A short run from a random start can leave a cat-like state whose
+    dominant transfer-matrix eigenvalue is nearly degenerate; the local
+    canonical iteration then does not converge in 1000 steps.  These seeds
+    converge in 65 and 187.)"""
+    sites = _state(6, chi, h=h)
+    g = gates.impo(1.0, h, 0.01)
+    new, (Lf, Rf), l1, err, F = imps.recycle_build(sites, g, chi)
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    lam = torch.empty((2, chi), dtype=torch.float64, device="cuda")
+    gerr, _, rc = ctx.itebd_step(A, 1.0, h, 0.01, env, mode=tn.TN_RECYCLE_BUILD, lam=lam)
+    assert rc == tn.TN_OK
+    assert abs(gerr - err) < 1e-9 * max(err, 1e-30) + 1e-15
+    np.testing.assert_allclose(host(lam), np.stack(l1), atol=1e-10)
+    n = 2 * chi
+    e = host(env)
+    gLf = e[4 * n * n:4 * n * n + 2 * chi * n].reshape(2, chi, n)
+    gRf = e[4 * n * n + 2 * chi * n:4 * n * n + 4 * chi * n].reshape(2, n, chi)
+    assert np.abs(gLf - np.stack(Lf)).max() < 1e-7 * np.abs(Lf).max()
+    assert np.abs(gRf - np.stack(Rf)).max() < 1e-7 * np.abs(Rf).max()
+    np.testing.assert_allclose(host(A), np.stack(new), atol=1e-8)
+    # one recycled step with the stored factors
+    nxt = imps.apply_renormalized(Lf, Rf, g, new)
+    _, ge, rc = ctx.itebd_step(A, 1.0, h, 0.01, env, mode=tn.TN_RECYCLE_APPLY, energy=True)
+    assert rc == tn.TN_OK
+    np.testing.assert_allclose(host(A), np.stack(nxt), atol=1e-8)
+    er = imps.energy_per_site(nxt, 1.0, h)
+    assert abs(ge - er) < 1e-9 * abs(er)
+
+
+def test_recycled_trajectory_parity(ctx):
+    """run_itebd with N_Re = 5 against the GPU steps: energies at the
+    environment steps and the final tensors."""
+    chi, h, dt, n_re, nsteps = 8, 1.0, 0.02, 5, 40
+    ga, _, gb, _ = tninputs.imps_two_site(5, chi)
+    sites = [ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)]
+    ref, log = imps.run_itebd(sites, 1.0, h, dt, chi, nsteps, n_re=n_re, energy_every=1)
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    got = []
+    for step in range(nsteps):
+        if step % n_re == 0:
+            _, e, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_BUILD, energy=True)
+            got.append((step + 1, e))
+        else:
+            _, _, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_APPLY)
+        assert rc >= 0
+    assert [s for s, _ in got] == [s for s, _ in log]
+    for (_, e), (_, er) in zip(got, log):
+        assert abs(e - er) < 1e-8 * abs(er)
+    np.testing.assert_allclose(host(A), np.stack(ref), atol=1e-6)
+
+
+def test_recycle_apply_needs_a_build(ctx):
+    A = dev(np.stack(_state(1, 4)))
+    with pytest.raises(tn.TNError):
+        ctx.itebd_step(A, 1.0, 1.0, 0.01, ctx.env1d(4), mode=tn.TN_RECYCLE_APPLY)
