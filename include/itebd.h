@@ -89,9 +89,18 @@ const char* tn_version(void);
  *   tol           convergence tolerance on delta
  *   precision     TN_FP64, TN_FP32 or TN_BF16 for the bulk contractions
  *                 (enlarged corners, renormalisation); SVDs stay FP64
- *   n_polish_fp64 with a reduced precision, the number of final iterations
- *                 run in FP64 (the reduced-precision phase stops at
- *                 delta < 1e-6 for FP32, 1e-3 for BF16)
+ *   n_polish_fp64 with a reduced precision, the minimum number of final
+ *                 FP64 iterations.  The reduced-precision phase stops at
+ *                 delta < sw (1e-6 FP32, 1e-3 BF16), or when delta stops
+ *                 improving at the precision's noise floor (after five
+ *                 iterations, the best delta of the last three is not below
+ *                 0.7 times the best before them), or after max_iter
+ *                 iterations; its projector SVDs stop at residuals of 2e-5
+ *                 (FP32) or 2e-2 (BF16) times s_1, or after 12 (6) subspace
+ *                 iterations.  The FP64 phase then runs at least
+ *                 n_polish_fp64 iterations and until delta < tol (at most
+ *                 max_iter + n_polish_fp64 iterations in all).  iters counts
+ *                 both phases
  *   iters, delta  host out: iterations done and the last delta
  * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL (bad sizes or pointers),
  * TN_ENUMERIC (non-finite values or a failed factorisation), TN_EHIP.
@@ -346,7 +355,9 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
  * tn_gemm -- the library's contraction engine on a plain matrix product, for
  * testing and measurement: C = alpha op(A) op(B) + beta C with row-major
  * storage, op(X) = X or X^T (ta, tb nonzero), leading dimensions lda, ldb,
- * ldc.  All matrices device, FP64.  precision must be TN_FP64 here.
+ * ldc.  All matrices device, FP64.  precision: TN_FP64, or TN_FP32 / TN_BF16
+ * (operands rounded to that format on the fly, FP32 accumulation on MFMA,
+ * FP64 result).
  */
 int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B,
             int ldb, int tb, double* C, int ldc, double alpha, double beta, int precision);

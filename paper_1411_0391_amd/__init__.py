@@ -354,12 +354,12 @@ class Context:
                     moves=cnt[0], svd_calls=cnt[1], svd_iters=cnt[2], svd_unconverged=cnt[3],
                     svd_explicit=cnt[4], jacobi_sweeps=cnt[5])
 
-    def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0):
+    def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0, precision="fp64"):
         M = A.shape[1] if ta else A.shape[0]
         K = A.shape[0] if ta else A.shape[1]
         N = B.shape[0] if tb else B.shape[1]
         rc = lib().tn_gemm(self._h, M, N, K, _ptr(A), A.shape[1], int(ta), _ptr(B), B.shape[1],
-                           int(tb), _ptr(C), C.shape[1], alpha, beta, TN_FP64)
+                           int(tb), _ptr(C), C.shape[1], alpha, beta, _PREC[precision])
         self._check(rc)
 
 

@@ -6,7 +6,8 @@
 
 int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
                    const int* cell, int chi, double* C, double* T, int max_iter, double tol,
-                   int n_moves, int first_dir, int* iters, double* delta);
+                   int n_moves, int first_dir, int* iters, double* delta, int prec,
+                   int n_polish);
 int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
                     const int* cell, int chi, const double* C, const double* T, double* rho1,
                     double* rhoh, double* rhov);
@@ -141,11 +142,9 @@ int ctmrg_iterate(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const do
   if (max_iter < 1) TN_FAIL(ctx, TN_EINVAL, "max_iter must be >= 1");
   if (precision != TN_FP64 && precision != TN_FP32 && precision != TN_BF16)
     TN_FAIL(ctx, TN_EINVAL, "unknown precision %d", precision);
-  if (precision != TN_FP64)
-    TN_FAIL(ctx, TN_EINVAL, "reduced-precision bulk contractions are not built in this library");
-  (void)n_polish_fp64;
+  if (n_polish_fp64 < 0) TN_FAIL(ctx, TN_EINVAL, "n_polish_fp64 must be >= 0");
   return ctmrg_run_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, max_iter, tol, 0, 0,
-                        iters, delta);
+                        iters, delta, precision, n_polish_fp64);
 }
 
 int ctmrg_moves(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
@@ -155,10 +154,10 @@ int ctmrg_moves(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const doub
   ctx->err.clear();
   if (n_moves < 1) TN_FAIL(ctx, TN_EINVAL, "n_moves must be >= 1");
   if (first_dir < 0 || first_dir > 3) TN_FAIL(ctx, TN_EINVAL, "first_dir must be 0..3");
-  if (precision != TN_FP64)
-    TN_FAIL(ctx, TN_EINVAL, "reduced-precision bulk contractions are not built in this library");
+  if (precision != TN_FP64 && precision != TN_FP32 && precision != TN_BF16)
+    TN_FAIL(ctx, TN_EINVAL, "unknown precision %d", precision);
   return ctmrg_run_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, 0, 0.0, n_moves,
-                        first_dir, nullptr, nullptr);
+                        first_dir, nullptr, nullptr, precision, 0);
 }
 
 int ipeps_rdms(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
@@ -174,8 +173,10 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
   if (M < 0 || N < 0 || K < 0 || !A || !B || !C) TN_FAIL(ctx, TN_EINVAL, "bad gemm arguments");
-  if (precision != TN_FP64) TN_FAIL(ctx, TN_EINVAL, "tn_gemm supports TN_FP64 only");
-  TN_TRY(gemm(ctx, M, N, K, A, lda, ta != 0, B, ldb, tb != 0, C, ldc, alpha, beta));
+  if (precision != TN_FP64 && precision != TN_FP32 && precision != TN_BF16)
+    TN_FAIL(ctx, TN_EINVAL, "unknown precision %d", precision);
+  TN_TRY(gemm(ctx, M, N, K, A, lda, ta != 0, B, ldb, tb != 0, C, ldc, alpha, beta, 1, 0, 0, 0,
+              precision));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
 }

@@ -205,6 +205,9 @@ Frames make_frames(int Lx, int Ly) {
 
 struct Geo {
   int Lx, Ly, D, d, nsite, chi, npos, n;
+  int prec = P_F64;       // bulk contractions: corners, K products, projectors, renormalisation
+  double svd_tol = 1e-13; // residual tolerance of the projector SVD (relative to s_1)
+  int svd_maxit = 40;
   std::vector<int> cell;
   Frames F;
   const double* arot[4];  // rotated site tensors [nsite][d][D^4]
@@ -230,9 +233,9 @@ int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, con
               const double* A, double* E, double* X1, double* X2, double* X3) {
   const long long chi = g.chi, D = g.D, d = g.d, D2 = D * D, D4 = D2 * D2, n = g.n;
   TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T4, (int)chi, false, Cc, (int)chi, false,
-              X1, (int)chi, 1.0, 0.0));
+              X1, (int)chi, 1.0, 0.0, 1, 0, 0, 0, g.prec));
   TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
-              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
+              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0, 1, 0, 0, 0, g.prec));
   Contraction c3;
   c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
   c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
@@ -240,7 +243,7 @@ int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, con
   c3.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
   c3.cm = grp({{(int)chi, chi * d * D4}, {(int)D, D}, {(int)D, 1}, {(int)chi, d * D4}});
   c3.cn = grp({{(int)d, D2}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
-  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
+  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0, g.prec));
   Contraction c4;
   c4.am = grp({{(int)chi, chi * d * D4}, {(int)chi, d * D4}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
   c4.ak = grp({{(int)d, D2}, {(int)D, D}, {(int)D, 1}});
@@ -248,7 +251,7 @@ int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, con
   c4.bn = grp({{(int)D, D2}, {(int)D, D}});
   c4.cm = grp({{(int)chi, D2 * n}, {(int)chi, D2}, {(int)D, D}, {(int)D, D * n}});
   c4.cn = grp({{(int)D, 1}, {(int)D, n}});
-  TN_TRY(tc_run(ctx, c4, X3, A, E, 1.0, 0.0));
+  TN_TRY(tc_run(ctx, c4, X3, A, E, 1.0, 0.0, g.prec));
   return TN_OK;
 }
 
@@ -262,6 +265,7 @@ int corner_of(tn_ctx* ctx, const Geo& g, int fj, int p, double* E, double* X1, d
 // corners of problem b are E[j] + b n^2; t1, t2 are [batch][n][k] scratch.
 struct TopK {
   int n, k, chi, batch;
+  int prec;  // precision of the products with the corners
   const double* E[4];
   double *t1, *t2;
 };
@@ -270,10 +274,10 @@ struct TopK {
 int applyK(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
   const int n = t.n, k = t.k, B = t.batch;
   const long long sE = (long long)n * n, sX = (long long)n * k;
-  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, false, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, false, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, false, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, false, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, false, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, false, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, false, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, false, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
   return TN_OK;
 }
 
@@ -281,10 +285,10 @@ int applyK(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
 int applyKT(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
   const int n = t.n, k = t.k, B = t.batch;
   const long long sE = (long long)n * n, sX = (long long)n * k;
-  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, true, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, true, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, true, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX));
-  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, true, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX));
+  TN_TRY(gemm(ctx, n, k, n, t.E[2], n, true, X, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[3], n, true, t.t1, k, false, t.t2, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[0], n, true, t.t2, k, false, t.t1, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
+  TN_TRY(gemm(ctx, n, k, n, t.E[1], n, true, t.t1, k, false, Y, k, 1.0, 0.0, B, sE, sX, sX, t.prec));
   return TN_OK;
 }
 
@@ -433,9 +437,11 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     const long long sE = (long long)n * n;
     for (int b = 0; b < B; ++b) {
       TN_TRY(gemm(ctx, n, n, n, t.E[0] + b * sE, n, false, t.E[1] + b * sE, n, false, Km, n, 1.0,
-                  0.0));
-      TN_TRY(gemm(ctx, n, n, n, t.E[3] + b * sE, n, false, Km, n, false, K2, n, 1.0, 0.0));
-      TN_TRY(gemm(ctx, n, n, n, t.E[2] + b * sE, n, false, K2, n, false, Km, n, 1.0, 0.0));
+                  0.0, 1, 0, 0, 0, t.prec));
+      TN_TRY(gemm(ctx, n, n, n, t.E[3] + b * sE, n, false, Km, n, false, K2, n, 1.0, 0.0, 1, 0, 0,
+                  0, t.prec));
+      TN_TRY(gemm(ctx, n, n, n, t.E[2] + b * sE, n, false, K2, n, false, Km, n, 1.0, 0.0, 1, 0, 0,
+                  0, t.prec));
       TN_TRY(jacobi_svd(ctx, 1, n, n, Km, n, 0, Uf, n, 0, Sf, 0, Vf, n, 0));
       hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((nchi + 255) / 256)), dim3(256), 0,
                          ctx->stream, n, n, chi, Uf, Vout + b * nchi);
@@ -566,6 +572,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
   t.k = b.k;
   t.chi = chi;
   t.batch = Lyf;
+  t.prec = g.prec;
   for (int j = 0; j < 4; ++j) t.E[j] = b.E[j];
   t.t1 = b.t1;
   t.t2 = b.t2;
@@ -576,19 +583,20 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
   bool wv = wQ != nullptr;
   for (int y = 0; y < Lyf && wv; ++y) wv = warm_ok[slot0 + y];
   const size_t mark = ctx->arena_off;
-  TN_TRY(topk_svd(ctx, t, wQ, wS, wv, b.V, b.S, b.W, 1e-13, 40, 0x5DEECE66DULL * (slot0 + 1), st));
+  TN_TRY(topk_svd(ctx, t, wQ, wS, wv, b.V, b.S, b.W, g.svd_tol, g.svd_maxit,
+                  0x5DEECE66DULL * (slot0 + 1), st));
   ctx->arena_off = mark;
   if (wQ)
     for (int y = 0; y < Lyf; ++y) warm_ok[slot0 + y] = true;
   // P = E3^T (E2^T V) S^-1/2 ; Pt^T = E0 (E1 W) S^-1/2, all rows at once
   TN_TRY(gemm(ctx, n, chi, n, b.E[2], n, true, b.V, chi, false, b.G1, chi, 1.0, 0.0, Lyf, nn,
-              nchi, nchi));
+              nchi, nchi, g.prec));
   TN_TRY(gemm(ctx, n, chi, n, b.E[3], n, true, b.G1, chi, false, b.P, chi, 1.0, 0.0, Lyf, nn,
-              nchi, nchi));
+              nchi, nchi, g.prec));
   TN_TRY(gemm(ctx, n, chi, n, b.E[1], n, false, b.W, chi, false, b.G1, chi, 1.0, 0.0, Lyf, nn,
-              nchi, nchi));
+              nchi, nchi, g.prec));
   TN_TRY(gemm(ctx, n, chi, n, b.E[0], n, false, b.G1, chi, false, b.PtT, chi, 1.0, 0.0, Lyf, nn,
-              nchi, nchi));
+              nchi, nchi, g.prec));
   for (int y = 0; y < Lyf; ++y) {
     TN_TRY(scale_columns(ctx, n, chi, b.P + y * nchi, chi, b.S + y * chi, 1));
     TN_TRY(scale_columns(ctx, n, chi, b.PtT + y * nchi, chi, b.S + y * chi, 1));
@@ -602,8 +610,9 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
     const double* PtTm = b.PtT + (size_t)((y - 1 + Lyf) % Lyf) * nchi;
     // C1 of (x+1, y+1) = P_y^T (C1 T1)(x, y+1)
     TN_TRY(gemm(ctx, chi, (int)(D2 * chi), chi, g.Cp(s1, f), chi, false, g.Tp(s1, f),
-                (int)(D2 * chi), false, b.CT, (int)(D2 * chi), 1.0, 0.0));
-    TN_TRY(gemm(ctx, chi, chi, n, P, chi, true, b.CT, chi, false, b.Cn1 + y * csz, chi, 1.0, 0.0));
+                (int)(D2 * chi), false, b.CT, (int)(D2 * chi), 1.0, 0.0, 1, 0, 0, 0, g.prec));
+    TN_TRY(gemm(ctx, chi, chi, n, P, chi, true, b.CT, chi, false, b.Cn1 + y * csz, chi, 1.0, 0.0, 1, 0, 0,
+                0, g.prec));
     // C4 of (x+1, y) = [T3 C4](x, y) Pt_y^T, Z[a3, (b4, k, b)]
     {
       Contraction c;
@@ -613,9 +622,9 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       c.bn = grp({{chi, 1}});
       c.cm = grp({{chi, (long long)n}, {D, D}, {D, 1}});
       c.cn = grp({{chi, D2}});
-      TN_TRY(tc_run(ctx, c, g.Tp(src, f + 2), g.Cp(src, f + 3), b.CT, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, c, g.Tp(src, f + 2), g.Cp(src, f + 3), b.CT, 1.0, 0.0, g.prec));
       TN_TRY(gemm(ctx, chi, chi, n, b.CT, n, false, PtTy, chi, false, b.Cn4 + y * csz, chi, 1.0,
-                  0.0));
+                  0.0, 1, 0, 0, 0, g.prec));
     }
     // T4 of (x+1, y) = Pt_{y-1} (T4 a a)(x, y) P_y
     {
@@ -632,7 +641,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       a.bn = grp({{chi, D2 * chi}, {D, (long long)D * chi}, {D, chi}});
       a.cm = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
       a.cn = grp({{chi, D2}, {D, D}, {D, 1}});
-      TN_TRY(tc_run(ctx, a, PtTm, T4, Y1, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, a, PtTm, T4, Y1, 1.0, 0.0, g.prec));
       Contraction bk;  // Y2[c, a, rk, dk, s, lb, ub] = sum_{lk,uk} Y1[...] A[s,lk,rk,dk,uk]
       bk.am = grp({{chi, D2 * nn}, {D, nn}, {chi, D2}, {D, 1}});
       bk.ak = grp({{D, D}, {D, (long long)D * nn}});
@@ -640,7 +649,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       bk.bn = grp({{d, D2 * D2}, {D, D2}, {D, D}});
       bk.cm = grp({{chi, chi * dD4}, {D, 1}, {chi, dD4}, {D, D}});
       bk.cn = grp({{d, D2}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
-      TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0, g.prec));
       Contraction cb;  // Y3[c, rk, rb, a, dk, db] = sum_{s,lb,ub} Y2[...] A[s,lb,rb,db,ub]
       cb.am = grp({{chi, chi * dD4}, {chi, dD4}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
       cb.ak = grp({{d, D2}, {D, D}, {D, 1}});
@@ -648,7 +657,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       cb.bn = grp({{D, D2}, {D, D}});
       cb.cm = grp({{chi, D2 * nn}, {chi, D2}, {D, (long long)D * nn}, {D, D}});
       cb.cn = grp({{D, nn}, {D, 1}});
-      TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0, g.prec));
       Contraction dp;  // T4new[e, rk, rb, c] = sum_i Y3[c, rk, rb, i] P[i, e]
       dp.am = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
       dp.ak = grp({{(int)nn, 1}});
@@ -656,7 +665,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       dp.bn = grp({{chi, 1}});
       dp.cm = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}});
       dp.cn = grp({{chi, D2 * chi}});
-      TN_TRY(tc_run(ctx, dp, Y3, P, b.Tn4 + y * tsz, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, dp, Y3, P, b.Tn4 + y * tsz, 1.0, 0.0, g.prec));
     }
   }
   // write back and normalise
@@ -861,9 +870,27 @@ int half_left(tn_ctx* ctx, const Geo& g, int f, int p, double* L, double* X1, do
 // public entry points (C ABI wrappers live in abi.hip)
 // ---------------------------------------------------------------------------
 
+// Bulk precision of a phase: the contraction precision, and the projector
+// SVD tolerance and iteration cap that its rounding allows (the residual of
+// a reduced-precision product cannot drop below its rounding level).
+void set_precision(Geo& g, int prec) {
+  g.prec = prec;
+  if (prec == P_F64) {
+    g.svd_tol = 1e-13;
+    g.svd_maxit = 40;
+  } else if (prec == P_F32) {
+    g.svd_tol = 2e-5;
+    g.svd_maxit = 12;
+  } else {
+    g.svd_tol = 2e-2;
+    g.svd_maxit = 6;
+  }
+}
+
 int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const double* sites,
                    const int* cell, int chi, double* C, double* T, int max_iter, double tol,
-                   int n_moves, int first_dir, int* iters, double* delta) {
+                   int n_moves, int first_dir, int* iters, double* delta, int prec,
+                   int n_polish) {
   TN_TRY(check_geometry(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T));
   Geo g;
   const int n = chi * D * D;
@@ -899,6 +926,7 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
   if (fresh || flags.size() != (size_t)4 * g.npos) flags.assign((size_t)4 * g.npos, 0);
   bool* wok = reinterpret_cast<bool*>(flags.data());
   SvdStats st;
+  set_precision(g, prec);
   const size_t base = ctx->arena_off;
   if (n_moves > 0) {
     // exact move count, in iteration order starting at first_dir
@@ -930,9 +958,31 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
   TN_TRY(jacobi_svd(ctx, rows, chi, chi, C, chi, g.csz(), nullptr, 0, 0, Sc, chi, nullptr, 0, 0));
   hipLaunchKernelGGL(spectra_delta_kernel, dim3(1), dim3(1), 0, ctx->stream, Sc, Sprev, rows, chi,
                      dd);
-  int it = 0;
+  // Reduced bulk precision: iterate until delta reaches the precision's
+  // switch level sw (1e-6 FP32, 1e-3 BF16), or stops improving at the
+  // precision's noise floor (after five iterations, the best delta of the
+  // last three is not below 0.7 times the best before them); then FP64
+  // iterations, at least n_polish of them and until delta < tol.  At most
+  // max_iter iterations in all (plus n_polish if the reduced phase used them
+  // up).  FP64 throughout: until delta < tol or max_iter.
+  const double sw = prec == P_F32 ? 1e-6 : (prec == P_BF16 ? 1e-3 : tol);
+  const int polish = prec == P_F64 ? 0 : std::max(0, n_polish);
+  int it = 0, done_it = 0, fp64_it = 0;
   double hd = INFINITY;
-  for (it = 1; it <= max_iter; ++it) {
+  std::vector<double> hist;
+  const int cap = max_iter + polish;
+  for (it = 1; it <= cap; ++it) {
+    if (g.prec != P_F64) {
+      bool stalled = false;
+      const int nh = (int)hist.size();
+      if (nh >= 5) {
+        double recent = INFINITY, before = INFINITY;
+        for (int i = 0; i < nh; ++i) (i >= nh - 3 ? recent : before) =
+            std::min(i >= nh - 3 ? recent : before, hist[i]);
+        stalled = recent > 0.7 * before;
+      }
+      if (hd < sw || stalled || it > max_iter) set_precision(g, P_F64);
+    }
     for (int f = 0; f < 4; ++f)
       for (int x = 0; x < g.F.Lx[f]; ++x) {
         ctx->arena_off = base2;
@@ -946,12 +996,16 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
                                ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     hd = ctx->host_scratch[0];
+    hist.push_back(hd);
+    ++done_it;
+    if (g.prec == P_F64) ++fp64_it;
     if (!std::isfinite(hd)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite corner spectra");
-    if (hd < tol) break;
+    if (g.prec == P_F64 && hd < tol && fp64_it >= polish) break;
+    if (prec == P_F64 && it >= max_iter) break;
   }
-  if (iters) *iters = std::min(it, max_iter);
+  if (iters) *iters = done_it;
   if (delta) *delta = hd;
-  ctx->moves += (long long)std::min(it, max_iter) * (2 * (g.F.Lx[0] + g.F.Lx[1]));
+  ctx->moves += (long long)done_it * (2 * (g.F.Lx[0] + g.F.Lx[1]));
   ctx->svd_calls += st.calls;
   ctx->svd_iters += st.iters;
   ctx->svd_unconverged += st.unconverged;

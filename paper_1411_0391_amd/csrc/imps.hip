@@ -79,6 +79,9 @@ __device__ void tm_apply(const double* K, const double* B, int nsite, int chi, i
 
 // Power iteration: block 0 left, block 1 right.  The iterate is kept at unit
 // Frobenius norm with positive trace; stops when it moves by less than tol.
+// GLOBAL: the working set lives in gwork instead of LDS (a compile-time
+// choice, so that LDS accesses compile to LDS instructions)
+template <bool GLOBAL>
 __global__ __launch_bounds__(TM_THREADS) void tm_power_kernel(
     const double* __restrict__ kets, const double* __restrict__ bras, int nsite, int chi, int d,
     double* __restrict__ vout, double* __restrict__ eta, int* __restrict__ iters, double tol,
@@ -89,7 +92,11 @@ __global__ __launch_bounds__(TM_THREADS) void tm_power_kernel(
   const int tid = threadIdx.x;
   const int cdc = chi * d * chi, cc = chi * chi;
   const long long per = 2LL * nsite * cdc + 2LL * cc + cdc;
-  double* base = gwork ? gwork + blockIdx.x * per : lds;
+  double* base;
+  if constexpr (GLOBAL)
+    base = gwork + blockIdx.x * per;
+  else
+    base = lds;
   double* K = base;
   double* B = K + (long long)nsite * cdc;
   double* v = B + (long long)nsite * cdc;
@@ -254,8 +261,12 @@ int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const do
     if (!gwork) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (transfer matrix)");
     dyn = 0;
   }
-  hipLaunchKernelGGL(tm_power_kernel, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets, bras,
-                     nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
+  if (gwork)
+    hipLaunchKernelGGL(tm_power_kernel<true>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets,
+                       bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
+  else
+    hipLaunchKernelGGL(tm_power_kernel<false>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets,
+                       bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
   TN_HIP(ctx, hipGetLastError());
   hipLaunchKernelGGL(pair_normalize_kernel, dim3(1), dim3(256), 0, ctx->stream, v2,
                      v2 + (size_t)chi * chi, chi * chi);

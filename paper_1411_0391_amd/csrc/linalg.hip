@@ -31,8 +31,11 @@ __device__ inline double wave_max(double v) {
 constexpr int SVD_THREADS = 1024;
 constexpr int SVD_WAVES = SVD_THREADS / 64;
 
-// work == nullptr: the m x n work matrix and the n x n rotation accumulator
-// live in dynamic LDS; otherwise in the global buffer `work`.
+// GLOBAL_WORK false: the m x n work matrix and the n x n rotation accumulator
+// live in dynamic LDS; otherwise in the global buffer `work`.  The choice is
+// a template parameter so that the LDS pointers are known to be LDS and the
+// accesses compile to LDS instructions rather than generic (flat) ones.
+template <bool GLOBAL_WORK>
 __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     const double* __restrict__ Ain, int lda, long long sA, double* __restrict__ U, int ldu,
     long long sU, double* __restrict__ S, long long sS, double* __restrict__ V, int ldv,
@@ -42,28 +45,39 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
   const long long b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* A = Ain + b * sA;
-  double* X = work ? work + b * (long long)(m * n + n * n) : lds;  // X[j*m + i]
-  double* W = X + (long long)m * n;                                 // W[j*n + i] (V columns)
+  // columns padded to an odd number of doubles so that the columns the
+  // groups of one wave touch fall on different LDS banks
+  const int ldx = m | 1, ldw = n | 1;
+  double* X;  // X[j*ldx + i]
+  if constexpr (GLOBAL_WORK)
+    X = work + b * (long long)(ldx * n + ldw * n);
+  else
+    X = lds;
+  double* W = X + (long long)ldx * n;  // W[j*ldw + i] (V columns)
   __shared__ double colnorm[512];
   __shared__ int perm[512];
   __shared__ int done;
 
   for (long long t = tid; t < (long long)m * n; t += SVD_THREADS) {
     const int i = (int)(t / n), j = (int)(t % n);
-    X[(long long)j * m + i] = A[(long long)i * lda + j];
+    X[(long long)j * ldx + i] = A[(long long)i * lda + j];
   }
   for (long long t = tid; t < (long long)n * n; t += SVD_THREADS) {
     const int i = (int)(t / n), j = (int)(t % n);
-    W[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
+    W[(long long)j * ldw + i] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) done = 0;
   __syncthreads();
 
-  // 16-lane groups: one column pair per group per round (64 groups)
+  // 16-lane groups: one column pair per group per round (64 groups); a lane
+  // keeps its entries of the pair in registers between the dot products and
+  // the rotation when m <= 16 * JREG
+  constexpr int JREG = 8;
   const int grp = tid >> 4, gl = tid & 15;
   constexpr int NGRP = SVD_THREADS / 16;
   __shared__ double off_g[NGRP];
   const int N = (n + 1) & ~1;  // players incl. a dummy when n is odd
+  const bool regs = m <= 16 * JREG;
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
     double offmax = 0.0;
     for (int r = 0; r < N - 1; ++r) {
@@ -72,14 +86,30 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
         const int p1 = 1 + ((N - 2 - q + r) % (N - 1));
         if (p0 >= n || p1 >= n) continue;
         const int p = min(p0, p1), qq = max(p0, p1);
-        double* xp = X + (long long)p * m;
-        double* xq = X + (long long)qq * m;
+        double* xp = X + (long long)p * ldx;
+        double* xq = X + (long long)qq * ldx;
         double a = 0.0, bb = 0.0, g = 0.0;
-        for (int i = gl; i < m; i += 16) {
-          const double u = xp[i], v = xq[i];
-          a += u * u;
-          bb += v * v;
-          g += u * v;
+        double up[JREG], vq[JREG];
+        if (regs) {
+#pragma unroll
+          for (int e = 0; e < JREG; ++e) {
+            const int i = gl + 16 * e;
+            up[e] = i < m ? xp[i] : 0.0;
+            vq[e] = i < m ? xq[i] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < JREG; ++e) {
+            a += up[e] * up[e];
+            bb += vq[e] * vq[e];
+            g += up[e] * vq[e];
+          }
+        } else {
+          for (int i = gl; i < m; i += 16) {
+            const double u = xp[i], v = xq[i];
+            a += u * u;
+            bb += v * v;
+            g += u * v;
+          }
         }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) {
@@ -93,13 +123,24 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
         const double z = (bb - a) / (2.0 * g);
         const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = gl; i < m; i += 16) {
-          const double u = xp[i], v = xq[i];
-          xp[i] = c * u - s * v;
-          xq[i] = s * u + c * v;
+        if (regs) {
+#pragma unroll
+          for (int e = 0; e < JREG; ++e) {
+            const int i = gl + 16 * e;
+            if (i < m) {
+              xp[i] = c * up[e] - s * vq[e];
+              xq[i] = s * up[e] + c * vq[e];
+            }
+          }
+        } else {
+          for (int i = gl; i < m; i += 16) {
+            const double u = xp[i], v = xq[i];
+            xp[i] = c * u - s * v;
+            xq[i] = s * u + c * v;
+          }
         }
-        double* wp = W + (long long)p * n;
-        double* wq = W + (long long)qq * n;
+        double* wp = W + (long long)p * ldw;
+        double* wq = W + (long long)qq * ldw;
         for (int i = gl; i < n; i += 16) {
           const double u = wp[i], v = wq[i];
           wp[i] = c * u - s * v;
@@ -122,7 +163,7 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
   // column norms = singular values
   for (int j = wave; j < n; j += SVD_WAVES) {
     double a = 0.0;
-    for (int i = lane; i < m; i += 64) a += X[(long long)j * m + i] * X[(long long)j * m + i];
+    for (int i = lane; i < m; i += 64) a += X[(long long)j * ldx + i] * X[(long long)j * ldx + i];
     a = wave_sum(a);
     if (lane == 0) colnorm[j] = sqrt(a);
   }
@@ -145,23 +186,23 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
     // sign: the first entry within a relative 1e-8 of the largest magnitude
     double best = 0.0;
-    for (int i = lane; i < m; i += 64) best = fmax(best, fabs(X[(long long)j * m + i]));
+    for (int i = lane; i < m; i += 64) best = fmax(best, fabs(X[(long long)j * ldx + i]));
     best = wave_max(best);
     int bi = 0x7fffffff;
     for (int i = lane; i < m; i += 64)
-      if (fabs(X[(long long)j * m + i]) >= (1.0 - 1e-8) * best) {
+      if (fabs(X[(long long)j * ldx + i]) >= (1.0 - 1e-8) * best) {
         bi = i;
         break;
       }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) bi = min(bi, __shfl_xor(bi, o, 64));
-    const double sg = (bi < m && X[(long long)j * m + bi] < 0.0) ? -1.0 : 1.0;
+    const double sg = (bi < m && X[(long long)j * ldx + bi] < 0.0) ? -1.0 : 1.0;
     if (U)
       for (int i = lane; i < m; i += 64)
-        U[b * sU + (long long)i * ldu + r] = sg * inv * X[(long long)j * m + i];
+        U[b * sU + (long long)i * ldu + r] = sg * inv * X[(long long)j * ldx + i];
     if (V)
       for (int i = lane; i < n; i += 64)
-        V[b * sV + (long long)i * ldv + r] = sg * W[(long long)j * n + i];
+        V[b * sV + (long long)i * ldv + r] = sg * W[(long long)j * ldw + i];
     if (S && lane == 0) S[b * sS + r] = sj;
   }
 }
@@ -176,9 +217,11 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
 // ---------------------------------------------------------------------------
 constexpr int CHOL_THREADS = 1024;
 
+// R_IN_LDS: the rows of R are kept in LDS too (compile-time, see above)
+template <bool R_IN_LDS>
 __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
     const double* __restrict__ G, int k, double shift_rel, double* __restrict__ R,
-    double* __restrict__ Rinv, int* __restrict__ info, int r_in_lds) {
+    double* __restrict__ Rinv, int* __restrict__ info) {
   extern __shared__ double lds[];
   {
     const long long off = (long long)blockIdx.x * k * k;  // one matrix per workgroup
@@ -188,7 +231,11 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
     info += blockIdx.x;
   }
   double* Wk = lds;                        // k x k trailing matrix, later R^-1
-  double* Rl = r_in_lds ? lds + k * k : R;  // R rows as they are produced
+  double* Rl;  // R rows as they are produced
+  if constexpr (R_IN_LDS)
+    Rl = lds + k * k;
+  else
+    Rl = R;
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   __shared__ double shift;
   if (tid < 64) {
@@ -242,7 +289,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
   for (int t = tid; t < k * k; t += CHOL_THREADS) {
     const int i = t / k;
     Rinv[t] = Wk[t] / Rl[i * k + i];
-    if (r_in_lds) R[t] = Rl[t];
+    if constexpr (R_IN_LDS) R[t] = Rl[t];
   }
 }
 
@@ -311,20 +358,25 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
   if (batch <= 0 || n <= 0) return TN_OK;
   if (!g_sweeps) TN_HIP(ctx, hipGetSymbolAddress((void**)&g_sweeps, HIP_SYMBOL(g_sweep_counter)));
   const size_t mark = ctx->arena_off;  // stream order makes the slice reusable afterwards
-  const size_t lds_bytes = (size_t)(m * n + n * n) * sizeof(double);
+  const size_t per = (size_t)(m | 1) * n + (size_t)(n | 1) * n;  // padded columns
+  const size_t lds_bytes = per * sizeof(double);
   double* work = nullptr;
   size_t dyn = 0;
   if (lds_bytes <= LDS_LIMIT) {
     dyn = lds_bytes;
   } else {
-    work = ws_alloc<double>(ctx, (size_t)batch * (m * n + n * n));
+    work = ws_alloc<double>(ctx, (size_t)batch * per);
     if (!work) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in jacobi_svd");
   }
   // rotations stop once every column pair is orthogonal to the rounding
   // level of its dot product (about m ulp), or the sweeps would never end
   const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream, A, lda,
-                     sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
+  if (work)
+    hipLaunchKernelGGL(jacobi_svd_kernel<true>, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream,
+                       A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_svd_kernel<false>, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream,
+                       A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
   TN_HIP(ctx, hipGetLastError());
   ctx->arena_off = mark;
   return TN_OK;
@@ -336,8 +388,12 @@ int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* 
   if (one > LDS_LIMIT) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports k <= 137 (k=%d)", k);
   if (batch < 1) return TN_OK;
   const int r_in_lds = 2 * one <= LDS_LIMIT;
-  hipLaunchKernelGGL(cholesky_inv_kernel, dim3(batch), dim3(CHOL_THREADS), (r_in_lds ? 2 : 1) * one,
-                     ctx->stream, G, k, shift_rel, R, Rinv, info, r_in_lds);
+  if (r_in_lds)
+    hipLaunchKernelGGL(cholesky_inv_kernel<true>, dim3(batch), dim3(CHOL_THREADS), 2 * one,
+                       ctx->stream, G, k, shift_rel, R, Rinv, info);
+  else
+    hipLaunchKernelGGL(cholesky_inv_kernel<false>, dim3(batch), dim3(CHOL_THREADS), one,
+                       ctx->stream, G, k, shift_rel, R, Rinv, info);
   TN_HIP(ctx, hipGetLastError());
   return TN_OK;
 }

@@ -1,4 +1,7 @@
-// Table-driven tensor contraction on MFMA (FP64 16x16x4 tiles).
+// Table-driven tensor contraction on MFMA: FP64 16x16x4 tiles, and the
+// reduced-precision bulk forms (FP32 16x16x4 and BF16 16x16x32 with FP32
+// accumulation) that read the same FP64 operands, round them while staging
+// into LDS and write FP64 results.
 //
 // A contraction C[m, n] = alpha * sum_k A[m, k] B[k, n] + beta * C[m, n] over
 // arbitrary tensor layouts: every operand index group (rows, columns, the
@@ -9,12 +12,15 @@
 #include <algorithm>
 #include <cstring>
 #include <sstream>
+#include <type_traits>
 
 #include "common.h"
 
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 struct TDesc {
   int M, N, K;
@@ -174,6 +180,152 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
   }
 }
 
+// Reduced-precision form of the same tiling.  PREC_BF16: operands rounded to
+// bf16, k slices of 32 (one 16x16x32 MFMA per 16x16 block and slice), LDS
+// tiles k-contiguous so that a lane reads its 8 consecutive k values at once;
+// otherwise fp32, k slices of 16 (four 16x16x4 MFMAs).  Accumulation in fp32;
+// D layout of both (measured on gfx950): lane l, register r holds row
+// 4 (l/16) + r, column l%16.
+template <bool BF16, bool TABLE>
+__global__ __launch_bounds__(256) void tgemm_lp_kernel(const double* __restrict__ A,
+                                                       const double* __restrict__ B,
+                                                       double* __restrict__ C, TDesc d,
+                                                       double alpha, double beta) {
+  constexpr int KB = BF16 ? 32 : 16;
+  constexpr int NLD = KB / 4;  // elements of each operand a thread stages per slice
+  typedef typename std::conditional<BF16, __bf16, float>::type T;
+  // bf16: [row][k] with 8 k of padding (16-byte aligned rows); fp32: [k][row]
+  constexpr int R1 = BF16 ? BM : KB, R2 = BF16 ? KB + 8 : BM + PAD;
+  __shared__ __attribute__((aligned(16))) T As[2][R1][R2];
+  __shared__ __attribute__((aligned(16))) T Bs[2][R1][R2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int split = blockIdx.z % d.ksplit;
+  const long long bz = blockIdx.z / d.ksplit;
+  A += bz * d.sa;
+  B += bz * d.sb;
+  const int kbeg = split * d.kchunk;
+  const int kend = min(d.K, kbeg + d.kchunk);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  int am_[NLD], ak_[NLD], bk_[NLD], bn_[NLD];
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    if (d.a_mfast) {
+      am_[i] = tid & 63;
+      ak_[i] = (tid >> 6) + 4 * i;
+    } else {
+      ak_[i] = tid % KB;
+      am_[i] = tid / KB + (256 / KB) * i;
+    }
+    if (d.b_nfast) {
+      bn_[i] = tid & 63;
+      bk_[i] = (tid >> 6) + 4 * i;
+    } else {
+      bk_[i] = tid % KB;
+      bn_[i] = tid / KB + (256 / KB) * i;
+    }
+  }
+  double ra[NLD], rb[NLD];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int m = m0 + am_[i], k = k0 + ak_[i];
+      ra[i] = (m < d.M && k < kend) ? A[offA<TABLE>(d, m, k)] : 0.0;
+      const int n = n0 + bn_[i], kb = k0 + bk_[i];
+      rb[i] = (n < d.N && kb < kend) ? B[offB<TABLE>(d, kb, n)] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      if constexpr (BF16) {
+        As[buf][am_[i]][ak_[i]] = (__bf16)(float)ra[i];
+        Bs[buf][bn_[i]][bk_[i]] = (__bf16)(float)rb[i];
+      } else {
+        As[buf][ak_[i]][am_[i]] = (float)ra[i];
+        Bs[buf][bk_[i]][bn_[i]] = (float)rb[i];
+      }
+    }
+  };
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
+    const bool more = k0 + KB < kend;
+    if (more) fetch(k0 + KB);
+    if constexpr (BF16) {
+      bf8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf8*>(&As[buf][wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf8*>(&Bs[buf][wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 4) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[buf][kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (d.ksplit == 1) {
+    C += bz * d.sc;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < d.M && col < d.N) {
+            const long long off = offC<TABLE>(d, row, col);
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * C[off];
+            C[off] = v;
+          }
+        }
+  } else {
+    double* P = d.part + (long long)blockIdx.z * d.M * d.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < d.M && col < d.N) P[(long long)row * d.N + col] = (double)acc[i][j][r];
+        }
+  }
+}
+
 // C = alpha * sum_s part[s] + beta * C, partial order fixed (deterministic)
 template <bool TABLE>
 __global__ void splitk_reduce_kernel(double* __restrict__ C, TDesc d, double alpha, double beta,
@@ -238,17 +390,18 @@ namespace {
 // Launch with either tables (TABLE) or strides; picks split-K so that the
 // grid has enough workgroups to occupy the 256 compute units.
 int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const double* B,
-           double* C, double alpha, double beta) {
+           double* C, double alpha, double beta, int prec) {
   const long long tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   const long long tiles = tm * tn * batch;
   int ksplit = 1;
-  const int ktiles = (d.K + BK - 1) / BK;
+  const int kstep = prec == P_BF16 ? 32 : BK;  // k slice of the kernel
+  const int ktiles = (d.K + kstep - 1) / kstep;
   if (tiles < 512 && ktiles >= 8) {
     ksplit = (int)std::min<long long>((1024 + tiles - 1) / tiles, ktiles / 4);
     ksplit = std::max(1, std::min(ksplit, 64));
   }
   d.ksplit = ksplit;
-  d.kchunk = ((ktiles + ksplit - 1) / ksplit) * BK;
+  d.kchunk = ((ktiles + ksplit - 1) / ksplit) * kstep;
   d.part = nullptr;
   const size_t mark = ctx->arena_off;
   if (ksplit > 1) {
@@ -257,7 +410,7 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
       ctx->err.clear();
       ctx->arena_off = mark;
       d.ksplit = 1;
-      d.kchunk = ktiles * BK;
+      d.kchunk = ktiles * kstep;
     }
   }
   if (d.M > 0 && d.N > 0 && (long long)batch * d.ksplit > 65535)
@@ -276,12 +429,28 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
     ctx->prof_flops.push_back(2.0 * (double)d.M * (double)d.N * (double)d.K * (double)batch);
     TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
-  if (table)
-    hipLaunchKernelGGL(tgemm_f64_kernel<true>, grid, dim3(256), 0, ctx->stream, A, B, C, d, alpha,
-                       beta);
-  else
-    hipLaunchKernelGGL(tgemm_f64_kernel<false>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
-                       alpha, beta);
+  if (prec == P_F64) {
+    if (table)
+      hipLaunchKernelGGL(tgemm_f64_kernel<true>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
+                         alpha, beta);
+    else
+      hipLaunchKernelGGL(tgemm_f64_kernel<false>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
+                         alpha, beta);
+  } else if (prec == P_F32) {
+    if (table)
+      hipLaunchKernelGGL((tgemm_lp_kernel<false, true>), grid, dim3(256), 0, ctx->stream, A, B, C,
+                         d, alpha, beta);
+    else
+      hipLaunchKernelGGL((tgemm_lp_kernel<false, false>), grid, dim3(256), 0, ctx->stream, A, B,
+                         C, d, alpha, beta);
+  } else {
+    if (table)
+      hipLaunchKernelGGL((tgemm_lp_kernel<true, true>), grid, dim3(256), 0, ctx->stream, A, B, C,
+                         d, alpha, beta);
+    else
+      hipLaunchKernelGGL((tgemm_lp_kernel<true, false>), grid, dim3(256), 0, ctx->stream, A, B, C,
+                         d, alpha, beta);
+  }
   TN_HIP(ctx, hipGetLastError());
   if (d.ksplit > 1) {
     const long long tot = (long long)d.M * d.N * batch;
@@ -309,7 +478,8 @@ int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, 
   if (M == 0 || N == 0 || c.batch == 0) return TN_OK;
   if (M > 2147483647LL || N > 65535LL * BN || c.batch > 65535)
     TN_FAIL(ctx, TN_EINVAL, "contraction too large for one launch");
-  (void)prec;
+  if (prec != P_F64 && prec != P_F32 && prec != P_BF16)
+    TN_FAIL(ctx, TN_EINVAL, "unknown contraction precision %d", prec);
   TDesc d;
   std::memset(&d, 0, sizeof(d));
   d.M = (int)M;
@@ -338,7 +508,7 @@ int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, 
   d.sc = c.sc;
   d.a_mfast = unit_fast(c.am) || !unit_fast(c.ak);
   d.b_nfast = unit_fast(c.bn) || !unit_fast(c.bk);
-  return launch(ctx, !strided, d, c.batch, A, B, C, alpha, beta);
+  return launch(ctx, !strided, d, c.batch, A, B, C, alpha, beta, prec);
 }
 
 int gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, bool ta, const double* B,

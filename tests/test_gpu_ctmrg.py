@@ -130,6 +130,46 @@ def test_converged_energy_parity(ctx):
     assert abs(eg - er) < 1e-10 * abs(er)
 
 
+@pytest.mark.parametrize("precision,u_in", [("fp32", 2.0 ** -24), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("M,N,K,ta,tb", [(300, 200, 700, False, False), (2592, 96, 2592, True, False),
+                                         (65, 130, 33, False, True)])
+def test_reduced_precision_gemm(ctx, precision, u_in, M, N, K, ta, tb):
+    """Operands rounded to fp32 / bf16, fp32 accumulation: elementwise error
+    within (2 u_in + K u_fp32) (|A| |B|)."""
+    rng = np.random.default_rng(M + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    Ae, Be = (A.T if ta else A), (B.T if tb else B)
+    ref = Ae @ Be
+    bound = (2 * u_in + K * 2.0 ** -24) * (np.abs(Ae) @ np.abs(Be))
+    C = dev(np.zeros((M, N)))
+    ctx.gemm(dev(A), dev(B), C, ta=ta, tb=tb, precision=precision)
+    err = np.abs(host(C) - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+    # and it is not silently FP64
+    assert err.max() > 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_precision_form_converges_to_fp64_energy(ctx, precision):
+    """Bulk contractions in fp32 / bf16 until their delta stalls, then FP64
+    iterations to tol: the energy agrees with the oracle's converged FP64
+    CTMRG to 1e-10 relative (stated tolerance of the precision form)."""
+    D, chi = 3, 32
+    Lx, Ly, cell, sites, C, T = _setup(tninputs.CHECKERBOARD, D, chi, seed=0)
+    ocell = octm.Cell(Lx, Ly, cell)
+    Cr, Tr, itr, dr = octm.ctmrg(ocell, sites, C, T, chi, max_iter=100, tol=1e-11)
+    er = opeps.energy_per_site(ocell, sites, Cr, Tr, 1.0, 3.0)
+    Cg, Tg = dev(C), dev(T)
+    sg = dev(np.stack(sites))
+    ctx.clear_cache()
+    rc, it, delta = ctx.ctmrg_iterate(Lx, Ly, sg, cell, Cg, Tg, 100, 1e-10, precision=precision,
+                                      n_polish=3)
+    eg = ctx.ipeps_energy(Lx, Ly, sg, cell, Cg, Tg, 1.0, 3.0)
+    assert rc == tn.TN_OK and delta < 1e-10
+    assert abs(eg - er) < 1e-10 * abs(er)
+
+
 def test_invalid_arguments_are_rejected(ctx):
     sites = dev(np.zeros((1, 2, 2, 2, 2, 2)))
     C, T = dev(np.zeros((1, 4, 4, 4))), dev(np.zeros((1, 4, 4, 2, 2, 4)))
@@ -137,6 +177,8 @@ def test_invalid_arguments_are_rejected(ctx):
         ctx.ctmrg_moves(1, 1, sites, [3], C, T, 1)          # site index out of range
     with pytest.raises(tn.TNError):
         ctx.ctmrg_iterate(1, 1, sites, [0], C, T, 0, 1e-8)  # max_iter < 1
+    with pytest.raises(tn.TNError):
+        ctx.ctmrg_iterate(1, 1, sites, [0], C, T, 5, 1e-8, n_polish=-1)
 
 
 @pytest.mark.parametrize("cellspec,D,chi", [(tninputs.CHECKERBOARD, 3, 32),
