@@ -78,6 +78,103 @@ def cpu_baseline(sites, C, T, chi, cell, moves):
     return moves / dt, dt
 
 
+def run_chain(args):
+    """The 1D workload: two-site iMPS, chi = 16, J = h = 1, dt = 0.01, 2000
+    steps from seeded N(0,1) tensors, plain (environment every step) and
+    recycled (every 20 steps after gauge fixing); energy against -4/pi."""
+    import math
+    import numpy as np
+    import torch
+    import paper_1411_0391_amd as tn
+    import tninputs
+    chi, nsteps, n_re = 16, args.chain_steps, 20
+    ga, _, gb, _ = tninputs.imps_two_site(0, chi)
+    A0 = np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)])
+    ctx = tn.Context()
+    out = {"metric": "1D iTEBD step time and energy, recycled vs plain", "unit": "ms/step",
+           "config": {"workload": f"TFIM chain, two-site iMPS, chi={chi}, J=h=1, dt=0.01, "
+                                  f"{nsteps} steps, N_Re={n_re}", "chi": chi, "steps": nsteps},
+           "data": "synthetic", "dtype": "f64", "n_gpus": 1}
+    exact = -4.0 / math.pi
+    for label, recyc in (("plain", False), ("recycled", True)):
+        A = torch.from_numpy(A0.copy()).to("cuda")
+        env = ctx.env1d(chi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = None
+        for step in range(nsteps):
+            last = step == nsteps - 1
+            if not recyc:
+                _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, energy=last)
+            elif step % n_re == 0:
+                _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, mode=tn.TN_RECYCLE_BUILD,
+                                          energy=last)
+            else:
+                _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, mode=tn.TN_RECYCLE_APPLY,
+                                          energy=last)
+            if last:
+                e = e1
+            if step % 500 == 499:
+                print(f"[bench] chain {label} step {step + 1}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[label] = {"ms_per_step": round(1e3 * dt / nsteps, 4), "seconds": round(dt, 3),
+                      "energy": e, "error_vs_exact": abs(e - exact)}
+    out["value"] = out["recycled"]["ms_per_step"]
+    out["speedup_recycled_over_plain"] = round(out["plain"]["seconds"] /
+                                               out["recycled"]["seconds"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def run_full_update(args):
+    """The 2D full-update workload: checkerboard, D = 4, chi = 32, J = 1,
+    h = 3.0, dt = 0.01, CTMRG tolerance 1e-10, from seeded N(0,1) sites and a
+    positive random boundary; plain (environment every step) and recycled
+    (N_Re = 20 after --fu-warm plain steps, an environment step recycled
+    only when its gauge fix reaches F >= 1 - 1e-3).  Time-to-1e-6: wall time
+    until the energy at an environment step is within 1e-6 (relative) of
+    E_ref, the energy the plain run ends with."""
+    import numpy as np
+    import torch
+    import paper_1411_0391_amd as tn
+    from paper_1411_0391_amd import driver
+    import tninputs
+    D, chi, nsteps = 4, 32, args.fu_steps
+    Lx, Ly, cell = tninputs.CHECKERBOARD
+    cell = list(cell)
+    A0 = np.stack(tninputs.ipeps_sites(0, 2, D))
+    C0, T0 = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
+    ctx = tn.Context()
+    runs = {}
+    for label, n_re, n_warm in (("plain", 1, 0), ("recycled", 20, args.fu_warm)):
+        C = torch.from_numpy(C0.copy()).to("cuda")
+        T = torch.from_numpy(T0.copy()).to("cuda")
+        ctx.clear_cache()
+
+        def cb(step, e, label=label):
+            if step % 20 == 0:
+                print(f"[bench] fu {label} step {step + 1} E {e:.12f}", file=sys.stderr, flush=True)
+
+        _, log = driver.full_update(ctx, Lx, Ly, cell, torch.from_numpy(A0.copy()).to("cuda"),
+                                    C, T, 1.0, 3.0, 0.01, nsteps, n_re=n_re, n_warm=n_warm,
+                                    min_fidelity=1 - 1e-3, callback=cb)
+        runs[label] = log
+    e_ref = runs["plain"][-1][1]
+    out = {"metric": "time-to-1e-6 energy, recycled vs plain (2D full update)", "unit": "s",
+           "config": {"workload": f"TFIM iPEPS full update, checkerboard, D={D}, chi={chi}, "
+                                  f"h=3.0, dt=0.01, {nsteps} steps, CTMRG tol 1e-10",
+                      "D": D, "chi": chi, "steps": nsteps, "N_Re": 20,
+                      "N_warm": args.fu_warm, "min_fidelity": 1 - 1e-3},
+           "data": "synthetic", "dtype": "f64", "n_gpus": 1,
+           "E_ref": e_ref, "E_ref_definition": "energy per site at the last step of the plain run"}
+    for label, log in runs.items():
+        hit = next((t for _, e, t in log if abs(e - e_ref) <= 1e-6 * abs(e_ref)), None)
+        out[label] = {"seconds": round(log[-1][2], 3), "env_steps": len(log),
+                      "final_energy": log[-1][1], "time_to_1e-6": hit}
+    out["value"] = out["recycled"]["time_to_1e-6"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +188,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
+    ap.add_argument("--chain", action="store_true", help="run the 1D workload instead")
+    ap.add_argument("--chain-steps", type=int, default=2000)
+    ap.add_argument("--fu", action="store_true",
+                    help="run the 2D full-update time-to-1e-6 workload instead")
+    ap.add_argument("--fu-steps", type=int, default=500)
+    ap.add_argument("--fu-warm", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the method's environment "
@@ -99,6 +202,12 @@ def main():
 
     if args.copy_calibrate:
         copy_calibration(args.copy_calibrate)
+        return
+    if args.chain:
+        run_chain(args)
+        return
+    if args.fu:
+        run_full_update(args)
         return
 
     import numpy as np

@@ -376,6 +376,18 @@ int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, dou
            double* V);
 
 /*
+ * tn_cholesky_inv -- the library's small dense FP64 Cholesky (used by the
+ * Cholesky-QR orthonormalisation of the projector SVD and the ALS solves),
+ * for testing and measurement: for `batch` row-major k x k matrices G stored
+ * back to back (k <= 137), the upper factor R of G + shift I with
+ * shift = shift_rel tr(G), G + shift I = R^T R, and its inverse Rinv (device
+ * outputs of the same shape).  info (host, batch ints): 0, or the index + 1
+ * of the first non-positive pivot (then R and Rinv are unspecified).
+ */
+int tn_cholesky_inv(tn_ctx* ctx, int batch, int k, const double* G, double shift_rel, double* R,
+                    double* Rinv, int* info);
+
+/*
  * tn_clear_cache -- drop the state the context keeps between calls: the
  * start bases of the projector SVDs of ctmrg_iterate / ctmrg_moves (kept per
  * cell geometry so that a converging CTMRG restarts its subspace iterations

@@ -45,6 +45,8 @@ SIGNATURES = {
                                ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int]),
     "tn_clear_cache": (ctypes.c_int, [_vp]),
+    "tn_cholesky_inv": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double, _vp,
+                                       _vp, _c_int_p]),
     "tn_env1d_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "tm_fixed_point": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                       _vp, _vp, _c_double_p, ctypes.c_double, ctypes.c_int,
@@ -337,6 +339,17 @@ class Context:
         V = torch.empty((b, n, n), dtype=torch.float64, device=A.device)
         self._check(lib().tn_svd(self._h, b, m, n, _ptr(A), _ptr(U), _ptr(S), _ptr(V)))
         return U, S, V
+
+    def cholesky_inv(self, G, shift_rel=0.0):
+        """Batched Cholesky of device G [batch][k][k] -> (R, Rinv, info)."""
+        import torch
+        b, k, _ = G.shape
+        R = torch.empty_like(G)
+        Ri = torch.empty_like(G)
+        info = (ctypes.c_int * b)()
+        self._check(lib().tn_cholesky_inv(self._h, b, k, _ptr(G), shift_rel, _ptr(R), _ptr(Ri),
+                                          info))
+        return R, Ri, list(info)
 
     def clear_cache(self):
         self._check(lib().tn_clear_cache(self._h))

@@ -300,6 +300,22 @@ int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, dou
   return TN_OK;
 }
 
+int tn_cholesky_inv(tn_ctx* ctx, int batch, int k, const double* G, double shift_rel, double* R,
+                    double* Rinv, int* info) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  if (batch < 1 || k < 1 || k > 137 || !G || !R || !Rinv || !info)
+    TN_FAIL(ctx, TN_EINVAL, "tn_cholesky_inv needs batch >= 1, 1 <= k <= 137 (k=%d)", k);
+  TN_TRY(ws_reserve(ctx, (size_t)batch * sizeof(int) + (1 << 16)));
+  ws_reset(ctx);
+  int* dinfo = ws_alloc<int>(ctx, batch);
+  if (!dinfo) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted");
+  TN_TRY(cholesky_inv(ctx, k, G, shift_rel, R, Rinv, dinfo, batch));
+  TN_HIP(ctx, hipMemcpyAsync(info, dinfo, batch * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return TN_OK;
+}
+
 int tn_clear_cache(tn_ctx* ctx) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();

@@ -413,6 +413,31 @@ int orth_robust(tn_ctx* ctx, int n, int k, int batch, double* X, const double* s
   return TN_OK;
 }
 
+// Orthonormalisation of a Ritz-ordered block without a host round trip: the
+// column pre-scaling by `scale` makes the block nearly orthonormal, and two
+// plain Cholesky-QR passes follow.  The Cholesky status of every pass and
+// problem goes to info[4 * batch] and is checked by the caller later; a
+// breakdown is then redone through orth_robust.
+int orth_fast(tn_ctx* ctx, int n, int k, int batch, double* X, const double* scale,
+              double* Rout, double* tmp, int* info) {
+  const size_t mark = ctx->arena_off;
+  double* sc = ws_alloc<double>(ctx, (size_t)batch * k);
+  if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in orth_fast");
+  const long long tot = (long long)batch * n * k;
+  hipLaunchKernelGGL(inv_scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, n, k, batch, X, scale, 1e-15, sc);
+  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(cholqr_passes(ctx, n, k, batch, X, Rout, tmp, info, 2, 0));
+  if (Rout) {
+    const long long tk = (long long)batch * k * k;
+    hipLaunchKernelGGL(right_scale_kernel, dim3((unsigned)((tk + 255) / 256)), dim3(256), 0,
+                       ctx->stream, k, batch, Rout, sc);
+    TN_HIP(ctx, hipGetLastError());
+  }
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
 struct SvdStats {
   long long iters = 0, calls = 0, unconverged = 0, explicit_calls = 0;
 };
@@ -472,7 +497,11 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   double* colres = ws_alloc<double>(ctx, (size_t)B * chi);
   double* res = ws_alloc<double>(ctx, 1);
   int* info = ws_alloc<int>(ctx, 8 * B);
-  if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
+  int* info_b = ws_alloc<int>(ctx, 4 * B);  // orth of K^T Q, this iteration
+  int* info_q = ws_alloc<int>(ctx, 4 * B);  // orth of the previous K W
+  double* Ysave = ws_alloc<double>(ctx, bnk);
+  double* Ssave = ws_alloc<double>(ctx, (size_t)B * k);
+  if (!Ssave) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
   const long long kk = (long long)k * k, snk = (long long)nk;
   bool have_s = false;
   if (warmQ && warm_valid) {
@@ -485,11 +514,23 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     TN_TRY(fill_random(ctx, Q, (long long)bnk, seed));
   }
   TN_TRY(orth_robust(ctx, n, k, B, Q, nullptr, nullptr, tmp, save, info));
+  // One host round trip per iteration: the orthonormalisations of a warm,
+  // Ritz-scaled block run without checking their Cholesky status at once;
+  // the status comes back with the residual, and a breakdown redoes the
+  // iteration through the robust path (from the saved K W of the previous
+  // iteration when the current basis is the one that broke down).
+  bool q_pending = false, robust = false;
+  int retries = 0;
   int it = 0;
   double hres = 1.0;
+  int* hinfo = reinterpret_cast<int*>(ctx->host_scratch + 8);
   for (it = 1; it <= maxit; ++it) {
     TN_TRY(applyKT(ctx, t, Q, Bm));
-    TN_TRY(orth_robust(ctx, n, k, B, Bm, have_s ? Sprev : nullptr, R, tmp, save, info));
+    const bool fast = have_s && !robust;
+    if (fast)
+      TN_TRY(orth_fast(ctx, n, k, B, Bm, Sprev, R, tmp, info_b));
+    else
+      TN_TRY(orth_robust(ctx, n, k, B, Bm, have_s ? Sprev : nullptr, R, tmp, save, info));
     TN_TRY(jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk));
     TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
     TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
@@ -500,12 +541,42 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
                        res);
     TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, res, sizeof(double), hipMemcpyDeviceToHost,
                                ctx->stream));
+    if (fast)
+      TN_HIP(ctx, hipMemcpyAsync(hinfo, info_b, 2 * B * sizeof(int), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    if (q_pending)
+      TN_HIP(ctx, hipMemcpyAsync(hinfo + 2 * B, info_q, 2 * B * sizeof(int),
+                                 hipMemcpyDeviceToHost, ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    bool bad_b = false, bad_q = false;
+    for (int i = 0; i < 2 * B; ++i) {
+      bad_b = bad_b || (fast && hinfo[i] != 0);
+      bad_q = bad_q || (q_pending && hinfo[2 * B + i] != 0);
+    }
+    if (bad_q || bad_b) {
+      if (++retries > 2) TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
+      if (bad_q) {  // the basis of this iteration was not orthonormal
+        TN_HIP(ctx, hipMemcpyAsync(Q, Ysave, bnk * sizeof(double), hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        TN_TRY(orth_robust(ctx, n, k, B, Q, Ssave, nullptr, tmp, save, info));
+      }
+      q_pending = false;
+      robust = true;
+      --it;
+      continue;
+    }
+    q_pending = false;
+    robust = false;
     hres = ctx->host_scratch[0];
     if (!std::isfinite(hres)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite residual in the projector SVD");
     if (hres <= tol || it == maxit) break;
+    TN_HIP(ctx, hipMemcpyAsync(Ysave, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(Ssave, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
     TN_HIP(ctx, hipMemcpyAsync(Q, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    TN_TRY(orth_robust(ctx, n, k, B, Q, S, nullptr, tmp, save, info));
+    TN_TRY(orth_fast(ctx, n, k, B, Q, S, nullptr, tmp, info_q));
+    q_pending = true;
     TN_HIP(ctx, hipMemcpyAsync(Sprev, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
     have_s = true;
@@ -756,9 +827,10 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
   (void)warm;
   add(Lm * (16 * n * k + 64 * (size_t)k * k));  // split-K partials of the n x n x k products
   // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
-  add(std::max(Lm * 7 * n * k, 4 * n * n + n));
+  add(std::max(Lm * 8 * n * k, 4 * n * n + n));
   add(Lm * 3 * k * k);
-  add(Lm * (3 * k + chi) + 64);
+  add(Lm * (4 * k + chi) + 64);
+  add(Lm * 16 + 64);
   add(Lm * (8 * k * k + k) + 64);                 // Cholesky-QR passes (one alive at a time)
   add(Lm * (2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k));  // jacobi work
   // rotated sites

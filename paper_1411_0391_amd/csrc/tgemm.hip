@@ -56,36 +56,41 @@ __device__ inline long long offC(const TDesc& d, int m, int n) {
   return (long long)m * d.scm + (long long)n * d.scn;
 }
 
-// 256 threads = 4 waves; each wave owns a 32x32 quarter of the 64x64 tile as
-// 2x2 MFMA blocks.  Operand tiles are staged through two LDS buffers: the
+// 256 threads = 4 waves; the 64 x TBN tile (TBN = 64, 96 or 128) is split
+// 2 x 2 between the waves, each owning 32 x TBN/2 as 2 x TBN/32 MFMA blocks.
+// The wide tiles serve products with a narrow N (the n x n x k products of
+// the projector SVD): the whole width is one tile, so the large operand is
+// streamed once.  Operand tiles are staged through two LDS buffers: the
 // next k-slice is fetched into registers while the MFMAs consume the current
 // one.  With split-K each z-slice of the grid sums one chunk of k into a
 // partial tile; a second kernel reduces the partials in a fixed order.
-template <bool TABLE>
+template <bool TABLE, int TBN>
 __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict__ A,
                                                         const double* __restrict__ B,
                                                         double* __restrict__ C, TDesc d,
                                                         double alpha, double beta) {
+  constexpr int NB = TBN * BK / 256;  // B elements a thread stages per slice
+  constexpr int NJ = TBN / 32;        // MFMA column blocks per wave
   __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  __shared__ double Bs[2][BK][TBN + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * TBN;
   const int split = blockIdx.z % d.ksplit;
   const long long bz = blockIdx.z / d.ksplit;
   A += bz * d.sa;
   B += bz * d.sb;
   const int kbeg = split * d.kchunk;
   const int kend = min(d.K, kbeg + d.kchunk);
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  d4 acc[2][2];
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * (TBN / 2);
+  d4 acc[2][NJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // per-thread coordinates of its 4 A and 4 B tile elements
-  int am_[4], ak_[4], bk_[4], bn_[4];
+  // per-thread coordinates of its 4 A and NB B tile elements
+  int am_[4], ak_[4], bk_[NB], bn_[NB];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (d.a_mfast) {
@@ -95,30 +100,36 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
       ak_[i] = tid & 15;
       am_[i] = (tid >> 4) + 16 * i;
     }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int e = tid + 256 * i;
     if (d.b_nfast) {
-      bn_[i] = tid & 63;
-      bk_[i] = (tid >> 6) + 4 * i;
+      bn_[i] = e % TBN;
+      bk_[i] = e / TBN;
     } else {
-      bk_[i] = tid & 15;
-      bn_[i] = (tid >> 4) + 16 * i;
+      bk_[i] = e % BK;
+      bn_[i] = e / BK;
     }
   }
-  double ra[4], rb[4];
+  double ra[4], rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = m0 + am_[i], k = k0 + ak_[i];
       ra[i] = (m < d.M && k < kend) ? A[offA<TABLE>(d, m, k)] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
       const int n = n0 + bn_[i], kb = k0 + bk_[i];
       rb[i] = (n < d.N && kb < kend) ? B[offB<TABLE>(d, kb, n)] : 0.0;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      As[buf][ak_[i]][am_[i]] = ra[i];
-      Bs[buf][bk_[i]][bn_[i]] = rb[i];
-    }
+    for (int i = 0; i < 4; ++i) As[buf][ak_[i]][am_[i]] = ra[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Bs[buf][bk_[i]][bn_[i]] = rb[i];
   };
   int buf = 0;
   if (kbeg < kend) {
@@ -131,15 +142,15 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
     if (more) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double a[2], b[2];
+      double a[2], b[NJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[buf][kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < NJ; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) stash(buf ^ 1);
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
@@ -170,7 +181,7 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
@@ -391,7 +402,10 @@ namespace {
 // grid has enough workgroups to occupy the 256 compute units.
 int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const double* B,
            double* C, double alpha, double beta, int prec) {
-  const long long tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  // FP64: one tile across a narrow N (65..128 columns)
+  const int tbn = (prec == P_F64 && d.N > 64 && d.N <= 96) ? 96
+                  : (prec == P_F64 && d.N > 96 && d.N <= 128) ? 128 : BN;
+  const long long tm = (d.M + BM - 1) / BM, tn = (d.N + tbn - 1) / tbn;
   const long long tiles = tm * tn * batch;
   int ksplit = 1;
   const int kstep = prec == P_BF16 ? 32 : BK;  // k slice of the kernel
@@ -430,12 +444,21 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
     TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
   if (prec == P_F64) {
-    if (table)
-      hipLaunchKernelGGL(tgemm_f64_kernel<true>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
-                         alpha, beta);
-    else
-      hipLaunchKernelGGL(tgemm_f64_kernel<false>, grid, dim3(256), 0, ctx->stream, A, B, C, d,
-                         alpha, beta);
+#define TN_LAUNCH_F64(TB)                                                                   \
+  if (table)                                                                                \
+    hipLaunchKernelGGL((tgemm_f64_kernel<true, TB>), grid, dim3(256), 0, ctx->stream, A, B, C, \
+                       d, alpha, beta);                                                     \
+  else                                                                                      \
+    hipLaunchKernelGGL((tgemm_f64_kernel<false, TB>), grid, dim3(256), 0, ctx->stream, A, B,  \
+                       C, d, alpha, beta);
+    if (tbn == 96) {
+      TN_LAUNCH_F64(96)
+    } else if (tbn == 128) {
+      TN_LAUNCH_F64(128)
+    } else {
+      TN_LAUNCH_F64(64)
+    }
+#undef TN_LAUNCH_F64
   } else if (prec == P_F32) {
     if (table)
       hipLaunchKernelGGL((tgemm_lp_kernel<false, true>), grid, dim3(256), 0, ctx->stream, A, B, C,

@@ -18,13 +18,17 @@ import time
 
 def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm=0,
                 ctm_tol=1e-10, ctm_max=100, als_tol=1e-12, als_max=50, canon_tol=1e-14,
-                canon_max=1000, gauge_tol=1e-12, gauge_max=1000, callback=None):
+                canon_max=1000, gauge_tol=1e-12, gauge_max=1000, min_fidelity=None,
+                callback=None):
     """Evolve the iPEPS ``sites`` (device [nsite][d][D]^4) for ``nsteps``
     steps of size dt.  C, T (device) are the start environment and are
     updated in place.  Returns (sites, log) with log entries
     (step, energy_per_site, seconds since start) at environment steps; the
     environment is recomputed every ``n_re`` steps after ``n_warm`` plain
-    steps."""
+    steps.  With ``min_fidelity``, an environment step whose gauge fix ends
+    below that fidelity (the new state is too far from the previous one for
+    its gate to stand in for the environment) is not recycled: the
+    evolution continues with the plain step."""
     import torch
     D = sites.shape[2]
     kappa = 2
@@ -52,7 +56,11 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
         a1, _, Pc, Qc, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, new, tol=canon_tol,
                                                       max_iter=canon_max)
         U = ctx.fu_gauge_start(P, Q, Pc, Qc, kappa)
-        ctx.gauge_fix(Lx, Ly, cell, sites, a1, U, tol=gauge_tol, max_iter=gauge_max)
+        F, _, _ = ctx.gauge_fix(Lx, Ly, cell, sites, a1, U, tol=gauge_tol, max_iter=gauge_max)
+        if min_fidelity is not None and F < min_fidelity:
+            sites = new
+            step += 1
+            continue
         Rf, Lf = ctx.fu_renormalized_gate(P, Q, Pc, Qc, U)
         sites = ctx.ipeps_truncate(Lx, Ly, cell, Th, Rf, Lf)
         step += 1

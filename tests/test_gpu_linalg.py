@@ -15,6 +15,14 @@ def ctx():
     c.close()
 
 
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
 def _graded(rng, n, decades):
     q1, _ = np.linalg.qr(rng.standard_normal((n, n)))
     q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
@@ -65,3 +73,24 @@ def test_svd_near_diagonal_converges_fast(ctx):
     ctx.prof_enable(False)
     print("sweeps", st["jacobi_sweeps"])
     assert st["jacobi_sweeps"] <= 6
+
+
+@pytest.mark.parametrize("k", [1, 7, 16, 33, 96, 128])
+def test_cholesky_inv_parity(ctx, k):
+    """Blocked Cholesky and its inverse against LAPACK on SPD matrices, and a
+    failing pivot reported on an indefinite one."""
+    rng = np.random.default_rng(k)
+    A = rng.standard_normal((2, k + 5, k))
+    G = np.einsum("bik,bil->bkl", A, A)
+    R, Ri, info = ctx.cholesky_inv(dev(G))
+    assert info == [0, 0]
+    for b in range(2):
+        Rr = np.linalg.cholesky(G[b]).T
+        np.testing.assert_allclose(np.triu(host(R)[b]), Rr, rtol=0, atol=1e-12 * np.abs(Rr).max())
+        np.testing.assert_allclose(host(Ri)[b] @ Rr, np.eye(k), rtol=0,
+                                   atol=1e-10 * np.linalg.cond(Rr))
+    if k > 1:
+        Gbad = G.copy()
+        Gbad[1] = -Gbad[1]
+        _, _, info = ctx.cholesky_inv(dev(Gbad))
+        assert info[0] == 0 and info[1] == 1
