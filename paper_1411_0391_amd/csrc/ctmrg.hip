@@ -223,6 +223,167 @@ struct Geo {
 };
 
 // ---------------------------------------------------------------------------
+// Absorption of one site into a half-contracted network, ket and bra layers in
+// one kernel:
+//   Out[c,a,rk,dk,rb,db] = sum_{s,lk,uk,lb,ub} In[c,a,lk,uk,lb,ub]
+//                              A[s,lk,rk,dk,uk] A[s,lb,rb,db,ub]
+// (the site-tensor step of the enlarged corners and of the edge
+// renormalisation, Sec. VI B).  Read as matrices over index pairs of
+// P = D^2 entries, with Am[s] the P x P matrix Am[s][(l,u)][(r,dn)] =
+// A[s,l,r,dn,u], the product is two chained small GEMMs per (c, a) pair:
+//   T[(l,u')][s][R1] = sum_K1 In[K1][(l,u')] Am[s][K1][R1]    (ket layer)
+//   Out[R1][R2]      = sum_{s,L} T[L][s][R1] Am[s][L][R2]      (bra layer)
+// A workgroup takes G = 4 consecutive (c, a) pairs and one wave per 16 rows
+// of the stacked G*P rows.  Both products are FP64 MFMA 16x16x4 tiles with
+// the same B operand, Am[s] staged in LDS; the ket result passes to the bra product through LDS (transposed), one
+// physical index s at a time, so the 2 d D^4-entry intermediate of every
+// pair never reaches HBM.  In and Out are addressed by strides, so the same
+// kernel serves both index layouts.
+// ---------------------------------------------------------------------------
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+struct AbsorbDesc {
+  long long in_c, in_a, in_lk, in_uk, in_lb, in_ub;
+  long long out_c, out_a, out_rk, out_dk, out_rb, out_db;
+  int nc, na, d;
+};
+
+constexpr int ABS_G = 4;
+
+template <int D>
+constexpr int absorb_threads() {
+  return 64 * ((ABS_G * D * D + 15) / 16);
+}
+
+template <int D>
+__global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
+    const double* __restrict__ In, const double* __restrict__ A, double* __restrict__ Out,
+    AbsorbDesc g) {
+  constexpr int P = D * D;
+  constexpr int ROWS = ABS_G * P;
+  constexpr int NJ = (P + 15) / 16;  // 16-column blocks over P
+  constexpr int NQ = (P + 3) / 4;    // k-steps of 4 over P
+  constexpr int S = NJ * 16 + 1;     // LDS row stride (odd)
+  __shared__ double Ts[ROWS * S];
+  __shared__ double Bs[NQ * 4 * S];
+  const int lane = threadIdx.x & 63, blk = threadIdx.x >> 6;
+  const int hi = lane >> 4, lo = lane & 15;
+  const long long npair = (long long)g.nc * g.na;
+  const long long p0 = (long long)blockIdx.x * ABS_G;
+  // operand-A row of this lane: m = 16 blk + lo, i.e. pair m / P, index pair m % P
+  const int mA = 16 * blk + lo;
+  const int aA = mA / P, LA = mA % P;
+  const bool rowA = mA < ROWS;
+  const bool okA = rowA && p0 + aA < npair;
+  double inA[NQ];
+  {
+    long long base = 0;
+    if (okA) {
+      const long long pr = p0 + aA, c = pr / g.na, a = pr % g.na;
+      base = c * g.in_c + a * g.in_a + (long long)(LA / D) * g.in_lb + (long long)(LA % D) * g.in_ub;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k1 = 4 * q + hi;
+      inA[q] = (okA && k1 < P)
+                   ? In[base + (long long)(k1 / D) * g.in_lk + (long long)(k1 % D) * g.in_uk]
+                   : 0.0;
+    }
+  }
+  dv4 acc2[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc2[j] = dv4{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < g.d; ++s) {
+    // Am[s] into LDS, zero-padded to NQ*4 rows and NJ*16 columns: the B
+    // operand of both products, Bs[4q + lane/16][16j + lane%16]
+    for (int t = threadIdx.x; t < NQ * 4 * NJ * 16; t += blockDim.x) {
+      const int row = t / (NJ * 16), col = t % (NJ * 16);
+      Bs[row * S + col] = (row < P && col < P)
+                              ? A[(long long)s * P * P + (row / D) * D * P + (col / D) * P +
+                                  (col % D) * D + (row % D)]
+                              : 0.0;
+    }
+    __syncthreads();
+    // ket layer: rows (pair, l, u') of this wave, all columns R1
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      dv4 acc1 = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(inA[q], Bs[(4 * q + hi) * S + 16 * j + lo],
+                                                    acc1, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * blk + hi + 4 * r;
+        if (row < ROWS) Ts[row * S + 16 * j + lo] = acc1[r];
+      }
+    }
+    __syncthreads();
+    // bra layer: rows (pair, R1) of this wave, k over (l, u') of the same pair
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int L = 4 * q + hi;
+      const double a2 = (rowA && L < P) ? Ts[(aA * P + L) * S + LA] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        acc2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, Bs[(4 * q + hi) * S + 16 * j + lo],
+                                                       acc2[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * blk + hi + 4 * r;
+    const int ap = row / P, R1 = row % P;
+    const long long pr = p0 + ap;
+    if (row >= ROWS || pr >= npair) continue;
+    const long long c = pr / g.na, a = pr % g.na;
+    const long long base = c * g.out_c + a * g.out_a + (long long)(R1 / D) * g.out_rk +
+                           (long long)(R1 % D) * g.out_dk;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int R2 = 16 * j + lo;
+      if (R2 < P)
+        Out[base + (long long)(R2 / D) * g.out_rb + (long long)(R2 % D) * g.out_db] = acc2[j][r];
+    }
+  }
+}
+
+// Fused absorption for D = 2..6 in FP64; returns false (nothing launched)
+// for other bond dimensions or precisions, where the caller runs the two
+// products as separate contractions.
+bool absorb_site(tn_ctx* ctx, int D, int prec, const double* In, const double* A, double* Out,
+                 const AbsorbDesc& g) {
+  if (prec != P_F64 || D < 2 || D > 6) return false;
+  const long long npair = (long long)g.nc * g.na;
+  if (npair <= 0) return true;
+  const dim3 grid((unsigned)((npair + ABS_G - 1) / ABS_G));
+  switch (D) {
+    case 2:
+      hipLaunchKernelGGL(absorb_kernel<2>, grid, dim3(absorb_threads<2>()), 0, ctx->stream, In, A,
+                         Out, g);
+      break;
+    case 3:
+      hipLaunchKernelGGL(absorb_kernel<3>, grid, dim3(absorb_threads<3>()), 0, ctx->stream, In, A,
+                         Out, g);
+      break;
+    case 4:
+      hipLaunchKernelGGL(absorb_kernel<4>, grid, dim3(absorb_threads<4>()), 0, ctx->stream, In, A,
+                         Out, g);
+      break;
+    case 5:
+      hipLaunchKernelGGL(absorb_kernel<5>, grid, dim3(absorb_threads<5>()), 0, ctx->stream, In, A,
+                         Out, g);
+      break;
+    default:
+      hipLaunchKernelGGL(absorb_kernel<6>, grid, dim3(absorb_threads<6>()), 0, ctx->stream, In, A,
+                         Out, g);
+      break;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // contractions
 // ---------------------------------------------------------------------------
 
@@ -236,6 +397,19 @@ int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, con
               X1, (int)chi, 1.0, 0.0, 1, 0, 0, 0, g.prec));
   TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
               (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0, 1, 0, 0, 0, g.prec));
+  {
+    // X2[a, lk, lb, uk, ub, b] -> E[(a, dk, db), (b, rk, rb)], both layers at once
+    AbsorbDesc ad;
+    ad.in_c = D4 * chi, ad.in_a = 1, ad.in_lk = D2 * D * chi, ad.in_uk = D * chi;
+    ad.in_lb = D2 * chi, ad.in_ub = chi;
+    ad.out_c = D2 * n, ad.out_a = D2, ad.out_rk = D, ad.out_dk = D * n, ad.out_rb = 1;
+    ad.out_db = n;
+    ad.nc = (int)chi, ad.na = (int)chi, ad.d = (int)d;
+    if (absorb_site(ctx, (int)D, g.prec, X2, A, E, ad)) {
+      TN_HIP(ctx, hipGetLastError());
+      return TN_OK;
+    }
+  }
   Contraction c3;
   c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
   c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
@@ -567,9 +741,12 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     }
     q_pending = false;
     robust = false;
+    const double hprev = hres;
     hres = ctx->host_scratch[0];
     if (!std::isfinite(hres)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite residual in the projector SVD");
     if (hres <= tol || it == maxit) break;
+    // the rounding floor lies above tol: the residual has stopped falling
+    if (it >= 3 && hres <= 30.0 * tol && hres > 0.7 * hprev) break;
     TN_HIP(ctx, hipMemcpyAsync(Ysave, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
     TN_HIP(ctx, hipMemcpyAsync(Ssave, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
@@ -713,6 +890,18 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       a.cm = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
       a.cn = grp({{chi, D2}, {D, D}, {D, 1}});
       TN_TRY(tc_run(ctx, a, PtTm, T4, Y1, 1.0, 0.0, g.prec));
+      AbsorbDesc ad;  // Y1 -> Y3 with both layers in one kernel
+      ad.in_c = D2 * nn, ad.in_a = D2, ad.in_lk = D, ad.in_uk = D * nn, ad.in_lb = 1;
+      ad.in_ub = nn;
+      ad.out_c = D2 * nn, ad.out_a = D2, ad.out_rk = D * nn, ad.out_dk = D, ad.out_rb = nn;
+      ad.out_db = 1;
+      ad.nc = chi, ad.na = chi, ad.d = d;
+      // out of place: Y3 may not overwrite Y1 while other workgroups read it
+      const bool fused = absorb_site(ctx, D, g.prec, Y1, A, b.X3, ad);
+      if (fused) {
+        TN_HIP(ctx, hipGetLastError());
+        Y3 = b.X3;
+      }
       Contraction bk;  // Y2[c, a, rk, dk, s, lb, ub] = sum_{lk,uk} Y1[...] A[s,lk,rk,dk,uk]
       bk.am = grp({{chi, D2 * nn}, {D, nn}, {chi, D2}, {D, 1}});
       bk.ak = grp({{D, D}, {D, (long long)D * nn}});
@@ -720,7 +909,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       bk.bn = grp({{d, D2 * D2}, {D, D2}, {D, D}});
       bk.cm = grp({{chi, chi * dD4}, {D, 1}, {chi, dD4}, {D, D}});
       bk.cn = grp({{d, D2}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
-      TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0, g.prec));
+      if (!fused) TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0, g.prec));
       Contraction cb;  // Y3[c, rk, rb, a, dk, db] = sum_{s,lb,ub} Y2[...] A[s,lb,rb,db,ub]
       cb.am = grp({{chi, chi * dD4}, {chi, dD4}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
       cb.ak = grp({{d, D2}, {D, D}, {D, 1}});
@@ -728,7 +917,7 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       cb.bn = grp({{D, D2}, {D, D}});
       cb.cm = grp({{chi, D2 * nn}, {chi, D2}, {D, (long long)D * nn}, {D, D}});
       cb.cn = grp({{D, nn}, {D, 1}});
-      TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0, g.prec));
+      if (!fused) TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0, g.prec));
       Contraction dp;  // T4new[e, rk, rb, c] = sum_i Y3[c, rk, rb, i] P[i, e]
       dp.am = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
       dp.ak = grp({{(int)nn, 1}});

@@ -1,6 +1,7 @@
 // Small dense FP64 linear algebra on the device: one-sided Jacobi SVD,
 // Cholesky with inverse, and element-wise helpers.  One workgroup works on
 // one (small) matrix; batches run as a grid of workgroups.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -35,6 +36,63 @@ constexpr int SVD_WAVES = SVD_THREADS / 64;
 // live in dynamic LDS; otherwise in the global buffer `work`.  The choice is
 // a template parameter so that the LDS pointers are known to be LDS and the
 // accesses compile to LDS instructions rather than generic (flat) ones.
+// Singular values (column norms of the converged X), sorted descending with
+// ties by index, left vectors normalised and sign-fixed (the first entry
+// within a relative 1e-8 of the largest magnitude is made positive), right
+// vectors from the accumulated rotations W.
+__device__ __forceinline__ void jacobi_emit(const double* X, int ldx, const double* W, int ldw, int m, int n,
+                            double* colnorm, int* perm, long long b, double* __restrict__ U,
+                            int ldu, long long sU, double* __restrict__ S, long long sS,
+                            double* __restrict__ V, int ldv, long long sV) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwave = (int)blockDim.x >> 6;
+  // column norms = singular values
+  for (int j = wave; j < n; j += nwave) {
+    double a = 0.0;
+    for (int i = lane; i < m; i += 64) a += X[(long long)j * ldx + i] * X[(long long)j * ldx + i];
+    a = wave_sum(a);
+    if (lane == 0) colnorm[j] = sqrt(a);
+  }
+  __syncthreads();
+  // rank sort, descending, ties by index
+  for (int j = tid; j < n; j += (int)blockDim.x) {
+    int rank = 0;
+    const double sj = colnorm[j];
+    for (int i = 0; i < n; ++i) {
+      const double si = colnorm[i];
+      rank += (si > sj) || (si == sj && i < j);
+    }
+    perm[rank] = j;
+  }
+  __syncthreads();
+  // outputs; each left vector sign-fixed (largest-magnitude entry positive)
+  for (int r = wave; r < n; r += nwave) {
+    const int j = perm[r];
+    const double sj = colnorm[j];
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    // sign: the first entry within a relative 1e-8 of the largest magnitude
+    double best = 0.0;
+    for (int i = lane; i < m; i += 64) best = fmax(best, fabs(X[(long long)j * ldx + i]));
+    best = wave_max(best);
+    int bi = 0x7fffffff;
+    for (int i = lane; i < m; i += 64)
+      if (fabs(X[(long long)j * ldx + i]) >= (1.0 - 1e-8) * best) {
+        bi = i;
+        break;
+      }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bi = min(bi, __shfl_xor(bi, o, 64));
+    const double sg = (bi < m && X[(long long)j * ldx + bi] < 0.0) ? -1.0 : 1.0;
+    if (U)
+      for (int i = lane; i < m; i += 64)
+        U[b * sU + (long long)i * ldu + r] = sg * inv * X[(long long)j * ldx + i];
+    if (V)
+      for (int i = lane; i < n; i += 64)
+        V[b * sV + (long long)i * ldv + r] = sg * W[(long long)j * ldw + i];
+    if (S && lane == 0) S[b * sS + r] = sj;
+  }
+}
+
 template <bool GLOBAL_WORK>
 __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     const double* __restrict__ Ain, int lda, long long sA, double* __restrict__ U, int ldu,
@@ -160,51 +218,143 @@ __global__ __launch_bounds__(SVD_THREADS) void jacobi_svd_kernel(
     if (tid == 0 && sweep_count) atomicAdd(sweep_count, 1ULL);
     if (done) break;
   }
-  // column norms = singular values
-  for (int j = wave; j < n; j += SVD_WAVES) {
-    double a = 0.0;
-    for (int i = lane; i < m; i += 64) a += X[(long long)j * ldx + i] * X[(long long)j * ldx + i];
-    a = wave_sum(a);
-    if (lane == 0) colnorm[j] = sqrt(a);
+  jacobi_emit(X, ldx, W, ldw, m, n, colnorm, perm, b, U, ldu, sU, S, sS, V, ldv, sV);
+}
+
+// ---------------------------------------------------------------------------
+// The same one-sided Jacobi SVD for m, n <= 128 with the work matrix and the
+// rotation accumulator in LDS, organised for round latency: columns are
+// zero-padded to a multiple of 16 rows (so a 16-lane group reads a column
+// with unmasked loads), each group loads its pair of X and W columns at
+// once, the three dot products are reduced inside the group with row
+// rotations (DPP, no LDS round trip; every lane ends with the same sum), and
+// the round-robin pairing advances by increments instead of divisions.  One
+// barrier per round.  Results are those of jacobi_svd_kernel up to rounding.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ inline double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 16 lanes of a row by rotations of 8, 4, 2, 1 lanes
+__device__ inline double row_sum16(double v) {
+  v += dpp_row<0x128>(v);
+  v += dpp_row<0x124>(v);
+  v += dpp_row<0x122>(v);
+  v += dpp_row<0x121>(v);
+  return v;
+}
+
+constexpr int JF_MAX = 8;  // 16-row slices per column: m, n <= 128
+
+__global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
+    const double* __restrict__ Ain, int lda, long long sA, double* __restrict__ U, int ldu,
+    long long sU, double* __restrict__ S, long long sS, double* __restrict__ V, int ldv,
+    long long sV, int m, int n, int max_sweeps, double tol,
+    unsigned long long* __restrict__ sweep_count) {
+  extern __shared__ double lds[];
+  const long long b = blockIdx.x;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const double* A = Ain + b * sA;
+  const int me = (m + 15) >> 4, ne = (n + 15) >> 4;  // 16-row slices of X and W columns
+  const int ldx = 16 * me + 1, ldw = 16 * ne + 1;     // odd strides
+  double* X = lds;                                    // X[j * ldx + i], rows >= m zero
+  double* W = lds + (size_t)ldx * n;                  // W[j * ldw + i], rows >= n zero
+  __shared__ double colnorm[128];
+  __shared__ int perm[128];
+  __shared__ double off_g[64];
+  __shared__ int done;
+  for (int t = tid; t < ldx * n; t += nthr) {
+    const int j = t / ldx, i = t % ldx;
+    X[t] = i < m ? A[(long long)i * lda + j] : 0.0;
   }
-  __syncthreads();
-  // rank sort, descending, ties by index
-  for (int j = tid; j < n; j += SVD_THREADS) {
-    int rank = 0;
-    const double sj = colnorm[j];
-    for (int i = 0; i < n; ++i) {
-      const double si = colnorm[i];
-      rank += (si > sj) || (si == sj && i < j);
-    }
-    perm[rank] = j;
+  for (int t = tid; t < ldw * n; t += nthr) {
+    const int j = t / ldw, i = t % ldw;
+    W[t] = i == j ? 1.0 : 0.0;
   }
+  if (tid == 0) done = 0;
   __syncthreads();
-  // outputs; each left vector sign-fixed (largest-magnitude entry positive)
-  for (int r = wave; r < n; r += SVD_WAVES) {
-    const int j = perm[r];
-    const double sj = colnorm[j];
-    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-    // sign: the first entry within a relative 1e-8 of the largest magnitude
-    double best = 0.0;
-    for (int i = lane; i < m; i += 64) best = fmax(best, fabs(X[(long long)j * ldx + i]));
-    best = wave_max(best);
-    int bi = 0x7fffffff;
-    for (int i = lane; i < m; i += 64)
-      if (fabs(X[(long long)j * ldx + i]) >= (1.0 - 1e-8) * best) {
-        bi = i;
-        break;
-      }
+  const int grp = tid >> 4, gl = tid & 15;
+  const int N = (n + 1) & ~1;  // players incl. a dummy when n is odd
+  const bool active = grp < N / 2;
+  // round r pairs player 0 (group 0 only) or 1 + (grp - 1 + r) mod (N - 1)
+  // with 1 + (N - 2 - grp + r) mod (N - 1)
+  int u = grp >= 1 ? grp - 1 : 0, v = N - 2 - grp;
+  for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+    double offmax = 0.0;
+    for (int r = 0; r < N - 1; ++r) {
+      if (active) {
+        const int p0 = grp == 0 ? 0 : 1 + u, p1 = 1 + v;
+        if (p0 < n && p1 < n) {
+          const int p = min(p0, p1), q = max(p0, p1);
+          double* xp = X + p * ldx + gl;
+          double* xq = X + q * ldx + gl;
+          double* wp = W + p * ldw + gl;
+          double* wq = W + q * ldw + gl;
+          double xu[JF_MAX], xv[JF_MAX], wu[JF_MAX], wv[JF_MAX];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) bi = min(bi, __shfl_xor(bi, o, 64));
-    const double sg = (bi < m && X[(long long)j * ldx + bi] < 0.0) ? -1.0 : 1.0;
-    if (U)
-      for (int i = lane; i < m; i += 64)
-        U[b * sU + (long long)i * ldu + r] = sg * inv * X[(long long)j * ldx + i];
-    if (V)
-      for (int i = lane; i < n; i += 64)
-        V[b * sV + (long long)i * ldv + r] = sg * W[(long long)j * ldw + i];
-    if (S && lane == 0) S[b * sS + r] = sj;
+          for (int e = 0; e < JF_MAX; ++e)
+            if (e < me) {
+              xu[e] = xp[16 * e];
+              xv[e] = xq[16 * e];
+            }
+#pragma unroll
+          for (int e = 0; e < JF_MAX; ++e)
+            if (e < ne) {
+              wu[e] = wp[16 * e];
+              wv[e] = wq[16 * e];
+            }
+          double a = 0.0, bb = 0.0, g = 0.0;
+#pragma unroll
+          for (int e = 0; e < JF_MAX; ++e)
+            if (e < me) {
+              a += xu[e] * xu[e];
+              bb += xv[e] * xv[e];
+              g += xu[e] * xv[e];
+            }
+          a = row_sum16(a);
+          bb = row_sum16(bb);
+          g = row_sum16(g);
+          const double scale = sqrt(a * bb);
+          if (scale != 0.0 && fabs(g) > tol * scale) {
+            offmax = fmax(offmax, fabs(g) / scale);
+            const double z = (bb - a) / (2.0 * g);
+            const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+            for (int e = 0; e < JF_MAX; ++e)
+              if (e < me) {
+                xp[16 * e] = c * xu[e] - sn * xv[e];
+                xq[16 * e] = sn * xu[e] + c * xv[e];
+              }
+#pragma unroll
+            for (int e = 0; e < JF_MAX; ++e)
+              if (e < ne) {
+                wp[16 * e] = c * wu[e] - sn * wv[e];
+                wq[16 * e] = sn * wu[e] + c * wv[e];
+              }
+          }
+        }
+        u = u + 1 == N - 1 ? 0 : u + 1;
+        v = v + 1 == N - 1 ? 0 : v + 1;
+      }
+      __syncthreads();
+    }
+    if (gl == 0 && active) off_g[grp] = offmax;
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int w = 0; w < N / 2; ++w) mx = fmax(mx, off_g[w]);
+      done = (mx <= tol) ? 1 : 0;
+      if (sweep_count) atomicAdd(sweep_count, 1ULL);
+    }
+    __syncthreads();
+    if (done) break;
   }
+  jacobi_emit(X, ldx, W, ldw, m, n, colnorm, perm, b, U, ldu, sU, S, sS, V, ldv, sV);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,6 +443,138 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same factorisation and inverse for k <= 128 with the trailing matrix in
+// registers: thread (ty, tx) of a 32 x 32 grid holds the entries of rows
+// ty + 32a and columns tx + 32b (a, b < 4).  Cholesky step j: the 32 threads
+// holding row j scale it by 1/sqrt(pivot) and publish it as row j of R in
+// LDS; after one barrier every thread applies W[r][c] -= R[j][r] R[j][c] to
+// its 16 entries (entries of finished rows and columns are updated too and
+// never read again).  Inverse by the column sweep X = R^-1: B = I; for
+// j = k-1 .. 0 the holders of row j publish X[j][:] = B[j][:] / R[j][j] (a
+// double-buffered LDS row), then every thread applies
+// B[i][c] -= R[i][j] X[j][c].  One barrier per step in both parts.
+// ---------------------------------------------------------------------------
+constexpr int CHOLR_MAX = 128;
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __restrict__ G, int k,
+                                                                double shift_rel,
+                                                                double* __restrict__ R,
+                                                                double* __restrict__ Rinv,
+                                                                int* __restrict__ info) {
+  extern __shared__ double lds[];
+  {
+    const long long off = (long long)blockIdx.x * k * k;  // one matrix per workgroup
+    G += off;
+    R += off;
+    Rinv += off;
+    info += blockIdx.x;
+  }
+  const int ldr = k | 1;
+  double* Rl = lds;                      // R, row j at Rl + j * ldr
+  double* xrow = lds + (size_t)k * ldr;  // [2][CHOLR_MAX], rows of X in flight
+  double* piv = xrow + 2 * CHOLR_MAX;    // [CHOLR_MAX], pivot of each step
+  const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+  __shared__ double shift;
+  if (tid < 64) {
+    double tr = 0.0;
+    for (int i = tid; i < k; i += 64) tr += G[i * k + i];
+    tr = wave_sum(tr);
+    if (tid == 0) shift = shift_rel * tr;
+  }
+  for (int t = tid; t < k * ldr; t += 1024) Rl[t] = 0.0;
+  __syncthreads();
+  double W[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 32 * a, c = tx + 32 * b;
+      W[a][b] = (r < k && c < k) ? G[r * k + c] + (r == c ? shift : 0.0) : 0.0;
+    }
+  int fail = 0;
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    for (int jj = 0; jj < 32 && !fail; ++jj) {
+      const int j = 32 * jb + jj;
+      if (j >= k) break;
+      if (ty == jj) {
+        // the pivot W[j][j] sits in lane 32 (jj & 1) + jj of this wave
+        const double d = readlane_d(W[jb][jb], ((jj & 1) << 5) + jj);
+        const double ir = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = tx + 32 * b;
+          if (c < k) {
+            const double v = c >= j ? W[jb][b] * ir : 0.0;
+            Rl[j * ldr + c] = v;
+            R[j * k + c] = v;
+          }
+        }
+        if (tx == 0) piv[j] = d;
+      }
+      __syncthreads();
+      if (!(piv[j] > 0.0)) {  // the same value in every thread
+        fail = j + 1;
+        break;
+      }
+      double rr[4], rc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) rr[a] = ty + 32 * a < k ? Rl[j * ldr + ty + 32 * a] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) rc[b] = tx + 32 * b < k ? Rl[j * ldr + tx + 32 * b] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) W[a][b] -= rr[a] * rc[b];
+    }
+  }
+  if (tid == 0) *info = fail;
+  if (fail) return;
+  // W is free: it becomes B = I
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) W[a][b] = (ty + 32 * a == tx + 32 * b) ? 1.0 : 0.0;
+#pragma unroll
+  for (int jb = 3; jb >= 0; --jb) {
+    for (int jj = 31; jj >= 0; --jj) {
+      const int j = 32 * jb + jj;
+      if (j >= k) continue;
+      double* xr = xrow + (j & 1) * CHOLR_MAX;
+      if (ty == jj) {
+        const double ir = 1.0 / Rl[j * ldr + j];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = tx + 32 * b;
+          if (c < k) {
+            const double x = W[jb][b] * ir;
+            xr[c] = x;
+            Rinv[j * k + c] = x;
+          }
+        }
+      }
+      __syncthreads();
+      double rr[4], xc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) rr[a] = ty + 32 * a < k ? Rl[(ty + 32 * a) * ldr + j] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) xc[b] = tx + 32 * b < k ? xr[tx + 32 * b] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) W[a][b] -= rr[a] * xc[b];
+    }
+  }
+}
+
 __global__ void scale_columns_kernel(int m, int n, double* X, int ldx, const double* s,
                                      int invsqrt, double cut) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -371,6 +653,19 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
   // rotations stop once every column pair is orthogonal to the rounding
   // level of its dot product (about m ulp), or the sweeps would never end
   const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
+  {
+    const int me = (m + 15) / 16, ne = (n + 15) / 16;
+    const size_t fast_bytes = (size_t)(16 * me + 1 + 16 * ne + 1) * n * sizeof(double);
+    if (m <= 16 * JF_MAX && fast_bytes <= LDS_LIMIT) {
+      const int groups = ((n + 1) & ~1) / 2;
+      const unsigned threads = (unsigned)std::max(64, (16 * groups + 63) / 64 * 64);
+      hipLaunchKernelGGL(jacobi_svd_fast_kernel, dim3(batch), dim3(threads), fast_bytes,
+                         ctx->stream, A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, 80, tol,
+                         g_sweeps);
+      TN_HIP(ctx, hipGetLastError());
+      return TN_OK;
+    }
+  }
   if (work)
     hipLaunchKernelGGL(jacobi_svd_kernel<true>, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream,
                        A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
@@ -387,6 +682,13 @@ int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* 
   const size_t one = (size_t)k * k * sizeof(double);
   if (one > LDS_LIMIT) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports k <= 137 (k=%d)", k);
   if (batch < 1) return TN_OK;
+  if (k <= CHOLR_MAX) {
+    const size_t dyn = ((size_t)k * (k | 1) + 3 * CHOLR_MAX) * sizeof(double);
+    hipLaunchKernelGGL(cholesky_inv_reg_kernel, dim3(batch), dim3(1024), dyn, ctx->stream, G, k,
+                       shift_rel, R, Rinv, info);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+  }
   const int r_in_lds = 2 * one <= LDS_LIMIT;
   if (r_in_lds)
     hipLaunchKernelGGL(cholesky_inv_kernel<true>, dim3(batch), dim3(CHOL_THREADS), 2 * one,

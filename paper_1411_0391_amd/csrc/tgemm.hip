@@ -14,6 +14,8 @@
 #include <sstream>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace {
@@ -430,62 +432,52 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
   if (d.M > 0 && d.N > 0 && (long long)batch * d.ksplit > 65535)
     TN_FAIL(ctx, TN_EINVAL, "contraction batch too large for one launch");
   dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)(batch * d.ksplit));
+  // Profiling: the start and stop times are stamped by the dispatches
+  // themselves (the contraction kernel's start, the last kernel's end), so
+  // that the measurement adds no marker packets between kernels.
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->prof) {
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {
       hipEvent_t e;
-      TN_HIP(ctx, hipEventCreate(&e));
+      // timing only: no system-scope fence (L2 write-back) at the stamps
+      TN_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       ctx->ev_pool.push_back(e);
     }
     e0 = ctx->ev_pool[ctx->ev_used];
     e1 = ctx->ev_pool[ctx->ev_used + 1];
     ctx->ev_used += 2;
     ctx->prof_flops.push_back(2.0 * (double)d.M * (double)d.N * (double)d.K * (double)batch);
-    TN_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
+  hipEvent_t stop_main = d.ksplit > 1 ? nullptr : e1;
+#define TN_GO(KERNEL)                                                                          \
+  hipExtLaunchKernelGGL(KERNEL, grid, dim3(256), 0, ctx->stream, e0, stop_main, 0, A, B, C, d, \
+                        alpha, beta)
   if (prec == P_F64) {
-#define TN_LAUNCH_F64(TB)                                                                   \
-  if (table)                                                                                \
-    hipLaunchKernelGGL((tgemm_f64_kernel<true, TB>), grid, dim3(256), 0, ctx->stream, A, B, C, \
-                       d, alpha, beta);                                                     \
-  else                                                                                      \
-    hipLaunchKernelGGL((tgemm_f64_kernel<false, TB>), grid, dim3(256), 0, ctx->stream, A, B,  \
-                       C, d, alpha, beta);
     if (tbn == 96) {
-      TN_LAUNCH_F64(96)
+      if (table) TN_GO((tgemm_f64_kernel<true, 96>)); else TN_GO((tgemm_f64_kernel<false, 96>));
     } else if (tbn == 128) {
-      TN_LAUNCH_F64(128)
+      if (table) TN_GO((tgemm_f64_kernel<true, 128>)); else TN_GO((tgemm_f64_kernel<false, 128>));
     } else {
-      TN_LAUNCH_F64(64)
+      if (table) TN_GO((tgemm_f64_kernel<true, 64>)); else TN_GO((tgemm_f64_kernel<false, 64>));
     }
-#undef TN_LAUNCH_F64
   } else if (prec == P_F32) {
-    if (table)
-      hipLaunchKernelGGL((tgemm_lp_kernel<false, true>), grid, dim3(256), 0, ctx->stream, A, B, C,
-                         d, alpha, beta);
-    else
-      hipLaunchKernelGGL((tgemm_lp_kernel<false, false>), grid, dim3(256), 0, ctx->stream, A, B,
-                         C, d, alpha, beta);
+    if (table) TN_GO((tgemm_lp_kernel<false, true>)); else TN_GO((tgemm_lp_kernel<false, false>));
   } else {
-    if (table)
-      hipLaunchKernelGGL((tgemm_lp_kernel<true, true>), grid, dim3(256), 0, ctx->stream, A, B, C,
-                         d, alpha, beta);
-    else
-      hipLaunchKernelGGL((tgemm_lp_kernel<true, false>), grid, dim3(256), 0, ctx->stream, A, B, C,
-                         d, alpha, beta);
+    if (table) TN_GO((tgemm_lp_kernel<true, true>)); else TN_GO((tgemm_lp_kernel<true, false>));
   }
+#undef TN_GO
   TN_HIP(ctx, hipGetLastError());
   if (d.ksplit > 1) {
     const long long tot = (long long)d.M * d.N * batch;
+    const dim3 rgrid((unsigned)((tot + 255) / 256));
     if (table)
-      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)((tot + 255) / 256)),
-                         dim3(256), 0, ctx->stream, C, d, alpha, beta, batch);
+      hipExtLaunchKernelGGL(splitk_reduce_kernel<true>, rgrid, dim3(256), 0, ctx->stream, nullptr,
+                            e1, 0, C, d, alpha, beta, batch);
     else
-      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)((tot + 255) / 256)),
-                         dim3(256), 0, ctx->stream, C, d, alpha, beta, batch);
+      hipExtLaunchKernelGGL(splitk_reduce_kernel<false>, rgrid, dim3(256), 0, ctx->stream,
+                            nullptr, e1, 0, C, d, alpha, beta, batch);
     TN_HIP(ctx, hipGetLastError());
   }
-  if (ctx->prof) TN_HIP(ctx, hipEventRecord(e1, ctx->stream));
   ctx->arena_off = mark;  // partials are consumed in stream order
   return TN_OK;
 }
