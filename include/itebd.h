@@ -352,6 +352,35 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
                  double* energy);
 
 /*
+ * energy_grad -- TFIM energy per site E(A) of a single-site iPEPS (1 x 1
+ * cell, Sec. VI A, VI D) after exactly n_iter CTMRG iterations (Sec. VI B,
+ * no convergence test) from the environment (C0, T0), and its gradient
+ * dE/dA by a hand-written reverse pass through the iterations and the
+ * energy.  The environment is an input, not a function of A, so no gradient
+ * flows into it.  Projectors come from the full SVD of the explicitly formed
+ * ring product of the four enlarged corners (n = chi D^2 <= 512); the SVD
+ * adjoint uses the broadened inverse gaps g / (g^2 + svd_broadening
+ * (s_i^2 + s_j^2)^2), g = s_j^2 - s_i^2 (0 broadens nothing; exactly
+ * degenerate pairs then contribute nothing).  The
+ * iterations are checkpointed every ckpt_every iterations and recomputed
+ * segment by segment in the reverse pass.
+ *   A      device [d][D][D][D][D] (s, l, r, d, u); d must be 2
+ *   C0, T0 device [4][chi][chi], [4][chi][D][D][chi] (the slots of the one
+ *          position, as for ctmrg_iterate)
+ *   precision  TN_FP64, or TN_FP32: the contractions of all but the last
+ *          5 iterations, and their adjoints, in FP32 on MFMA; the last 5
+ *          iterations (the FP64 polish of the precision form), the energy,
+ *          the SVDs and their adjoints in FP64
+ *   energy host out; dEdA device out, shape of A
+ * TN_EINVAL for d != 2, n > 512, n_iter < 0, ckpt_every < 1, other
+ * precisions or a negative broadening.  Device memory: about 2 GB per
+ * checkpoint segment at D = 4, chi = 32, allocated for the call.
+ */
+int energy_grad(tn_ctx* ctx, int D, int d, double J, double h, const double* A, int chi,
+                const double* C0, const double* T0, int n_iter, int ckpt_every, int precision,
+                double svd_broadening, double* energy, double* dEdA);
+
+/*
  * tn_gemm -- the library's contraction engine on a plain matrix product, for
  * testing and measurement: C = alpha op(A) op(B) + beta C with row-major
  * storage, op(X) = X or X^T (ta, tb nonzero), leading dimensions lda, ldb,
@@ -364,7 +393,8 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
 
 /*
  * tn_svd -- the library's small dense FP64 SVD (one-sided Jacobi, one
- * workgroup per matrix), used for the Rayleigh-Ritz step of the projector
+ * workgroup per matrix; a single matrix with n > 128 is spread over the
+ * whole GPU, one launch per round of column pairs), used for the Rayleigh-Ritz step of the projector
  * SVD, the corner spectra, the canonical-form and gauge-fixing
  * factorisations.  A = U diag(S) V^T for `batch` row-major m x n matrices
  * (m >= n, n <= 512) stored back to back; U [batch][m][n], S [batch][n]

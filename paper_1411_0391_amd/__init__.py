@@ -81,6 +81,9 @@ SIGNATURES = {
     "ipeps_energy": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, _vp, _c_int_p, ctypes.c_int, _vp, _vp,
                                     ctypes.c_double, ctypes.c_double, _c_double_p]),
+    "energy_grad": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, _c_double_p, _vp]),
     "tn_svd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tn_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tn_prof_read": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
@@ -207,6 +210,20 @@ class Context:
                                 _ptr(C), _ptr(T), J, h, ctypes.byref(e))
         self._check(rc)
         return e.value
+
+    def energy_grad(self, A, C0, T0, J, h, n_iter=20, ckpt_every=5, precision="fp64",
+                    broadening=1e-12):
+        """E(A) after n_iter CTMRG iterations of the single-site cell from
+        (C0, T0), and dE/dA (same shape as A, device)."""
+        import torch
+        d, D = A.shape[0], A.shape[1]
+        chi = C0.shape[-1]
+        g = torch.empty_like(A)
+        e = ctypes.c_double(0.0)
+        rc = lib().energy_grad(self._h, D, d, J, h, _ptr(A), chi, _ptr(C0), _ptr(T0), n_iter,
+                               ckpt_every, _PREC[precision], broadening, ctypes.byref(e), _ptr(g))
+        self._check(rc)
+        return e.value, g
 
     # -- full update -----------------------------------------------------------
     def cell_links(self, Lx, Ly, nsite, cell):
@@ -374,6 +391,41 @@ class Context:
         rc = lib().tn_gemm(self._h, M, N, K, _ptr(A), A.shape[1], int(ta), _ptr(B), B.shape[1],
                            int(tb), _ptr(C), C.shape[1], alpha, beta, _PREC[precision])
         self._check(rc)
+
+
+def _energy_grad_function():
+    import torch
+
+    class EnergyGrad(torch.autograd.Function):
+        """E(A) of ``Context.energy_grad`` as a differentiable function of
+        the site tensor A (the environment (C0, T0) is a constant)."""
+
+        @staticmethod
+        def forward(fctx, A, C0, T0, ctx, J, h, n_iter, ckpt_every, precision, broadening):
+            e, g = ctx.energy_grad(A.detach().contiguous(), C0, T0, J, h, n_iter, ckpt_every,
+                                   precision, broadening)
+            fctx.save_for_backward(g)
+            return torch.tensor(e, dtype=A.dtype, device=A.device)
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            (g,) = fctx.saved_tensors
+            return (grad_out * g,) + (None,) * 9
+
+    return EnergyGrad
+
+
+def energy(A, C0, T0, ctx, J=1.0, h=3.0, n_iter=20, ckpt_every=5, precision="fp64",
+           broadening=1e-12):
+    """Differentiable E(A) (torch.autograd): the forward call computes the
+    gradient with the hand-written reverse pass and keeps it for backward."""
+    global _EnergyGrad
+    if _EnergyGrad is None:
+        _EnergyGrad = _energy_grad_function()
+    return _EnergyGrad.apply(A, C0, T0, ctx, J, h, n_iter, ckpt_every, precision, broadening)
+
+
+_EnergyGrad = None
 
 
 def cell_links(Lx, Ly, nsite, cell):

@@ -50,6 +50,10 @@ int ipeps_energy_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, cons
                       const int* cell, int chi, const double* C, const double* T, double J,
                       double h, double* energy);
 
+int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double* A, int chi,
+                     const double* C0, const double* T0, int n_iter, int ckpt, int prec, double eps,
+                     double* energy, double* dEdA);
+
 int ws_reserve(tn_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_size) return TN_OK;
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -286,6 +290,19 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
   return ipeps_energy_impl(ctx, Lx, Ly, D, d, nsite, sites, cell, chi, C, T, J, h, energy);
 }
 
+int energy_grad(tn_ctx* ctx, int D, int d, double J, double h, const double* A, int chi,
+                const double* C0, const double* T0, int n_iter, int ckpt_every, int precision,
+                double svd_broadening, double* energy, double* dEdA) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  // the split-K partials and the Jacobi work matrix of the n x n products
+  const size_t n = (size_t)chi * D * D;
+  TN_TRY(ws_reserve(ctx, 24 * n * n * sizeof(double) + ((size_t)16 << 20)));
+  ws_reset(ctx);
+  return energy_grad_impl(ctx, D, d, J, h, A, chi, C0, T0, n_iter, ckpt_every, precision,
+                          svd_broadening, energy, dEdA);
+}
+
 int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, double* S,
            double* V) {
   if (!ctx) return TN_EINVAL;
@@ -294,8 +311,11 @@ int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, dou
     TN_FAIL(ctx, TN_EINVAL, "tn_svd needs batch >= 1, m >= n >= 1, n <= 512 (m=%d n=%d)", m, n);
   TN_TRY(ws_reserve(ctx, (size_t)batch * (m * n + n * n) * sizeof(double) + (1 << 20)));
   ws_reset(ctx);
-  TN_TRY(jacobi_svd(ctx, batch, m, n, const_cast<double*>(A), n, (long long)m * n, U, n,
-                    (long long)m * n, S, n, V, n, (long long)n * n));
+  if (batch == 1 && n > 128)  // one large matrix: spread over the GPU
+    TN_TRY(jacobi_svd_large(ctx, m, n, A, n, U, n, S, V, n));
+  else
+    TN_TRY(jacobi_svd(ctx, batch, m, n, const_cast<double*>(A), n, (long long)m * n, U, n,
+                      (long long)m * n, S, n, V, n, (long long)n * n));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
 }

@@ -133,6 +133,12 @@ int gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, bool ta, co
 int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long long sA, double* U,
                int ldu, long long sU, double* S, long long sS, double* V, int ldv, long long sV);
 
+// The same SVD for one matrix with n <= 512, spread over the whole GPU (one
+// launch per round of column pairs, one workgroup per pair).  A is not
+// modified; U m x n, S n, V n x n as for jacobi_svd.
+int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
+                     double* S, double* V, int ldv);
+
 // Upper Cholesky factor of (G + shift*I) and its inverse, k x k row-major, for
 // `batch` matrices stored back to back (info: one int per matrix, 0 or the
 // failing pivot + 1).  The shift is shift_rel times the trace of G.

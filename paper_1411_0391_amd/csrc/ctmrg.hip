@@ -21,6 +21,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "nets.h"
 
 namespace {
 
@@ -410,22 +411,8 @@ int corner_ul(tn_ctx* ctx, const Geo& g, const double* Cc, const double* T1, con
       return TN_OK;
     }
   }
-  Contraction c3;
-  c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
-  c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
-  c3.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
-  c3.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
-  c3.cm = grp({{(int)chi, chi * d * D4}, {(int)D, D}, {(int)D, 1}, {(int)chi, d * D4}});
-  c3.cn = grp({{(int)d, D2}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
-  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0, g.prec));
-  Contraction c4;
-  c4.am = grp({{(int)chi, chi * d * D4}, {(int)chi, d * D4}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
-  c4.ak = grp({{(int)d, D2}, {(int)D, D}, {(int)D, 1}});
-  c4.bk = grp({{(int)d, D4}, {(int)D, D2 * D}, {(int)D, 1}});
-  c4.bn = grp({{(int)D, D2}, {(int)D, D}});
-  c4.cm = grp({{(int)chi, D2 * n}, {(int)chi, D2}, {(int)D, D}, {(int)D, D * n}});
-  c4.cn = grp({{(int)D, 1}, {(int)D, n}});
-  TN_TRY(tc_run(ctx, c4, X3, A, E, 1.0, 0.0, g.prec));
+  TN_TRY(tc_run(ctx, nets::corner_ket(chi, D, d), X2, A, X3, 1.0, 0.0, g.prec));
+  TN_TRY(tc_run(ctx, nets::corner_bra(chi, D, d, n), X3, A, E, 1.0, 0.0, g.prec));
   return TN_OK;
 }
 
@@ -850,7 +837,6 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
     TN_TRY(scale_columns(ctx, n, chi, b.PtT + y * nchi, chi, b.S + y * chi, 1));
   }
   const long long csz = (long long)chi * chi, tsz = (long long)chi * D2 * chi;
-  const long long dD4 = (long long)d * D2 * D2;
   for (int y = 0; y < Lyf; ++y) {
     const int src = F.at(f, x, y), s1 = F.at(f, x, y + 1);
     const double* P = b.P + (size_t)y * nchi;
@@ -863,14 +849,8 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
                 0, g.prec));
     // C4 of (x+1, y) = [T3 C4](x, y) Pt_y^T, Z[a3, (b4, k, b)]
     {
-      Contraction c;
-      c.am = grp({{chi, D2 * chi}, {D, (long long)D * chi}, {D, chi}});
-      c.ak = grp({{chi, 1}});
-      c.bk = grp({{chi, chi}});
-      c.bn = grp({{chi, 1}});
-      c.cm = grp({{chi, (long long)n}, {D, D}, {D, 1}});
-      c.cn = grp({{chi, D2}});
-      TN_TRY(tc_run(ctx, c, g.Tp(src, f + 2), g.Cp(src, f + 3), b.CT, 1.0, 0.0, g.prec));
+      TN_TRY(tc_run(ctx, nets::t3_c4(chi, D, n), g.Tp(src, f + 2), g.Cp(src, f + 3), b.CT, 1.0,
+                    0.0, g.prec));
       TN_TRY(gemm(ctx, chi, chi, n, b.CT, n, false, PtTy, chi, false, b.Cn4 + y * csz, chi, 1.0,
                   0.0, 1, 0, 0, 0, g.prec));
     }
@@ -882,14 +862,8 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
       double* Y1 = b.X2;  // chi * D2 * n
       double* Y2 = b.X3;  // chi * d * D4 * chi
       double* Y3 = b.X2;  // chi * D2 * n (Y1 is dead by then)
-      Contraction a;  // Y1[c, uk, ub, a, lk, lb] = sum_b PtT[(b,uk,ub), c] T4[a, lk, lb, b]
-      a.am = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}});
-      a.ak = grp({{chi, D2 * chi}});
-      a.bk = grp({{chi, 1}});
-      a.bn = grp({{chi, D2 * chi}, {D, (long long)D * chi}, {D, chi}});
-      a.cm = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
-      a.cn = grp({{chi, D2}, {D, D}, {D, 1}});
-      TN_TRY(tc_run(ctx, a, PtTm, T4, Y1, 1.0, 0.0, g.prec));
+      // Y1[c, uk, ub, a, lk, lb] = sum_b PtT[(b,uk,ub), c] T4[a, lk, lb, b]
+      TN_TRY(tc_run(ctx, nets::edge_pt(chi, D, nn), PtTm, T4, Y1, 1.0, 0.0, g.prec));
       AbsorbDesc ad;  // Y1 -> Y3 with both layers in one kernel
       ad.in_c = D2 * nn, ad.in_a = D2, ad.in_lk = D, ad.in_uk = D * nn, ad.in_lb = 1;
       ad.in_ub = nn;
@@ -902,30 +876,13 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
         TN_HIP(ctx, hipGetLastError());
         Y3 = b.X3;
       }
-      Contraction bk;  // Y2[c, a, rk, dk, s, lb, ub] = sum_{lk,uk} Y1[...] A[s,lk,rk,dk,uk]
-      bk.am = grp({{chi, D2 * nn}, {D, nn}, {chi, D2}, {D, 1}});
-      bk.ak = grp({{D, D}, {D, (long long)D * nn}});
-      bk.bk = grp({{D, D2 * D}, {D, 1}});
-      bk.bn = grp({{d, D2 * D2}, {D, D2}, {D, D}});
-      bk.cm = grp({{chi, chi * dD4}, {D, 1}, {chi, dD4}, {D, D}});
-      bk.cn = grp({{d, D2}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
-      if (!fused) TN_TRY(tc_run(ctx, bk, Y1, A, Y2, 1.0, 0.0, g.prec));
-      Contraction cb;  // Y3[c, rk, rb, a, dk, db] = sum_{s,lb,ub} Y2[...] A[s,lb,rb,db,ub]
-      cb.am = grp({{chi, chi * dD4}, {chi, dD4}, {D, (long long)d * D2 * D}, {D, (long long)d * D2}});
-      cb.ak = grp({{d, D2}, {D, D}, {D, 1}});
-      cb.bk = grp({{d, D2 * D2}, {D, D2 * D}, {D, 1}});
-      cb.bn = grp({{D, D2}, {D, D}});
-      cb.cm = grp({{chi, D2 * nn}, {chi, D2}, {D, (long long)D * nn}, {D, D}});
-      cb.cn = grp({{D, nn}, {D, 1}});
-      if (!fused) TN_TRY(tc_run(ctx, cb, Y2, A, Y3, 1.0, 0.0, g.prec));
-      Contraction dp;  // T4new[e, rk, rb, c] = sum_i Y3[c, rk, rb, i] P[i, e]
-      dp.am = grp({{chi, D2 * nn}, {D, (long long)D * nn}, {D, nn}});
-      dp.ak = grp({{(int)nn, 1}});
-      dp.bk = grp({{(int)nn, chi}});
-      dp.bn = grp({{chi, 1}});
-      dp.cm = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}});
-      dp.cn = grp({{chi, D2 * chi}});
-      TN_TRY(tc_run(ctx, dp, Y3, P, b.Tn4 + y * tsz, 1.0, 0.0, g.prec));
+      // unfused: Y2 = Y1 A (ket layer), Y3 = Y2 A (bra layer)
+      if (!fused) {
+        TN_TRY(tc_run(ctx, nets::edge_ket(chi, D, d, nn), Y1, A, Y2, 1.0, 0.0, g.prec));
+        TN_TRY(tc_run(ctx, nets::edge_bra(chi, D, d, nn), Y2, A, Y3, 1.0, 0.0, g.prec));
+      }
+      // T4new[e, rk, rb, c] = sum_i Y3[c, rk, rb, i] P[i, e]
+      TN_TRY(tc_run(ctx, nets::edge_p(chi, D, nn), Y3, P, b.Tn4 + y * tsz, 1.0, 0.0, g.prec));
     }
   }
   // write back and normalise
@@ -1080,7 +1037,7 @@ int finite_or_fail(tn_ctx* ctx, const double* x, long long n, const char* what) 
 // position p: L[t, s, s', rk, rb, b] (t = T1.b, b = T3.a in frame f).
 int half_left(tn_ctx* ctx, const Geo& g, int f, int p, double* L, double* X1, double* X2,
               double* X3, double* X4, double* Y) {
-  const long long chi = g.chi, D = g.D, d = g.d, D2 = D * D, D4 = D2 * D2, n = g.n;
+  const long long chi = g.chi, D = g.D, d = g.d, D2 = D * D, n = g.n;
   const double* C1 = g.Cp(p, f);
   const double* T1 = g.Tp(p, f);
   const double* T4 = g.Tp(p, f + 3);
@@ -1091,37 +1048,14 @@ int half_left(tn_ctx* ctx, const Geo& g, int f, int p, double* L, double* X1, do
               X1, (int)chi, 1.0, 0.0));
   TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
               (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
-  Contraction c3;  // as the corner: X3[e][t][rk][dk][s][lb][ub]
-  c3.am = grp({{(int)chi, D4 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
-  c3.ak = grp({{(int)D, D2 * D * chi}, {(int)D, D * chi}});
-  c3.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
-  c3.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
-  c3.cm = grp({{(int)chi, chi * d * D4}, {(int)D, D}, {(int)D, 1}, {(int)chi, d * D4}});
-  c3.cn = grp({{(int)d, D2}, {(int)D, d * D2 * D}, {(int)D, d * D2}});
-  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
-  // X4[t][s][s'][rk][rb][e][dk][db] = sum_{lb,ub} X3[e,t,rk,dk,s,lb,ub] A[s',lb,rb,db,ub]
-  Contraction c4;
-  c4.am = grp({{(int)chi, chi * d * D4}, {(int)chi, d * D4}, {(int)D, d * D2 * D},
-               {(int)D, d * D2}, {(int)d, D2}});
-  c4.ak = grp({{(int)D, D}, {(int)D, 1}});
-  c4.bk = grp({{(int)D, D2 * D}, {(int)D, 1}});
-  c4.bn = grp({{(int)d, D4}, {(int)D, D2}, {(int)D, D}});
-  c4.cm = grp({{(int)chi, D2}, {(int)chi, d * d * D2 * n}, {(int)D, D * n}, {(int)D, D},
-               {(int)d, d * D2 * n}});
-  c4.cn = grp({{(int)d, D2 * n}, {(int)D, n}, {(int)D, 1}});
-  TN_TRY(tc_run(ctx, c4, X3, A, X4, 1.0, 0.0));
+  // X3[e][t][rk][dk][s][lb][ub] as in the corner, then the bra layer with s' open
+  TN_TRY(tc_run(ctx, nets::corner_ket(chi, D, d), X2, A, X3, 1.0, 0.0));
+  TN_TRY(tc_run(ctx, nets::half_bra(chi, D, d, n), X3, A, X4, 1.0, 0.0));
   // Y[(b, dk, db), e] = T3[(b,dk,db), f] C4[f, e]
   TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T3, (int)chi, false, C4, (int)chi, false,
               Y, (int)chi, 1.0, 0.0));
   // L[(t,s,s',rk,rb), b] = sum_{e,dk,db} X4[..., e, dk, db] Y[b, dk, db, e]
-  Contraction c6;
-  c6.am = grp({{(int)(chi * d * d * D2), n}});
-  c6.ak = grp({{(int)chi, D2}, {(int)D, D}, {(int)D, 1}});
-  c6.bk = grp({{(int)chi, 1}, {(int)D, D * chi}, {(int)D, chi}});
-  c6.bn = grp({{(int)chi, D2 * chi}});
-  c6.cm = grp({{(int)(chi * d * d * D2), chi}});
-  c6.cn = grp({{(int)chi, 1}});
-  TN_TRY(tc_run(ctx, c6, X4, Y, L, 1.0, 0.0));
+  TN_TRY(tc_run(ctx, nets::half_close(chi, D, d, n), X4, Y, L, 1.0, 0.0));
   return TN_OK;
 }
 
@@ -1315,24 +1249,12 @@ int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const 
                   (int)(D2 * chi_), false, X1, (int)(D2 * chi_), 1.0, 0.0));
       TN_TRY(gemm(ctx, (int)(chi_ * D2), chi, chi, X1, chi, false, g.Cp(p, 2), chi, false, Rc, chi,
                   1.0, 0.0));
-      Contraction c1;
-      c1.am = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
-      c1.ak = grp({{chi, dd * dd * D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
-      c1.bk = grp({{chi, (long long)D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
-      c1.bn = grp({{1, 0}});
-      c1.cm = grp({{d, dd}, {d, 1}});
-      c1.cn = grp({{1, 0}});
-      TN_TRY(tc_run(ctx, c1, L1, Rc, rho1 + (long long)p * d * d, 1.0, 0.0));
+      TN_TRY(tc_run(ctx, nets::rdm_one(chi, D, d), L1, Rc, rho1 + (long long)p * d * d, 1.0,
+                    0.0));
       // horizontal pair (x, y)-(x+1, y): L(0, p) with L(2, q)
       const int q = g.F.at(0, x + 1, y);
       TN_TRY(half_left(ctx, g, 2, q, L2, X1, X2, X3, X4, Y));
-      Contraction c2;
-      c2.am = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
-      c2.ak = grp({{chi, dd * dd * D2 * chi}, {D, (long long)D * chi}, {D, chi}, {chi, 1}});
-      c2.bk = grp({{chi, 1}, {D, (long long)D * chi}, {D, chi}, {chi, dd * dd * D2 * chi}});
-      c2.bn = grp({{d, dd * D2 * chi}, {d, (long long)D2 * chi}});
-      c2.cm = grp({{d, dd * dd * dd}, {d, dd}});
-      c2.cn = grp({{d, dd * dd}, {d, 1}});
+      const Contraction c2 = nets::rdm_two(chi, D, d);
       TN_TRY(tc_run(ctx, c2, L1, L2, rhoh + (long long)p * d * d * d * d, 1.0, 0.0));
       // vertical pair: frame 1 (top site on the left) with frame 3 (bottom site)
       const int pb = g.F.at(0, x, y + 1);

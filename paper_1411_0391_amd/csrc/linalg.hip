@@ -358,6 +358,89 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of one large matrix (n <= 512) across the whole GPU:
+// the work matrix and the rotation accumulator live in global memory as
+// contiguous columns, and each launch is one round of the round-robin
+// ordering with one workgroup per column pair.  The largest relative
+// off-diagonal of a sweep is collected with an atomic maximum on the bit
+// pattern (order-preserving for non-negative doubles).
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ X, int ldx,
+                                                           double* __restrict__ W, int ldw, int m,
+                                                           int n, int N, int r, double tol,
+                                                           unsigned long long* __restrict__ offbits) {
+  __shared__ double red[3][4];
+  const int q = blockIdx.x;
+  const int p0 = q == 0 ? 0 : 1 + (q - 1 + r) % (N - 1);
+  const int p1 = 1 + (N - 2 - q + r) % (N - 1);
+  if (p0 >= n || p1 >= n) return;
+  const int p = min(p0, p1), qq = max(p0, p1);
+  double* xp = X + (long long)p * ldx;
+  double* xq = X + (long long)qq * ldx;
+  double a = 0.0, bb = 0.0, g = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double u = xp[i], v = xq[i];
+    a += u * u;
+    bb += v * v;
+    g += u * v;
+  }
+  a = block_sum256(a, red[0]);
+  bb = block_sum256(bb, red[1]);
+  g = block_sum256(g, red[2]);
+  const double scale = sqrt(a * bb);
+  if (scale == 0.0 || fabs(g) <= tol * scale) return;
+  if (threadIdx.x == 0)
+    atomicMax(offbits, (unsigned long long)__double_as_longlong(fabs(g) / scale));
+  const double z = (bb - a) / (2.0 * g);
+  const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+  const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double u = xp[i], v = xq[i];
+    xp[i] = c * u - sn * v;
+    xq[i] = sn * u + c * v;
+  }
+  double* wp = W + (long long)p * ldw;
+  double* wq = W + (long long)qq * ldw;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double u = wp[i], v = wq[i];
+    wp[i] = c * u - sn * v;
+    wq[i] = sn * u + c * v;
+  }
+}
+
+// X[j][i] = A[i][j] (columns contiguous), W = I
+__global__ void jacobi_setup_kernel(const double* __restrict__ A, int lda, int m, int n,
+                                    double* __restrict__ X, double* __restrict__ W) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (long long)m * n) {
+    const int j = (int)(t / m), i = (int)(t % m);
+    X[t] = A[(long long)i * lda + j];
+  }
+  if (t < (long long)n * n) {
+    const int j = (int)(t / n), i = (int)(t % n);
+    W[t] = i == j ? 1.0 : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void jacobi_emit_kernel(const double* X, int ldx,
+                                                           const double* W, int ldw, int m, int n,
+                                                           double* __restrict__ U, int ldu,
+                                                           double* __restrict__ S,
+                                                           double* __restrict__ V, int ldv) {
+  __shared__ double colnorm[512];
+  __shared__ int perm[512];
+  jacobi_emit(X, ldx, W, ldw, m, n, colnorm, perm, 0, U, ldu, 0, S, 0, V, ldv, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Cholesky of G + shift I and the inverse of its upper factor.  The trailing
 // matrix lives in LDS; step j reads the unscaled row j, writes row j of R
 // (divided by sqrt of the pivot) and updates the trailing block with
@@ -672,6 +755,39 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
   else
     hipLaunchKernelGGL(jacobi_svd_kernel<false>, dim3(batch), dim3(SVD_THREADS), dyn, ctx->stream,
                        A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, work, 80, tol, g_sweeps);
+  TN_HIP(ctx, hipGetLastError());
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
+int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
+                     double* S, double* V, int ldv) {
+  if (m < n || n < 1 || n > 512) TN_FAIL(ctx, TN_EINVAL, "jacobi_svd_large needs 1 <= n <= m, n <= 512");
+  const size_t mark = ctx->arena_off;
+  double* X = ws_alloc<double>(ctx, (size_t)m * n);
+  double* W = ws_alloc<double>(ctx, (size_t)n * n);
+  unsigned long long* off = ws_alloc<unsigned long long>(ctx, 1);
+  if (!off) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in jacobi_svd_large");
+  const long long tot = (long long)std::max(m, n) * n;
+  hipLaunchKernelGGL(jacobi_setup_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, A, lda, m, n, X, W);
+  TN_HIP(ctx, hipGetLastError());
+  const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
+  const int N = (n + 1) & ~1;
+  unsigned long long* hoff = reinterpret_cast<unsigned long long*>(ctx->host_scratch + 16);
+  for (int sweep = 0; sweep < 80 && n > 1; ++sweep) {
+    TN_HIP(ctx, hipMemsetAsync(off, 0, sizeof(unsigned long long), ctx->stream));
+    for (int r = 0; r < N - 1; ++r)
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(N / 2), dim3(256), 0, ctx->stream, X, m, W, n,
+                         m, n, N, r, tol, off);
+    TN_HIP(ctx, hipGetLastError());
+    TN_HIP(ctx, hipMemcpyAsync(hoff, off, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*hoff == 0) break;  // no rotation in the whole sweep
+  }
+  hipLaunchKernelGGL(jacobi_emit_kernel, dim3(1), dim3(1024), 0, ctx->stream, X, m, W, n, m, n, U,
+                     ldu, S, V, ldv);
   TN_HIP(ctx, hipGetLastError());
   ctx->arena_off = mark;
   return TN_OK;

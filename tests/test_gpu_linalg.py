@@ -44,6 +44,20 @@ def test_svd_random_parity(ctx, m, n):
         np.testing.assert_allclose(V[b].T @ V[b], np.eye(n), atol=1e-12)
 
 
+@pytest.mark.parametrize("m,n", [(300, 256), (512, 512), (200, 129)])
+def test_svd_single_large_matrix(ctx, m, n):
+    # one matrix with n > 128 runs across the GPU, one launch per round
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((1, m, n)) * np.logspace(0, -6, n)[None, None, :]
+    U, S, V = ctx.svd(dev(A))
+    U, S, V = host(U)[0], host(S)[0], host(V)[0]
+    ref = np.linalg.svd(A[0], compute_uv=False)
+    np.testing.assert_allclose(S, ref, rtol=1e-10, atol=1e-13 * ref[0])
+    np.testing.assert_allclose((U * S) @ V.T, A[0], atol=1e-12 * ref[0])
+    np.testing.assert_allclose(V.T @ V, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(U.T @ U, np.eye(n), atol=1e-9)
+
+
 def test_svd_graded_high_relative_accuracy_and_sweeps(ctx):
     # A = B diag(d) with B well conditioned and d over 12 decades: one-sided
     # Jacobi resolves every singular value to high relative accuracy
