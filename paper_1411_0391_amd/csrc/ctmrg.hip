@@ -660,6 +660,8 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   int* info = ws_alloc<int>(ctx, 8 * B);
   int* info_b = ws_alloc<int>(ctx, 4 * B);  // orth of K^T Q, this iteration
   int* info_q = ws_alloc<int>(ctx, 4 * B);  // orth of the previous K W
+  constexpr int MAX_PLAIN = 3;
+  int* info_p = ws_alloc<int>(ctx, 2 * MAX_PLAIN * 2 * B);  // orths of the plain steps
   double* Ysave = ws_alloc<double>(ctx, bnk);
   double* Ssave = ws_alloc<double>(ctx, (size_t)B * k);
   if (!Ssave) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
@@ -680,12 +682,29 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   // the status comes back with the residual, and a breakdown redoes the
   // iteration through the robust path (from the saved K W of the previous
   // iteration when the current basis is the one that broke down).
-  bool q_pending = false, robust = false;
-  int retries = 0;
+  // Between Rayleigh-Ritz steps the iteration may take plain steps,
+  // Q <- orth(K orth(K^T Q)) scaled by the last Ritz values, with no SVD of
+  // the k x k factor and no host round trip: after the third iteration the
+  // residual's rate of decrease predicts how many steps remain, and all but
+  // the last of them (at most MAX_PLAIN) are plain.  Their Cholesky status is
+  // checked with the next Rayleigh-Ritz step; a breakdown restarts from the
+  // last checked block on the robust path, without further plain steps.
+  bool q_pending = false, robust = false, allow_plain = true;
+  int retries = 0, plain_left = 0, plain_done = 0, it_prev = 0;
   int it = 0;
-  double hres = 1.0;
+  double hres = 1.0, r_prev = -1.0;
   int* hinfo = reinterpret_cast<int*>(ctx->host_scratch + 8);
   for (it = 1; it <= maxit; ++it) {
+    if (plain_left > 0 && allow_plain && have_s && !robust) {
+      int* ip = info_p + plain_done * 4 * B;
+      TN_TRY(applyKT(ctx, t, Q, Bm));
+      TN_TRY(orth_fast(ctx, n, k, B, Bm, Sprev, nullptr, tmp, ip));
+      TN_TRY(applyK(ctx, t, Bm, Q));
+      TN_TRY(orth_fast(ctx, n, k, B, Q, Sprev, nullptr, tmp, ip + 2 * B));
+      --plain_left;
+      ++plain_done;
+      continue;
+    }
     TN_TRY(applyKT(ctx, t, Q, Bm));
     const bool fast = have_s && !robust;
     if (fast)
@@ -708,12 +727,18 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     if (q_pending)
       TN_HIP(ctx, hipMemcpyAsync(hinfo + 2 * B, info_q, 2 * B * sizeof(int),
                                  hipMemcpyDeviceToHost, ctx->stream));
+    if (plain_done)
+      TN_HIP(ctx, hipMemcpyAsync(hinfo + 4 * B, info_p, plain_done * 4 * B * sizeof(int),
+                                 hipMemcpyDeviceToHost, ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     bool bad_b = false, bad_q = false;
     for (int i = 0; i < 2 * B; ++i) {
       bad_b = bad_b || (fast && hinfo[i] != 0);
       bad_q = bad_q || (q_pending && hinfo[2 * B + i] != 0);
     }
+    for (int i = 0; i < plain_done * 4 * B; ++i) bad_q = bad_q || hinfo[4 * B + i] != 0;
+    if (plain_done && bad_q) allow_plain = false;
+    plain_done = 0;
     if (bad_q || bad_b) {
       if (++retries > 2) TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
       if (bad_q) {  // the basis of this iteration was not orthonormal
@@ -734,6 +759,15 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     if (hres <= tol || it == maxit) break;
     // the rounding floor lies above tol: the residual has stopped falling
     if (it >= 3 && hres <= 30.0 * tol && hres > 0.7 * hprev) break;
+    // plain steps until the predicted last one (the drop of the first
+    // iteration, from the warm start, says nothing about the rate)
+    if (it >= 3 && r_prev > 0.0 && hres < r_prev) {
+      const double rho = std::min(0.7, std::max(0.02, std::pow(hres / r_prev, 1.0 / (it - it_prev))));
+      const int m = (int)std::ceil(std::log(tol / hres) / std::log(rho));
+      plain_left = std::min(std::max(m - 1, 0), std::min(MAX_PLAIN, maxit - it - 1));
+    }
+    r_prev = hres;
+    it_prev = it;
     TN_HIP(ctx, hipMemcpyAsync(Ysave, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice,
                                ctx->stream));
     TN_HIP(ctx, hipMemcpyAsync(Ssave, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
@@ -977,6 +1011,7 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
   add(Lm * 3 * k * k);
   add(Lm * (4 * k + chi) + 64);
   add(Lm * 16 + 64);
+  add(64);                                        // status of the plain steps
   add(Lm * (8 * k * k + k) + 64);                 // Cholesky-QR passes (one alive at a time)
   add(Lm * (2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k));  // jacobi work
   // rotated sites

@@ -292,20 +292,12 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
           const int p = min(p0, p1), q = max(p0, p1);
           double* xp = X + p * ldx + gl;
           double* xq = X + q * ldx + gl;
-          double* wp = W + p * ldw + gl;
-          double* wq = W + q * ldw + gl;
-          double xu[JF_MAX], xv[JF_MAX], wu[JF_MAX], wv[JF_MAX];
+          double xu[JF_MAX], xv[JF_MAX];
 #pragma unroll
           for (int e = 0; e < JF_MAX; ++e)
             if (e < me) {
               xu[e] = xp[16 * e];
               xv[e] = xq[16 * e];
-            }
-#pragma unroll
-          for (int e = 0; e < JF_MAX; ++e)
-            if (e < ne) {
-              wu[e] = wp[16 * e];
-              wv[e] = wq[16 * e];
             }
           double a = 0.0, bb = 0.0, g = 0.0;
 #pragma unroll
@@ -329,6 +321,16 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
               if (e < me) {
                 xp[16 * e] = c * xu[e] - sn * xv[e];
                 xq[16 * e] = sn * xu[e] + c * xv[e];
+              }
+            // the accumulator columns only for pairs that rotate
+            double* wp = W + p * ldw + gl;
+            double* wq = W + q * ldw + gl;
+            double wu[JF_MAX], wv[JF_MAX];
+#pragma unroll
+            for (int e = 0; e < JF_MAX; ++e)
+              if (e < ne) {
+                wu[e] = wp[16 * e];
+                wv[e] = wq[16 * e];
               }
 #pragma unroll
             for (int e = 0; e < JF_MAX; ++e)
@@ -774,7 +776,7 @@ int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double
   TN_HIP(ctx, hipGetLastError());
   const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
   const int N = (n + 1) & ~1;
-  unsigned long long* hoff = reinterpret_cast<unsigned long long*>(ctx->host_scratch + 16);
+  unsigned long long* hoff = reinterpret_cast<unsigned long long*>(ctx->host_scratch + 40);
   for (int sweep = 0; sweep < 80 && n > 1; ++sweep) {
     TN_HIP(ctx, hipMemsetAsync(off, 0, sizeof(unsigned long long), ctx->stream));
     for (int r = 0; r < N - 1; ++r)
