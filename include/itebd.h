@@ -290,16 +290,18 @@ int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, in
  * links already updated); i, j are the ket link legs of the first and second
  * site, i', j' the bra legs; N is symmetrised in ket <-> bra.  Then
  * alternating least squares on f = <(I - PQ)|N|(I - PQ)>: P = R^-1 S with Q
- * fixed, then Q with P fixed, each solve on R + 1e-14 tr(R) I (Cholesky),
- * after each pair the pair is balanced through the SVD of PQ; stops when
+ * fixed, then Q with P fixed, each solve on R + 1e-14 tr(R) I (Gaussian
+ * elimination with partial pivoting: R is indefinite when N is not
+ * positive), after each pair the pair is balanced through the SVD of PQ;
+ * kappa D^2 <= 140; stops when
  * |df| < tol <I|N|I> or after max_sweeps.
  *   Theta        device [nsite][d][Dk]^4, Dk = kappa D
  *   C, T         device, the environment of the truncated state (bond D)
  *   P, Q         device in/out [nlink][Dk][D], [nlink][D][Dk]
  *   cost         host out (may be NULL) [nlink]: final f per link
  *   sweeps       host out (may be NULL): sweeps summed over links
- * Returns TN_OK, TN_EINVAL, TN_ENUMERIC (a normal matrix that is not
- * positive definite, non-finite values), TN_EHIP.
+ * Returns TN_OK, TN_EINVAL, TN_ENUMERIC (a singular normal matrix,
+ * non-finite values), TN_EHIP.
  */
 int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                       int Dk, const double* Theta, int chi, const double* C, const double* T,

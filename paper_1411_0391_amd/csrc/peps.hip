@@ -767,22 +767,87 @@ __global__ void als_normal_kernel(int mode, const double* __restrict__ N,
   R[t] = 0.5 * (a + b);
 }
 
-// x = Rinv Rinv^T S (the solution of (R + shift) x = S from the Cholesky
-// factor's inverse); one workgroup
-__global__ __launch_bounds__(1024) void chol_solve_kernel(int k, const double* __restrict__ Rinv,
-                                                          const double* __restrict__ S,
-                                                          double* __restrict__ x) {
-  extern __shared__ double y[];
-  for (int i = threadIdx.x; i < k; i += 1024) {
-    double a = 0.0;
-    for (int j = 0; j <= i; ++j) a += Rinv[(long long)j * k + i] * S[j];
-    y[i] = a;
+// x = (R + shift I)^-1 S with shift = shift_rel tr(R), by Gaussian
+// elimination with partial pivoting (the first row of largest magnitude) in
+// LDS, one workgroup.  R is symmetric but need not be positive definite: with
+// an environment N that is not positive, the ALS normal matrix is indefinite.
+// info = 0, or j + 1 when pivot j is zero.
+__global__ __launch_bounds__(1024) void lu_solve_kernel(int k, const double* __restrict__ R,
+                                                        double shift_rel,
+                                                        const double* __restrict__ S,
+                                                        double* __restrict__ x,
+                                                        int* __restrict__ info) {
+  extern __shared__ double lds[];
+  const int ld = k + 1;                // row stride of the augmented matrix [A | S]
+  double* M = lds;                     // k x (k + 1)
+  __shared__ double shift;
+  __shared__ int piv, fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid < 64) {
+    double tr = 0.0;
+    for (int i = tid; i < k; i += 64) tr += R[(long long)i * k + i];
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    if (tid == 0) {
+      shift = shift_rel * tr;
+      fail = 0;
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += 1024) {
-    double a = 0.0;
-    for (int j = i; j < k; ++j) a += Rinv[(long long)i * k + j] * y[j];
-    x[i] = a;
+  for (int t = tid; t < k * ld; t += nt) {
+    const int i = t / ld, j = t % ld;
+    M[t] = j < k ? R[(long long)i * k + j] + (i == j ? shift : 0.0) : S[i];
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid < 64) {  // pivot: the first row of largest magnitude in column j
+      double best = -1.0;
+      int bi = k;
+      for (int i = j + tid; i < k; i += 64) {
+        const double a = fabs(M[i * ld + j]);
+        if (a > best) {
+          best = a;
+          bi = i;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        piv = bi;
+        if (!(best > 0.0) && !fail) fail = j + 1;
+      }
+    }
+    __syncthreads();
+    if (fail) break;
+    const int p = piv;
+    if (p != j)
+      for (int c = j + tid; c < ld; c += nt) {
+        const double t = M[j * ld + c];
+        M[j * ld + c] = M[p * ld + c];
+        M[p * ld + c] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / M[j * ld + j];
+    const int w = ld - j - 1;  // columns right of j, including S
+    for (int t = tid; t < (k - j - 1) * w; t += nt) {
+      const int i = j + 1 + t / w, c = j + 1 + t % w;
+      M[i * ld + c] -= M[i * ld + j] * inv * M[j * ld + c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *info = fail;
+  if (fail) return;
+  // back substitution, one column at a time
+  for (int j = k - 1; j >= 0; --j) {
+    const double xj = M[j * ld + k] / M[j * ld + j];
+    for (int i = tid; i < j; i += nt) M[i * ld + k] -= M[i * ld + j] * xj;
+    if (tid == 0) x[j] = xj;
+    __syncthreads();
   }
 }
 
@@ -1459,7 +1524,8 @@ int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* ce
   TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, P, Q));
   if (max_sweeps < 1) TN_FAIL(ctx, TN_EINVAL, "max_sweeps must be >= 1");
   const int nl = L.nl, n = Dk, k = Dk * D;
-  if (k > 512) TN_FAIL(ctx, TN_EINVAL, "kappa*D*D = %d too large for the ALS solve", k);
+  // the augmented k x (k + 1) system of the solve lives in LDS
+  if (k > 140) TN_FAIL(ctx, TN_EINVAL, "kappa*D*D = %d too large for the ALS solve", k);
   const size_t n_ = n;
   size_t need = BondEnv::bytes(d, D, Dk, chi);
   auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
@@ -1508,9 +1574,8 @@ int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* ce
         hipLaunchKernelGGL(als_normal_kernel, dim3(nblk((long long)k * k + k)), dim3(256), 0,
                            ctx->stream, mode, Ns, tb, mode == 0 ? Qb : Pb, n, D, R, S);
         TN_HIP(ctx, hipGetLastError());
-        TN_TRY(cholesky_inv(ctx, k, R, 1e-14, Rc, Rinv, info + mode));
-        hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), k * sizeof(double), ctx->stream,
-                           k, Rinv, S, mode == 0 ? Pb : Qb);
+        hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(1024), (size_t)k * (k + 1) * sizeof(double),
+                           ctx->stream, k, R, 1e-14, S, mode == 0 ? Pb : Qb, info + mode);
         TN_HIP(ctx, hipGetLastError());
       }
       // balance the pair through the SVD of P Q
@@ -1530,8 +1595,7 @@ int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* ce
       TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
       const int* hinfo = reinterpret_cast<const int*>(ctx->host_scratch + 2);
       if (hinfo[0] || hinfo[1])
-        TN_FAIL(ctx, TN_ENUMERIC,
-                "ALS normal matrix of link %d not positive definite (pivot %d/%d)", b,
+        TN_FAIL(ctx, TN_ENUMERIC, "ALS normal matrix of link %d singular (pivot %d/%d)", b,
                 hinfo[0], hinfo[1]);
       const double fn = ctx->host_scratch[0];
       if (!std::isfinite(fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite ALS cost");

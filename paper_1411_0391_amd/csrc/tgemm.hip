@@ -10,6 +10,7 @@
 // layout the next step needs -- no transpose kernels between contractions.
 // Tables are built once per shape on the host and cached in the context.
 #include <algorithm>
+#include <map>
 #include <cstring>
 #include <sstream>
 #include <type_traits>
@@ -400,8 +401,41 @@ bool unit_fast(const IdxGroup& g) { return !g.str.empty() && g.str.back() == 1; 
 
 namespace {
 
-// Launch with either tables (TABLE) or strides; picks split-K so that the
-// grid has enough workgroups to occupy the 256 compute units.
+// Workgroups of a kernel that the device runs at once (occupancy per CU
+// times the CU count), queried once per kernel.
+long long concurrent_groups(const void* fn) {
+  static std::map<const void*, long long> cache;
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  long long slots = 512;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) == hipSuccess && per > 0)
+    slots = (long long)per * cus;
+  (void)hipGetLastError();
+  cache[fn] = slots;
+  return slots;
+}
+
+const void* kernel_of(int prec, int tbn, bool table) {
+  if (prec == P_F64) {
+    if (tbn == 96)
+      return table ? (const void*)tgemm_f64_kernel<true, 96> : (const void*)tgemm_f64_kernel<false, 96>;
+    if (tbn == 128)
+      return table ? (const void*)tgemm_f64_kernel<true, 128>
+                   : (const void*)tgemm_f64_kernel<false, 128>;
+    return table ? (const void*)tgemm_f64_kernel<true, 64> : (const void*)tgemm_f64_kernel<false, 64>;
+  }
+  if (prec == P_F32)
+    return table ? (const void*)tgemm_lp_kernel<false, true> : (const void*)tgemm_lp_kernel<false, false>;
+  return table ? (const void*)tgemm_lp_kernel<true, true> : (const void*)tgemm_lp_kernel<true, false>;
+}
+
+// Launch with either tables (TABLE) or strides.  A grid of fewer tiles than
+// the device holds at once is split along K: the split minimises the number
+// of k slices on the critical path, (full rounds of workgroups) x (slices
+// per workgroup), plus a small charge per split for the partial sums.
 int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const double* B,
            double* C, double alpha, double beta, int prec) {
   // FP64: one tile across a narrow N (65..128 columns)
@@ -412,9 +446,18 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
   int ksplit = 1;
   const int kstep = prec == P_BF16 ? 32 : BK;  // k slice of the kernel
   const int ktiles = (d.K + kstep - 1) / kstep;
-  if (tiles < 512 && ktiles >= 8) {
-    ksplit = (int)std::min<long long>((1024 + tiles - 1) / tiles, ktiles / 4);
-    ksplit = std::max(1, std::min(ksplit, 64));
+  const long long slots = concurrent_groups(kernel_of(prec, tbn, table));
+  if (tiles < slots && ktiles >= 8) {
+    const int kmax = std::max(1, std::min(64, ktiles / 4));
+    long long best = -1;
+    for (int ks = 1; ks <= kmax; ++ks) {
+      const long long rounds = (tiles * ks + slots - 1) / slots;
+      const long long cost = rounds * ((ktiles + ks - 1) / ks) + ks / 4;
+      if (best < 0 || cost < best) {
+        best = cost;
+        ksplit = ks;
+      }
+    }
   }
   d.ksplit = ksplit;
   d.kchunk = ((ktiles + ksplit - 1) / ksplit) * kstep;
