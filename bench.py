@@ -277,7 +277,9 @@ def main():
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "avg_launch_ms": round(avg_ms, 5), "launches": prof["gemm_launches"],
-                     "flops_per_launch": flops_per_launch},
+                     "flops_per_launch": flops_per_launch,
+                     "algorithmic_bytes_per_launch":
+                         prof["gemm_bytes"] / max(1, prof["gemm_launches"])},
         "step_mfma_tflops": round(prof["gemm_flops"] / elapsed / 1e12, 3),
         "svd_iters_per_projector": round(prof["svd_iters"] / max(1, prof["svd_calls"]), 3),
         "svd_at_cap": prof["svd_unconverged"],

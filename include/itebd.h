@@ -433,10 +433,11 @@ int tn_clear_cache(tn_ctx* ctx);
  * the contraction kernel with HIP events on the context stream (and resets
  * the counters); tn_prof_read returns, since the last enable/read: total
  * kernel milliseconds, total algorithmic flops (2 M N K per product), the
- * launch count, and counters[6] = {CTMRG moves, projector SVDs, subspace
- * iterations, SVDs stopped at the iteration cap, SVDs done by the explicit
- * small-n path, Jacobi sweeps of the small dense SVDs}.  Reading resets everything.  Host pointers; any may be
- * NULL.
+ * launch count, and counters[7] = {CTMRG moves, projector SVDs, subspace
+ * iterations, SVDs above the residual tolerance at their stop, SVDs done by
+ * the explicit small-n path, Jacobi sweeps of the small dense SVDs,
+ * algorithmic bytes of the timed contractions (8 (MK + KN + MN) per
+ * product)}.  Reading resets everything.  Host pointers; any may be NULL.
  */
 int tn_prof_enable(tn_ctx* ctx, int on);
 int tn_prof_read(tn_ctx* ctx, double* gemm_ms, double* gemm_flops, long long* gemm_launches,

@@ -377,12 +377,12 @@ class Context:
     def prof_read(self):
         ms, fl = ctypes.c_double(0), ctypes.c_double(0)
         nl = ctypes.c_longlong(0)
-        cnt = (ctypes.c_longlong * 6)()
+        cnt = (ctypes.c_longlong * 7)()
         self._check(lib().tn_prof_read(self._h, ctypes.byref(ms), ctypes.byref(fl),
                                        ctypes.byref(nl), cnt))
         return dict(gemm_ms=ms.value, gemm_flops=fl.value, gemm_launches=nl.value,
                     moves=cnt[0], svd_calls=cnt[1], svd_iters=cnt[2], svd_unconverged=cnt[3],
-                    svd_explicit=cnt[4], jacobi_sweeps=cnt[5])
+                    svd_explicit=cnt[4], jacobi_sweeps=cnt[5], gemm_bytes=cnt[6])
 
     def gemm(self, A, B, C, ta=False, tb=False, alpha=1.0, beta=0.0, precision="fp64"):
         M = A.shape[1] if ta else A.shape[0]

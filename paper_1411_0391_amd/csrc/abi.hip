@@ -353,6 +353,7 @@ int tn_prof_enable(tn_ctx* ctx, int on) {
   ctx->prof = on != 0;
   ctx->ev_used = 0;
   ctx->prof_flops.clear();
+  ctx->prof_bytes = 0.0;
   ctx->svd_iters = ctx->svd_calls = ctx->svd_unconverged = ctx->svd_explicit = ctx->moves = 0;
   return TN_OK;
 }
@@ -381,9 +382,11 @@ int tn_prof_read(tn_ctx* ctx, double* gemm_ms, double* gemm_flops, long long* ge
     counters[2] = ctx->svd_iters;
     counters[3] = ctx->svd_unconverged;
     counters[4] = ctx->svd_explicit;
+    counters[6] = (long long)ctx->prof_bytes;
   }
   ctx->ev_used = 0;
   ctx->prof_flops.clear();
+  ctx->prof_bytes = 0.0;
   ctx->svd_iters = ctx->svd_calls = ctx->svd_unconverged = ctx->svd_explicit = ctx->moves = 0;
   return TN_OK;
 }

@@ -33,6 +33,7 @@ struct tn_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<double> prof_flops;
+  double prof_bytes = 0.0;  // algorithmic bytes of the timed contractions
   // solver counters since the last read
   long long svd_iters = 0, svd_calls = 0, svd_unconverged = 0, svd_explicit = 0, moves = 0;
 };

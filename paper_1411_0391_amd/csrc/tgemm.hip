@@ -490,6 +490,8 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
     e1 = ctx->ev_pool[ctx->ev_used + 1];
     ctx->ev_used += 2;
     ctx->prof_flops.push_back(2.0 * (double)d.M * (double)d.N * (double)d.K * (double)batch);
+    // operands read once and the result written once
+    ctx->prof_bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (double)d.M * d.N) * batch;
   }
   hipEvent_t stop_main = d.ksplit > 1 ? nullptr : e1;
 #define TN_GO(KERNEL)                                                                          \
