@@ -270,7 +270,15 @@ __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
   const int lane = threadIdx.x & 63, blk = threadIdx.x >> 6;
   const int hi = lane >> 4, lo = lane & 15;
   const long long npair = (long long)g.nc * g.na;
-  const long long p0 = (long long)blockIdx.x * ABS_G;
+  // consecutive workgroups go to different XCDs (each with its own L2), and
+  // neighbouring pair blocks share the cache lines of In: give the blocks
+  // that one XCD runs (physical ids b, b + 8, b + 16, ...) consecutive pairs
+  long long bid = blockIdx.x;
+  {
+    const long long per = gridDim.x / 8;
+    if (bid < per * 8) bid = (bid % 8) * per + bid / 8;
+  }
+  const long long p0 = bid * ABS_G;
   // operand-A row of this lane: m = 16 blk + lo, i.e. pair m / P, index pair m % P
   const int mA = 16 * blk + lo;
   const int aA = mA / P, LA = mA % P;

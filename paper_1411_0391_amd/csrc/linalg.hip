@@ -584,16 +584,21 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
       const int r = ty + 32 * a, c = tx + 32 * b;
       W[a][b] = (r < k && c < k) ? G[r * k + c] + (r == c ? shift : 0.0) : 0.0;
     }
-  int fail = 0;
+  // A failing pivot (not positive) zeroes its row of R, and the elimination
+  // runs on to the end; the first failure is reported afterwards, so no step
+  // waits on a status read.  The holders of row j keep 1 / R[j][j] for the
+  // inverse.
+  double irow[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) {
-    for (int jj = 0; jj < 32 && !fail; ++jj) {
+    for (int jj = 0; jj < 32; ++jj) {
       const int j = 32 * jb + jj;
       if (j >= k) break;
       if (ty == jj) {
         // the pivot W[j][j] sits in lane 32 (jj & 1) + jj of this wave
         const double d = readlane_d(W[jb][jb], ((jj & 1) << 5) + jj);
-        const double ir = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        const double ir = d > 0.0 ? rsqrt(d) : 0.0;
+        irow[jb] = d > 0.0 ? sqrt(d) : 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int c = tx + 32 * b;
@@ -606,10 +611,6 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
         if (tx == 0) piv[j] = d;
       }
       __syncthreads();
-      if (!(piv[j] > 0.0)) {  // the same value in every thread
-        fail = j + 1;
-        break;
-      }
       double rr[4], rc[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) rr[a] = ty + 32 * a < k ? Rl[j * ldr + ty + 32 * a] : 0.0;
@@ -621,7 +622,18 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
         for (int b = 0; b < 4; ++b) W[a][b] -= rr[a] * rc[b];
     }
   }
-  if (tid == 0) *info = fail;
+  __shared__ int fail;
+  if (tid < 64) {
+    int f = 0x7fffffff;
+    for (int j = tid; j < k; j += 64)
+      if (!(piv[j] > 0.0)) f = min(f, j + 1);
+    for (int o = 32; o > 0; o >>= 1) f = min(f, __shfl_xor(f, o, 64));
+    if (tid == 0) {
+      fail = f == 0x7fffffff ? 0 : f;
+      *info = fail;
+    }
+  }
+  __syncthreads();
   if (fail) return;
   // W is free: it becomes B = I
 #pragma unroll
@@ -635,7 +647,7 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
       if (j >= k) continue;
       double* xr = xrow + (j & 1) * CHOLR_MAX;
       if (ty == jj) {
-        const double ir = 1.0 / Rl[j * ldr + j];
+        const double ir = 1.0 / irow[jb];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int c = tx + 32 * b;
