@@ -125,6 +125,12 @@ int tn_create(tn_ctx** out, void* hip_stream) {
 int tn_destroy(tn_ctx* ctx) {
   if (!ctx) return TN_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->arena) (void)hipFree(ctx->arena);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   for (auto& kv : ctx->keep) (void)hipFree(kv.second.first);

@@ -27,6 +27,10 @@ struct tn_ctx {
   std::map<std::string, std::vector<char>> keep_flags;  // host validity flags per buffer slot
   // pinned host staging for small scalar read-backs
   double* host_scratch = nullptr;
+  // a second stream of the library's own (default priority) for work that
+  // overlaps the context stream; forked from it and joined back by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional per-launch timing of the contraction kernel (HIP events on the
   // context stream) and the algorithmic flops of each timed launch
   bool prof = false;
@@ -133,6 +137,13 @@ int gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, bool ta, co
 // returns the sweep count.
 int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long long sA, double* U,
                int ldu, long long sU, double* S, long long sS, double* V, int ldv, long long sV);
+
+// Whether jacobi_svd of these sizes takes workspace from the arena (else it
+// runs in LDS alone).
+bool jacobi_svd_needs_workspace(int m, int n);
+
+// The side stream and its fork / join events, created on first use.
+int side_stream_ready(tn_ctx* ctx);
 
 // The same SVD for one matrix with n <= 512, spread over the whole GPU (one
 // launch per round of column pairs, one workgroup per pair).  A is not

@@ -671,6 +671,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   constexpr int MAX_PLAIN = 3;
   int* info_p = ws_alloc<int>(ctx, 2 * MAX_PLAIN * 2 * B);  // orths of the plain steps
   double* Ysave = ws_alloc<double>(ctx, bnk);
+  double* Zk = ws_alloc<double>(ctx, bnk);
   double* Ssave = ws_alloc<double>(ctx, (size_t)B * k);
   if (!Ssave) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
   const long long kk = (long long)k * k, snk = (long long)nk;
@@ -719,10 +720,30 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       TN_TRY(orth_fast(ctx, n, k, B, Bm, Sprev, R, tmp, info_b));
     else
       TN_TRY(orth_robust(ctx, n, k, B, Bm, have_s ? Sprev : nullptr, R, tmp, save, info));
-    TN_TRY(jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk));
-    TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
-    TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
-    TN_TRY(applyK(ctx, t, Wb, Y));
+    // The Ritz rotation UR only turns the basis inside span(Bm), so K Bm can
+    // be formed while the SVD of R (a few workgroups) runs on the side
+    // stream; then K Wb = (K Bm) UR.
+    if (!jacobi_svd_needs_workspace(k, k)) {
+      TN_TRY(side_stream_ready(ctx));
+      TN_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
+      TN_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+      hipStream_t main_stream = ctx->stream;
+      ctx->stream = ctx->side;
+      const int rc = jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk);
+      ctx->stream = main_stream;
+      if (rc != TN_OK) return rc;
+      TN_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side));
+      TN_TRY(applyK(ctx, t, Bm, Zk));
+      TN_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+      TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
+      TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
+      TN_TRY(gemm(ctx, n, k, k, Zk, k, false, UR, k, false, Y, k, 1.0, 0.0, B, snk, kk, snk));
+    } else {
+      TN_TRY(jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk));
+      TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
+      TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
+      TN_TRY(applyK(ctx, t, Wb, Y));
+    }
     hipLaunchKernelGGL(resid_kernel, dim3(chi, B), dim3(256), 0, ctx->stream, n, k, chi, Y, Vr, S,
                        colres);
     hipLaunchKernelGGL(max_over_kernel, dim3(1), dim3(1), 0, ctx->stream, colres, chi, B, S, k,

@@ -535,10 +535,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
 // holding row j scale it by 1/sqrt(pivot) and publish it as row j of R in
 // LDS; after one barrier every thread applies W[r][c] -= R[j][r] R[j][c] to
 // its 16 entries (entries of finished rows and columns are updated too and
-// never read again).  Inverse by the column sweep X = R^-1: B = I; for
-// j = k-1 .. 0 the holders of row j publish X[j][:] = B[j][:] / R[j][j] (a
-// double-buffered LDS row), then every thread applies
-// B[i][c] -= R[i][j] X[j][c].  One barrier per step in both parts.
+// never read again).  The same row operations carried on an identity block
+// give R^-T in the same k steps (Gauss-Jordan on [G | I]), so the inverse
+// costs no second sweep.  One barrier per step.
 // ---------------------------------------------------------------------------
 constexpr int CHOLR_MAX = 128;
 
@@ -576,29 +575,35 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
   }
   for (int t = tid; t < k * ldr; t += 1024) Rl[t] = 0.0;
   __syncthreads();
-  double W[4][4];
+  // The elimination runs on [G | I]: row operations that take G to R take
+  // the identity to R^-T, so the inverse comes out of the same sweep.
+  // Thread (ty, tx) holds G entries and identity entries (ty + 32 a,
+  // tx + 32 b).
+  double W[4][4], Z[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = ty + 32 * a, c = tx + 32 * b;
       W[a][b] = (r < k && c < k) ? G[r * k + c] + (r == c ? shift : 0.0) : 0.0;
+      Z[a][b] = r == c ? 1.0 : 0.0;
     }
-  // A failing pivot (not positive) zeroes its row of R, and the elimination
-  // runs on to the end; the first failure is reported afterwards, so no step
-  // waits on a status read.  The holders of row j keep 1 / R[j][j] for the
-  // inverse.
-  double irow[4] = {0.0, 0.0, 0.0, 0.0};
+  // Step j: the holders of row j scale it by 1 / sqrt(pivot), which gives
+  // row j of R and row j of R^-T (column j of R^-1); every row i then takes
+  // R[j][i] times those rows (row j itself drops to zero).  A failing pivot
+  // (not positive) zeroes its rows and the elimination runs on to the end;
+  // the first failure is reported afterwards, so no step waits on a status
+  // read.  One barrier per step: the R^-T rows in flight are double-buffered.
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) {
     for (int jj = 0; jj < 32; ++jj) {
       const int j = 32 * jb + jj;
       if (j >= k) break;
+      double* xr = xrow + (j & 1) * CHOLR_MAX;
       if (ty == jj) {
         // the pivot W[j][j] sits in lane 32 (jj & 1) + jj of this wave
         const double d = readlane_d(W[jb][jb], ((jj & 1) << 5) + jj);
         const double ir = d > 0.0 ? rsqrt(d) : 0.0;
-        irow[jb] = d > 0.0 ? sqrt(d) : 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int c = tx + 32 * b;
@@ -606,69 +611,37 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
             const double v = c >= j ? W[jb][b] * ir : 0.0;
             Rl[j * ldr + c] = v;
             R[j * k + c] = v;
+            const double x = c <= j ? Z[jb][b] * ir : 0.0;
+            xr[c] = x;
+            Rinv[c * k + j] = x;
           }
         }
         if (tx == 0) piv[j] = d;
       }
       __syncthreads();
-      double rr[4], rc[4];
+      double rr[4], rc[4], xc[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) rr[a] = ty + 32 * a < k ? Rl[j * ldr + ty + 32 * a] : 0.0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) rc[b] = tx + 32 * b < k ? Rl[j * ldr + tx + 32 * b] : 0.0;
+      for (int b = 0; b < 4; ++b) {
+        rc[b] = tx + 32 * b < k ? Rl[j * ldr + tx + 32 * b] : 0.0;
+        xc[b] = tx + 32 * b < k ? xr[tx + 32 * b] : 0.0;
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) W[a][b] -= rr[a] * rc[b];
+        for (int b = 0; b < 4; ++b) {
+          W[a][b] -= rr[a] * rc[b];
+          Z[a][b] -= rr[a] * xc[b];
+        }
     }
   }
-  __shared__ int fail;
   if (tid < 64) {
     int f = 0x7fffffff;
     for (int j = tid; j < k; j += 64)
       if (!(piv[j] > 0.0)) f = min(f, j + 1);
     for (int o = 32; o > 0; o >>= 1) f = min(f, __shfl_xor(f, o, 64));
-    if (tid == 0) {
-      fail = f == 0x7fffffff ? 0 : f;
-      *info = fail;
-    }
-  }
-  __syncthreads();
-  if (fail) return;
-  // W is free: it becomes B = I
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) W[a][b] = (ty + 32 * a == tx + 32 * b) ? 1.0 : 0.0;
-#pragma unroll
-  for (int jb = 3; jb >= 0; --jb) {
-    for (int jj = 31; jj >= 0; --jj) {
-      const int j = 32 * jb + jj;
-      if (j >= k) continue;
-      double* xr = xrow + (j & 1) * CHOLR_MAX;
-      if (ty == jj) {
-        const double ir = 1.0 / irow[jb];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int c = tx + 32 * b;
-          if (c < k) {
-            const double x = W[jb][b] * ir;
-            xr[c] = x;
-            Rinv[j * k + c] = x;
-          }
-        }
-      }
-      __syncthreads();
-      double rr[4], xc[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) rr[a] = ty + 32 * a < k ? Rl[(ty + 32 * a) * ldr + j] : 0.0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) xc[b] = tx + 32 * b < k ? xr[tx + 32 * b] : 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) W[a][b] -= rr[a] * xc[b];
-    }
+    if (tid == 0) *info = f == 0x7fffffff ? 0 : f;
   }
 }
 
@@ -727,6 +700,22 @@ int jacobi_sweeps_read(tn_ctx* ctx, unsigned long long* out) {
   TN_HIP(ctx, hipMemcpy(out, g_sweeps, sizeof(unsigned long long), hipMemcpyDeviceToHost));
   const unsigned long long zero = 0;
   TN_HIP(ctx, hipMemcpy(g_sweeps, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  return TN_OK;
+}
+
+bool jacobi_svd_needs_workspace(int m, int n) {
+  const int me = (m + 15) / 16, ne = (n + 15) / 16;
+  const size_t fast_bytes = (size_t)(16 * me + 1 + 16 * ne + 1) * n * sizeof(double);
+  if (m <= 16 * JF_MAX && fast_bytes <= LDS_LIMIT) return false;
+  const size_t per = (size_t)(m | 1) * n + (size_t)(n | 1) * n;
+  return per * sizeof(double) > LDS_LIMIT;
+}
+
+int side_stream_ready(tn_ctx* ctx) {
+  if (ctx->side) return TN_OK;
+  TN_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  TN_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  TN_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
   return TN_OK;
 }
 

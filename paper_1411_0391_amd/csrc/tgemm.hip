@@ -115,17 +115,48 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
       bn_[i] = e / BK;
     }
   }
+  // The k-independent half of each operand offset, computed once.  Rows of
+  // A past M and columns of B past N are clamped into range instead of
+  // masked: they only feed outputs that are never stored.  Strided mode
+  // folds the element's k within the slice into it as well, so that a full
+  // slice's addresses are this plus the slice's uniform k0 offset.
+  long long ca[4], cb[NB];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = min(m0 + am_[i], d.M - 1);
+    ca[i] = TABLE ? (long long)d.am[m] : (long long)m * d.sam + (long long)ak_[i] * d.sak;
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int n = min(n0 + bn_[i], d.N - 1);
+    cb[i] = TABLE ? (long long)d.bn[n] : (long long)n * d.sbn + (long long)bk_[i] * d.sbk;
+  }
   double ra[4], rb[NB];
+  // a full slice: every k below kend, no tests
   auto fetch = [&](int k0) {
+    const double* Ak = TABLE ? A : A + (long long)k0 * d.sak;
+    const double* Bk = TABLE ? B : B + (long long)k0 * d.sbk;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ra[i] = Ak[TABLE ? ca[i] + d.ak[k0 + ak_[i]] : ca[i]];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) rb[i] = Bk[TABLE ? cb[i] + d.bk[k0 + bk_[i]] : cb[i]];
+  };
+  // the ragged last slice: k clamped below kend for the address, the value
+  // zeroed past it
+  auto fetch_tail = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int m = m0 + am_[i], k = k0 + ak_[i];
-      ra[i] = (m < d.M && k < kend) ? A[offA<TABLE>(d, m, k)] : 0.0;
+      const int k = min(k0 + ak_[i], kend - 1);
+      const double v =
+          A[TABLE ? ca[i] + d.ak[k] : ca[i] + (long long)(k - ak_[i]) * d.sak];
+      ra[i] = k0 + ak_[i] < kend ? v : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int n = n0 + bn_[i], kb = k0 + bk_[i];
-      rb[i] = (n < d.N && kb < kend) ? B[offB<TABLE>(d, kb, n)] : 0.0;
+      const int k = min(k0 + bk_[i], kend - 1);
+      const double v =
+          B[TABLE ? cb[i] + d.bk[k] : cb[i] + (long long)(k - bk_[i]) * d.sbk];
+      rb[i] = k0 + bk_[i] < kend ? v : 0.0;
     }
   };
   auto stash = [&](int buf) {
@@ -136,13 +167,14 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
   };
   int buf = 0;
   if (kbeg < kend) {
-    fetch(kbeg);
+    if (kbeg + BK <= kend) fetch(kbeg); else fetch_tail(kbeg);
     stash(0);
   }
   __syncthreads();
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) fetch(k0 + BK);
+    const int kn = k0 + BK;
+    if (kn + BK <= kend) fetch(kn);
+    else if (kn < kend) fetch_tail(kn);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double a[2], b[NJ];
@@ -156,7 +188,7 @@ __global__ __launch_bounds__(256) void tgemm_f64_kernel(const double* __restrict
         for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) stash(buf ^ 1);
+    if (kn < kend) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }

@@ -30,7 +30,11 @@ def host(t):
 
 @pytest.mark.parametrize("M,N,K,ta,tb", [(64, 64, 16, False, False), (70, 33, 19, False, False),
                                          (130, 97, 200, True, False), (5, 129, 64, False, True),
-                                         (257, 65, 33, True, True), (1, 1, 1, False, False)])
+                                         (257, 65, 33, True, True), (1, 1, 1, False, False),
+                                         # split along K with a ragged last slice, on the
+                                         # 96- and 128-wide tiles
+                                         (300, 96, 1000, False, False), (200, 120, 333, True, False),
+                                         (77, 90, 517, False, True), (64, 64, 4099, True, True)])
 def test_gemm_parity(ctx, M, N, K, ta, tb):
     rng = np.random.default_rng(M * 7 + N)
     A = rng.standard_normal((K, M) if ta else (M, K))
