@@ -160,4 +160,7 @@ int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* 
 // Misc kernels.
 int scale_columns(tn_ctx* ctx, int m, int n, double* X, int ldx, const double* s, int invsqrt);
 int frob_normalize(tn_ctx* ctx, double* x, long long n, double* norm_out);
+// dst = src / ||src||_F (dst may be src; a zero tensor is copied as is)
+int frob_normalize_to(tn_ctx* ctx, const double* src, double* dst, long long n,
+                      double* norm_out);
 int fill_random(tn_ctx* ctx, double* x, long long n, unsigned long long seed);

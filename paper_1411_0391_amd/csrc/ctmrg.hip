@@ -313,19 +313,25 @@ __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
                               : 0.0;
     }
     __syncthreads();
-    // ket layer: rows (pair, l, u') of this wave, all columns R1
+    // ket layer: rows (pair, l, u') of this wave, all columns R1 (the
+    // column blocks as independent accumulation chains)
+    {
+      dv4 acc1[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      dv4 acc1 = dv4{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < NJ; ++j) acc1[j] = dv4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(inA[q], Bs[(4 * q + hi) * S + 16 * j + lo],
-                                                    acc1, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * blk + hi + 4 * r;
-        if (row < ROWS) Ts[row * S + 16 * j + lo] = acc1[r];
-      }
+        for (int j = 0; j < NJ; ++j)
+          acc1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              inA[q], Bs[(4 * q + hi) * S + 16 * j + lo], acc1[j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * blk + hi + 4 * r;
+          if (row < ROWS) Ts[row * S + 16 * j + lo] = acc1[j][r];
+        }
     }
     __syncthreads();
     // bra layer: rows (pair, R1) of this wave, k over (l, u') of the same pair
@@ -463,9 +469,10 @@ int applyKT(tn_ctx* ctx, const TopK& t, const double* X, double* Y) {
 
 // Column scaling by 1 / max(s_j, floor * s_0) per problem (floor keeps
 // columns below the FP64 resolution of the block at unit scale instead of
-// blowing them up); X [batch][n][k], s and sc [batch][k].
-__global__ void inv_scale_cols_kernel(int n, int k, int batch, double* X, const double* s,
-                                      double floor_rel, double* sc) {
+// blowing them up); X = Src scaled (Src may be X), [batch][n][k]; s and sc
+// [batch][k].
+__global__ void inv_scale_cols_kernel(int n, int k, int batch, const double* Src, double* X,
+                                      const double* s, double floor_rel, double* sc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < (long long)batch * k) {
     const long long b = t / k;
@@ -475,7 +482,7 @@ __global__ void inv_scale_cols_kernel(int n, int k, int batch, double* X, const 
   const long long b = t / ((long long)n * k);
   const int j = (int)(t % k);
   const double* sb = s + b * k;
-  X[t] /= fmax(sb[j], floor_rel * sb[0]);
+  X[t] = Src[t] / fmax(sb[j], floor_rel * sb[0]);
 }
 
 // R <- R diag(sc) per problem (R [batch][k][k], sc [batch][k])
@@ -517,14 +524,17 @@ int cholqr_passes(tn_ctx* ctx, int n, int k, int batch, double* X, double* Rout,
     TN_HIP(ctx, hipMemcpyAsync(X, src, (size_t)batch * nk * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
   if (Rout) {
-    // R = R_last ... R_1
-    TN_HIP(ctx, hipMemcpyAsync(Rout, R + (size_t)(npass - 1) * batch * kk,
-                               (size_t)batch * kk * 8, hipMemcpyDeviceToDevice, ctx->stream));
-    for (int pass = npass - 2; pass >= 0; --pass) {
-      TN_TRY(gemm(ctx, k, k, k, Rout, k, false, R + (size_t)pass * batch * kk, k, false, Racc, k,
-                  1.0, 0.0, batch, kk, kk, kk));
-      TN_HIP(ctx, hipMemcpyAsync(Rout, Racc, (size_t)batch * kk * 8, hipMemcpyDeviceToDevice,
+    // R = R_last ... R_1, the partial products alternating between Racc and
+    // Rout so that the last lands in Rout
+    const double* acc = R + (size_t)(npass - 1) * batch * kk;
+    if (npass == 1)
+      TN_HIP(ctx, hipMemcpyAsync(Rout, acc, (size_t)batch * kk * 8, hipMemcpyDeviceToDevice,
                                  ctx->stream));
+    for (int pass = npass - 2; pass >= 0; --pass) {
+      double* dst = pass % 2 == 0 ? Rout : Racc;
+      TN_TRY(gemm(ctx, k, k, k, acc, k, false, R + (size_t)pass * batch * kk, k, false, dst, k,
+                  1.0, 0.0, batch, kk, kk, kk));
+      acc = dst;
     }
   }
   ctx->arena_off = mark;
@@ -544,7 +554,7 @@ int orth_robust(tn_ctx* ctx, int n, int k, int batch, double* X, const double* s
   const long long tot = (long long)batch * n * k;
   if (scale) {
     hipLaunchKernelGGL(inv_scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       ctx->stream, n, k, batch, X, scale, 1e-15, sc);
+                       ctx->stream, n, k, batch, X, X, scale, 1e-15, sc);
     TN_HIP(ctx, hipGetLastError());
   }
   TN_HIP(ctx, hipMemcpyAsync(save, X, (size_t)tot * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -586,15 +596,16 @@ int orth_robust(tn_ctx* ctx, int n, int k, int batch, double* X, const double* s
 // column pre-scaling by `scale` makes the block nearly orthonormal, and two
 // plain Cholesky-QR passes follow.  The Cholesky status of every pass and
 // problem goes to info[4 * batch] and is checked by the caller later; a
-// breakdown is then redone through orth_robust.
+// breakdown is then redone through orth_robust.  The block is read from src
+// when given (X is then written, not read).
 int orth_fast(tn_ctx* ctx, int n, int k, int batch, double* X, const double* scale,
-              double* Rout, double* tmp, int* info) {
+              double* Rout, double* tmp, int* info, const double* src = nullptr) {
   const size_t mark = ctx->arena_off;
   double* sc = ws_alloc<double>(ctx, (size_t)batch * k);
   if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in orth_fast");
   const long long tot = (long long)batch * n * k;
   hipLaunchKernelGGL(inv_scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                     ctx->stream, n, k, batch, X, scale, 1e-15, sc);
+                     ctx->stream, n, k, batch, src ? src : X, X, scale, 1e-15, sc);
   TN_HIP(ctx, hipGetLastError());
   TN_TRY(cholqr_passes(ctx, n, k, batch, X, Rout, tmp, info, 2, 0));
   if (Rout) {
@@ -672,8 +683,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   int* info_p = ws_alloc<int>(ctx, 2 * MAX_PLAIN * 2 * B);  // orths of the plain steps
   double* Ysave = ws_alloc<double>(ctx, bnk);
   double* Zk = ws_alloc<double>(ctx, bnk);
-  double* Ssave = ws_alloc<double>(ctx, (size_t)B * k);
-  if (!Ssave) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
+  if (!Zk) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in topk_svd");
   const long long kk = (long long)k * k, snk = (long long)nk;
   bool have_s = false;
   if (warmQ && warm_valid) {
@@ -698,7 +708,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   // the last of them (at most MAX_PLAIN) are plain.  Their Cholesky status is
   // checked with the next Rayleigh-Ritz step; a breakdown restarts from the
   // last checked block on the robust path, without further plain steps.
-  bool q_pending = false, robust = false, allow_plain = true;
+  bool q_pending = false, robust = false, allow_plain = true, s_current = true;
   int retries = 0, plain_left = 0, plain_done = 0, it_prev = 0;
   int it = 0;
   double hres = 1.0, r_prev = -1.0;
@@ -744,6 +754,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
       TN_TRY(applyK(ctx, t, Wb, Y));
     }
+    s_current = true;
     hipLaunchKernelGGL(resid_kernel, dim3(chi, B), dim3(256), 0, ctx->stream, n, k, chi, Y, Vr, S,
                        colres);
     hipLaunchKernelGGL(max_over_kernel, dim3(1), dim3(1), 0, ctx->stream, colres, chi, B, S, k,
@@ -773,7 +784,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       if (bad_q) {  // the basis of this iteration was not orthonormal
         TN_HIP(ctx, hipMemcpyAsync(Q, Ysave, bnk * sizeof(double), hipMemcpyDeviceToDevice,
                                    ctx->stream));
-        TN_TRY(orth_robust(ctx, n, k, B, Q, Ssave, nullptr, tmp, save, info));
+        TN_TRY(orth_robust(ctx, n, k, B, Q, Sprev, nullptr, tmp, save, info));
       }
       q_pending = false;
       robust = true;
@@ -797,17 +808,17 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     }
     r_prev = hres;
     it_prev = it;
-    TN_HIP(ctx, hipMemcpyAsync(Ysave, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(Ssave, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(Q, Y, bnk * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    TN_TRY(orth_fast(ctx, n, k, B, Q, S, nullptr, tmp, info_q));
+    // K Wb is kept (as Ysave) for a redo, and the Ritz values become the
+    // scaling of the next iteration, by exchanging buffers: the next Y and S
+    // are written in full before they are read
+    std::swap(Y, Ysave);
+    std::swap(S, Sprev);
+    s_current = false;
+    TN_TRY(orth_fast(ctx, n, k, B, Q, Sprev, nullptr, tmp, info_q, Ysave));
     q_pending = true;
-    TN_HIP(ctx, hipMemcpyAsync(Sprev, S, (size_t)B * k * sizeof(double), hipMemcpyDeviceToDevice,
-                               ctx->stream));
     have_s = true;
   }
+  if (!s_current) std::swap(S, Sprev);  // the last Ritz values
   if (st) {
     st->iters += (long long)it * B;
     st->calls += B;
@@ -951,15 +962,9 @@ int left_move(tn_ctx* ctx, const Geo& g, int f, int x, MoveBufs& b, SvdStats* st
   // write back and normalise
   for (int y = 0; y < Lyf; ++y) {
     const int dst = F.at(f, x + 1, y), d1 = F.at(f, x + 1, y + 1);
-    TN_HIP(ctx, hipMemcpyAsync(g.Cp(d1, f), b.Cn1 + y * csz, csz * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(g.Tp(dst, f + 3), b.Tn4 + y * tsz, tsz * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(g.Cp(dst, f + 3), b.Cn4 + y * csz, csz * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
-    TN_TRY(frob_normalize(ctx, g.Cp(d1, f), csz, nullptr));
-    TN_TRY(frob_normalize(ctx, g.Tp(dst, f + 3), tsz, nullptr));
-    TN_TRY(frob_normalize(ctx, g.Cp(dst, f + 3), csz, nullptr));
+    TN_TRY(frob_normalize_to(ctx, b.Cn1 + y * csz, g.Cp(d1, f), csz, nullptr));
+    TN_TRY(frob_normalize_to(ctx, b.Tn4 + y * tsz, g.Tp(dst, f + 3), tsz, nullptr));
+    TN_TRY(frob_normalize_to(ctx, b.Cn4 + y * csz, g.Cp(dst, f + 3), csz, nullptr));
   }
   return TN_OK;
 }
@@ -1036,11 +1041,12 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
   (void)warm;
   add(Lm * (16 * n * k + 64 * (size_t)k * k));  // split-K partials of the n x n x k products
   // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
-  add(std::max(Lm * 8 * n * k, 4 * n * n + n));
+  add(std::max(Lm * 9 * n * k, 4 * n * n + n));
   add(Lm * 3 * k * k);
   add(Lm * (4 * k + chi) + 64);
   add(Lm * 16 + 64);
   add(64);                                        // status of the plain steps
+  add(256);                                       // partial sums of the normalisations
   add(Lm * (8 * k * k + k) + 64);                 // Cholesky-QR passes (one alive at a time)
   add(Lm * (2 * std::max((size_t)k * k, n * n) + 2 * (size_t)k * k));  // jacobi work
   // rotated sites

@@ -655,11 +655,13 @@ __global__ void scale_columns_kernel(int m, int n, double* X, int ldx, const dou
   X[(long long)i * ldx + j] *= f;
 }
 
-__global__ __launch_bounds__(1024) void frob_normalize_kernel(double* x, long long n,
-                                                              double* norm_out) {
+// dst = src / ||src||_F in one workgroup (small tensors); a zero tensor is
+// copied unchanged
+__global__ __launch_bounds__(1024) void frob_normalize_kernel(const double* src, double* dst,
+                                                              long long n, double* norm_out) {
   __shared__ double part[16];
   double a = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 1024) a += x[i] * x[i];
+  for (long long i = threadIdx.x; i < n; i += 1024) a += src[i] * src[i];
   a = wave_sum(a);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
   __syncthreads();
@@ -671,9 +673,45 @@ __global__ __launch_bounds__(1024) void frob_normalize_kernel(double* x, long lo
   }
   __syncthreads();
   const double nrm = part[0];
-  if (!(nrm > 0.0)) return;
-  const double inv = 1.0 / nrm;
-  for (long long i = threadIdx.x; i < n; i += 1024) x[i] *= inv;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+  for (long long i = threadIdx.x; i < n; i += 1024) dst[i] = src[i] * inv;
+}
+
+// The same for large tensors over many workgroups: per-workgroup sums of
+// squares, then every workgroup of the scaling pass adds them up in the same
+// order (so all use the same norm) and scales its part.
+constexpr int FROB_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void frob_partial_kernel(const double* src, long long n,
+                                                           double* part) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    a += src[i] * src[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void frob_scale_kernel(const double* src, double* dst,
+                                                         long long n, const double* part,
+                                                         int nparts, double* norm_out) {
+  __shared__ double inv;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 64) s += part[i];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+      const double nrm = sqrt(s);
+      inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+      if (norm_out && blockIdx.x == 0) *norm_out = nrm;
+    }
+  }
+  __syncthreads();
+  const double f = inv;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    dst[i] = src[i] * f;
 }
 
 // splitmix64 (Steele, Lea, Flood 2014) mapped to a uniform value in [-1, 1)
@@ -828,10 +866,28 @@ int scale_columns(tn_ctx* ctx, int m, int n, double* X, int ldx, const double* s
   return TN_OK;
 }
 
-int frob_normalize(tn_ctx* ctx, double* x, long long n, double* norm_out) {
-  hipLaunchKernelGGL(frob_normalize_kernel, dim3(1), dim3(1024), 0, ctx->stream, x, n, norm_out);
+int frob_normalize_to(tn_ctx* ctx, const double* src, double* dst, long long n,
+                      double* norm_out) {
+  if (n <= 32768) {
+    hipLaunchKernelGGL(frob_normalize_kernel, dim3(1), dim3(1024), 0, ctx->stream, src, dst, n,
+                       norm_out);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+  }
+  const size_t mark = ctx->arena_off;  // consumed in stream order
+  double* part = ws_alloc<double>(ctx, FROB_BLOCKS);
+  if (!part) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in frob_normalize");
+  const int nb = (int)std::min<long long>(FROB_BLOCKS, (n + 2047) / 2048);
+  hipLaunchKernelGGL(frob_partial_kernel, dim3(nb), dim3(256), 0, ctx->stream, src, n, part);
+  hipLaunchKernelGGL(frob_scale_kernel, dim3(nb), dim3(256), 0, ctx->stream, src, dst, n, part,
+                     nb, norm_out);
   TN_HIP(ctx, hipGetLastError());
+  ctx->arena_off = mark;
   return TN_OK;
+}
+
+int frob_normalize(tn_ctx* ctx, double* x, long long n, double* norm_out) {
+  return frob_normalize_to(ctx, x, x, n, norm_out);
 }
 
 int fill_random(tn_ctx* ctx, double* x, long long n, unsigned long long seed) {
