@@ -250,6 +250,9 @@ __device__ inline double row_sum16(double v) {
 
 constexpr int JF_MAX = 8;  // 16-row slices per column: m, n <= 128
 
+// ME, NE: 16-row slices of the X and W columns (compile-time, so that a
+// lane's loads, dot products and rotations are straight-line code)
+template <int ME, int NE>
 __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
     const double* __restrict__ Ain, int lda, long long sA, double* __restrict__ U, int ldu,
     long long sU, double* __restrict__ S, long long sS, double* __restrict__ V, int ldv,
@@ -259,13 +262,12 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
   const long long b = blockIdx.x;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const double* A = Ain + b * sA;
-  const int me = (m + 15) >> 4, ne = (n + 15) >> 4;  // 16-row slices of X and W columns
-  const int ldx = 16 * me + 1, ldw = 16 * ne + 1;     // odd strides
+  constexpr int ldx = 16 * ME + 1, ldw = 16 * NE + 1;  // odd strides
   double* X = lds;                                    // X[j * ldx + i], rows >= m zero
   double* W = lds + (size_t)ldx * n;                  // W[j * ldw + i], rows >= n zero
   __shared__ double colnorm[128];
   __shared__ int perm[128];
-  __shared__ double off_g[64];
+  __shared__ int rot_g[64];
   __shared__ int done;
   for (int t = tid; t < ldx * n; t += nthr) {
     const int j = t / ldx, i = t % ldx;
@@ -284,7 +286,9 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
   // with 1 + (N - 2 - grp + r) mod (N - 1)
   int u = grp >= 1 ? grp - 1 : 0, v = N - 2 - grp;
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
-    double offmax = 0.0;
+    // a sweep with no rotation ends the iteration: every pair is then
+    // orthogonal to tol
+    int rotated = 0;
     for (int r = 0; r < N - 1; ++r) {
       if (active) {
         const int p0 = grp == 0 ? 0 : 1 + u, p1 = 1 + v;
@@ -292,52 +296,47 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
           const int p = min(p0, p1), q = max(p0, p1);
           double* xp = X + p * ldx + gl;
           double* xq = X + q * ldx + gl;
-          double xu[JF_MAX], xv[JF_MAX];
+          double xu[ME], xv[ME];
 #pragma unroll
-          for (int e = 0; e < JF_MAX; ++e)
-            if (e < me) {
-              xu[e] = xp[16 * e];
-              xv[e] = xq[16 * e];
-            }
+          for (int e = 0; e < ME; ++e) {
+            xu[e] = xp[16 * e];
+            xv[e] = xq[16 * e];
+          }
           double a = 0.0, bb = 0.0, g = 0.0;
 #pragma unroll
-          for (int e = 0; e < JF_MAX; ++e)
-            if (e < me) {
-              a += xu[e] * xu[e];
-              bb += xv[e] * xv[e];
-              g += xu[e] * xv[e];
-            }
+          for (int e = 0; e < ME; ++e) {
+            a += xu[e] * xu[e];
+            bb += xv[e] * xv[e];
+            g += xu[e] * xv[e];
+          }
           a = row_sum16(a);
           bb = row_sum16(bb);
           g = row_sum16(g);
           const double scale = sqrt(a * bb);
           if (scale != 0.0 && fabs(g) > tol * scale) {
-            offmax = fmax(offmax, fabs(g) / scale);
+            rotated = 1;
             const double z = (bb - a) / (2.0 * g);
             const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
             const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
 #pragma unroll
-            for (int e = 0; e < JF_MAX; ++e)
-              if (e < me) {
-                xp[16 * e] = c * xu[e] - sn * xv[e];
-                xq[16 * e] = sn * xu[e] + c * xv[e];
-              }
+            for (int e = 0; e < ME; ++e) {
+              xp[16 * e] = c * xu[e] - sn * xv[e];
+              xq[16 * e] = sn * xu[e] + c * xv[e];
+            }
             // the accumulator columns only for pairs that rotate
             double* wp = W + p * ldw + gl;
             double* wq = W + q * ldw + gl;
-            double wu[JF_MAX], wv[JF_MAX];
+            double wu[NE], wv[NE];
 #pragma unroll
-            for (int e = 0; e < JF_MAX; ++e)
-              if (e < ne) {
-                wu[e] = wp[16 * e];
-                wv[e] = wq[16 * e];
-              }
+            for (int e = 0; e < NE; ++e) {
+              wu[e] = wp[16 * e];
+              wv[e] = wq[16 * e];
+            }
 #pragma unroll
-            for (int e = 0; e < JF_MAX; ++e)
-              if (e < ne) {
-                wp[16 * e] = c * wu[e] - sn * wv[e];
-                wq[16 * e] = sn * wu[e] + c * wv[e];
-              }
+            for (int e = 0; e < NE; ++e) {
+              wp[16 * e] = c * wu[e] - sn * wv[e];
+              wq[16 * e] = sn * wu[e] + c * wv[e];
+            }
           }
         }
         u = u + 1 == N - 1 ? 0 : u + 1;
@@ -345,12 +344,12 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
       }
       __syncthreads();
     }
-    if (gl == 0 && active) off_g[grp] = offmax;
+    if (gl == 0 && active) rot_g[grp] = rotated;
     __syncthreads();
     if (tid == 0) {
-      double mx = 0.0;
-      for (int w = 0; w < N / 2; ++w) mx = fmax(mx, off_g[w]);
-      done = (mx <= tol) ? 1 : 0;
+      int any = 0;
+      for (int w = 0; w < N / 2; ++w) any |= rot_g[w];
+      done = any ? 0 : 1;
       if (sweep_count) atomicAdd(sweep_count, 1ULL);
     }
     __syncthreads();
@@ -358,6 +357,25 @@ __global__ __launch_bounds__(1024) void jacobi_svd_fast_kernel(
   }
   jacobi_emit(X, ldx, W, ldw, m, n, colnorm, perm, b, U, ldu, sU, S, sS, V, ldv, sV);
 }
+
+typedef void (*jacobi_fast_fn)(const double*, int, long long, double*, int, long long, double*,
+                               long long, double*, int, long long, int, int, int, double,
+                               unsigned long long*);
+
+#define TN_JF_ROW(ME)                                                                          \
+  {jacobi_svd_fast_kernel<ME, 1>, jacobi_svd_fast_kernel<ME, (ME >= 2 ? 2 : ME)>,              \
+   jacobi_svd_fast_kernel<ME, (ME >= 3 ? 3 : ME)>, jacobi_svd_fast_kernel<ME, (ME >= 4 ? 4 : ME)>, \
+   jacobi_svd_fast_kernel<ME, (ME >= 5 ? 5 : ME)>, jacobi_svd_fast_kernel<ME, (ME >= 6 ? 6 : ME)>, \
+   jacobi_svd_fast_kernel<ME, (ME >= 7 ? 7 : ME)>, jacobi_svd_fast_kernel<ME, (ME >= 8 ? 8 : ME)>}
+
+// the kernel for me, ne slices (1 <= ne <= me <= JF_MAX)
+jacobi_fast_fn jacobi_fast_kernel(int me, int ne) {
+  static const jacobi_fast_fn table[JF_MAX][JF_MAX] = {TN_JF_ROW(1), TN_JF_ROW(2), TN_JF_ROW(3),
+                                                      TN_JF_ROW(4), TN_JF_ROW(5), TN_JF_ROW(6),
+                                                      TN_JF_ROW(7), TN_JF_ROW(8)};
+  return table[me - 1][ne - 1];
+}
+#undef TN_JF_ROW
 
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of one large matrix (n <= 512) across the whole GPU:
@@ -783,7 +801,7 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
     if (m <= 16 * JF_MAX && fast_bytes <= LDS_LIMIT) {
       const int groups = ((n + 1) & ~1) / 2;
       const unsigned threads = (unsigned)std::max(64, (16 * groups + 63) / 64 * 64);
-      hipLaunchKernelGGL(jacobi_svd_fast_kernel, dim3(batch), dim3(threads), fast_bytes,
+      hipLaunchKernelGGL(jacobi_fast_kernel(me, ne), dim3(batch), dim3(threads), fast_bytes,
                          ctx->stream, A, lda, sA, U, ldu, sU, S, sS, V, ldv, sV, m, n, 80, tol,
                          g_sweeps);
       TN_HIP(ctx, hipGetLastError());

@@ -81,8 +81,15 @@ def test_tm_fixed_point_mixed_brute_force(ctx):
     np.testing.assert_allclose(E @ y, geta * y, atol=1e-10 * abs(geta) * np.abs(y).max())
 
 
-@pytest.mark.parametrize("chi,h", [(8, 1.0), (16, 1.0), (12, 0.5)])
-def test_itebd_plain_step_parity(ctx, chi, h):
+# The (8, 1.0) state is cat-like: its unit-cell transfer matrix has
+# |l2 / l1| = 1 - 1.5e-5, so the dominant fixed points that build P and Q are
+# determined only to about (residual) / 1.5e-5, and the two sides reach them
+# by different iterations; in the oracle a 1e-13 perturbation of those
+# environments already moves A by up to 1.1e-8.  The other two states have
+# transfer-matrix gaps of 0.14 and 0.18.  Spectra, truncation error and
+# energy are compared at 1e-10 in every case.
+@pytest.mark.parametrize("chi,h,atol_a", [(8, 1.0, 1e-6), (16, 1.0, 1e-8), (12, 0.5, 1e-8)])
+def test_itebd_plain_step_parity(ctx, chi, h, atol_a):
     sites = _state(2, chi, h=h)
     g = gates.impo(1.0, h, 0.01)
     new, P, Q, spec, err = imps.itebd_plain_step(sites, g, chi)
@@ -95,7 +102,7 @@ def test_itebd_plain_step_parity(ctx, chi, h):
     np.testing.assert_allclose(host(lam), np.stack(spec), atol=1e-10)
     assert abs(gerr - err) < 1e-10 * max(err, 1e-30) + 1e-15
     assert abs(ge - e_ref) < 1e-10 * abs(e_ref)
-    np.testing.assert_allclose(host(A), np.stack(new), atol=1e-8)
+    np.testing.assert_allclose(host(A), np.stack(new), atol=atol_a)
 
 
 def test_itebd_trajectory_parity(ctx):
@@ -149,12 +156,15 @@ def test_recycle_build_and_apply_parity(ctx, chi, h):
     gRf = e[4 * n * n + 2 * chi * n:4 * n * n + 4 * chi * n].reshape(2, n, chi)
     assert np.abs(gLf - np.stack(Lf)).max() < 1e-7 * np.abs(Lf).max()
     assert np.abs(gRf - np.stack(Rf)).max() < 1e-7 * np.abs(Rf).max()
-    np.testing.assert_allclose(host(A), np.stack(new), atol=1e-8)
+    # the new sites are the two factors applied to g A_0: their relative
+    # deviation is at most the sum of the factors' (each within 1e-7)
+    np.testing.assert_allclose(host(A), np.stack(new), atol=2e-7 * np.abs(np.stack(new)).max())
     # one recycled step with the stored factors
     nxt = imps.apply_renormalized(Lf, Rf, g, new)
     _, ge, rc = ctx.itebd_step(A, 1.0, h, 0.01, env, mode=tn.TN_RECYCLE_APPLY, energy=True)
     assert rc == tn.TN_OK
-    np.testing.assert_allclose(host(A), np.stack(nxt), atol=1e-8)
+    # the factors once more, on sites that already carry their deviation
+    np.testing.assert_allclose(host(A), np.stack(nxt), atol=4e-7 * np.abs(np.stack(nxt)).max())
     er = imps.energy_per_site(nxt, 1.0, h)
     assert abs(ge - er) < 1e-9 * abs(er)
 
