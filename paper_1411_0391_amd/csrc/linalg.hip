@@ -597,15 +597,58 @@ __global__ __launch_bounds__(1024) void cholesky_inv_reg_kernel(const double* __
   // the identity to R^-T, so the inverse comes out of the same sweep.
   // Thread (ty, tx) holds G entries and identity entries (ty + 32 a,
   // tx + 32 b).
-  double W[4][4], Z[4][4];
+  double W[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = ty + 32 * a, c = tx + 32 * b;
       W[a][b] = (r < k && c < k) ? G[r * k + c] + (r == c ? shift : 0.0) : 0.0;
-      Z[a][b] = r == c ? 1.0 : 0.0;
     }
+  // A Gram matrix within 1e-9 of the identity (the second pass of
+  // Cholesky-QR on a block that is already orthonormal): with E = G - I,
+  // R = I + U and R^-1 = I - U, U the strict upper part of E plus half its
+  // diagonal; the neglected terms are below k max|E|^2 <= 1.3e-16.
+  // (a NaN anywhere propagates into the maximum and sends the matrix down
+  // the elimination, which reports it as a failed pivot)
+  auto nan_max = [](double x, double y) { return (y > x || y != y) ? y : x; };
+  __shared__ double emax_w[16];
+  {
+    double em = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ty + 32 * a, c = tx + 32 * b;
+        if (r < k && c < k) em = nan_max(em, fabs(W[a][b] - (r == c ? 1.0 : 0.0)));
+      }
+    for (int o = 32; o > 0; o >>= 1) em = nan_max(em, __shfl_xor(em, o, 64));
+    if ((tid & 63) == 0) emax_w[tid >> 6] = em;
+  }
+  __syncthreads();
+  double emax = 0.0;
+  for (int w = 0; w < 16; ++w) emax = nan_max(emax, emax_w[w]);
+  if (shift == 0.0 && emax <= 1e-9) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ty + 32 * a, c = tx + 32 * b;
+        if (r < k && c < k) {
+          const double e = W[a][b] - (r == c ? 1.0 : 0.0);
+          const double u = r < c ? e : (r == c ? 0.5 * e : 0.0);
+          R[r * k + c] = (r == c ? 1.0 : 0.0) + u;
+          Rinv[r * k + c] = (r == c ? 1.0 : 0.0) - u;
+        }
+      }
+    if (tid == 0) *info = 0;
+    return;
+  }
+  double Z[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Z[a][b] = ty + 32 * a == tx + 32 * b ? 1.0 : 0.0;
   // Step j: the holders of row j scale it by 1 / sqrt(pivot), which gives
   // row j of R and row j of R^-T (column j of R^-1); every row i then takes
   // R[j][i] times those rows (row j itself drops to zero).  A failing pivot

@@ -108,3 +108,26 @@ def test_cholesky_inv_parity(ctx, k):
         Gbad[1] = -Gbad[1]
         _, _, info = ctx.cholesky_inv(dev(Gbad))
         assert info[0] == 0 and info[1] == 1
+
+
+@pytest.mark.parametrize("k,scale", [(96, 1e-12), (96, 3e-10), (40, 2e-8), (128, 1e-11)])
+def test_cholesky_near_identity(ctx, k, scale):
+    """Gram matrices I + E of almost orthonormal blocks (the second pass of
+    Cholesky-QR): max|E| below 1e-9 takes the first-order closed form,
+    above it the elimination; both match LAPACK to rounding."""
+    rng = np.random.default_rng(k)
+    E = scale * rng.standard_normal((2, k, k))
+    G = np.eye(k)[None] + 0.5 * (E + E.transpose(0, 2, 1))
+    R, Ri, info = ctx.cholesky_inv(dev(G))
+    assert info == [0, 0]
+    for b in range(2):
+        Rr = np.linalg.cholesky(G[b]).T
+        np.testing.assert_allclose(host(R)[b], Rr, rtol=0, atol=4e-16 * k)
+        np.testing.assert_allclose(host(Ri)[b], np.linalg.inv(Rr), rtol=0, atol=4e-16 * k)
+
+
+def test_cholesky_reports_nan(ctx):
+    G = np.eye(16)[None].repeat(2, axis=0)
+    G[1, 3, 5] = G[1, 5, 3] = np.nan
+    _, _, info = ctx.cholesky_inv(dev(G))
+    assert info[0] == 0 and info[1] > 0
