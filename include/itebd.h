@@ -51,7 +51,11 @@ enum {
 enum { TN_FP64 = 0, TN_FP32 = 1, TN_BF16 = 2 };
 
 /* Create a context on the current HIP device.  hip_stream may be NULL (the
- * null stream) or a hipStream_t owned by the caller.  Errors: TN_EHIP. */
+ * null stream) or a hipStream_t owned by the caller.  The context may also
+ * create one stream of its own (default priority, on first use) for work
+ * that overlaps the caller's stream inside a call; every such fork is
+ * joined back to hip_stream by an event before the work that depends on
+ * it, and tn_destroy releases it.  Errors: TN_EHIP. */
 int tn_create(tn_ctx** ctx, void* hip_stream);
 
 /* Release the context and everything it allocated. */

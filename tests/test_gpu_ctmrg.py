@@ -56,7 +56,11 @@ def _setup(cellspec, D, chi, seed=0):
 
 @pytest.mark.parametrize("cellspec,D,chi", [(tninputs.CHECKERBOARD, 2, 6),
                                             (tninputs.SINGLE_SITE, 3, 7),
-                                            (tninputs.CHECKERBOARD, 3, 9)])
+                                            (tninputs.CHECKERBOARD, 3, 9),
+                                            # the fused site absorption at D = 5 and 6
+                                            (tninputs.SINGLE_SITE, 5, 5),
+                                            (tninputs.CHECKERBOARD, 6, 4),
+                                            (tninputs.SINGLE_SITE, 6, 5)])
 def test_single_left_move_parity(ctx, cellspec, D, chi):
     Lx, Ly, cell, sites, C, T = _setup(cellspec, D, chi)
     ocell = octm.Cell(Lx, Ly, cell)
