@@ -59,7 +59,7 @@ __device__ inline long long offC(const TDesc& d, int m, int n) {
   return (long long)m * d.scm + (long long)n * d.scn;
 }
 
-// 256 threads = 4 waves; the 64 x TBN tile (TBN = 64, 96 or 128) is split
+// 256 threads = 4 waves; the 64 x TBN tile (TBN = 32, 64, 96 or 128) is split
 // 2 x 2 between the waves, each owning 32 x TBN/2 as 2 x TBN/32 MFMA blocks.
 // The wide tiles serve products with a narrow N (the n x n x k products of
 // the projector SVD): the whole width is one tile, so the large operand is
@@ -452,6 +452,8 @@ long long concurrent_groups(const void* fn) {
 
 const void* kernel_of(int prec, int tbn, bool table) {
   if (prec == P_F64) {
+    if (tbn == 32)
+      return table ? (const void*)tgemm_f64_kernel<true, 32> : (const void*)tgemm_f64_kernel<false, 32>;
     if (tbn == 96)
       return table ? (const void*)tgemm_f64_kernel<true, 96> : (const void*)tgemm_f64_kernel<false, 96>;
     if (tbn == 128)
@@ -470,14 +472,20 @@ const void* kernel_of(int prec, int tbn, bool table) {
 // per workgroup), plus a small charge per split for the partial sums.
 int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const double* B,
            double* C, double alpha, double beta, int prec) {
-  // FP64: one tile across a narrow N (65..128 columns)
-  const int tbn = (prec == P_F64 && d.N > 64 && d.N <= 96) ? 96
-                  : (prec == P_F64 && d.N > 96 && d.N <= 128) ? 128 : BN;
+  // FP64: one tile across a narrow N (65..128 columns), so that the large
+  // operand streams once; but with a short K (no split) the product is
+  // spread over 32-column tiles when they fit in one round of workgroups
+  int tbn = (prec == P_F64 && d.N > 64 && d.N <= 96) ? 96
+            : (prec == P_F64 && d.N > 96 && d.N <= 128) ? 128 : BN;
+  const int kstep = prec == P_BF16 ? 32 : BK;  // k slice of the kernel
+  const int ktiles = (d.K + kstep - 1) / kstep;
+  if (tbn > BN && ktiles < 8) {
+    const long long t32 = (long long)((d.M + BM - 1) / BM) * ((d.N + 31) / 32) * batch;
+    if (t32 <= concurrent_groups(kernel_of(prec, 32, table))) tbn = 32;
+  }
   const long long tm = (d.M + BM - 1) / BM, tn = (d.N + tbn - 1) / tbn;
   const long long tiles = tm * tn * batch;
   int ksplit = 1;
-  const int kstep = prec == P_BF16 ? 32 : BK;  // k slice of the kernel
-  const int ktiles = (d.K + kstep - 1) / kstep;
   const long long slots = concurrent_groups(kernel_of(prec, tbn, table));
   if (tiles < slots && ktiles >= 8) {
     const int kmax = std::max(1, std::min(64, ktiles / 4));
@@ -530,7 +538,9 @@ int launch(tn_ctx* ctx, bool table, TDesc& d, int batch, const double* A, const 
   hipExtLaunchKernelGGL(KERNEL, grid, dim3(256), 0, ctx->stream, e0, stop_main, 0, A, B, C, d, \
                         alpha, beta)
   if (prec == P_F64) {
-    if (tbn == 96) {
+    if (tbn == 32) {
+      if (table) TN_GO((tgemm_f64_kernel<true, 32>)); else TN_GO((tgemm_f64_kernel<false, 32>));
+    } else if (tbn == 96) {
       if (table) TN_GO((tgemm_f64_kernel<true, 96>)); else TN_GO((tgemm_f64_kernel<false, 96>));
     } else if (tbn == 128) {
       if (table) TN_GO((tgemm_f64_kernel<true, 128>)); else TN_GO((tgemm_f64_kernel<false, 128>));

@@ -34,7 +34,10 @@ def host(t):
                                          # split along K with a ragged last slice, on the
                                          # 96- and 128-wide tiles
                                          (300, 96, 1000, False, False), (200, 120, 333, True, False),
-                                         (77, 90, 517, False, True), (64, 64, 4099, True, True)])
+                                         (77, 90, 517, False, True), (64, 64, 4099, True, True),
+                                         # short K: 32-column tiles, ragged in M, N and K
+                                         (2592, 96, 96, False, False), (300, 100, 50, True, True),
+                                         (65, 127, 20, False, True)])
 def test_gemm_parity(ctx, M, N, K, ta, tb):
     rng = np.random.default_rng(M * 7 + N)
     A = rng.standard_normal((K, M) if ta else (M, K))
