@@ -47,6 +47,14 @@ int bondnet_canonicalize(tn_ctx* ctx, const BondNet& net, int n, const double* A
                          int max_iter, double* lams, double* Pc, double* Qc, double* Aout,
                          int* iters);
 
+// The canonical sign and scale of a gauge pair on each of nl links (as
+// bondnet_canonicalize leaves them): P [nl][n][n] acts on the first ends and
+// Q, its inverse up to a factor, on the second.  The sign rule goes on the
+// columns of P (the rows of Q flip with them); then P Q = I through its
+// trace and |P|_F = |Q|_F.  n <= 32.
+int canonical_pq(tn_ctx* ctx, int nl, int n, const double* P, const double* Q, double* Pc,
+                 double* Qc);
+
 // out_s = (P on first ends, Q on second ends) in_s, unit norm per site;
 // P [nl][n_in][n_out], Q [nl][n_out][n_in]; sc: scratch of two input sites.
 int bondnet_truncate(tn_ctx* ctx, const BondNet& net, int n_in, int n_out, const double* in,

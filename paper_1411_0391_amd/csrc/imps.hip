@@ -401,6 +401,44 @@ int bond_truncation(tn_ctx* ctx, int n, int chi, int d, const double* th /*[2][n
   return TN_OK;
 }
 
+// Canonical form of a two-site A-form cell (Sec. III A) from the exact
+// environments of its bonds.  With the transfer-matrix fixed points
+// V_L = Y^T Y and V_R = X X^T of a bond and the SVD Y X = U S V^T, the gauge
+// P = Y^+ U S^1/2 on the left site's right leg and Q = S^1/2 V^T X^+ on the
+// right site's left leg leaves both environments of the bond equal to S:
+// the fixed point that the paper's local iteration converges to, reached in
+// one step (the iteration converges at the rate of the transfer matrix's
+// gap, thousands of steps near the critical field).  Outputs: Pc, Qc
+// [2][chi][chi] in the canonical sign and scale, lam_out [2][chi] (unit
+// norm; may be null), Aout [2][chi][d][chi] = Qc A Pc per site, unit norm.
+int canonical_1d(tn_ctx* ctx, const BondNet& net, int chi, int d, const double* A, double tol,
+                 double* Pc, double* Qc, double* lam_out, double* Aout) {
+  const size_t cc = (size_t)chi * chi, cdc = (size_t)chi * d * chi;
+  const size_t mark = ctx->arena_off;  // consumed in stream order
+  double* P = ws_alloc<double>(ctx, 2 * cc);
+  double* Q = ws_alloc<double>(ctx, 2 * cc);
+  double* lam = ws_alloc<double>(ctx, 2 * (size_t)chi);
+  double* vw = ws_alloc<double>(ctx, 4 * cc);
+  double* err = ws_alloc<double>(ctx, 1);
+  double* sc = ws_alloc<double>(ctx, 2 * cdc);
+  if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (canonical form)");
+  TN_HIP(ctx, hipMemsetAsync(err, 0, sizeof(double), ctx->stream));
+  for (int b = 0; b < 2; ++b) {
+    const size_t m2 = ctx->arena_off;
+    int it = 0;
+    TN_TRY(bond_truncation(ctx, chi, chi, d, A, b, vw + 2 * b * cc, 0, tol, P + b * cc,
+                           Q + b * cc, lam + b * chi, err, &it));
+    ctx->arena_off = m2;
+  }
+  TN_TRY(canonical_pq(ctx, 2, chi, P, Q, Pc, Qc));
+  if (lam_out)
+    TN_HIP(ctx, hipMemcpyAsync(lam_out, lam, 2 * (size_t)chi * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  TN_TRY(bondnet_truncate(ctx, net, chi, chi, A, Pc, Qc, Aout, sc));
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
 // out[i][s][j] = sum Q[i][a] th[a][s][b] P[b][j]   (chi x d x chi)
 int sandwich(tn_ctx* ctx, int n, int chi, int d, const double* Q, const double* th, const double* P,
              double* tmp, double* out) {
@@ -543,9 +581,7 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
     if (!l1) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (recycling)");
     // the scheme starts from the canonical form of A_0 (Sec. V B (i))
     const size_t mark = ctx->arena_off;
-    const int rc = bondnet_canonicalize(ctx, net, chi, A, 1e-14, 1000, nullptr, Pc, Qc, a0c,
-                                        nullptr);
-    if (rc < 0) return rc;
+    TN_TRY(canonical_1d(ctx, net, chi, d, A, tol, Pc, Qc, nullptr, a0c));
     ctx->arena_off = mark;
     a0 = a0c;
   }
@@ -572,12 +608,11 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
     // renormalized gate G = U^T (Qc Q) g (P Pc) U (Sec. V B (i)-(iii))
     TN_TRY(truncate2(Q, P, tr));
     size_t mark = ctx->arena_off;
-    int rc = bondnet_canonicalize(ctx, net, chi, tr, 1e-14, 1000, l1, Pc, Qc, a1, nullptr);
-    if (rc < 0) return rc;
+    TN_TRY(canonical_1d(ctx, net, chi, d, tr, tol, Pc, Qc, l1, a1));
     ctx->arena_off = mark;
     TN_TRY(recycle_gauge_start(ctx, 2, n, chi, kap, P, Q, Pc, Qc, U));
     double F = 0.0;
-    rc = bondnet_gauge_fix(ctx, net, chi, a0c, a1, U, 1e-12, 1000, &F, nullptr);
+    const int rc = bondnet_gauge_fix(ctx, net, chi, a0c, a1, U, 1e-12, 1000, &F, nullptr);
     if (rc < 0) return rc;
     ctx->arena_off = mark;
     TN_TRY(recycle_factors(ctx, 2, n, chi, P, Q, Pc, Qc, U, Rf, Lf));

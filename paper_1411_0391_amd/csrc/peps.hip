@@ -1004,6 +1004,20 @@ long long net_max_size(const BondNet& net, int n) {
 // network-level canonical form, truncation and gauge fixing
 // ---------------------------------------------------------------------------
 
+int canonical_pq(tn_ctx* ctx, int nl, int n, const double* P, const double* Q, double* Pc,
+                 double* Qc) {
+  if (n < 1 || n > MAXN) TN_FAIL(ctx, TN_EINVAL, "canonical gauge needs 1 <= n <= %d", MAXN);
+  const size_t mark = ctx->arena_off;  // consumed in stream order
+  double* ones = ws_alloc<double>(ctx, (size_t)nl * n);
+  if (!ones) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (canonical gauge)");
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(nl * n)), dim3(256), 0, ctx->stream, ones,
+                     (long long)nl * n, 1.0);
+  hipLaunchKernelGGL(canon_pq_kernel, dim3(nl), dim3(256), 0, ctx->stream, n, P, Q, ones, Pc, Qc);
+  TN_HIP(ctx, hipGetLastError());
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
 BondNet bondnet_chain2(int d) {
   BondNet net;
   net.nsite = 2;
