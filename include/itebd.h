@@ -418,7 +418,11 @@ int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, dou
  * back to back (k <= 137), the upper factor R of G + shift I with
  * shift = shift_rel tr(G), G + shift I = R^T R, and its inverse Rinv (device
  * outputs of the same shape).  info (host, batch ints): 0, or the index + 1
- * of the first non-positive pivot (then R and Rinv are unspecified).
+ * of the first non-positive pivot (then R and Rinv are unspecified).  With
+ * shift_rel = 0 and every entry of G - I within 1e-9 of zero (k <= 128),
+ * R = I + U and Rinv = I - U with U the strict upper part of G - I plus
+ * half its diagonal, exact up to k max|G - I|^2; a NaN in G always takes
+ * the elimination and is reported as a failed pivot.
  */
 int tn_cholesky_inv(tn_ctx* ctx, int batch, int k, const double* G, double shift_rel, double* R,
                     double* Rinv, int* info);
