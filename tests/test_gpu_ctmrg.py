@@ -57,19 +57,24 @@ def _setup(cellspec, D, chi, seed=0):
     return Lx, Ly, list(cell), sites, C, T
 
 
-@pytest.mark.parametrize("cellspec,D,chi", [(tninputs.CHECKERBOARD, 2, 6),
-                                            (tninputs.SINGLE_SITE, 3, 7),
-                                            (tninputs.CHECKERBOARD, 3, 9),
-                                            # the fused site absorption at D = 5 and 6
-                                            (tninputs.SINGLE_SITE, 5, 5),
-                                            (tninputs.CHECKERBOARD, 6, 4),
-                                            (tninputs.SINGLE_SITE, 6, 5)])
-def test_single_left_move_parity(ctx, cellspec, D, chi):
-    Lx, Ly, cell, sites, C, T = _setup(cellspec, D, chi)
+@pytest.mark.parametrize("cellspec,D,chi,seed", [(tninputs.CHECKERBOARD, 2, 6, 4),
+                                                 (tninputs.SINGLE_SITE, 3, 7, 0),
+                                                 (tninputs.CHECKERBOARD, 3, 9, 0),
+                                                 # the fused site absorption at D = 5 and 6
+                                                 (tninputs.SINGLE_SITE, 5, 5, 0),
+                                                 (tninputs.CHECKERBOARD, 6, 4, 0),
+                                                 (tninputs.SINGLE_SITE, 6, 5, 0)])
+def test_single_left_move_parity(ctx, cellspec, D, chi, seed):
+    Lx, Ly, cell, sites, C, T = _setup(cellspec, D, chi, seed=seed)
     ocell = octm.Cell(Lx, Ly, cell)
     Cr, Tr, spectra = octm.left_move(ocell, sites, C, T, 0, chi)
     gap = min(s[chi - 1] / s[chi] for s in spectra)
     assert gap > 1 + 1e-6, "test input has no gap at chi"
+    # the new boundary tensors are compared entry by entry, so every kept
+    # singular vector must be determined: a pair of kept values closer than
+    # 1e-5 s_1 leaves its vectors (and C', T') fixed only to ~1e-16 / gap
+    sep = min(np.min(np.abs(np.diff(s[:chi]))) / s[0] for s in spectra)
+    assert sep > 1e-5, "test input has nearly degenerate kept singular values"
     Cg, Tg = dev(C), dev(T)
     ctx.ctmrg_moves(Lx, Ly, dev(np.stack(sites)), cell, Cg, Tg, 1, 0)
     # raw tensors: same sign convention on both sides
