@@ -415,7 +415,7 @@ int tn_svd(tn_ctx* ctx, int batch, int m, int n, const double* A, double* U, dou
  * tn_cholesky_inv -- the library's small dense FP64 Cholesky (used by the
  * Cholesky-QR orthonormalisation of the projector SVD and the ALS solves),
  * for testing and measurement: for `batch` row-major k x k matrices G stored
- * back to back (k <= 137), the upper factor R of G + shift I with
+ * back to back (k <= 512), the upper factor R of G + shift I with
  * shift = shift_rel tr(G), G + shift I = R^T R, and its inverse Rinv (device
  * outputs of the same shape).  info (host, batch ints): 0, or the index + 1
  * of the first non-positive pivot (then R and Rinv are unspecified).  With

@@ -330,8 +330,8 @@ int tn_cholesky_inv(tn_ctx* ctx, int batch, int k, const double* G, double shift
                     double* Rinv, int* info) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  if (batch < 1 || k < 1 || k > 137 || !G || !R || !Rinv || !info)
-    TN_FAIL(ctx, TN_EINVAL, "tn_cholesky_inv needs batch >= 1, 1 <= k <= 137 (k=%d)", k);
+  if (batch < 1 || k < 1 || k > 512 || !G || !R || !Rinv || !info)
+    TN_FAIL(ctx, TN_EINVAL, "tn_cholesky_inv needs batch >= 1, 1 <= k <= 512 (k=%d)", k);
   TN_TRY(ws_reserve(ctx, (size_t)batch * sizeof(int) + (1 << 16)));
   ws_reset(ctx);
   int* dinfo = ws_alloc<int>(ctx, batch);

@@ -470,8 +470,12 @@ __global__ __launch_bounds__(1024) void jacobi_emit_kernel(const double* X, int 
 // ---------------------------------------------------------------------------
 constexpr int CHOL_THREADS = 1024;
 
-// R_IN_LDS: the rows of R are kept in LDS too (compile-time, see above)
-template <bool R_IN_LDS>
+// R_IN_LDS: the rows of R are kept in LDS too (compile-time, see above).
+// W_IN_LDS false: the trailing matrix lives in the Rinv output instead (for
+// k whose k x k block does not fit in LDS; it becomes R^-1 in place), and R
+// in the R output; the barriers order these global accesses within the
+// workgroup.
+template <bool R_IN_LDS, bool W_IN_LDS = true>
 __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
     const double* __restrict__ G, int k, double shift_rel, double* __restrict__ R,
     double* __restrict__ Rinv, int* __restrict__ info) {
@@ -483,7 +487,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
     Rinv += off;
     info += blockIdx.x;
   }
-  double* Wk = lds;                        // k x k trailing matrix, later R^-1
+  double* Wk = W_IN_LDS ? lds : Rinv;  // k x k trailing matrix, later R^-1
   double* Rl;  // R rows as they are produced
   if constexpr (R_IN_LDS)
     Rl = lds + k * k;
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void cholesky_inv_kernel(
   }
   for (int t = tid; t < k * k; t += CHOL_THREADS) {
     const int i = t / k;
-    Rinv[t] = Wk[t] / Rl[i * k + i];
+    Rinv[t] = Wk[t] / Rl[i * k + i];  // in place when Wk is Rinv
     if constexpr (R_IN_LDS) R[t] = Rl[t];
   }
 }
@@ -898,8 +902,16 @@ int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double
 int cholesky_inv(tn_ctx* ctx, int k, const double* G, double shift_rel, double* R, double* Rinv,
                  int* info, int batch) {
   const size_t one = (size_t)k * k * sizeof(double);
-  if (one > LDS_LIMIT) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports k <= 137 (k=%d)", k);
+  if (k < 1 || k > 512) TN_FAIL(ctx, TN_EINVAL, "cholesky_inv supports 1 <= k <= 512 (k=%d)", k);
   if (batch < 1) return TN_OK;
+  if (one > LDS_LIMIT) {
+    // the k x k block does not fit in LDS: trailing matrix and R in global
+    // memory (the Rinv and R outputs)
+    hipLaunchKernelGGL((cholesky_inv_kernel<false, false>), dim3(batch), dim3(CHOL_THREADS), 0,
+                       ctx->stream, G, k, shift_rel, R, Rinv, info);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+  }
   if (k <= CHOLR_MAX) {
     const size_t dyn = ((size_t)k * (k | 1) + 3 * CHOLR_MAX) * sizeof(double);
     hipLaunchKernelGGL(cholesky_inv_reg_kernel, dim3(batch), dim3(1024), dyn, ctx->stream, G, k,

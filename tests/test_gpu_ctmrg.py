@@ -63,7 +63,12 @@ def _setup(cellspec, D, chi, seed=0):
                                                  # the fused site absorption at D = 5 and 6
                                                  (tninputs.SINGLE_SITE, 5, 5, 0),
                                                  (tninputs.CHECKERBOARD, 6, 4, 0),
-                                                 (tninputs.SINGLE_SITE, 6, 5, 0)])
+                                                 (tninputs.SINGLE_SITE, 6, 5, 0),
+                                                 # D = 8: the two table contractions of
+                                                 # the site layers (no fused kernel);
+                                                 # chi = 5 takes the subspace projector SVD
+                                                 (tninputs.SINGLE_SITE, 8, 5, 0),
+                                                 (tninputs.CHECKERBOARD, 8, 4, 0)])
 def test_single_left_move_parity(ctx, cellspec, D, chi, seed):
     Lx, Ly, cell, sites, C, T = _setup(cellspec, D, chi, seed=seed)
     ocell = octm.Cell(Lx, Ly, cell)
@@ -216,3 +221,40 @@ def test_subspace_projector_path_parity(ctx, cellspec, D, chi):
     assert st["svd_explicit"] == 0 and st["svd_calls"] == Ly
     np.testing.assert_allclose(host(Cg), Cr, atol=1e-9)
     np.testing.assert_allclose(host(Tg), Tr, atol=1e-9)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_move_d8_chi128(ctx):
+    """One left move of the large configuration: checkerboard, D = 8,
+    chi = 128, so n = 8192 and a projector subspace of k = 160 (Cholesky and
+    Jacobi with their work matrices beyond LDS).  The oracle needs minutes
+    per move at this size (the SVD of an 8192 x 8192 matrix), so the checks
+    are properties of the move: one subspace-iteration projector problem per
+    row cut, finite output, unit Frobenius norm on every tensor the move
+    writes (C1 of column x+1, row y+1; T4 and C4 of column x+1, row y) and
+    every other tensor untouched."""
+    D, chi = 8, 128
+    Lx, Ly, cell, sites, C, T = _setup(tninputs.CHECKERBOARD, D, chi)
+    ocell = octm.Cell(Lx, Ly, cell)
+    written = set()
+    for y in range(Ly):
+        written.add((ocell.pos(1, y + 1), 0, "C"))
+        written.add((ocell.pos(1, y), 3, "T"))
+        written.add((ocell.pos(1, y), 3, "C"))
+    Cg, Tg = dev(C), dev(T)
+    ctx.prof_enable(True)
+    ctx.prof_read()
+    ctx.ctmrg_moves(Lx, Ly, dev(np.stack(sites)), cell, Cg, Tg, 1, 0)
+    st = ctx.prof_read()
+    ctx.prof_enable(False)
+    print("projector problems", st["svd_calls"], "subspace iterations", st["svd_iters"])
+    assert st["svd_calls"] == Ly and st["svd_explicit"] == 0
+    Ch, Th = host(Cg), host(Tg)
+    assert np.isfinite(Ch).all() and np.isfinite(Th).all()
+    for p in range(Lx * Ly):
+        for k in range(4):
+            for name, new, old in (("C", Ch, C), ("T", Th, T)):
+                if (p, k, name) in written:
+                    assert abs(np.linalg.norm(new[p, k]) - 1.0) < 1e-12
+                else:
+                    np.testing.assert_array_equal(new[p, k], old[p, k])

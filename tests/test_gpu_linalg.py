@@ -30,7 +30,9 @@ def _graded(rng, n, decades):
     return (q1 * s) @ q2.T, s
 
 
-@pytest.mark.parametrize("m,n", [(96, 96), (130, 70), (33, 33), (7, 5), (1, 1)])
+@pytest.mark.parametrize("m,n", [(96, 96), (130, 70), (33, 33), (7, 5), (1, 1),
+                                 # batched, work matrix beyond LDS (global memory)
+                                 (160, 160)])
 def test_svd_random_parity(ctx, m, n):
     rng = np.random.default_rng(m + 7 * n)
     A = rng.standard_normal((3, m, n))
@@ -89,7 +91,7 @@ def test_svd_near_diagonal_converges_fast(ctx):
     assert st["jacobi_sweeps"] <= 6
 
 
-@pytest.mark.parametrize("k", [1, 7, 16, 33, 96, 128])
+@pytest.mark.parametrize("k", [1, 7, 16, 33, 96, 128, 137, 160, 200])
 def test_cholesky_inv_parity(ctx, k):
     """Blocked Cholesky and its inverse against LAPACK on SPD matrices, and a
     failing pivot reported on an indefinite one."""
