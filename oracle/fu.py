@@ -20,8 +20,19 @@ Readings taken where the paper is silent or describes a one-site cell:
   R[(i c),(i' c')] = sum_{j j'} Q[c,j] N[i,j,i',j'] Q[c',j'] and
   S[(i c)] = sum_{j i'} Q[c,j] N[i,j,i',i']; then Q likewise; after each
   pair the pair is balanced through the SVD of P Q; solves use
-  R + 1e-14 tr(R) I; one pass over the links in cell order (r, d, l, u for
-  the checkerboard), each link iterated until |df|/f_0 < tol;
+  R + 1e-14 tr(R) I;
+* the links are updated in cell order (r, d, l, u for the checkerboard),
+  each with its N rebuilt from the current zeta, and the whole cycle is
+  repeated until the cost of every link, traced from one cycle to the next,
+  changes by less than tol <I|N|I> (Sec. VI B: the cycle over r, d, l, u
+  is iterated until every tensor of zeta is converged, recognised from the
+  cost of Eq. (var)); each visit makes ``max_sweeps`` ALS sweeps on its
+  link (1 is the literal order of the section: one P and one Q update per
+  link per cycle);
+* recycling (Sec. VI C): the state A_0 that the renormalized gate is
+  applied to is in canonical form (A form) -- the section assumes it, and
+  the gauge fix U relates two canonical states; the environment step brings
+  A_0 to canonical form first;
 * energies are measured at environment steps, for the pre-truncated state
   the environment was computed for.
 """
@@ -50,88 +61,168 @@ def su_truncation(cell, thetas, D, tol=1e-14, max_iter=1000):
 
 
 # ---------------------------------------------------------------------------
-# bond environment
+# bond environment: the 2x2 block B of Fig. 21(a)
 # ---------------------------------------------------------------------------
 
-def theta_hat(cell, thetas, P, Q, site, open_leg):
-    """Theta of ``site`` with every leg except ``open_leg`` truncated."""
+# Slots of the block's four internal links, in the order they are visited:
+# (name, first end, its leg, second end, its leg); block positions TL, TR,
+# BR, BL.  The first end carries P, the second Q (A~ = Q Theta P).
+SLOTS = (("top", "TL", "r", "TR", "l"),
+         ("left", "TL", "d", "BL", "u"),
+         ("bottom", "BL", "r", "BR", "l"),
+         ("right", "TR", "d", "BR", "u"))
+# internal legs of each block position, the rest face the environment
+INTERNAL = {"TL": ("r", "d"), "TR": ("l", "d"), "BR": ("l", "u"), "BL": ("r", "u")}
+
+
+def block_positions(cell, x0=0, y0=0):
+    """Cell positions of the block with its top-left site at (x0, y0)."""
+    return {"TL": cell.pos(x0, y0), "TR": cell.pos(x0 + 1, y0),
+            "BR": cell.pos(x0 + 1, y0 + 1), "BL": cell.pos(x0, y0 + 1)}
+
+
+def block_slot_links(cell):
+    """Cell link of each slot of the block at the origin; raises if some
+    link of the cell is not inside the block (the truncation of such a cell
+    is not one block's variational problem)."""
     links, leg_link = cell_links(cell)
-    t = thetas[site]
-    for leg in LEGS:
-        if leg == open_leg:
-            continue
-        b = leg_link[site][leg]
-        s1, l1, s2, l2 = links[b]
-        if site == s1 and leg == l1:
-            t = apply_leg(t, leg, P[b].T)
-        else:
-            t = apply_leg(t, leg, Q[b])
-    return t
+    pos = block_positions(cell)
+    out = []
+    for _, e1, l1, e2, l2 in SLOTS:
+        s1, s2 = cell.sites[pos[e1]], cell.sites[pos[e2]]
+        b = leg_link[s1][l1]
+        assert leg_link[s2][l2] == b and links[b][0] == s1 and links[b][2] == s2
+        out.append(b)
+    if sorted(set(out)) != list(range(len(links))):
+        raise ValueError("the 2x2 block does not hold every link of this cell")
+    return out
 
 
-def _find_h(cell, s1, s2):
-    for y in range(cell.Ly):
-        for x in range(cell.Lx):
-            if cell.sites[cell.pos(x, y)] == s1 and cell.sites[cell.pos(x + 1, y)] == s2:
-                return x, y
-    raise ValueError("link not found")
+def _trunc_leg(t, site, leg, b, links, P, Q):
+    """Truncate ``leg`` of ``site``'s tensor with link b's P (first end) or
+    Q (second end)."""
+    s1, l1, _, _ = links[b]
+    return apply_leg(t, leg, P[b].T if (site == s1 and leg == l1) else Q[b])
 
 
-def _n_horizontal(cell, C, T, x, y, ket1, ket2):
-    p, q = cell.pos(x, y), cell.pos(x + 1, y)
-    L = np.einsum("gh,hpqt,eijg,fe,bmnf,sikmp,sjlnq->tklb",
-                  C[p, 0], T[p, 0], T[p, 3], C[p, 3], T[p, 2], ket1, ket1, optimize=PATH_HALF)
-    R = np.einsum("tpqh,he,eklf,fg,gmnb,sikmp,sjlnq->tijb",
-                  T[q, 0], C[q, 1], T[q, 1], C[q, 2], T[q, 2], ket2, ket2, optimize=PATH_HALF)
-    return np.einsum("tkKb,tiIb->kiKI", L, R, optimize=True)
+def block_tensors(cell, thetas, Psu, Qsu, Pz, Qz, open_slot):
+    """Site tensors of the four block positions: the legs facing the
+    environment truncated by the pre-truncation (Psu, Qsu) that the
+    environment was computed for; internal legs by the slot's current
+    (Pz[slot], Qz[slot]) when Pz is given, untruncated when Pz is None; the
+    open slot's legs untruncated."""
+    links, leg_link = cell_links(cell)
+    pos = block_positions(cell)
+    slot_of = {}
+    for k, (_, e1, l1, e2, l2) in enumerate(SLOTS):
+        slot_of[(e1, l1)] = k
+        slot_of[(e2, l2)] = k
+    out = {}
+    for X, p in pos.items():
+        s = cell.sites[p]
+        t = thetas[s]
+        for leg in LEGS:
+            b = leg_link[s][leg]
+            if leg not in INTERNAL[X]:
+                t = _trunc_leg(t, s, leg, b, links, Psu, Qsu)
+                continue
+            k = slot_of[(X, leg)]
+            if k == open_slot or Pz is None:
+                continue
+            first = SLOTS[k][1] == X
+            t = apply_leg(t, leg, Pz[k].T if first else Qz[k])
+        out[X] = t
+    return out
 
 
-def bond_environment(cell, thetas, P, Q, C, T, b):
-    """N[i, j, i', j'] of link b (see module docstring); the environment C,
-    T belongs to the pre-truncated state on ``cell``."""
-    links, _ = cell_links(cell)
-    s1, l1, s2, l2 = links[b]
-    t1 = theta_hat(cell, thetas, P, Q, s1, l1)
-    t2 = theta_hat(cell, thetas, P, Q, s2, l2)
-    if l1 == "r":
-        x, y = _find_h(cell, s1, s2)
-        N = _n_horizontal(cell, C, T, x, y, t1, t2)
-    else:
-        # a vertical link is horizontal in the lattice rotated by 90 degrees
-        rc, rt, rC, rT = rotate_ccw(cell, [t1, t2], C, T)
-        x, y = None, None
-        for yy in range(cell.Ly):
-            for xx in range(cell.Lx):
-                if cell.sites[cell.pos(xx, yy)] == s1 and cell.sites[cell.pos(xx, yy + 1)] == s2:
-                    x, y = xx, yy
-                    break
-            if x is not None:
-                break
-        if x is None:
-            raise ValueError("link not found")
-        N = _n_horizontal(rc, rC, rT, y, -x, rt[0], rt[1])
+def block_corners(cell, C, T, kets, bras):
+    """The four enlarged corners of the block (environment tensors of the
+    block's positions, Sec. VI B): each carries its two boundary legs and
+    the ket and bra index of its two internal legs.
+      E_TL[t, rk, rb, dk, db, x]   t: to T1 of TR, x: to T4 of BL
+      E_TR[t, lk, lb, dk, db, f]   f: to T2 of BR
+      E_BR[f, uk, ub, lk, lb, y]   y: to T3 of BL
+      E_BL[y, rk, rb, uk, ub, x]"""
+    P = block_positions(cell)
+    tl, tr, br, bl = P["TL"], P["TR"], P["BR"], P["BL"]
+    E = {}
+    E["TL"] = np.einsum("gh,huUt,xlLg,slrdu,sLRDU->trRdDx", C[tl, 0], T[tl, 0], T[tl, 3],
+                        kets["TL"], bras["TL"], optimize=True)
+    E["TR"] = np.einsum("tuUh,he,erRf,slrdu,sLRDU->tlLdDf", T[tr, 0], C[tr, 1], T[tr, 1],
+                        kets["TR"], bras["TR"], optimize=True)
+    E["BR"] = np.einsum("frRg,gh,hdDy,slrdu,sLRDU->fuUlLy", T[br, 1], C[br, 2], T[br, 2],
+                        kets["BR"], bras["BR"], optimize=True)
+    E["BL"] = np.einsum("ydDg,ge,elLx,slrdu,sLRDU->yrRuUx", T[bl, 2], C[bl, 3], T[bl, 3],
+                        kets["BL"], bras["BL"], optimize=True)
+    return E
+
+
+# The ring of enlarged corners, one index letter per leg: top link (a, A at
+# TL; c, C at TR), right link (e, E at TR; g, G at BR), bottom link (h, H at
+# BR; k, K at BL), left link (b, B at TL; m, M at BL); boundary legs t, f,
+# y, x.  Closing a link identifies its two letters; the open slot keeps both
+# ends and lists them as (first ket, second ket, first bra, second bra).
+_OPEN = {0: "taAbBx,tcCeEf,feEhHy,yhHbBx->acAC",
+         1: "taAbBx,taAeEf,feEhHy,yhHmMx->bmBM",
+         2: "taAbBx,taAeEf,feEhHy,ykKbBx->khKH",
+         3: "taAbBx,taAeEf,fgGhHy,yhHbBx->egEG"}
+
+
+def block_open(E, slot):
+    """Contract the ring of enlarged corners with slot ``slot`` cut:
+    N[i, j, i', j'] with i, j the ket index of its first and second end and
+    i', j' the bra index."""
+    return np.einsum(_OPEN[slot], E["TL"], E["TR"], E["BR"], E["BL"], optimize=True)
+
+
+def block_closed(E):
+    """The closed ring: the block's norm network."""
+    return float(np.einsum("taAbBx,taAeEf,feEhHy,yhHbBx->", E["TL"], E["TR"], E["BR"], E["BL"],
+                           optimize=True))
+
+
+def block_norm(cell, thetas, Psu, Qsu, C, T):
+    """<Psi_g|Psi_g> of the block: every internal link untruncated."""
+    t = block_tensors(cell, thetas, Psu, Qsu, None, None, -1)
+    return block_closed(block_corners(cell, C, T, t, t))
+
+
+def bond_environment(cell, thetas, Psu, Qsu, Pz, Qz, C, T, slot):
+    """The two environments of slot ``slot`` (see module docstring):
+    N[i, j, i', j'] with the other internal links truncated by zeta in both
+    layers, symmetrised in ket <-> bra, and M[i, j, i', j'] with zeta in the
+    ket layer and the untruncated bra layer of Psi_g.  Both unnormalised,
+    in the sign of the raw network."""
+    kz = block_tensors(cell, thetas, Psu, Qsu, Pz, Qz, slot)
+    kg = block_tensors(cell, thetas, Psu, Qsu, None, None, slot)
+    N = block_open(block_corners(cell, C, T, kz, kz), slot)
+    M = block_open(block_corners(cell, C, T, kz, kg), slot)
     n = N.shape[0]
     N2 = N.reshape(n * n, n * n)
     N = (0.5 * (N2 + N2.T)).reshape(n, n, n, n)
-    # the boundary fixes N only up to an overall factor (its tensors are
-    # normalised, their sign is free): take the sign with <I|N|I> > 0
-    if np.einsum("iiaa->", N) < 0:
-        N = -N
-    return N
+    return N, M
 
 
 # ---------------------------------------------------------------------------
 # ALS (Eqs. (var), (var1))
 # ---------------------------------------------------------------------------
 
-def cost(N, P, Q):
-    """f = <I|N|I> - 2 <PQ|N|I> + <PQ|N|PQ> (Eq. (var), real case)."""
+def cost(N, P, Q, tb=None, t=None):
+    """f = <Psi_g|Psi_g> - 2 <Psi_g|Psi_zeta> + <Psi_zeta|Psi_zeta> (Eq. (var),
+    real case) as a function of one link's (P, Q): <PQ|N|PQ> is the last
+    term, sum_ij (PQ)_ij tb_ij the middle one and t the first.  Without tb
+    and t, the first two come from N itself (tb_ij = sum_a N[i, j, a, a],
+    t = <I|N|I>): the cost of a single link whose environment is N.
+    Returns (f, t)."""
     n = N.shape[0]
     I = np.eye(n)
     O = P @ Q
-    t = np.einsum("ijab,ij,ab->", N, I, I)
-    c = np.einsum("ijab,ij,ab->", N, O, I)
-    q = np.einsum("ijab,ij,ab->", N, O, O)
+    if tb is None:
+        tb = np.einsum("ijaa->ij", N)
+    if t is None:
+        t = float(np.einsum("ijab,ij,ab->", N, I, I))
+    c = float(np.sum(O * tb))
+    q = float(np.einsum("ijab,ij,ab->", N, O, O))
     return float(t - 2 * c + q), float(t)
 
 
@@ -156,30 +247,36 @@ def _svd_signfix(m):
     return u, s, vt
 
 
-def als(N, P, Q, tol=1e-12, max_sweeps=50):
-    """Alternating least squares for one link.  Returns (P, Q, f, sweeps,
-    history) with history the cost after each sweep."""
+def als(N, P, Q, tol=1e-12, max_sweeps=50, tb=None, t=None):
+    """Alternating least squares on one link (Eq. (var1)): P = R^-1 S with Q
+    fixed, then Q with P fixed, then the pair balanced through the SVD of
+    P Q (which leaves P Q, hence f, unchanged); ``cost`` explains N, tb, t.
+    Stops when a sweep changes f by less than tol t.  Returns (P, Q, f,
+    sweeps, history) with history the cost at the start and after every
+    half step."""
     n, D = P.shape
-    trace_b = np.einsum("ijaa->ij", N)            # sum_i' N[i,j,i',i']
-    f, f0 = cost(N, P, Q)
+    if tb is None:
+        tb = np.einsum("ijaa->ij", N)             # sum_i' N[i,j,i',i']
+    f, t = cost(N, P, Q, tb, t)
     hist = [f]
     sw = 0
     for sw in range(1, max_sweeps + 1):
         # P with Q fixed
         R = np.einsum("cj,ijak,dk->icad", Q, N, Q).reshape(n * D, n * D)
-        S = np.einsum("cj,ij->ic", Q, trace_b).reshape(n * D)
+        S = np.einsum("cj,ij->ic", Q, tb).reshape(n * D)
         P = _solve(0.5 * (R + R.T), S).reshape(n, D)
+        hist.append(cost(N, P, Q, tb, t)[0])
         # Q with P fixed
         R = np.einsum("ic,ijak,ad->cjdk", P, N, P).reshape(D * n, D * n)
-        S = np.einsum("ic,ij->cj", P, trace_b).reshape(D * n)
+        S = np.einsum("ic,ij->cj", P, tb).reshape(D * n)
         Q = _solve(0.5 * (R + R.T), S).reshape(D, n)
         # balance the pair
         u, s, vt = _svd_signfix(P @ Q)
         sq = np.sqrt(s[:D])
         P, Q = u[:, :D] * sq[None, :], sq[:, None] * vt[:D]
-        fn, _ = cost(N, P, Q)
+        fn, _ = cost(N, P, Q, tb, t)
         hist.append(fn)
-        done = abs(fn - f) < tol * abs(f0)
+        done = abs(fn - f) < tol * abs(t)
         f = fn
         if done:
             break
@@ -187,28 +284,77 @@ def als(N, P, Q, tol=1e-12, max_sweeps=50):
 
 
 # ---------------------------------------------------------------------------
+# the truncation of all links (Sec. VI B)
+# ---------------------------------------------------------------------------
+
+def fu_truncate(cell, thetas, Psu, Qsu, C, T, tol=1e-12, max_passes=50, max_sweeps=1,
+                P0=None, Q0=None):
+    """Minimise the block cost f(zeta) of Eq. (var) over zeta = (P, Q) of
+    the block's four internal links (Sec. VI B), starting from (P0, Q0) per
+    link (default: the pre-truncation (Psu, Qsu), which also truncates the
+    legs facing the environment throughout): cycles over the slots top, left, bottom,
+    right; each visit builds the slot's two environments from the current
+    zeta and makes ``max_sweeps`` ALS sweeps (1: one P and one Q update per
+    link per cycle, the section's order); the cycles stop when one changes f
+    by less than tol <Psi_g|Psi_g>, or after ``max_passes``.  A link that
+    several slots hold (a one-site cell) gets the mean of their (P, Q).
+    Returns (P, Q, f, passes, sweeps, history) with history f at the start
+    and after every half step."""
+    links, _ = cell_links(cell)
+    slot_link = block_slot_links(cell)
+    Pz = [(Psu if P0 is None else P0)[b].copy() for b in slot_link]
+    Qz = [(Qsu if Q0 is None else Q0)[b].copy() for b in slot_link]
+    tn = block_norm(cell, thetas, Psu, Qsu, C, T)
+    # the normalised boundary fixes the networks only up to a common sign:
+    # take the one with <Psi_g|Psi_g> > 0
+    sg = 1.0 if tn > 0 else -1.0
+    tn = abs(tn)
+    history, sweeps, passes = [], 0, 0
+    f_prev = None
+    for passes in range(1, max_passes + 1):
+        for k in range(len(SLOTS)):
+            N, M = bond_environment(cell, thetas, Psu, Qsu, Pz, Qz, C, T, k)
+            N, M = sg * N, sg * M
+            Pz[k], Qz[k], f, sw, h = als(N, Pz[k], Qz[k], tol, max_sweeps,
+                                         tb=np.einsum("ijaa->ij", M), t=tn)
+            if not history:
+                history.append(h[0])
+                f_prev = h[0]
+            history.extend(h[1:])
+            sweeps += sw
+        done = abs(f - f_prev) < tol * tn
+        f_prev = f
+        if done:
+            break
+    P, Q = [], []
+    for b in range(len(links)):
+        ks = [k for k, lb in enumerate(slot_link) if lb == b]
+        P.append(sum(Pz[k] for k in ks) / len(ks))
+        Q.append(sum(Qz[k] for k in ks) / len(ks))
+    return P, Q, f_prev, passes, sweeps, history
+
+
+# ---------------------------------------------------------------------------
 # drivers
 # ---------------------------------------------------------------------------
 
 def fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol=1e-10, ctm_max=100, J=1.0, h=3.0,
-                als_tol=1e-12, als_max=50):
+                als_tol=1e-12, als_passes=50, als_sweeps=1):
     """One full-update step with a freshly computed environment: Theta = g A,
-    pre-truncation, CTMRG (warm-started from C, T), energy, ALS on every link,
-    A~ = Q Theta P.  Returns a dict."""
+    pre-truncation, CTMRG (warm-started from C, T), energy, the ALS cycles
+    over all links, A~ = Q Theta P.  Returns a dict."""
     links, _ = cell_links(cell)
     thetas = [gates.apply_ipepo(g, a) for a in sites]
     P, Q = su_truncation(cell, thetas, D)
     pre = truncate(thetas, links, P, Q)
     C, T, iters, delta = ctmrg(cell, pre, C, T, chi, ctm_max, ctm_tol)
     E = energy_per_site(cell, pre, C, T, J, h)
-    costs = []
-    for b in range(len(links)):
-        N = bond_environment(cell, thetas, P, Q, C, T, b)
-        P[b], Q[b], f, _, _ = als(N, P[b], Q[b], als_tol, als_max)
-        costs.append(f)
+    P, Q, f, passes, sweeps, _ = fu_truncate(cell, thetas, P, Q, C, T, als_tol, als_passes,
+                                             als_sweeps)
     new = truncate(thetas, links, P, Q)
     return dict(sites=new, thetas=thetas, P=P, Q=Q, C=C, T=T, energy=E,
-                ctm_iters=iters, ctm_delta=delta, costs=costs)
+                ctm_iters=iters, ctm_delta=delta, cost=f, als_passes=passes,
+                als_sweeps=sweeps)
 
 
 def gauge_start(P, Q, Pc, Qc, kappa):
@@ -234,37 +380,61 @@ def renormalized_gate(P, Q, Pc, Qc, U):
     return Rf, Lf
 
 
+def recycle_build(cell, a0, out, kappa, gauge_tol=1e-12):
+    """Steps (i)-(iii) of Sec. VI C for the canonical state a0 and the
+    full-update step ``out`` computed from it: canonical form of A~ (A~_1,
+    Pc, Qc), the gauge U with A~_1 ~ U a0 U^T, and the renormalized gate's
+    factors.  Returns (Rf, Lf, U, F)."""
+    a1, _, Pc, Qc, _ = canonicalize_a_form(cell, out["sites"])
+    U0 = gauge_start(out["P"], out["Q"], Pc, Qc, kappa)
+    U, F, _ = gauge_fix(cell, a0, a1, tol=gauge_tol, U0=U0)
+    Rf, Lf = renormalized_gate(out["P"], out["Q"], Pc, Qc, U)
+    return Rf, Lf, U, F
+
+
 def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=None,
-           ctm_tol=1e-10, ctm_max=100, seed_env=0, callback=None):
+           ctm_tol=1e-10, ctm_max=100, seed_env=0, callback=None, min_fidelity=None,
+           force_recycle=False, als_tol=1e-12, als_passes=50, als_sweeps=1):
     """Imaginary-time evolution of an iPEPS by full update, the environment
     recomputed every ``n_re`` steps after ``n_warm`` plain steps and the
-    renormalized gate applied in between (Sec. VI C).  Returns (sites, log)
-    with log entries (step, energy_per_site) at environment steps."""
+    renormalized gate applied in between (Sec. VI C).  A recycling step
+    first brings A_0 to canonical form.  With ``min_fidelity``, a recycling
+    step whose gauge fix ends below it takes the plain step instead (the new
+    state is too far from A_0 for G to stand in for the environment).
+    ``force_recycle`` takes the recycling branch even for n_re = 1, where it
+    must reproduce the plain trajectory (the renormalized gate applied once
+    is the full-update step in another gauge).  Returns (sites, log) with
+    log entries (step, energy_per_site, recycled) at environment steps."""
     links, _ = cell_links(cell)
     g = gates.ipepo(J, h, dt)
+    kappa = g.shape[0]
     sites = [s / np.linalg.norm(s) for s in sites]
     npos = cell.Lx * cell.Ly
     if C is None:
         import tninputs
         C, T = tninputs.ctm_env(seed_env, npos, chi, D, positive=True)
-    log, fac = [], None
+    log = []
     step = 0
     while step < nsteps:
-        warm = step < n_warm
-        out = fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol, ctm_max, J, h)
+        recycle = step >= n_warm and (n_re > 1 or force_recycle)
+        if recycle:
+            sites = canonicalize_a_form(cell, sites)[0]
+        out = fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol, ctm_max, J, h, als_tol,
+                          als_passes, als_sweeps)
         C, T = out["C"], out["T"]
-        log.append((step + 1, out["energy"]))
+        F = None
+        if recycle:
+            Rf, Lf, U, F = recycle_build(cell, sites, out, kappa)
+            if min_fidelity is not None and F < min_fidelity:
+                recycle = False
+        out["fidelity"] = F
+        log.append((step + 1, out["energy"], recycle))
         if callback:
             callback(step, out)
-        if warm or n_re == 1:
+        if not recycle:
             sites = out["sites"]
             step += 1
             continue
-        a1, _, Pc, Qc, _ = canonicalize_a_form(cell, out["sites"])
-        U0 = gauge_start(out["P"], out["Q"], Pc, Qc, g.shape[0])
-        U, _, _ = gauge_fix(cell, sites, a1, U0=U0)
-        Rf, Lf = renormalized_gate(out["P"], out["Q"], Pc, Qc, U)
-        a0 = sites
         sites = truncate(out["thetas"], links, Rf, Lf)
         step += 1
         for _ in range(n_re - 1):
@@ -272,5 +442,4 @@ def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=No
                 break
             sites = truncate([gates.apply_ipepo(g, a) for a in sites], links, Rf, Lf)
             step += 1
-        del a0
     return sites, log

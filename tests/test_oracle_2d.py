@@ -191,6 +191,9 @@ def test_ipeps_gauge_fix_known_answer():
     start = [polar_orthogonal(v + 0.1 * rng.standard_normal(v.shape)) for v in V]
     U, F, _ = peps.gauge_fix(cell, a, new, U0=start, tol=1e-14)
     assert abs(F - 1) < 1e-10
+    # the canonical spectra are non-degenerate, so the gauge is unique: U = V
+    for u, v in zip(U, V):
+        np.testing.assert_allclose(u, v, atol=1e-8)
 
 
 # --- ALS (Eqs. (var), (var1)) ---------------------------------------------------
@@ -227,6 +230,155 @@ def test_als_full_rank_target_is_exact():
     P, Q, f, _, _ = fu.als(N, rng.standard_normal((n, n)), rng.standard_normal((n, n)))
     _, t = fu.cost(N, P, Q)
     assert abs(f) < 1e-10 * t
+
+
+# --- the 2x2 block of Sec. VI B (Fig. 21): networks and the joint cost ---------
+
+def _qmat(beta):
+    W = np.array([[np.exp(beta / 2), np.exp(-beta / 2)], [np.exp(-beta / 2), np.exp(beta / 2)]])
+    from scipy.linalg import sqrtm
+    return np.real(sqrtm(W))
+
+
+def test_block_network_onsager():
+    # Ising PEPS A = prod Q_{s,leg}: on a link, sum_ij Q_{s1 i} O_ij Q_{s2 j}
+    # = (Q O Q^T)_{s1 s2}; O = Q^-1 sz Q puts sz on the first end (ket layer),
+    # O' = Q sz Q^-1 on the second end (bra layer).  The block's network with
+    # the slot cut, closed by (O, O'), over the closed block, is then
+    # <s s>_nn along the slot's direction (Onsager); anisotropic couplings
+    # tell horizontal slots from vertical ones and any swap of the two ends
+    # gives 1 instead
+    bh, bv, chi = 0.35, 0.15, 16
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    A = pins.ising_peps_aniso(bh, bv)
+    C, T = _env(cell, chi, 2)
+    C, T, _, _ = ctmrg.ctmrg(cell, [A, A], C, T, chi, max_iter=80, tol=1e-12)
+    ch, cv = pins.onsager_nn_aniso(bh, bv)
+    t = {X: A for X in ("TL", "TR", "BR", "BL")}
+    E = fu.block_corners(cell, C, T, t, t)
+    Z = fu.block_closed(E)
+    for slot in range(4):
+        horiz = fu.SLOTS[slot][2] == "r"
+        Qm = _qmat(bh if horiz else bv)
+        O = np.linalg.solve(Qm, pins.SZ @ Qm)
+        O2 = Qm @ pins.SZ @ np.linalg.inv(Qm)
+        N = fu.block_open(E, slot)
+        assert abs(np.einsum("ijab,ij,ab->", N, np.eye(2), np.eye(2)) / Z - 1) < 1e-12
+        val = np.einsum("ijab,ij,ab->", N, O, O2) / Z
+        assert abs(val - (ch if horiz else cv)) < 1e-9, slot
+
+
+def test_block_network_product_state_factorizes():
+    # D = 1 with a scalar environment: the open network of a slot is the
+    # Gram matrix of the first end's open leg times that of the second end's
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    rng = np.random.default_rng(3)
+    sites = [rng.standard_normal((2, 1, 1, 1, 1)) for _ in range(2)]
+    th = [gates.apply_ipepo(gates.ipepo(1.0, 3.0, 0.1), a) for a in sites]
+    P, Q = fu.su_truncation(cell, th, 1)
+    C, T = np.ones((4, 4, 1, 1)), np.ones((4, 4, 1, 1, 1, 1))
+    for slot, (_, e1, l1, e2, l2) in enumerate(fu.SLOTS):
+        N, M = fu.bond_environment(cell, th, P, Q, P, Q, C, T, slot)
+        t = fu.block_tensors(cell, th, P, Q, P, Q, slot)
+        g1 = np.moveaxis(t[e1], peps.LEGS[l1], 0).reshape(2, -1)
+        g2 = np.moveaxis(t[e2], peps.LEGS[l2], 0).reshape(2, -1)
+        ref = np.einsum("ia,jb->ijab", g1 @ g1.T, g2 @ g2.T)
+        c = np.sum(N * ref) / np.sum(ref * ref)
+        np.testing.assert_allclose(N, c * ref, atol=1e-14 * np.abs(N).max())
+
+
+def _block_problem(D=2, chi=6, seed=0):
+    """A gated state one full-update step from the seeded start, its
+    pre-truncation and the converged environment of the pre-truncated state."""
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    g = gates.ipepo(1.0, 3.0, 0.01)
+    sites = [s / np.linalg.norm(s) for s in tninputs.ipeps_sites(seed, 2, D)]
+    C, T = _env(cell, chi, D)
+    out = fu.fu_env_step(cell, sites, g, D, chi, C, T)
+    th = [gates.apply_ipepo(g, a) for a in out["sites"]]
+    P, Q = fu.su_truncation(cell, th, D)
+    links, _ = peps.cell_links(cell)
+    C, T, _, _ = ctmrg.ctmrg(cell, peps.truncate(th, links, P, Q), out["C"], out["T"], chi,
+                             100, 1e-10)
+    return cell, th, P, Q, C, T
+
+
+def test_block_truncation_joint_cost():
+    cell, th, P, Q, C, T = _block_problem()
+    tn = abs(fu.block_norm(cell, th, P, Q, C, T))
+    P1, Q1, f, passes, sweeps, hist = fu.fu_truncate(cell, th, P, Q, C, T, 1e-15, 300, 1)
+    assert passes < 300
+    # every update minimises the one cost f(zeta) exactly in its variable:
+    # f never increases (Sec. VI B, block coordinate descent)
+    assert all(b <= a + 1e-13 * tn for a, b in zip(hist, hist[1:]))
+    assert f < hist[0]
+    # f is one function of zeta: the four slots' environments give one value
+    sg = np.sign(fu.block_norm(cell, th, P, Q, C, T))
+    fs = []
+    for k in range(4):
+        N, M = fu.bond_environment(cell, th, P, Q, P1, Q1, C, T, k)
+        fs.append(fu.cost(sg * N, P1[k], Q1[k], np.einsum("ijaa->ij", sg * M), tn)[0])
+    assert max(fs) - min(fs) < 1e-12 * tn
+    assert abs(fs[0] - f) < 1e-12 * tn
+    # converged: one more cycle leaves f where it is; the truncations move
+    # only along the directions f weighs least, by the square root of what
+    # the cost still changes (f is quadratic at its minimum)
+    P2, Q2, f2, _, _, _ = fu.fu_truncate(cell, th, P, Q, C, T, 0.0, 1, 1, P1, Q1)
+    assert abs(f2 - f) < 1e-14 * tn
+    for b in range(4):
+        assert np.abs(P2[b] @ Q2[b] - P1[b] @ Q1[b]).max() < 1e-6
+
+
+def test_block_truncation_full_rank_is_exact():
+    # keeping the full bond kappa D, PQ = I is feasible and f reaches 0
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    g = gates.ipepo(1.0, 3.0, 0.05)
+    sites = tninputs.ipeps_sites(4, 2, 1)
+    th = [gates.apply_ipepo(g, a) for a in sites]
+    Dk = th[0].shape[1]
+    P, Q = fu.su_truncation(cell, th, Dk)
+    links, _ = peps.cell_links(cell)
+    C, T = _env(cell, 4, Dk)
+    C, T, _, _ = ctmrg.ctmrg(cell, peps.truncate(th, links, P, Q), C, T, 4, 60, 1e-10)
+    rng = np.random.default_rng(5)
+    P0 = [p + 0.2 * rng.standard_normal(p.shape) for p in P]
+    Q0 = [q + 0.2 * rng.standard_normal(q.shape) for q in Q]
+    tn = abs(fu.block_norm(cell, th, P, Q, C, T))
+    _, _, f, _, _, hist = fu.fu_truncate(cell, th, P, Q, C, T, 1e-15, 50, 1)
+    assert hist[0] < 1e-12 * tn        # the pre-truncation itself is exact here
+    P1, Q1, f, _, _, hist = fu.fu_truncate(cell, th, P, Q, C, T, 1e-15, 100, 1, P0, Q0)
+    # from a perturbed start of the internal links
+    assert hist[0] > 1e-2 * tn
+    assert f < 1e-13 * tn
+
+
+def test_recycling_with_one_step_is_plain_2d():
+    # N_Re = 1 through the recycling branch: the renormalized gate applied
+    # once is the full-update step in another gauge, so every energy of the
+    # trajectory is the plain one
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    D, chi = 2, 6
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_sites(2, 2, D)]
+    C, T = tninputs.ctm_env(3, 4, chi, D, positive=True)
+    _, log_p = fu.run_fu(cell, A, 1.0, 3.0, 0.01, D, chi, 3, n_re=1, C=C, T=T)
+    _, log_r = fu.run_fu(cell, A, 1.0, 3.0, 0.01, D, chi, 3, n_re=1, C=C, T=T,
+                         force_recycle=True)
+    assert [r for _, _, r in log_r] == [True] * 3
+    for (_, ep, _), (_, er, _) in zip(log_p, log_r):
+        assert abs(ep - er) < 1e-10 * abs(ep)
+
+
+def test_recycle_fidelity_near_one_for_slow_evolution():
+    # a short time step changes the state little: the gauge fix of the
+    # canonical truncated state against the canonical A_0 reaches F ~ 1
+    cell = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    D, chi, dt = 2, 6, 1e-4
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_sites(2, 2, D)]
+    a0 = peps.canonicalize_a_form(cell, A)[0]
+    C, T = tninputs.ctm_env(3, 4, chi, D, positive=True)
+    out = fu.fu_env_step(cell, a0, gates.ipepo(1.0, 3.0, dt), D, chi, C, T)
+    _, _, _, F = fu.recycle_build(cell, a0, out, 2)
+    assert F > 1 - 1e-6
 
 
 def test_full_update_product_state_mean_field():
