@@ -286,40 +286,67 @@ int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, in
               double* fidelity, int* iters);
 
 /*
- * bond_env_truncate -- full-update truncation of every link (Sec. VI B,
- * Eqs. (var), (var1)), links in enumeration order.  For link b the bond
- * environment N[i][j][i'][j'] is the CTM network (C, T of the truncated
- * state, bond D) around the link's two sites, each carrying Theta-hat:
- * Theta with its other three legs truncated by the current P, Q (earlier
- * links already updated); i, j are the ket link legs of the first and second
- * site, i', j' the bra legs; N is symmetrised in ket <-> bra.  Then
- * alternating least squares on f = <(I - PQ)|N|(I - PQ)>: P = R^-1 S with Q
- * fixed, then Q with P fixed, each solve on R + 1e-14 tr(R) I (Gaussian
- * elimination with partial pivoting: R is indefinite when N is not
- * positive), after each pair the pair is balanced through the SVD of PQ;
- * kappa D^2 <= 140; stops when
- * |df| < tol <I|N|I> or after max_sweeps.
+ * The full-update truncation works on a 2x2 block of sites (Sec. VI B,
+ * Fig. 21(a)): positions TL = (0, 0), TR = (1, 0), BR = (1, 1), BL = (0, 1)
+ * of the cell, surrounded by their CTM corners and edges.  Its four internal
+ * links are the slots, visited in the order
+ *   0 top    (TL.r - TR.l),   1 left  (TL.d - BL.u),
+ *   2 bottom (BL.r - BR.l),   3 right (TR.d - BR.u),
+ * the first end of each carrying P.  The block's legs that face the
+ * environment carry the pre-truncation (Psu, Qsu) the environment was
+ * computed for.  A cell is accepted when every one of its links is a slot
+ * (the checkerboard: slot k is link k; the 1 x 1 cell: slots 0, 2 are link 0
+ * and slots 1, 3 link 1); other cells give TN_EINVAL.
+ */
+
+/*
+ * bond_env_truncate -- the full-update truncation of every link (Sec. VI B,
+ * Eqs. (var), (var1)): minimises the block cost
+ *   f(zeta) = <Psi_g|Psi_g> - 2 <Psi_g|Psi_zeta> + <Psi_zeta|Psi_zeta>
+ * over zeta = (P, Q) of the four slots, Psi_g having every internal link at
+ * the full bond Dk and Psi_zeta each truncated by its (P, Q).  Cycles over
+ * the slots; a visit builds the slot's two environments from the current
+ * zeta (bond_environment) and makes up to max_sweeps ALS sweeps: P = R^-1 S
+ * with Q fixed, then Q with P fixed, each solve on R + 1e-14 tr(R) I by
+ * Gaussian elimination with partial pivoting (R is indefinite when the
+ * environment is not positive), then the pair balanced through the SVD of
+ * P Q; a visit stops early when a sweep changes f by less than
+ * tol <Psi_g|Psi_g>, and the cycles stop when one changes f by less than
+ * that, or after max_passes.  Each update minimises f exactly in its
+ * variable, so f does not increase.  max_sweeps = 1 is the section's order:
+ * one P and one Q update per link per cycle.  A link held by two slots (the
+ * 1 x 1 cell) gets the mean of their (P, Q).  kappa D^2 <= 140.
  *   Theta        device [nsite][d][Dk]^4, Dk = kappa D
- *   C, T         device, the environment of the truncated state (bond D)
- *   P, Q         device in/out [nlink][Dk][D], [nlink][D][Dk]
- *   cost         host out (may be NULL) [nlink]: final f per link
- *   sweeps       host out (may be NULL): sweeps summed over links
+ *   C, T         device, the environment of the pre-truncated state (bond D)
+ *   Psu, Qsu     device [nlink][Dk][D], [nlink][D][Dk]: the pre-truncation
+ *   P, Q         device in/out [nlink][Dk][D], [nlink][D][Dk]: start, result
+ *   cost         host out (may be NULL) [2]: final f and <Psi_g|Psi_g>
+ *   passes, sweeps  host out (may be NULL): cycles and total ALS sweeps
  * Returns TN_OK, TN_EINVAL, TN_ENUMERIC (a singular normal matrix,
- * non-finite values), TN_EHIP.
+ * non-finite values, a zero block norm), TN_EHIP.
  */
 int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                       int Dk, const double* Theta, int chi, const double* C, const double* T,
-                      double* P, double* Q, int max_sweeps, double tol, double* cost,
-                      int* sweeps);
+                      const double* Psu, const double* Qsu, double* P, double* Q, int max_passes,
+                      int max_sweeps, double tol, double* cost, int* passes, int* sweeps);
 
 /*
- * bond_environment -- the symmetrised bond environment N of one link, as
- * bond_env_truncate computes it before its ALS (same arguments; P, Q are
- * read only).  N device out [Dk][Dk][Dk][Dk] indexed [i][j][i'][j'].
+ * bond_environment -- the two environments of one slot of the truncation
+ * block (same arguments as bond_env_truncate; P, Q read only, per link):
+ *   N device out [Dk][Dk][Dk][Dk], [i][j][i'][j']: the block with the slot
+ *     cut, every other internal link truncated by (P, Q) in both layers;
+ *     i, j the ket index of the slot's first and second end, i', j' the bra
+ *     index; symmetrised in ket <-> bra
+ *   M device out, same layout: the ket layer as for N, the bra layer with
+ *     every internal link at the full bond (Psi_g)
+ * so that f = <Psi_g|Psi_g> - 2 sum (PQ)_ij M[i][j][a][a] + <PQ|N|PQ> for
+ * the slot's (P, Q).  Both carry the sign of the raw network (the
+ * normalised boundary leaves a common sign free).
  */
 int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                      int Dk, const double* Theta, int chi, const double* C, const double* T,
-                     const double* P, const double* Q, int link, double* N);
+                     const double* Psu, const double* Qsu, const double* P, const double* Q,
+                     int slot, double* N, double* M);
 
 /*
  * fu_gauge_start -- start of the gauge fix inside the recycling step

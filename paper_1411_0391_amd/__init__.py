@@ -69,11 +69,13 @@ SIGNATURES = {
                                  ctypes.c_int, _c_double_p, _c_int_p]),
     "bond_env_truncate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
-                                         ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int,
-                                         ctypes.c_double, _c_double_p, _c_int_p]),
+                                         ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         _c_double_p, _c_int_p, _c_int_p]),
     "bond_environment": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
-                                        ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+                                        ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_int, _vp, _vp]),
     "fu_gauge_start": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
     "fu_renormalized_gate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
@@ -275,30 +277,34 @@ class Context:
         self._check(rc, allow_nc=True)
         return F.value, it.value, rc
 
-    def bond_env_truncate(self, Lx, Ly, cell, Theta, C, T, P, Q, max_sweeps=50, tol=1e-12):
-        """P, Q (device) are updated in place; returns (costs, sweeps)."""
+    def bond_env_truncate(self, Lx, Ly, cell, Theta, C, T, Psu, Qsu, P, Q, max_passes=50,
+                          max_sweeps=1, tol=1e-12):
+        """P, Q (device, per link) are updated in place from their start;
+        returns (f, <Psi_g|Psi_g>, passes, sweeps)."""
         nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
         D = P.shape[2]
         chi = C.shape[-1]
-        nl = P.shape[0]
-        cost = (ctypes.c_double * nl)()
-        sw = ctypes.c_int(0)
+        cost = (ctypes.c_double * 2)()
+        npass, sw = ctypes.c_int(0), ctypes.c_int(0)
         rc = lib().bond_env_truncate(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
-                                     _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(P), _ptr(Q),
-                                     max_sweeps, tol, cost, ctypes.byref(sw))
+                                     _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(Psu), _ptr(Qsu),
+                                     _ptr(P), _ptr(Q), max_passes, max_sweeps, tol, cost,
+                                     ctypes.byref(npass), ctypes.byref(sw))
         self._check(rc)
-        return list(cost), sw.value
+        return cost[0], cost[1], npass.value, sw.value
 
-    def bond_environment(self, Lx, Ly, cell, Theta, C, T, P, Q, link):
+    def bond_environment(self, Lx, Ly, cell, Theta, C, T, Psu, Qsu, P, Q, slot):
+        """(N, M) of one slot of the truncation block (device)."""
         import torch
         nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
         D = P.shape[2]
         chi = C.shape[-1]
         N = torch.empty((Dk,) * 4, dtype=torch.float64, device=Theta.device)
+        M = torch.empty((Dk,) * 4, dtype=torch.float64, device=Theta.device)
         self._check(lib().bond_environment(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
-                                           _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(P), _ptr(Q),
-                                           link, _ptr(N)))
-        return N
+                                           _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(Psu),
+                                           _ptr(Qsu), _ptr(P), _ptr(Q), slot, _ptr(N), _ptr(M)))
+        return N, M
 
     def fu_gauge_start(self, P, Q, Pc, Qc, kappa=2):
         import torch

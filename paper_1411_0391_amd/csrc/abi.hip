@@ -36,11 +36,13 @@ int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int 
                    double* fidelity, int* iters);
 int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                            int Dk, const double* Theta, int chi, const double* C, const double* T,
-                           double* P, double* Q, int max_sweeps, double tol, double* cost,
+                           const double* Psu, const double* Qsu, double* P, double* Q,
+                           int max_passes, int max_sweeps, double tol, double* cost, int* passes,
                            int* sweeps);
 int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                           int Dk, const double* Theta, int chi, const double* C, const double* T,
-                          const double* P, const double* Q, int link, double* N_out);
+                          const double* Psu, const double* Qsu, const double* P, const double* Q,
+                          int slot, double* N_out, double* M_out);
 int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
                         const double* Q, const double* Pc, const double* Qc, double* U0);
 int fu_renormalized_gate_impl(tn_ctx* ctx, int nlink, int Dk, int D, const double* P,
@@ -111,7 +113,8 @@ int tn_create(tn_ctx** out, void* hip_stream) {
   tn_ctx* ctx = new tn_ctx();
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&ctx->device) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&ctx->host_scratch), 64 * sizeof(double)) !=
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->host_scratch),
+                    TN_HOST_SCRATCH * sizeof(double)) !=
           hipSuccess) {
     (void)hipGetLastError();
     delete ctx;
@@ -223,11 +226,12 @@ int ipeps_cell_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, in
 
 int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                      int Dk, const double* Theta, int chi, const double* C, const double* T,
-                     const double* P, const double* Q, int link, double* N) {
+                     const double* Psu, const double* Qsu, const double* P, const double* Q,
+                     int slot, double* N, double* M) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  return bond_environment_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, P, Q, link,
-                               N);
+  return bond_environment_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, Psu, Qsu, P,
+                               Q, slot, N, M);
 }
 
 int fu_gauge_start(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
@@ -272,12 +276,12 @@ int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, in
 
 int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                       int Dk, const double* Theta, int chi, const double* C, const double* T,
-                      double* P, double* Q, int max_sweeps, double tol, double* cost,
-                      int* sweeps) {
+                      const double* Psu, const double* Qsu, double* P, double* Q, int max_passes,
+                      int max_sweeps, double tol, double* cost, int* passes, int* sweeps) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  return bond_env_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, P, Q,
-                                max_sweeps, tol, cost, sweeps);
+  return bond_env_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, Psu, Qsu, P,
+                                Q, max_passes, max_sweeps, tol, cost, passes, sweeps);
 }
 
 int fu_renormalized_gate(tn_ctx* ctx, int nlink, int Dk, int D, const double* P, const double* Q,

@@ -12,6 +12,10 @@
 
 #include "itebd.h"
 
+// Capacity in doubles of the context's pinned host staging buffer; every
+// read-back into it checks its extent against this.
+constexpr size_t TN_HOST_SCRATCH = 1024;
+
 struct tn_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
@@ -25,7 +29,7 @@ struct tn_ctx {
   // persistent per-key device buffers (warm starts of iterative solvers)
   std::map<std::string, std::pair<void*, size_t>> keep;
   std::map<std::string, std::vector<char>> keep_flags;  // host validity flags per buffer slot
-  // pinned host staging for small scalar read-backs
+  // pinned host staging for small scalar read-backs (TN_HOST_SCRATCH doubles)
   double* host_scratch = nullptr;
   // a second stream of the library's own (default priority) for work that
   // overlaps the context stream; forked from it and joined back by events
@@ -118,6 +122,13 @@ struct Contraction {
 
 int tc_run(tn_ctx* ctx, const Contraction& c, const double* A, const double* B, double* C,
            double alpha, double beta, int prec = P_F64);
+
+// Pairwise contraction by index labels ("xlLg,gh->xlLh"): labels shared by
+// A and B and absent from the output are summed; every output label comes
+// from exactly one operand; all operands row-major with the given extents.
+int ein(tn_ctx* ctx, const char* spec, const double* A, std::initializer_list<int> da,
+        const double* B, std::initializer_list<int> db, double* C, double alpha = 1.0,
+        double beta = 0.0, int prec = P_F64);
 
 // Plain strided GEMM helper (row-major storage with leading dimensions;
 // ta/tb transpose the stored operand).

@@ -712,6 +712,11 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   int retries = 0, plain_left = 0, plain_done = 0, it_prev = 0;
   int it = 0;
   double hres = 1.0, r_prev = -1.0;
+  // Cholesky status read back per Rayleigh-Ritz step: 2B (basis) + 2B
+  // (pending orth) + MAX_PLAIN 4B (plain steps) ints after 8 doubles
+  if (8 * sizeof(double) + (size_t)(4 + 4 * MAX_PLAIN) * B * sizeof(int) >
+      TN_HOST_SCRATCH * sizeof(double))
+    TN_FAIL(ctx, TN_EINVAL, "%d row cuts exceed the projector SVD's status buffer", B);
   int* hinfo = reinterpret_cast<int*>(ctx->host_scratch + 8);
   for (it = 1; it <= maxit; ++it) {
     if (plain_left > 0 && allow_plain && have_s && !robust) {

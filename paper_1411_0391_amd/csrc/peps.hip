@@ -624,82 +624,12 @@ struct Env {
   }
 };
 
-// Left half of the link network in frame f at position p, with the site
-// tensor A (dims d, D, nr, D, D: its r leg is the open link leg) as ket and
-// bra: L[t, rk, rb, b] (t = T1 boundary leg, b = T3 boundary leg).
-int half_open(tn_ctx* ctx, const Env& env, int f, int p, const double* A, int d, int nr,
-              double* L, double* X1, double* X2, double* X3, double* X4, double* Y) {
-  const long long chi = env.chi, D = env.D, D2 = D * D, dd = d, n = nr;
-  const double* C1 = env.Cp(p, f);
-  const double* T1 = env.Tp(p, f);
-  const double* T4 = env.Tp(p, f + 3);
-  const double* C4 = env.Cp(p, f + 3);
-  const double* T3 = env.Tp(p, f + 2);
-  // site strides (s, l, r, d, u)
-  const long long su = 1, sd = D, sr = D2, sl = n * D2, ss = D * n * D2;
-  // X1[(e,lk,lb), h] = T4 C1;  X2[(e,lk,lb),(uk,ub,t)] = X1 T1
-  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T4, (int)chi, false, C1, (int)chi, false,
-              X1, (int)chi, 1.0, 0.0));
-  TN_TRY(gemm(ctx, (int)(chi * D2), (int)(D2 * chi), (int)chi, X1, (int)chi, false, T1,
-              (int)(D2 * chi), false, X2, (int)(D2 * chi), 1.0, 0.0));
-  // X3[e][t][rk][dk][s][lb][ub] = sum_{lk,uk} X2[e,lk,lb,uk,ub,t] A[s,lk,rk,dk,uk]
-  const long long x3_ub = 1, x3_lb = D, x3_s = D2, x3_dk = dd * D2, x3_rk = D * dd * D2,
-                  x3_t = n * x3_rk, x3_e = chi * x3_t;
-  Contraction c3;
-  c3.am = grp({{(int)chi, D2 * D2 * chi}, {(int)D, D2 * chi}, {(int)D, chi}, {(int)chi, 1}});
-  c3.ak = grp({{(int)D, D * D2 * chi}, {(int)D, D * chi}});
-  c3.bk = grp({{(int)D, sl}, {(int)D, su}});
-  c3.bn = grp({{(int)d, ss}, {(int)n, sr}, {(int)D, sd}});
-  c3.cm = grp({{(int)chi, x3_e}, {(int)D, x3_lb}, {(int)D, x3_ub}, {(int)chi, x3_t}});
-  c3.cn = grp({{(int)d, x3_s}, {(int)n, x3_rk}, {(int)D, x3_dk}});
-  TN_TRY(tc_run(ctx, c3, X2, A, X3, 1.0, 0.0));
-  // X4[t][rk][rb][e][dk][db] = sum_{s,lb,ub} X3[e,t,rk,dk,s,lb,ub] A[s,lb,rb,db,ub]
-  const long long x4_db = 1, x4_dk = D, x4_e = D2, x4_rb = chi * D2, x4_rk = n * x4_rb,
-                  x4_t = n * x4_rk;
-  Contraction c4;
-  c4.am = grp({{(int)chi, x3_t}, {(int)n, x3_rk}, {(int)chi, x3_e}, {(int)D, x3_dk}});
-  c4.ak = grp({{(int)d, x3_s}, {(int)D, x3_lb}, {(int)D, x3_ub}});
-  c4.bk = grp({{(int)d, ss}, {(int)D, sl}, {(int)D, su}});
-  c4.bn = grp({{(int)n, sr}, {(int)D, sd}});
-  c4.cm = grp({{(int)chi, x4_t}, {(int)n, x4_rk}, {(int)chi, x4_e}, {(int)D, x4_dk}});
-  c4.cn = grp({{(int)n, x4_rb}, {(int)D, x4_db}});
-  TN_TRY(tc_run(ctx, c4, X3, A, X4, 1.0, 0.0));
-  // Y[(b,dk,db), e] = T3 C4
-  TN_TRY(gemm(ctx, (int)(chi * D2), (int)chi, (int)chi, T3, (int)chi, false, C4, (int)chi, false,
-              Y, (int)chi, 1.0, 0.0));
-  // L[(t,rk,rb), b] = sum_{e,dk,db} X4[(t,rk,rb),(e,dk,db)] Y[b,dk,db,e]
-  Contraction c6;
-  c6.am = grp({{(int)(chi * n * n), chi * D2}});
-  c6.ak = grp({{(int)chi, D2}, {(int)D, D}, {(int)D, 1}});
-  c6.bk = grp({{(int)chi, 1}, {(int)D, D * chi}, {(int)D, chi}});
-  c6.bn = grp({{(int)chi, D2 * chi}});
-  c6.cm = grp({{(int)(chi * n * n), chi}});
-  c6.cn = grp({{(int)chi, 1}});
-  TN_TRY(tc_run(ctx, c6, X4, Y, L, 1.0, 0.0));
-  return TN_OK;
-}
-
 // Ns = (N + N^T) / 2 for N an m x m matrix
 __global__ void symmetrize_kernel(const double* __restrict__ N, double* __restrict__ Ns, int m) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)m * m) return;
   const int i = (int)(t / m), j = (int)(t % m);
   Ns[t] = 0.5 * (N[t] + N[(long long)j * m + i]);
-}
-
-// The normalised boundary leaves the overall sign of N free: flip N so that
-// <I|N|I> = sum_{i,a} N[i][i][a][a] > 0 (one workgroup)
-__global__ __launch_bounds__(256) void n_sign_kernel(double* __restrict__ N, int n) {
-  __shared__ double red[4];
-  const long long n2 = (long long)n * n, n4 = n2 * n2;
-  double t = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int i = e / n, a = e % n;
-    t += N[(long long)(i * n + i) * n2 + a * n + a];
-  }
-  t = block_sum256(t, red);
-  if (t < 0.0)
-    for (long long e = threadIdx.x; e < n4; e += 256) N[e] = -N[e];
 }
 
 // tb[i][j] = sum_a N[i][j][a][a]; t = <I|N|I> = sum_{i,a} N[i][i][a][a]
@@ -872,6 +802,29 @@ __global__ void als_balance_kernel(int n, int D, const double* __restrict__ u,
   const double sq = sqrt(s[c]);
   P[i * D + c] = u[i * n + c] * sq;
   Q[c * n + i] = sq * V[i * n + c];
+}
+
+// P[b] = mean of Pz[s] over the slots s that hold link b (Q likewise); a
+// link held by one slot takes its truncation as it is
+__global__ void slot_mean_kernel(int nl, int per, int l0, int l1, int l2, int l3,
+                                 const double* __restrict__ Pz, const double* __restrict__ Qz,
+                                 double* __restrict__ P, double* __restrict__ Q) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nl * per) return;
+  const int b = (int)(t / per), e = (int)(t % per);
+  const int sl[4] = {l0, l1, l2, l3};
+  double p = 0.0, q = 0.0;
+  int cnt = 0;
+  for (int s = 0; s < 4; ++s)
+    if (sl[s] == b) {
+      p += Pz[(long long)s * per + e];
+      q += Qz[(long long)s * per + e];
+      ++cnt;
+    }
+  if (cnt) {
+    P[t] = p / cnt;
+    Q[t] = q / cnt;
+  }
 }
 
 // f = t - 2 <PQ|N|I> + <PQ|N|PQ> (Eq. (var), real case); out[0] = f
@@ -1397,113 +1350,261 @@ int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int 
 
 namespace {
 
-// Buffers and steps of the bond environment of one link.
-struct BondEnv {
-  const CellLinks* L;
-  int Lx, Ly, d, D, n, chi;
-  size_t tsz;
-  const double* Theta;
-  Env env;
-  double *sc, *th, *thr, *rtmp, *X1, *X2, *X3, *X4, *Y, *L1, *L2, *N, *Ns;
+// ---------------------------------------------------------------------------
+// the truncation block (Sec. VI B, Fig. 21(a)): a 2x2 block of sites, its
+// four internal links (slots) and the CTM environment around it
+// ---------------------------------------------------------------------------
 
+// block positions (x, y) = (0, 0), (1, 0), (1, 1), (0, 1)
+enum { B_TL = 0, B_TR = 1, B_BR = 2, B_BL = 3 };
+// slots in visiting order: top, left, bottom, right; the first end carries P
+struct SlotDef {
+  int e1, ax1, e2, ax2;
+};
+constexpr SlotDef SLOT[4] = {{B_TL, AX_R, B_TR, AX_L},
+                             {B_TL, AX_D, B_BL, AX_U},
+                             {B_BL, AX_R, B_BR, AX_L},
+                             {B_TR, AX_D, B_BR, AX_U}};
+
+// slot of axis ax of block position X, or -1 when the axis faces the environment
+int slot_of(int X, int ax) {
+  for (int k = 0; k < 4; ++k) {
+    if (SLOT[k].e1 == X && SLOT[k].ax1 == ax) return k;
+    if (SLOT[k].e2 == X && SLOT[k].ax2 == ax) return k;
+  }
+  return -1;
+}
+
+// How the internal links of a layer are closed: truncated by the slots'
+// current (P, Q), or left at the full bond (the gated state Psi_g).
+enum { L_ZETA = 0, L_FULL = 1 };
+
+struct Block {
+  const CellLinks* L;
+  int d, D, n, chi;
+  int pos[4], site[4], slot_link[4];
+  Env env;
+  const double* Theta;  // [nsite][d][n]^4
+  const double *Psu, *Qsu;  // [nlink][n][D], [nlink][D][n]: legs facing the environment
+  double *Pz, *Qz;          // [4][n][D], [4][D][n]: the slots' current truncation
+  size_t big;               // doubles of the largest corner or ring intermediate
+  double *ket[4], *bra[4], *sc1, *sc2;
+  TDims kd[4], bd[4];
+  double *E[4], *X1, *X2, *X3, *R1, *R2;
+
+  static size_t big_of(int d, int D, int n, int chi) {
+    const size_t c2 = (size_t)chi * chi, n2 = (size_t)n * n;
+    return std::max(c2 * n2 * n2, c2 * (size_t)D * D * d * n2);
+  }
   static size_t bytes(int d, int D, int n, int chi) {
-    const size_t chi_ = chi, D_ = D, D2 = D_ * D_, n_ = n, d_ = d;
-    const size_t tsz = d_ * n_ * n_ * n_ * n_;
+    const size_t tsz = (size_t)d * n * n * n * n, big = big_of(d, D, n, chi);
     size_t need = 0;
     auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
-    add(2 * tsz);
-    add(2 * tsz);
-    add(2 * tsz);
+    for (int k = 0; k < 8; ++k) add(tsz);   // ket, bra per position
     add(tsz);
-    add(chi_ * D2 * chi_);
-    add(chi_ * D2 * D2 * chi_);
-    add(chi_ * chi_ * n_ * D_ * d_ * D2);
-    add(chi_ * chi_ * n_ * n_ * D2);
-    add(chi_ * D2 * chi_);
-    add(2 * chi_ * n_ * n_ * chi_);
-    add(2 * n_ * n_ * n_ * n_);
+    add(tsz);                                // apply_legs scratch
+    for (int k = 0; k < 4; ++k) add(big);    // corners
+    add((size_t)chi * chi * D * D);          // X1
+    add(big);                                // X2 (chi^2 D^4 fits)
+    add(big);                                // X3
+    add(big);
+    add(big);                                // ring intermediates
+    add(4 * (size_t)n * D);
+    add(4 * (size_t)n * D);                  // Pz, Qz
     return need;
   }
 
   int alloc(tn_ctx* ctx) {
-    const size_t chi_ = chi, D_ = D, D2 = D_ * D_, n_ = n, d_ = d;
-    tsz = d_ * n_ * n_ * n_ * n_;
-    sc = ws_alloc<double>(ctx, 2 * tsz);
-    th = ws_alloc<double>(ctx, 2 * tsz);
-    thr = ws_alloc<double>(ctx, 2 * tsz);
-    rtmp = ws_alloc<double>(ctx, tsz);
-    X1 = ws_alloc<double>(ctx, chi_ * D2 * chi_);
-    X2 = ws_alloc<double>(ctx, chi_ * D2 * D2 * chi_);
-    X3 = ws_alloc<double>(ctx, chi_ * chi_ * n_ * D_ * d_ * D2);
-    X4 = ws_alloc<double>(ctx, chi_ * chi_ * n_ * n_ * D2);
-    Y = ws_alloc<double>(ctx, chi_ * D2 * chi_);
-    L1 = ws_alloc<double>(ctx, 2 * chi_ * n_ * n_ * chi_);
-    L2 = L1 ? L1 + chi_ * n_ * n_ * chi_ : nullptr;
-    N = ws_alloc<double>(ctx, 2 * n_ * n_ * n_ * n_);
-    Ns = N ? N + n_ * n_ * n_ * n_ : nullptr;
-    if (!Ns) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (bond environment)");
+    const size_t tsz = (size_t)d * n * n * n * n;
+    big = big_of(d, D, n, chi);
+    for (int k = 0; k < 4; ++k) {
+      ket[k] = ws_alloc<double>(ctx, tsz);
+      bra[k] = ws_alloc<double>(ctx, tsz);
+    }
+    sc1 = ws_alloc<double>(ctx, tsz);
+    sc2 = ws_alloc<double>(ctx, tsz);
+    for (int k = 0; k < 4; ++k) E[k] = ws_alloc<double>(ctx, big);
+    X1 = ws_alloc<double>(ctx, (size_t)chi * chi * D * D);
+    X2 = ws_alloc<double>(ctx, big);
+    X3 = ws_alloc<double>(ctx, big);
+    R1 = ws_alloc<double>(ctx, big);
+    R2 = ws_alloc<double>(ctx, big);
+    Pz = ws_alloc<double>(ctx, 4 * (size_t)n * D);
+    Qz = ws_alloc<double>(ctx, 4 * (size_t)n * D);
+    if (!Qz) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (truncation block)");
     return TN_OK;
   }
 
-  // Ns of link b with the current P, Q
-  int compute(tn_ctx* ctx, int b, const double* P, const double* Q) {
-    const CellLinks& Lk = *L;
-    auto pos = [&](int x, int y) { return (((y % Ly) + Ly) % Ly) * Lx + (((x % Lx) + Lx) % Lx); };
-    const long long per = (long long)n * D;
-    const bool horiz = Lk.l1[b] == AX_R;
-    const int frames[2] = {horiz ? 0 : 1, horiz ? 2 : 3};
-    // Theta-hat of both ends (every leg but the link's truncated with the
-    // current P, Q), rotated so that the open leg is the r leg of its frame
-    for (int side = 0; side < 2; ++side) {
-      const int s = side ? Lk.s2[b] : Lk.s1[b];
-      const int open = side ? Lk.l2[b] : Lk.l1[b];
-      LegMats lm;
-      for (int ax = 1; ax <= 4; ++ax) {
-        if (ax == open) continue;
-        const int bb = Lk.leg_link[s][ax];
-        const bool first = (Lk.s1[bb] == s && Lk.l1[bb] == ax);
-        lm.m[ax] = (first ? P : Q) + bb * per;
+  // Site tensor of block position X for one layer: legs facing the
+  // environment truncated by the pre-truncation, internal legs by the
+  // slot's (Pz, Qz) (mode L_ZETA, except the open slot) or untruncated.
+  int layer(tn_ctx* ctx, int X, int mode, int open, double* out, TDims* dout) {
+    const int s = site[X];
+    LegMats lm;
+    for (int ax = 1; ax <= 4; ++ax) {
+      const int k = slot_of(X, ax);
+      if (k < 0) {
+        const int b = L->leg_link[s][ax];
+        const bool first = (L->s1[b] == s && L->l1[b] == ax);
+        lm.m[ax] = (first ? Psu : Qsu) + (long long)b * n * D;
+        lm.trans[ax] = first ? 1 : 0;
+        lm.nnew[ax] = D;
+      } else if (k != open && mode == L_ZETA) {
+        const bool first = SLOT[k].e1 == X;
+        lm.m[ax] = (first ? Pz : Qz) + (long long)k * n * D;
         lm.trans[ax] = first ? 1 : 0;
         lm.nnew[ax] = D;
       }
-      TDims dh;
-      TN_TRY(apply_legs(ctx, Theta + s * tsz, th + side * tsz, dims5(d, n, n, n, n), lm, sc,
-                        sc + tsz, &dh));
-      TDims dr;
-      TN_TRY(rotate_times(ctx, th + side * tsz, thr + side * tsz, rtmp, dh, frames[side], &dr));
-      if (dr.n[AX_R] != n || dr.n[AX_L] != D)
-        TN_FAIL(ctx, TN_EINVAL, "internal: open leg not on the r axis after rotation");
     }
-    const int p = pos(Lk.x[b], Lk.y[b]);
-    const int q = horiz ? pos(Lk.x[b] + 1, Lk.y[b]) : pos(Lk.x[b], Lk.y[b] + 1);
-    TN_TRY(half_open(ctx, env, frames[0], p, thr, d, n, L1, X1, X2, X3, X4, Y));
-    TN_TRY(half_open(ctx, env, frames[1], q, thr + tsz, d, n, L2, X1, X2, X3, X4, Y));
-    // N[k][i][K][I] = sum_{t,b} L1[t,k,K,b] L2[b,i,I,t]
-    const long long cn = chi, nn_ = n;
-    Contraction cN;
-    cN.am = grp({{n, nn_ * cn}, {n, cn}});
-    cN.ak = grp({{chi, nn_ * nn_ * cn}, {chi, 1}});
-    cN.bk = grp({{chi, 1}, {chi, nn_ * nn_ * cn}});
-    cN.bn = grp({{n, nn_ * cn}, {n, cn}});
-    cN.cm = grp({{n, nn_ * nn_ * nn_}, {n, nn_}});
-    cN.cn = grp({{n, nn_ * nn_}, {n, 1}});
-    TN_TRY(tc_run(ctx, cN, L1, L2, N, 1.0, 0.0));
-    const long long n4 = nn_ * nn_ * nn_ * nn_;
-    hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(n4)), dim3(256), 0, ctx->stream, N, Ns, n * n);
-    hipLaunchKernelGGL(n_sign_kernel, dim3(1), dim3(256), 0, ctx->stream, Ns, n);
-    TN_HIP(ctx, hipGetLastError());
+    return apply_legs(ctx, Theta + (long long)s * d * n * n * n * n, out, dims5(d, n, n, n, n),
+                      lm, sc1, sc2, dout);
+  }
+
+  // The four enlarged corners of the block, ket and bra layers as given:
+  //   E_TL[t, rk, rb, dk, db, x], E_TR[t, lk, lb, dk, db, f],
+  //   E_BR[f, uk, ub, lk, lb, y], E_BL[y, rk, rb, uk, ub, x]
+  int corners(tn_ctx* ctx, int kmode, int bmode, int open) {
+    for (int X = 0; X < 4; ++X) {
+      TN_TRY(layer(ctx, X, kmode, open, ket[X], &kd[X]));
+      TN_TRY(layer(ctx, X, bmode, open, bra[X], &bd[X]));
+    }
+    const int c = chi, e = D, dd = d;
+    auto K = [&](int X, int ax) { return kd[X].n[ax]; };
+    auto Bd = [&](int X, int ax) { return bd[X].n[ax]; };
+    // top-left: C1 of TL, T1 of TL, T4 of TL
+    {
+      const int X = B_TL, p = pos[X];
+      TN_TRY(ein(ctx, "xlLg,gh->xlLh", env.Tp(p, 3), {c, e, e, c}, env.Cp(p, 0), {c, c}, X1));
+      TN_TRY(ein(ctx, "xlLh,huUt->xlLuUt", X1, {c, e, e, c}, env.Tp(p, 0), {c, e, e, c}, X2));
+      TN_TRY(ein(ctx, "xlLuUt,slrdu->xLUtsrd", X2, {c, e, e, e, e, c}, ket[X],
+                 {dd, e, K(X, AX_R), K(X, AX_D), e}, X3));
+      TN_TRY(ein(ctx, "xLUtsrd,sLRDU->trRdDx", X3, {c, e, e, c, dd, K(X, AX_R), K(X, AX_D)},
+                 bra[X], {dd, e, Bd(X, AX_R), Bd(X, AX_D), e}, E[X]));
+    }
+    // top-right: T1 of TR, C2 of TR, T2 of TR
+    {
+      const int X = B_TR, p = pos[X];
+      TN_TRY(ein(ctx, "tuUh,he->tuUe", env.Tp(p, 0), {c, e, e, c}, env.Cp(p, 1), {c, c}, X1));
+      TN_TRY(ein(ctx, "tuUe,erRf->tuUrRf", X1, {c, e, e, c}, env.Tp(p, 1), {c, e, e, c}, X2));
+      TN_TRY(ein(ctx, "tuUrRf,slrdu->tURfsld", X2, {c, e, e, e, e, c}, ket[X],
+                 {dd, K(X, AX_L), e, K(X, AX_D), e}, X3));
+      TN_TRY(ein(ctx, "tURfsld,sLRDU->tlLdDf", X3, {c, e, e, c, dd, K(X, AX_L), K(X, AX_D)},
+                 bra[X], {dd, Bd(X, AX_L), e, Bd(X, AX_D), e}, E[X]));
+    }
+    // bottom-right: T2 of BR, C3 of BR, T3 of BR
+    {
+      const int X = B_BR, p = pos[X];
+      TN_TRY(ein(ctx, "frRg,gh->frRh", env.Tp(p, 1), {c, e, e, c}, env.Cp(p, 2), {c, c}, X1));
+      TN_TRY(ein(ctx, "frRh,hdDy->frRdDy", X1, {c, e, e, c}, env.Tp(p, 2), {c, e, e, c}, X2));
+      TN_TRY(ein(ctx, "frRdDy,slrdu->fRDysul", X2, {c, e, e, e, e, c}, ket[X],
+                 {dd, K(X, AX_L), e, e, K(X, AX_U)}, X3));
+      TN_TRY(ein(ctx, "fRDysul,sLRDU->fuUlLy", X3, {c, e, e, c, dd, K(X, AX_U), K(X, AX_L)},
+                 bra[X], {dd, Bd(X, AX_L), e, e, Bd(X, AX_U)}, E[X]));
+    }
+    // bottom-left: T3 of BL, C4 of BL, T4 of BL
+    {
+      const int X = B_BL, p = pos[X];
+      TN_TRY(ein(ctx, "ydDg,ge->ydDe", env.Tp(p, 2), {c, e, e, c}, env.Cp(p, 3), {c, c}, X1));
+      TN_TRY(ein(ctx, "ydDe,elLx->ydDlLx", X1, {c, e, e, c}, env.Tp(p, 3), {c, e, e, c}, X2));
+      TN_TRY(ein(ctx, "ydDlLx,slrdu->yDLxsru", X2, {c, e, e, e, e, c}, ket[X],
+                 {dd, e, K(X, AX_R), e, K(X, AX_U)}, X3));
+      TN_TRY(ein(ctx, "yDLxsru,sLRDU->yrRuUx", X3, {c, e, e, c, dd, K(X, AX_R), K(X, AX_U)},
+                 bra[X], {dd, e, Bd(X, AX_R), e, Bd(X, AX_U)}, E[X]));
+    }
     return TN_OK;
+  }
+
+  // The ring with slot `open` cut, scaled by alpha: out[i][j][i'][j'], i, j
+  // the ket index of the slot's first and second end, i', j' the bra index;
+  // open < 0 closes every link and writes the scalar norm network.
+  int ring(tn_ctx* ctx, int open, double alpha, double* out) {
+    const int c = chi;
+    const std::initializer_list<int> tl = {c, kd[0].n[AX_R], bd[0].n[AX_R], kd[0].n[AX_D],
+                                           bd[0].n[AX_D], c};
+    const std::initializer_list<int> tr = {c, kd[1].n[AX_L], bd[1].n[AX_L], kd[1].n[AX_D],
+                                           bd[1].n[AX_D], c};
+    const std::initializer_list<int> br = {c, kd[2].n[AX_U], bd[2].n[AX_U], kd[2].n[AX_L],
+                                           bd[2].n[AX_L], c};
+    const std::initializer_list<int> bl = {c, kd[3].n[AX_R], bd[3].n[AX_R], kd[3].n[AX_U],
+                                           bd[3].n[AX_U], c};
+    const int a = kd[0].n[AX_R], A = bd[0].n[AX_R], b = kd[0].n[AX_D], B = bd[0].n[AX_D];
+    const int e = kd[1].n[AX_D], Ee = bd[1].n[AX_D], h = kd[2].n[AX_L], H = bd[2].n[AX_L];
+    switch (open) {
+      case 0:  // top
+        TN_TRY(ein(ctx, "feEhHy,yhHbBx->feEbBx", E[2], br, E[3], bl, R1));
+        TN_TRY(ein(ctx, "taAbBx,feEbBx->taAfeE", E[0], tl, R1, {c, e, Ee, b, B, c}, R2));
+        TN_TRY(ein(ctx, "taAfeE,tcCeEf->acAC", R2, {c, a, A, c, e, Ee}, E[1], tr, out, alpha));
+        break;
+      case 1:  // left
+        TN_TRY(ein(ctx, "taAeEf,feEhHy->taAhHy", E[1], tr, E[2], br, R1));
+        TN_TRY(ein(ctx, "taAbBx,taAhHy->bBxhHy", E[0], tl, R1, {c, a, A, h, H, c}, R2));
+        TN_TRY(ein(ctx, "bBxhHy,yhHmMx->bmBM", R2, {b, B, c, h, H, c}, E[3], bl, out, alpha));
+        break;
+      case 2:  // bottom
+        TN_TRY(ein(ctx, "taAbBx,taAeEf->bBxeEf", E[0], tl, E[1], tr, R1));
+        TN_TRY(ein(ctx, "bBxeEf,feEhHy->bBxhHy", R1, {b, B, c, e, Ee, c}, E[2], br, R2));
+        TN_TRY(ein(ctx, "bBxhHy,ykKbBx->khKH", R2, {b, B, c, h, H, c}, E[3], bl, out, alpha));
+        break;
+      case 3:  // right
+        TN_TRY(ein(ctx, "yhHbBx,taAbBx->yhHtaA", E[3], bl, E[0], tl, R1));
+        TN_TRY(ein(ctx, "yhHtaA,taAeEf->yhHeEf", R1, {c, h, H, c, a, A}, E[1], tr, R2));
+        TN_TRY(ein(ctx, "yhHeEf,fgGhHy->egEG", R2, {c, h, H, e, Ee, c}, E[2], br, out, alpha));
+        break;
+      default:  // closed
+        TN_TRY(ein(ctx, "taAbBx,taAeEf->bBxeEf", E[0], tl, E[1], tr, R1));
+        TN_TRY(ein(ctx, "bBxeEf,feEhHy->bBxhHy", R1, {b, B, c, e, Ee, c}, E[2], br, R2));
+        TN_TRY(ein(ctx, "bBxhHy,yhHbBx->", R2, {b, B, c, h, H, c}, E[3], bl, out, alpha));
+    }
+    return TN_OK;
+  }
+
+  // The two environments of slot k (raw ring sign times sg): N with zeta in
+  // both layers, symmetrised in ket <-> bra (Ns), and M with zeta in the ket
+  // layer against the untruncated bra layer of Psi_g.
+  int envs(tn_ctx* ctx, int k, double sg, double* N, double* Ns, double* M) {
+    TN_TRY(corners(ctx, L_ZETA, L_ZETA, k));
+    TN_TRY(ring(ctx, k, sg, N));
+    const long long n2 = (long long)n * n;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(n2 * n2)), dim3(256), 0, ctx->stream, N, Ns,
+                       (int)n2);
+    TN_HIP(ctx, hipGetLastError());
+    TN_TRY(corners(ctx, L_ZETA, L_FULL, k));
+    return ring(ctx, k, sg, M);
   }
 };
 
+// Block geometry of a cell: positions, sites and the cell link of each slot;
+// TN_EINVAL when the block at the origin does not hold every link.
+int block_setup(tn_ctx* ctx, const CellLinks& L, int Lx, int Ly, const int* cell, Block& B) {
+  auto pos = [&](int x, int y) { return (y % Ly) * Lx + (x % Lx); };
+  B.pos[B_TL] = pos(0, 0);
+  B.pos[B_TR] = pos(1, 0);
+  B.pos[B_BR] = pos(1, 1);
+  B.pos[B_BL] = pos(0, 1);
+  for (int X = 0; X < 4; ++X) B.site[X] = cell[B.pos[X]];
+  bool seen[MAXL] = {false};
+  for (int k = 0; k < 4; ++k) {
+    const int s1 = B.site[SLOT[k].e1], s2 = B.site[SLOT[k].e2];
+    const int b = L.leg_link[s1][SLOT[k].ax1];
+    if (b < 0 || L.leg_link[s2][SLOT[k].ax2] != b || L.s1[b] != s1 || L.s2[b] != s2)
+      TN_FAIL(ctx, TN_EINVAL, "internal: slot %d does not match the cell links", k);
+    B.slot_link[k] = b;
+    seen[b] = true;
+  }
+  for (int b = 0; b < L.nl; ++b)
+    if (!seen[b])
+      TN_FAIL(ctx, TN_EINVAL, "link %d of the cell lies outside the 2x2 truncation block", b);
+  return TN_OK;
+}
+
 int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int chi, const void* Theta, const void* C,
-                   const void* T, const void* P, const void* Q) {
+                   const void* T, const void* Psu, const void* Qsu) {
   TN_TRY(check_bond(ctx, Dk, "theta bond"));
   if (D < 1 || D > Dk) TN_FAIL(ctx, TN_EINVAL, "truncated bond %d outside [1, %d]", D, Dk);
-  if (d < 1 || chi < 1 || !Theta || !C || !T || !P || !Q)
+  if (d < 1 || chi < 1 || !Theta || !C || !T || !Psu || !Qsu)
     TN_FAIL(ctx, TN_EINVAL, "bad bond environment arguments");
-  const long long n = (long long)chi * D * D;
-  if (n > 32768) TN_FAIL(ctx, TN_EINVAL, "chi*D*D = %lld too large", n);
+  const double big = (double)Block::big_of(d, D, Dk, chi);
+  if (big > 2.0e9) TN_FAIL(ctx, TN_EINVAL, "truncation block too large (chi %d, bond %d)", chi, Dk);
   return TN_OK;
 }
 
@@ -1511,114 +1612,173 @@ int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int chi, const void* Theta
 
 int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                           int Dk, const double* Theta, int chi, const double* C, const double* T,
-                          const double* P, const double* Q, int link, double* N_out) {
+                          const double* Psu, const double* Qsu, const double* P, const double* Q,
+                          int slot, double* N_out, double* M_out) {
   CellLinks L;
   TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
-  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, P, Q));
-  if (link < 0 || link >= L.nl) TN_FAIL(ctx, TN_EINVAL, "link %d outside [0, %d)", link, L.nl);
-  if (!N_out) TN_FAIL(ctx, TN_EINVAL, "null output");
-  TN_TRY(ws_reserve(ctx, BondEnv::bytes(d, D, Dk, chi) + (1 << 20)));
-  ws_reset(ctx);
-  BondEnv be{&L, Lx, Ly, d, D, Dk, chi, 0, Theta, Env{chi, D, C, T}};
-  TN_TRY(be.alloc(ctx));
-  TN_TRY(be.compute(ctx, link, P, Q));
+  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, Psu, Qsu));
+  if (!P || !Q) TN_FAIL(ctx, TN_EINVAL, "null truncation");
+  if (slot < 0 || slot > 3) TN_FAIL(ctx, TN_EINVAL, "slot %d outside [0, 4)", slot);
+  if (!N_out || !M_out) TN_FAIL(ctx, TN_EINVAL, "null output");
   const size_t n4 = (size_t)Dk * Dk * Dk * Dk;
-  TN_HIP(ctx, hipMemcpyAsync(N_out, be.Ns, n4 * sizeof(double), hipMemcpyDeviceToDevice,
-                             ctx->stream));
+  TN_TRY(ws_reserve(ctx, Block::bytes(d, D, Dk, chi) + n4 * 8 + (1 << 20)));
+  ws_reset(ctx);
+  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, D, C, T}, Theta, Psu, Qsu};
+  TN_TRY(block_setup(ctx, L, Lx, Ly, cell, B));
+  TN_TRY(B.alloc(ctx));
+  double* Nraw = ws_alloc<double>(ctx, n4);
+  if (!Nraw) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (bond environment)");
+  const size_t per = (size_t)Dk * D;
+  for (int k = 0; k < 4; ++k) {
+    TN_HIP(ctx, hipMemcpyAsync(B.Pz + k * per, P + B.slot_link[k] * per, per * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(B.Qz + k * per, Q + B.slot_link[k] * per, per * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  TN_TRY(B.envs(ctx, slot, 1.0, Nraw, N_out, M_out));
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return TN_OK;
 }
 
 int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                            int Dk, const double* Theta, int chi, const double* C, const double* T,
-                           double* P, double* Q, int max_sweeps, double tol, double* cost,
+                           const double* Psu, const double* Qsu, double* P, double* Q,
+                           int max_passes, int max_sweeps, double tol, double* cost, int* passes,
                            int* sweeps) {
   CellLinks L;
   TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
-  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, P, Q));
-  if (max_sweeps < 1) TN_FAIL(ctx, TN_EINVAL, "max_sweeps must be >= 1");
-  const int nl = L.nl, n = Dk, k = Dk * D;
+  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, Psu, Qsu));
+  if (!P || !Q) TN_FAIL(ctx, TN_EINVAL, "null truncation");
+  if (max_passes < 1 || max_sweeps < 1)
+    TN_FAIL(ctx, TN_EINVAL, "max_passes and max_sweeps must be >= 1");
+  const int n = Dk, k = Dk * D;
   // the augmented k x (k + 1) system of the solve lives in LDS
   if (k > 140) TN_FAIL(ctx, TN_EINVAL, "kappa*D*D = %d too large for the ALS solve", k);
-  const size_t n_ = n;
-  size_t need = BondEnv::bytes(d, D, Dk, chi);
+  const size_t n_ = n, n4 = n_ * n_ * n_ * n_;
+  size_t need = Block::bytes(d, D, Dk, chi);
   auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
-  add(n_ * n_ + 2);                     // tb, t
-  add(4 * (size_t)k * k + 2 * k);       // R, Rc, Rinv, S, x
+  add(3 * n4);                          // N raw, N symmetrised, M
+  add(n_ * n_ + 4);                     // tb, T, scratch
+  add(4 * (size_t)k * k + 2 * k);       // R and S
   add(4 * n_ * n_ + n_ + 8);            // O, u, V, s, f
+  add(64);                              // info
   TN_TRY(ws_reserve(ctx, need + (1 << 20)));
   ws_reset(ctx);
-  BondEnv be{&L, Lx, Ly, d, D, Dk, chi, 0, Theta, Env{chi, D, C, T}};
-  TN_TRY(be.alloc(ctx));
-  double* tb = ws_alloc<double>(ctx, n_ * n_ + 2);
-  double* tconst = tb + n_ * n_;
+  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, D, C, T}, Theta, Psu, Qsu};
+  TN_TRY(block_setup(ctx, L, Lx, Ly, cell, B));
+  TN_TRY(B.alloc(ctx));
+  double* Nraw = ws_alloc<double>(ctx, 3 * n4);
+  double* Ns = Nraw + n4;
+  double* M = Ns + n4;
+  double* tb = ws_alloc<double>(ctx, n_ * n_ + 4);
+  double* tdev = tb + n_ * n_;          // <Psi_g|Psi_g>
+  double* tjunk = tdev + 1;
   double* R = ws_alloc<double>(ctx, 4 * (size_t)k * k + 2 * k);
-  double* Rc = R + (size_t)k * k;
-  double* Rinv = Rc + (size_t)k * k;
-  double* S = Rinv + 2 * (size_t)k * k;
+  double* S = R + 4 * (size_t)k * k;
   double* O = ws_alloc<double>(ctx, 4 * n_ * n_ + n_ + 8);
   double* uo = O + n_ * n_;
   double* Vo = uo + n_ * n_;
   double* so = Vo + n_ * n_;
   double* fdev = so + n_;
-  int* info = ws_alloc<int>(ctx, 4);
+  int* info = ws_alloc<int>(ctx, 64);
   if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (ALS)");
-  double* Ns = be.Ns;
-  const long long per = (long long)Dk * D;
-  int total_sweeps = 0;
-  for (int b = 0; b < nl; ++b) {
-    TN_TRY(be.compute(ctx, b, P, Q));
-    hipLaunchKernelGGL(als_traces_kernel, dim3(1), dim3(256), 0, ctx->stream, Ns, n, tb, tconst);
-    double* Pb = P + b * per;
-    double* Qb = Q + b * per;
-    hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb, tconst,
-                       Pb, Qb, fdev);
-    TN_HIP(ctx, hipGetLastError());
-    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 1, tconst, sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    double f = ctx->host_scratch[0];
-    const double f0 = ctx->host_scratch[1];
-    if (!std::isfinite(f) || !std::isfinite(f0)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite bond environment");
-    for (int sw = 1; sw <= max_sweeps; ++sw) {
-      ++total_sweeps;
-      for (int mode = 0; mode < 2; ++mode) {
-        hipLaunchKernelGGL(als_normal_kernel, dim3(nblk((long long)k * k + k)), dim3(256), 0,
-                           ctx->stream, mode, Ns, tb, mode == 0 ? Qb : Pb, n, D, R, S);
-        TN_HIP(ctx, hipGetLastError());
-        hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(1024), (size_t)k * (k + 1) * sizeof(double),
-                           ctx->stream, k, R, 1e-14, S, mode == 0 ? Pb : Qb, info + mode);
-        TN_HIP(ctx, hipGetLastError());
-      }
-      // balance the pair through the SVD of P Q
-      hipLaunchKernelGGL(pq_kernel, dim3(nblk((long long)n * n)), dim3(256), 0, ctx->stream, n, D,
-                         Pb, Qb, O);
-      TN_TRY(jacobi_svd(ctx, 1, n, n, O, n, (long long)n * n, uo, n, (long long)n * n, so, n, Vo,
-                        n, (long long)n * n));
-      hipLaunchKernelGGL(als_balance_kernel, dim3(nblk(per)), dim3(256), 0, ctx->stream, n, D, uo,
-                         so, Vo, Pb, Qb);
-      hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb,
-                         tconst, Pb, Qb, fdev);
-      TN_HIP(ctx, hipGetLastError());
-      TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double), hipMemcpyDeviceToHost,
-                                 ctx->stream));
-      TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 2, info, 2 * sizeof(int),
-                                 hipMemcpyDeviceToHost, ctx->stream));
-      TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      const int* hinfo = reinterpret_cast<const int*>(ctx->host_scratch + 2);
-      if (hinfo[0] || hinfo[1])
-        TN_FAIL(ctx, TN_ENUMERIC, "ALS normal matrix of link %d singular (pivot %d/%d)", b,
-                hinfo[0], hinfo[1]);
-      const double fn = ctx->host_scratch[0];
-      if (!std::isfinite(fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite ALS cost");
-      const bool done = fabs(fn - f) < tol * fabs(f0);
-      f = fn;
-      if (done) break;
-    }
-    if (cost) cost[b] = f;
+  const size_t per = (size_t)Dk * D;
+  for (int s = 0; s < 4; ++s) {
+    TN_HIP(ctx, hipMemcpyAsync(B.Pz + s * per, P + B.slot_link[s] * per, per * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(B.Qz + s * per, Q + B.slot_link[s] * per, per * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
   }
+  // <Psi_g|Psi_g>: the closed block with every internal link untruncated; the
+  // normalised boundary leaves the common sign of all networks free, take
+  // the one that makes it positive
+  TN_TRY(B.corners(ctx, L_FULL, L_FULL, -1));
+  TN_TRY(B.ring(ctx, -1, 1.0, tdev));
+  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, tdev, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const double traw = ctx->host_scratch[0];
+  if (!std::isfinite(traw) || traw == 0.0)
+    TN_FAIL(ctx, TN_ENUMERIC, "block norm %g is not a usable scale", traw);
+  const double sg = traw > 0 ? 1.0 : -1.0, tn = fabs(traw);
+  ctx->host_scratch[0] = tn;
+  TN_HIP(ctx, hipMemcpyAsync(tdev, ctx->host_scratch, sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+  int total_sweeps = 0, pass = 0;
+  double f = 0.0, f_prev = 0.0;
+  bool have_prev = false;
+  for (pass = 1; pass <= max_passes; ++pass) {
+    for (int s = 0; s < 4; ++s) {
+      TN_TRY(B.envs(ctx, s, sg, Nraw, Ns, M));
+      hipLaunchKernelGGL(als_traces_kernel, dim3(1), dim3(256), 0, ctx->stream, M, n, tb, tjunk);
+      double* Pb = B.Pz + s * per;
+      double* Qb = B.Qz + s * per;
+      if (!have_prev) {
+        hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb,
+                           tdev, Pb, Qb, fdev);
+        TN_HIP(ctx, hipGetLastError());
+        TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        f_prev = f = ctx->host_scratch[0];
+        have_prev = true;
+        if (!std::isfinite(f)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite bond environment");
+      }
+      double fs = f;
+      for (int sw = 1; sw <= max_sweeps; ++sw) {
+        ++total_sweeps;
+        for (int mode = 0; mode < 2; ++mode) {
+          hipLaunchKernelGGL(als_normal_kernel, dim3(nblk((long long)k * k + k)), dim3(256), 0,
+                             ctx->stream, mode, Ns, tb, mode == 0 ? Qb : Pb, n, D, R, S);
+          TN_HIP(ctx, hipGetLastError());
+          hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(1024),
+                             (size_t)k * (k + 1) * sizeof(double), ctx->stream, k, R, 1e-14, S,
+                             mode == 0 ? Pb : Qb, info + mode);
+          TN_HIP(ctx, hipGetLastError());
+        }
+        // balance the pair through the SVD of P Q (P Q, hence f, unchanged)
+        hipLaunchKernelGGL(pq_kernel, dim3(nblk((long long)n * n)), dim3(256), 0, ctx->stream, n,
+                           D, Pb, Qb, O);
+        TN_TRY(jacobi_svd(ctx, 1, n, n, O, n, (long long)n * n, uo, n, (long long)n * n, so, n,
+                          Vo, n, (long long)n * n));
+        hipLaunchKernelGGL(als_balance_kernel, dim3(nblk((long long)per)), dim3(256), 0,
+                           ctx->stream, n, D, uo, so, Vo, Pb, Qb);
+        hipLaunchKernelGGL(als_cost_kernel, dim3(1), dim3(256), 0, ctx->stream, n, D, Ns, tb,
+                           tdev, Pb, Qb, fdev);
+        TN_HIP(ctx, hipGetLastError());
+        TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fdev, sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 2, info, 2 * sizeof(int),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const int* hinfo = reinterpret_cast<const int*>(ctx->host_scratch + 2);
+        if (hinfo[0] || hinfo[1])
+          TN_FAIL(ctx, TN_ENUMERIC, "ALS normal matrix of slot %d singular (pivot %d/%d)", s,
+                  hinfo[0], hinfo[1]);
+        const double fn = ctx->host_scratch[0];
+        if (!std::isfinite(fn)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite ALS cost");
+        const bool done = fabs(fn - fs) < tol * tn;
+        fs = fn;
+        if (done) break;
+      }
+      f = fs;
+    }
+    const bool done = fabs(f - f_prev) < tol * tn;
+    f_prev = f;
+    if (done) break;
+  }
+  if (pass > max_passes) pass = max_passes;
+  // the links' truncations: the mean over the slots that hold each link
+  hipLaunchKernelGGL(slot_mean_kernel, dim3(nblk((long long)L.nl * per)), dim3(256), 0,
+                     ctx->stream, L.nl, (int)per, B.slot_link[0], B.slot_link[1],
+                     B.slot_link[2], B.slot_link[3], B.Pz, B.Qz, P, Q);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (cost) {
+    cost[0] = f;
+    cost[1] = tn;
+  }
+  if (passes) *passes = pass;
   if (sweeps) *sweeps = total_sweeps;
   return TN_OK;
 }

@@ -17,18 +17,20 @@ import time
 
 
 def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm=0,
-                ctm_tol=1e-10, ctm_max=100, als_tol=1e-12, als_max=50, canon_tol=1e-14,
-                canon_max=1000, gauge_tol=1e-12, gauge_max=1000, min_fidelity=None,
-                callback=None):
+                ctm_tol=1e-10, ctm_max=100, als_tol=1e-12, als_passes=50, als_sweeps=1,
+                canon_tol=1e-14, canon_max=1000, gauge_tol=1e-12, gauge_max=1000,
+                min_fidelity=None, force_recycle=False, callback=None):
     """Evolve the iPEPS ``sites`` (device [nsite][d][D]^4) for ``nsteps``
     steps of size dt.  C, T (device) are the start environment and are
-    updated in place.  Returns (sites, log) with log entries
-    (step, energy_per_site, seconds since start) at environment steps; the
-    environment is recomputed every ``n_re`` steps after ``n_warm`` plain
-    steps.  With ``min_fidelity``, an environment step whose gauge fix ends
-    below that fidelity (the new state is too far from the previous one for
-    its gate to stand in for the environment) is not recycled: the
-    evolution continues with the plain step."""
+    updated in place.  Returns (sites, log) with log entries (step,
+    energy_per_site, seconds since start, recycled, fidelity) at
+    environment steps; the environment is recomputed every ``n_re`` steps
+    after ``n_warm`` plain steps.  A recycling step first brings the state
+    A_0 to canonical form (Sec. VI C assumes it).  With ``min_fidelity``, an
+    environment step whose gauge fix ends below that fidelity (the new state
+    is too far from the previous one for its gate to stand in for the
+    environment) is not recycled: the evolution continues with the plain
+    step.  ``force_recycle`` takes the recycling branch for n_re = 1 too."""
     import torch
     D = sites.shape[2]
     kappa = 2
@@ -36,28 +38,34 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
     t0 = time.perf_counter()
     step = 0
     while step < nsteps:
-        warm = step < n_warm
+        recycle = step >= n_warm and (n_re > 1 or force_recycle)
+        if recycle:
+            sites, _, _, _, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, sites, tol=canon_tol,
+                                                          max_iter=canon_max)
         Th = ctx.ipeps_gate(sites, J, h, dt)
-        _, _, P, Q, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
-                                                   max_iter=canon_max, a_out=False)
-        pre = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
+        _, _, Psu, Qsu, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
+                                                       max_iter=canon_max, a_out=False)
+        pre = ctx.ipeps_truncate(Lx, Ly, cell, Th, Psu, Qsu)
         ctx.ctmrg_iterate(Lx, Ly, pre, cell, C, T, ctm_max, ctm_tol)
         E = ctx.ipeps_energy(Lx, Ly, pre, cell, C, T, J, h)
-        ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, P, Q, als_max, als_tol)
+        P, Q = Psu.clone(), Qsu.clone()
+        ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, Psu, Qsu, P, Q, als_passes, als_sweeps,
+                              als_tol)
         new = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
+        F = None
+        if recycle:
+            a1, _, Pc, Qc, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, new, tol=canon_tol,
+                                                          max_iter=canon_max)
+            U = ctx.fu_gauge_start(P, Q, Pc, Qc, kappa)
+            F, _, _ = ctx.gauge_fix(Lx, Ly, cell, sites, a1, U, tol=gauge_tol,
+                                    max_iter=gauge_max)
+            if min_fidelity is not None and F < min_fidelity:
+                recycle = False
         torch.cuda.current_stream().synchronize()
-        log.append((step + 1, E, time.perf_counter() - t0))
+        log.append((step + 1, E, time.perf_counter() - t0, recycle, F))
         if callback:
-            callback(step, E)
-        if warm or n_re == 1:
-            sites = new
-            step += 1
-            continue
-        a1, _, Pc, Qc, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, new, tol=canon_tol,
-                                                      max_iter=canon_max)
-        U = ctx.fu_gauge_start(P, Q, Pc, Qc, kappa)
-        F, _, _ = ctx.gauge_fix(Lx, Ly, cell, sites, a1, U, tol=gauge_tol, max_iter=gauge_max)
-        if min_fidelity is not None and F < min_fidelity:
+            callback(step, E, recycle, F)
+        if not recycle:
             sites = new
             step += 1
             continue

@@ -87,6 +87,89 @@ def test_single_left_move_parity(ctx, cellspec, D, chi, seed):
     np.testing.assert_allclose(host(Tg), Tr, atol=1e-10)
 
 
+@pytest.fixture(scope="module")
+def headline():
+    """The measured workload: checkerboard, D = 6, chi = 72 (n = 2592), the
+    bench's seeded sites and positive seeded boundary, and that boundary
+    after one oracle iteration (8 moves)."""
+    D, chi = 6, 72
+    Lx, Ly, cell, sites, C0, T0 = _setup(tninputs.CHECKERBOARD, D, chi, seed=0)
+    ocell = octm.Cell(Lx, Ly, cell)
+    C, T = octm.iteration(ocell, sites, C0, T0, chi)
+    return Lx, Ly, cell, ocell, sites, C0, T0, C, T, chi
+
+
+def test_headline_move_parity(ctx, headline):
+    """The bench's path at its own size: one left move from the oracle's
+    warmed boundary, with the projector SVDs warm-started from the GPU's own
+    iteration from the seeded start (as in the bench), then cold.  n = 2592
+    takes the subspace projector SVD (split-K products, the Rayleigh-Ritz SVD
+    on the side stream, plain steps).  The kept singular values of this
+    boundary lie within 1e-6 s_1 of each other, so the comparison is gauge
+    invariant: normalised corner spectra and reduced density matrices.  The
+    kept subspace is fixed by the gap at the cut only to the rounding level
+    n u s_1 / (s_chi - s_chi+1) in any FP64 SVD (LAPACK's included), and a
+    direction of the cut enters the new boundary with weight s_chi / s_1: the
+    bound is ten times that product, or 1e-10 if larger."""
+    Lx, Ly, cell, ocell, sites, C0, T0, C, T, chi = headline
+    n = chi * sites[0].shape[1] ** 2
+    sd = dev(np.stack(sites))
+    ctx.clear_cache()
+    Cg, Tg = dev(C0), dev(T0)
+    ctx.ctmrg_moves(Lx, Ly, sd, cell, Cg, Tg, 4 * Lx, 0)
+    Cr, Tr, spectra = octm.left_move(ocell, sites, C, T, 0, chi)
+    assert min(s[chi - 1] / s[chi] for s in spectra) > 1 + 1e-4
+    cond = max(n * 1.11e-16 * s[0] / (s[chi - 1] - s[chi]) * s[chi - 1] / s[0] for s in spectra)
+    tol = max(1e-10, 10 * cond)
+    sr = octm.corner_spectra(Cr)
+    r1 = opeps.rdm_one(Cr, Tr, 0, sites[cell[0]])
+    rh = opeps.rdm_two_h(ocell, sites, Cr, Tr, 0, 0)
+    for warm in (True, False):
+        if not warm:
+            ctx.clear_cache()
+        Cg, Tg = dev(C), dev(T)
+        ctx.prof_enable(True)
+        ctx.ctmrg_moves(Lx, Ly, sd, cell, Cg, Tg, 1, 0)
+        prof = ctx.prof_read()
+        ctx.prof_enable(False)
+        assert prof["svd_explicit"] == 0
+        r1g, rhg, _ = ctx.ipeps_rdms(Lx, Ly, sd, cell, Cg, Tg)
+        errs = (np.abs(octm.corner_spectra(host(Cg)) - sr).max(),
+                np.abs(host(r1g)[0] - r1).max(), np.abs(host(rhg)[0] - rh).max())
+        print(f"headline move (warm={warm}): spectra {errs[0]:.2e} rho1 {errs[1]:.2e} "
+              f"rho_h {errs[2]:.2e}; bound {tol:.2e}; subspace iterations {prof['svd_iters']}, "
+              f"stopped at the rounding floor {prof['svd_unconverged']}")
+        assert max(errs) < tol, errs
+
+
+def test_eight_row_cell_move_parity(ctx):
+    """A left move of a 1 x 8 cell: eight row cuts batched into one projector
+    SVD on the subspace path (n = chi D^2 = 288), whose Cholesky status for
+    all row cuts is read back at every Rayleigh-Ritz step.  Gauge-invariant
+    comparison (the kept values lie within 1e-7 s_1 of each other)."""
+    cell = [0, 1, 0, 1, 0, 1, 0, 1]
+    D, chi = 4, 18
+    sites = tninputs.ipeps_sites(0, 2, D)
+    C, T = tninputs.ctm_env(1, 8, chi, D, positive=True)
+    ocell = octm.Cell(1, 8, cell)
+    Cr, Tr, spectra = octm.left_move(ocell, sites, C, T, 0, chi)
+    # a gap at the cut, and kept values far above the rounding floor of the
+    # projector problem (a kept value near 1e-14 s_1 is noise on both sides)
+    assert len(spectra) == 8 and min(s[chi - 1] / s[chi] for s in spectra) > 1 + 1e-2
+    assert min(s[chi - 1] / s[0] for s in spectra) > 1e-9
+    Cg, Tg = dev(C), dev(T)
+    ctx.prof_enable(True)
+    ctx.ctmrg_moves(1, 8, dev(np.stack(sites)), cell, Cg, Tg, 1, 0)
+    prof = ctx.prof_read()
+    ctx.prof_enable(False)
+    assert prof["svd_explicit"] == 0
+    np.testing.assert_allclose(octm.corner_spectra(host(Cg)), octm.corner_spectra(Cr), atol=1e-10)
+    r1g, _, _ = ctx.ipeps_rdms(1, 8, dev(np.stack(sites)), cell, Cg, Tg)
+    for p in (0, 3, 7):
+        np.testing.assert_allclose(host(r1g)[p], opeps.rdm_one(Cr, Tr, p, sites[cell[p]]),
+                                   atol=1e-10)
+
+
 @pytest.mark.parametrize("cellspec", [tninputs.CHECKERBOARD, tninputs.SINGLE_SITE])
 def test_one_iteration_parity_all_directions(ctx, cellspec):
     D, chi = 2, 8

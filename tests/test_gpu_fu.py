@@ -130,36 +130,116 @@ def _fu_state(spec, D, chi, converged, seed=0):
                                              (tninputs.CHECKERBOARD, 3, 8, True),
                                              (tninputs.SINGLE_SITE, 2, 7, True)])
 def test_bond_environment_parity(ctx, spec, D, chi, conv):
+    """Both environments of every slot of the truncation block (Sec. VI B),
+    entry by entry, with the internal links truncated by a zeta that differs
+    from the pre-truncation on the environment legs."""
     Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(spec, D, chi, conv)
-    args = (dev(np.stack(th)), dev(C), dev(T), dev(np.stack(P)), dev(np.stack(Q)))
-    for b in range(len(P)):
-        ref = ofu.bond_environment(oc, th, P, Q, C, T, b)
-        got = host(ctx.bond_environment(Lx, Ly, cell, *args, b))
-        assert rel(got, ref) < 1e-11, b
+    rng = np.random.default_rng(D * 100 + chi)
+    Pz = [p + 0.1 * rng.standard_normal(p.shape) for p in P]
+    Qz = [q + 0.1 * rng.standard_normal(q.shape) for q in Q]
+    slot_link = ofu.block_slot_links(oc)
+    args = (dev(np.stack(th)), dev(C), dev(T), dev(np.stack(P)), dev(np.stack(Q)),
+            dev(np.stack(Pz)), dev(np.stack(Qz)))
+    for k in range(4):
+        N, M = ofu.bond_environment(oc, th, P, Q, [Pz[b] for b in slot_link],
+                                    [Qz[b] for b in slot_link], C, T, k)
+        gN, gM = ctx.bond_environment(Lx, Ly, cell, *args, k)
+        assert rel(host(gN), N) < 1e-11, k
+        assert rel(host(gM), M) < 1e-11, k
+
+
+def _truncate_problem(spec, D, chi, seed=0):
+    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(spec, D, chi, True, seed)
+    return Lx, Ly, cell, oc, th, P, Q, C, T
 
 
 @pytest.mark.parametrize("spec,D,chi", [(tninputs.CHECKERBOARD, 2, 6),
                                         (tninputs.CHECKERBOARD, 3, 8),
                                         (tninputs.SINGLE_SITE, 3, 9)])
 def test_bond_env_truncate_parity(ctx, spec, D, chi):
-    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(spec, D, chi, True)
-    Pr, Qr, costs = list(P), list(Q), []
+    """A fixed number of cycles (the same arithmetic on both sides): the
+    block cost, its scale and the truncations; then the converged call."""
+    Lx, Ly, cell, oc, th, P, Q, C, T = _truncate_problem(spec, D, chi)
+    for passes, tol in ((3, 0.0), (200, 1e-12)):
+        Pr, Qr, fr, pr, swr, _ = ofu.fu_truncate(oc, th, P, Q, C, T, tol, passes, 1)
+        tn = abs(ofu.block_norm(oc, th, P, Q, C, T))
+        gP, gQ = dev(np.stack(P)), dev(np.stack(Q))
+        f, t, gp, gsw = ctx.bond_env_truncate(Lx, Ly, cell, dev(np.stack(th)), dev(C), dev(T),
+                                              dev(np.stack(P)), dev(np.stack(Q)), gP, gQ,
+                                              passes, 1, tol)
+        assert abs(t - tn) < 1e-12 * tn
+        # f = T - 2c + q cancels down from T: its rounding is relative to T
+        assert abs(f - fr) < 1e-11 * tn, (passes, f, fr)
+        if tol == 0.0:
+            assert gp == pr == passes and gsw == swr
+            for b in range(len(P)):
+                assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-9, b
+            assert rel(host(gP), np.stack(Pr)) < 1e-8
+            assert rel(host(gQ), np.stack(Qr)) < 1e-8
+        else:
+            assert abs(gp - pr) <= 1
+
+
+@pytest.fixture(scope="module")
+def c2_state():
+    """The full-update problem at the shape of the D = 4, chi = 32
+    configuration: a gated seeded state, its pre-truncation and the oracle's
+    environment of the pre-truncated state after 10 iterations (delta ~1e-5)
+    from the positive seeded boundary."""
+    Lx, Ly, cell, oc, th, P, Q, C, T = _fu_state(tninputs.CHECKERBOARD, 4, 32, False)
+    links, _ = opeps.cell_links(oc)
+    C, T, _, _ = octm.ctmrg(oc, opeps.truncate(th, links, P, Q), C, T, 32, 10, 0.0)
+    return Lx, Ly, cell, oc, th, P, Q, C, T
+
+
+def test_full_update_chain_d4_chi32(ctx, c2_state):
+    """The full-update calls at the D = 4, chi = 32 shape: the pre-truncation
+    (canonical form of Theta), two slots' environments, two cycles of the
+    truncation, and the gauge fix of the truncated state's canonical form
+    against a planted gauge."""
+    Lx, Ly, cell, oc, th, P, Q, C, T = c2_state
+    D = 4
+    # pre-truncation
+    Thg = dev(np.stack(th))
+    _, _, gPs, gQs, _, rc = ctx.ipeps_canonicalize(Lx, Ly, cell, Thg, D_keep=D, tol=1e-13,
+                                                   a_out=False)
+    assert rc == 0
+    Pt, Qt = ofu.su_truncation(oc, th, D, tol=1e-13)
     for b in range(len(P)):
-        N = ofu.bond_environment(oc, th, Pr, Qr, C, T, b)
-        Pr[b], Qr[b], f, _, _ = ofu.als(N, Pr[b], Qr[b], 1e-12, 50)
-        costs.append(f)
+        assert rel(host(gPs)[b] @ host(gQs)[b], Pt[b] @ Qt[b]) < 1e-8
+    # environments of the top and bottom slots
+    for k in (0, 2):
+        N, M = ofu.bond_environment(oc, th, P, Q, P, Q, C, T, k)
+        gN, gM = ctx.bond_environment(Lx, Ly, cell, Thg, dev(C), dev(T), dev(np.stack(P)),
+                                      dev(np.stack(Q)), dev(np.stack(P)), dev(np.stack(Q)), k)
+        assert rel(host(gN), N) < 1e-11
+        assert rel(host(gM), M) < 1e-11
+    # two cycles of the truncation
+    Pr, Qr, fr, _, _, _ = ofu.fu_truncate(oc, th, P, Q, C, T, 0.0, 2, 1)
+    tn = abs(ofu.block_norm(oc, th, P, Q, C, T))
     gP, gQ = dev(np.stack(P)), dev(np.stack(Q))
-    gcost, sweeps = ctx.bond_env_truncate(Lx, Ly, cell, dev(np.stack(th)), dev(C), dev(T), gP, gQ,
-                                          50, 1e-12)
-    assert sweeps >= len(P)
+    f, t, _, _ = ctx.bond_env_truncate(Lx, Ly, cell, Thg, dev(C), dev(T), dev(np.stack(P)),
+                                       dev(np.stack(Q)), gP, gQ, 2, 1, 0.0)
+    assert abs(t - tn) < 1e-12 * tn
+    assert abs(f - fr) < 1e-11 * tn
     for b in range(len(P)):
-        # the truncation PQ is gauge free; the balanced pair is fixed by the sign rule
-        assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-7, b
-        # f = t - 2c + q cancels down from t = <I|N|I>: rounding is relative to t
-        t = ofu.cost(ofu.bond_environment(oc, th, Pr, Qr, C, T, b), Pr[b], Qr[b])[1]
-        assert abs(gcost[b] - costs[b]) <= 1e-6 * abs(costs[b]) + 1e-12 * abs(t), b
-    assert rel(host(gP), np.stack(Pr)) < 1e-6
-    assert rel(host(gQ), np.stack(Qr)) < 1e-6
+        assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-8, b
+    # gauge fix of the canonical truncated state against a planted gauge
+    links, leg_link = opeps.cell_links(oc)
+    a1, _, _, _, _ = opeps.canonicalize_a_form(oc, opeps.truncate(th, links, Pr, Qr), tol=1e-13)
+    rng = np.random.default_rng(8)
+    Ut = [_rot(rng, D, 0.3) for _ in links]
+    a_new = [opeps._apply_all(a, s, leg_link, Ut) for s, a in enumerate(a1)]
+    U0 = [np.eye(D) for _ in links]
+    Ur, Fr, _ = opeps.gauge_fix(oc, a1, a_new, tol=1e-13, U0=U0)
+    Ug = dev(np.stack(U0))
+    Fg, _, rc = ctx.gauge_fix(Lx, Ly, cell, dev(np.stack(a1)), dev(np.stack(a_new)), Ug,
+                              tol=1e-13)
+    assert rc == 0
+    assert abs(Fg - Fr) < 1e-12 and abs(Fr - 1) < 1e-10
+    assert rel(host(Ug), np.stack(Ur)) < 1e-8
+    # F is stationary at its maximum: the stop |dF| < 1e-13 fixes U to ~sqrt(1e-13)
+    assert rel(host(Ug), np.stack(Ut)) < 1e-6
 
 
 def _rot(rng, D, eps):
@@ -229,29 +309,42 @@ def test_full_update_rejects_bad_arguments(ctx):
     with pytest.raises(tn.TNError):
         ctx.ipeps_truncate(2, 2, [0, 1, 2, 0], th, P, Q)      # site index out of range
     with pytest.raises(tn.TNError):
-        ctx.bond_env_truncate(2, 2, [0, 1, 1, 0], th, C, T, P, Q, max_sweeps=0)
+        ctx.bond_env_truncate(2, 2, [0, 1, 1, 0], th, C, T, P, Q, P.clone(), Q.clone(),
+                              max_sweeps=0)
     with pytest.raises(tn.TNError):
-        ctx.bond_environment(2, 2, [0, 1, 1, 0], th, C, T, P, Q, 7)   # no link 7
+        ctx.bond_environment(2, 2, [0, 1, 1, 0], th, C, T, P, Q, P, Q, 7)   # no slot 7
+    with pytest.raises(tn.TNError):
+        # a cell with links outside the 2x2 block at the origin
+        th3 = dev(np.zeros((3, 2, 4, 4, 4, 4)))
+        P9, Q9 = dev(np.zeros((6, 4, 2))), dev(np.zeros((6, 2, 4)))
+        C9, T9 = dev(np.zeros((3, 4, 3, 3))), dev(np.zeros((3, 4, 3, 2, 2, 3)))
+        ctx.bond_env_truncate(3, 1, [0, 1, 2], th3, C9, T9, P9, Q9, P9.clone(), Q9.clone())
     with pytest.raises(tn.TNError):
         ctx.ipeps_gate(dev(np.zeros((1, 3, 2, 2, 2, 2))), 1.0, 3.0, 0.01)  # d must be 2
 
 
-@pytest.mark.parametrize("n_re,n_warm,nsteps", [(1, 0, 3), (3, 1, 7)])
-def test_full_update_driver_parity(ctx, n_re, n_warm, nsteps):
+@pytest.mark.parametrize("n_re,n_warm,nsteps,force", [(1, 0, 3, False), (3, 1, 7, False),
+                                                    (1, 0, 2, True)])
+def test_full_update_driver_parity(ctx, n_re, n_warm, nsteps, force):
     """The GPU driver (library calls only) follows the oracle's full update
-    with recycling step by step: energies at every environment step and the
-    final tensors."""
+    with recycling step by step: energies at every environment step, which
+    steps were recycled, the gauge-fix fidelities and the final tensors."""
     from paper_1411_0391_amd import driver
     Lx, Ly, cell, oc, nsite = _cell(tninputs.CHECKERBOARD)
     D, chi = 2, 8
     A = [a / np.linalg.norm(a) for a in tninputs.ipeps_sites(2, nsite, D)]
     C, T = tninputs.ctm_env(3, Lx * Ly, chi, D, positive=True)
+    fids = []
     ref_sites, ref_log = ofu.run_fu(oc, A, 1.0, 3.0, 0.01, D, chi, nsteps, n_re=n_re,
-                                    n_warm=n_warm, C=C, T=T)
+                                    n_warm=n_warm, C=C, T=T, force_recycle=force,
+                                    callback=lambda st, out: fids.append(out["fidelity"]))
     Cg, Tg = dev(C), dev(T)
     sites, log = driver.full_update(ctx, Lx, Ly, cell, dev(np.stack(A)), Cg, Tg, 1.0, 3.0, 0.01,
-                                    nsteps, n_re=n_re, n_warm=n_warm)
-    assert [s for s, _, _ in log] == [s for s, _ in ref_log]
-    for (_, e, _), (_, er) in zip(log, ref_log):
+                                    nsteps, n_re=n_re, n_warm=n_warm, force_recycle=force)
+    assert [s for s, *_ in log] == [s for s, *_ in ref_log]
+    assert [r for _, _, _, r, _ in log] == [r for _, _, r in ref_log]
+    for (_, e, _, _, F), (_, er, _), Fr in zip(log, ref_log, fids):
         assert abs(e - er) < 1e-9 * abs(er)
+        if Fr is not None:
+            assert abs(F - Fr) < 1e-9
     assert rel(host(sites), np.stack(ref_sites)) < 1e-6
