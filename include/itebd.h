@@ -156,6 +156,25 @@ int tm_fixed_point(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket, 
                    double* vl, double* vr, double* eta, double tol, int max_iter, int* iters,
                    int flags);
 
+/*
+ * tm_fixed_point_noalloc -- tm_fixed_point for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the same arguments, kernels and results, with
+ * the iterate pair, the eigenvalue and iteration outputs and the kernels'
+ * working set in a fixed device array of 4 MiB (2^19 doubles) that the
+ * library holds on each GPU until the process ends; the call itself
+ * allocates nothing.  It needs 2 chi^2 + 32 doubles, plus 2 (2 n_sites d
+ * + d + 2) chi^2 when that working set exceeds 150 KiB of LDS (the
+ * two-site, d = 2 cell: chi <= 40 in LDS, chi <= 142 in all); larger
+ * problems return TN_EINVAL.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (several contexts or streams) race and give undefined
+ * results.  The array keeps the last call's contents; nothing in it needs
+ * clearing, the kernels write what they read.
+ */
+int tm_fixed_point_noalloc(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                           const double* bra, double* vl, double* vr, double* eta, double tol,
+                           int max_iter, int* iters, int flags);
+
 /* Size in doubles of the env1d workspace of itebd_step for bond chi. */
 size_t tn_env1d_size(int chi, int d);
 

@@ -47,6 +47,9 @@ SIGNATURES = {
     "tn_clear_cache": (ctypes.c_int, [_vp]),
     "tn_cholesky_inv": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double, _vp,
                                        _vp, _c_int_p]),
+    "tm_fixed_point_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                              _vp, _vp, _vp, _c_double_p, ctypes.c_double,
+                                              ctypes.c_int, _c_int_p, ctypes.c_int]),
     "tn_env1d_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "tm_fixed_point": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                       _vp, _vp, _c_double_p, ctypes.c_double, ctypes.c_int,
@@ -337,6 +340,19 @@ class Context:
                                   ctypes.byref(eta), tol, max_iter, ctypes.byref(it), int(warm))
         self._check(rc, allow_nc=True)
         return vl, vr, eta.value, it.value, rc
+
+    def tm_fixed_point_noalloc(self, kets, bras, vl, vr, tol=1e-14, max_iter=200000,
+                               warm=False):
+        """tm_fixed_point on the library's fixed scratch: vl, vr (device,
+        [chi][chi]) are outputs, and with ``warm`` also the start."""
+        ns, chi, d, _ = kets.shape
+        eta = ctypes.c_double(0)
+        it = ctypes.c_int(0)
+        rc = lib().tm_fixed_point_noalloc(self._h, ns, chi, d, _ptr(kets), _ptr(bras), _ptr(vl),
+                                          _ptr(vr), ctypes.byref(eta), tol, max_iter,
+                                          ctypes.byref(it), int(warm))
+        self._check(rc, allow_nc=True)
+        return eta.value, it.value, rc
 
     def env1d(self, chi, d=2):
         import torch

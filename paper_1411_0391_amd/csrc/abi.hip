@@ -17,6 +17,10 @@ size_t env1d_doubles(int chi, int d);
 int tm_fixed_point_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
                         const double* bra, double* vl, double* vr, double* eta, double tol,
                         int max_iter, int* iters, int flags);
+int tm_fixed_point_noalloc_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                                const double* bra, double* vl, double* vr, double* eta,
+                                double tol, int max_iter, int* iters, int flags);
+int noalloc_scratch_init(int device);
 int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
                     double* env1d, double* lambda_out, double tol, double* trunc_err,
                     double* energy_or_null);
@@ -112,10 +116,12 @@ int tn_create(tn_ctx** out, void* hip_stream) {
   if (!out) return TN_EINVAL;
   tn_ctx* ctx = new tn_ctx();
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  // the fixed scratch of the allocation-free calls: its address on this
+  // device, taken once per device with the device current
   if (hipGetDevice(&ctx->device) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->host_scratch),
-                    TN_HOST_SCRATCH * sizeof(double)) !=
-          hipSuccess) {
+                    TN_HOST_SCRATCH * sizeof(double)) != hipSuccess ||
+      noalloc_scratch_init(ctx->device) != TN_OK) {
     (void)hipGetLastError();
     delete ctx;
     *out = nullptr;
@@ -203,6 +209,15 @@ int tm_fixed_point(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket, 
   ctx->err.clear();
   return tm_fixed_point_impl(ctx, n_sites, chi, d, ket, bra, vl, vr, eta, tol, max_iter, iters,
                              flags);
+}
+
+int tm_fixed_point_noalloc(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                           const double* bra, double* vl, double* vr, double* eta, double tol,
+                           int max_iter, int* iters, int flags) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return tm_fixed_point_noalloc_impl(ctx, n_sites, chi, d, ket, bra, vl, vr, eta, tol, max_iter,
+                                     iters, flags);
 }
 
 int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,

@@ -9,6 +9,7 @@
 // factors the fixed points (vl = Y^T Y, vr = X X^T) with the small Jacobi
 // SVD, takes the SVD of Y X and keeps chi singular pairs (Eq. (EqCanoPQ1)).
 #include <cmath>
+#include <mutex>
 #include <cstring>
 
 #include "bondnet.h"
@@ -250,14 +251,26 @@ __global__ void tfim1d_energy_kernel(const double* __restrict__ r0, const double
   *out = -J * 0.5 * (z0 / tr0 + z1 / tr1) - h * 0.5 * (x1 + x2) / tr0;
 }
 
+// Doubles of the power kernel's working set per side (two cell tensors, two
+// iterates and one intermediate), and whether it exceeds LDS.
+size_t tm_work_per_side(int nsite, int chi, int d) {
+  return 2ULL * nsite * chi * d * chi + 2ULL * chi * chi + (size_t)chi * d * chi;
+}
+bool tm_work_in_global(int nsite, int chi, int d) {
+  return tm_work_per_side(nsite, chi, d) * sizeof(double) > 150 * 1024;
+}
+
+// Both fixed points: gwork holds 2 tm_work_per_side doubles when the working
+// set exceeds LDS (null: taken from the arena).
 int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const double* bras,
             double* v2 /*[2][chi][chi]*/, double* eta_d, int* it_d, double tol, int max_iter,
-            int warm) {
-  const size_t per = 2ULL * nsite * chi * d * chi + 2ULL * chi * chi + (size_t)chi * d * chi;
-  double* gwork = nullptr;
+            int warm, double* gwork = nullptr) {
+  const size_t per = tm_work_per_side(nsite, chi, d);
   size_t dyn = per * sizeof(double);
-  if (dyn > 150 * 1024) {
-    gwork = ws_alloc<double>(ctx, 2 * per);
+  if (!tm_work_in_global(nsite, chi, d)) {
+    gwork = nullptr;
+  } else {
+    if (!gwork) gwork = ws_alloc<double>(ctx, 2 * per);
     if (!gwork) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (transfer matrix)");
     dyn = 0;
   }
@@ -312,6 +325,25 @@ size_t env1d_doubles(int chi, int d) {
   return 4 * n * n + 4 * (size_t)chi * n + 16;
 }
 
+// Copy the fixed points out and read the eigenvalue and iteration counts
+// back through the context's pinned buffer.
+static int tm_finish(tn_ctx* ctx, int chi, const double* v2, const double* ed, const int* itd,
+              double* vl, double* vr, double* eta, int* iters, int max_iter) {
+  const size_t cc = (size_t)chi * chi;
+  TN_HIP(ctx, hipMemcpyAsync(vl, v2, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(vr, v2 + cc, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  double* he = ctx->host_scratch;
+  int* hi = reinterpret_cast<int*>(ctx->host_scratch + 2);
+  TN_HIP(ctx, hipMemcpyAsync(he, ed, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (eta) *eta = he[0];
+  if (iters) *iters = hi[0] > hi[1] ? hi[0] : hi[1];
+  if (!std::isfinite(he[0]) || !std::isfinite(he[1]))
+    TN_FAIL(ctx, TN_ENUMERIC, "non-finite transfer-matrix eigenvalue");
+  return (hi[0] >= max_iter || hi[1] >= max_iter) ? TN_NOT_CONVERGED : TN_OK;
+}
+
 int tm_fixed_point_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
                         const double* bra, double* vl, double* vr, double* eta, double tol,
                         int max_iter, int* iters, int flags) {
@@ -330,18 +362,64 @@ int tm_fixed_point_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* 
     TN_HIP(ctx, hipMemcpyAsync(v2 + cc, vr, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
   }
   TN_TRY(tm_pair(ctx, n_sites, chi, d, ket, bra, v2, ed, itd, tol, max_iter, flags & 1));
-  TN_HIP(ctx, hipMemcpyAsync(vl, v2, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  TN_HIP(ctx, hipMemcpyAsync(vr, v2 + cc, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  double he[2];
-  int hi[2];
-  TN_HIP(ctx, hipMemcpyAsync(he, ed, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (eta) *eta = he[0];
-  if (iters) *iters = hi[0] > hi[1] ? hi[0] : hi[1];
-  if (!std::isfinite(he[0]) || !std::isfinite(he[1]))
-    TN_FAIL(ctx, TN_ENUMERIC, "non-finite transfer-matrix eigenvalue");
-  return (hi[0] >= max_iter || hi[1] >= max_iter) ? TN_NOT_CONVERGED : TN_OK;
+  return tm_finish(ctx, chi, v2, ed, itd, vl, vr, eta, iters, max_iter);
+}
+
+// ---------------------------------------------------------------------------
+// tm_fixed_point without allocation: the same kernels on a fixed scratch
+// array.  Each GPU holds its own copy of `scratch` at its own address, taken
+// once per device at context creation (the name is a host-side stand-in and
+// is never passed to a kernel).
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr size_t TM_NOALLOC_DOUBLES = size_t(1) << 19;  // 4 MiB
+__device__ __align__(256) double scratch[TM_NOALLOC_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+double* scratch_addr[MAX_DEVICES] = {nullptr};
+std::mutex scratch_mu;
+}  // namespace
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return TN_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_addr[device]) return TN_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return TN_EHIP;
+  }
+  scratch_addr[device] = static_cast<double*>(p);
+  return TN_OK;
+}
+
+int tm_fixed_point_noalloc_impl(tn_ctx* ctx, int n_sites, int chi, int d, const double* ket,
+                                const double* bra, double* vl, double* vr, double* eta,
+                                double tol, int max_iter, int* iters, int flags) {
+  if (n_sites < 1 || chi < 1 || d < 1 || !ket || !bra || !vl || !vr || max_iter < 1)
+    TN_FAIL(ctx, TN_EINVAL, "bad tm_fixed_point_noalloc arguments");
+  double* base = (ctx->device >= 0 && ctx->device < MAX_DEVICES) ? scratch_addr[ctx->device]
+                                                                 : nullptr;
+  if (!base) TN_FAIL(ctx, TN_EHIP, "no scratch address for device %d", ctx->device);
+  const size_t cc = (size_t)chi * chi;
+  // iterate pair, eigenvalues, iteration counts, then the working set
+  const size_t head = (2 * cc + 4 + 31) & ~size_t(31);
+  const size_t work = tm_work_in_global(n_sites, chi, d) ? 2 * tm_work_per_side(n_sites, chi, d)
+                                                         : 0;
+  if (head + work > TM_NOALLOC_DOUBLES)
+    TN_FAIL(ctx, TN_EINVAL,
+            "chi = %d, %d sites need %zu doubles of scratch, more than the fixed %zu", chi,
+            n_sites, head + work, TM_NOALLOC_DOUBLES);
+  double* v2 = base;
+  double* ed = base + 2 * cc;
+  int* itd = reinterpret_cast<int*>(base + 2 * cc + 2);
+  double* gwork = work ? base + head : nullptr;
+  if (flags & 1) {
+    TN_HIP(ctx, hipMemcpyAsync(v2, vl, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(v2 + cc, vr, cc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  TN_TRY(tm_pair(ctx, n_sites, chi, d, ket, bra, v2, ed, itd, tol, max_iter, flags & 1, gwork));
+  return tm_finish(ctx, chi, v2, ed, itd, vl, vr, eta, iters, max_iter);
 }
 
 namespace {
