@@ -475,15 +475,65 @@ def recycle_build(sites, g, chi):
     return new, (Lf, Rf), l1, err, F
 
 
+def renormalized_gate_matrix(Lf, Rf, g, X):
+    """The map A_X -> G A_X of site X (0: left site of bond 0, 1: the right
+    one) as a dense matrix on the flattened site tensor [chi][d][chi]:
+    G[(i s j), (a t b)] = sum_{k k'} Lf[(i), (a k)] g[k, k', s, t] Rf[(b k'), j],
+    with the factors of the bonds to the left and right of X."""
+    lf, rf = (Lf[1], Rf[0]) if X == 0 else (Lf[0], Rf[1])
+    chi, n = lf.shape
+    kappa = g.shape[0]
+    d = g.shape[2]
+    lf3 = lf.reshape(chi, n // kappa, kappa)          # [i][a][k]
+    rf3 = rf.reshape(n // kappa, kappa, chi)          # [b][k'][j]
+    G = np.einsum("iak,kKst,bKj->isjatb", lf3, g, rf3, optimize=True)
+    return G.reshape(chi * d * chi, chi * d * chi)
+
+
+def recycle_limit(Lf, Rf, g, sites):
+    """N_Re -> infinity (Sec. V C, the limit lines of Fig. 19): recycling
+    the environment without end takes each site to the dominant eigenvector
+    of its renormalized gate, the map A_X -> G A_X.  Per site, the
+    eigenvector of the eigenvalue of largest magnitude (dense eig), which
+    must be real; scaled to unit norm with a positive overlap with the
+    current site.  Returns (sites, eigenvalues, gap ratios |l2 / l1|)."""
+    out, lams, ratios = [], [], []
+    for X in (0, 1):
+        G = renormalized_gate_matrix(Lf, Rf, g, X)
+        w, v = np.linalg.eig(G)
+        order = np.argsort(-np.abs(w))
+        l1, l2 = w[order[0]], w[order[1]]
+        if abs(l1.imag) > 1e-12 * abs(l1) or abs(l1 - l2) < 1e-12 * abs(l1):
+            raise ValueError("the renormalized gate has no simple real dominant eigenvalue")
+        vec = np.real(v[:, order[0]]).reshape(sites[X].shape)
+        vec = vec / np.linalg.norm(vec)
+        if np.sum(vec * sites[X]) < 0:
+            vec = -vec
+        out.append(vec)
+        lams.append(float(l1.real))
+        ratios.append(float(abs(l2) / abs(l1)))
+    return out, lams, ratios
+
+
 def run_itebd(sites, J, h, dt, chi, nsteps, n_re=1, energy_every=None):
     """Imaginary-time iTEBD (Eq. (eq), power method on the iMPO) with the
     environment recomputed every ``n_re`` steps and the renormalized gate
-    applied in between.  ``n_re=1`` is the plain algorithm.  Returns the
-    final sites and a list of (step, energy) taken at environment steps."""
+    applied in between.  ``n_re=1`` is the plain algorithm; ``n_re=None`` is
+    the limit N_Re -> infinity (each environment step jumps to the dominant
+    eigenvector of its renormalized gate; ``nsteps`` then counts environment
+    steps).  Returns the final sites and a list of (step, energy) taken at
+    environment steps."""
     g = gates.impo(J, h, dt)
     sites = [s / np.linalg.norm(s) for s in sites]
     log = []
     fac = None
+    if n_re is None:
+        for step in range(nsteps):
+            sites, fac, _, _, _ = recycle_build(sites, g, chi)
+            sites, _, _ = recycle_limit(fac[0], fac[1], g, sites)
+            if energy_every and step % energy_every == 0:
+                log.append((step + 1, energy_per_site(sites, J, h)))
+        return sites, log
     for step in range(nsteps):
         if step % n_re == 0:
             if n_re == 1:

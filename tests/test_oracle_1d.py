@@ -201,3 +201,60 @@ def test_critical_chain_recycled_reaches_exact_energy():
     sites, _ = imps.run_itebd(sites, 1.0, 1.0, 0.01, 16, 1700, n_re=20)
     e = imps.energy_per_site(sites, 1.0, 1.0)
     assert abs(e + 4 / np.pi) < 2e-4
+
+
+# --- N_Re -> infinity (Sec. V C, the limit lines of Fig. 19) -------------------
+
+def _after_plain(chi, h, dt, nplain, seed=0):
+    ga, _, gb, _ = tninputs.imps_two_site(seed, chi)
+    sites = [ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)]
+    g = gates.impo(1.0, h, dt)
+    for _ in range(nplain):
+        sites, _, _, _, _ = imps.itebd_plain_step(sites, g, chi)
+    return sites, g
+
+
+def test_recycle_limit_is_the_limit_of_recycling():
+    # the dominant eigenvector of each site's renormalized gate is a fixed
+    # point of the map, and repeated recycling (A <- G A, normalised)
+    # converges to it
+    chi = 8
+    sites, g = _after_plain(chi, 1.05, 0.05, 50)
+    new, (Lf, Rf), _, _, _ = imps.recycle_build(sites, g, chi)
+    lim, lams, ratios = imps.recycle_limit(Lf, Rf, g, new)
+    assert max(ratios) < 1
+    for X in (0, 1):
+        G = imps.renormalized_gate_matrix(Lf, Rf, g, X)
+        r = G @ lim[X].ravel() - lams[X] * lim[X].ravel()
+        assert np.abs(r).max() < 1e-12 * lams[X]
+    cur = new
+    for _ in range(5000):
+        cur = imps.apply_renormalized(Lf, Rf, g, cur)
+    for X in (0, 1):
+        assert np.abs(cur[X] - lim[X]).max() < 1e-10
+
+
+def test_recycle_limit_keeps_the_plain_fixed_point():
+    # at a converged state of plain iTEBD the truncated gated state is the
+    # state itself up to gauge, so the recycling limit leaves its energy
+    chi, h = 4, 2.0
+    sites, g = _after_plain(chi, h, 0.05, 600)
+    e0 = imps.energy_per_site(sites, 1.0, h)
+    s1, _, _, _, _ = imps.itebd_plain_step(sites, g, chi)
+    assert abs(imps.energy_per_site(s1, 1.0, h) - e0) < 1e-13
+    new, (Lf, Rf), _, _, F = imps.recycle_build(sites, g, chi)
+    assert F > 1 - 1e-12
+    lim, _, _ = imps.recycle_limit(Lf, Rf, g, new)
+    assert abs(imps.energy_per_site(lim, 1.0, h) - e0) < 1e-10
+
+
+def test_recycle_limit_trajectory_reaches_the_plain_energy():
+    # the N_Re -> infinity scheme converges in a few environment steps to the
+    # state plain iTEBD reaches after hundreds of steps
+    chi, h, dt = 4, 2.0, 0.05
+    ref, _ = _after_plain(chi, h, dt, 600)
+    e_ref = imps.energy_per_site(ref, 1.0, h)
+    sites, _ = _after_plain(chi, h, dt, 3)
+    _, log = imps.run_itebd(sites, 1.0, h, dt, chi, 12, n_re=None, energy_every=1)
+    assert abs(log[-1][1] - e_ref) < 1e-9
+    assert abs(log[0][1] - e_ref) > 1e-2
