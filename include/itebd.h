@@ -104,7 +104,9 @@ const char* tn_version(void);
  *                 iterations.  The FP64 phase then runs at least
  *                 n_polish_fp64 iterations and until delta < tol (at most
  *                 max_iter + n_polish_fp64 iterations in all).  iters counts
- *                 both phases
+ *                 both phases.  The FP64 iterations also stop (TN_NOT_CONVERGED)
+ *                 when delta stalls: after 20 of them, the best delta of the
+ *                 last 10 is not below 0.9 times the best before them
  *   iters, delta  host out: iterations done and the last delta
  * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL (bad sizes or pointers),
  * TN_ENUMERIC (non-finite values or a failed factorisation), TN_EHIP.
@@ -419,14 +421,17 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
  *   A      device [d][D][D][D][D] (s, l, r, d, u); d must be 2
  *   C0, T0 device [4][chi][chi], [4][chi][D][D][chi] (the slots of the one
  *          position, as for ctmrg_iterate)
- *   precision  TN_FP64, or TN_FP32: the contractions of all but the last
- *          5 iterations, and their adjoints, in FP32 on MFMA; the last 5
- *          iterations (the FP64 polish of the precision form), the energy,
- *          the SVDs and their adjoints in FP64
+ *   precision  TN_FP64 (the only one accepted: with FP32 bulk contractions
+ *          E(A) after a fixed number of iterations from a random boundary is
+ *          ill-conditioned -- the rounding of the early iterations decides
+ *          which small singular values of the projector problems come close,
+ *          and the inverse gaps of the SVD adjoint amplify it -- so that
+ *          form's gradient has no bound to state)
  *   energy host out; dEdA device out, shape of A
- * TN_EINVAL for d != 2, n > 512, n_iter < 0, ckpt_every < 1, other
- * precisions or a negative broadening.  Device memory: about 2 GB per
- * checkpoint segment at D = 4, chi = 32, allocated for the call.
+ * TN_EINVAL for d != 2, n > 512, n_iter < 0, ckpt_every < 1, a precision
+ * other than TN_FP64 or a negative broadening.  Device memory: about 2 GB
+ * per checkpoint segment at D = 4, chi = 32, in 256 MiB chunks that the
+ * context keeps for later calls (tn_clear_cache releases them).
  */
 int energy_grad(tn_ctx* ctx, int D, int d, double J, double h, const double* A, int chi,
                 const double* C0, const double* T0, int n_iter, int ckpt_every, int precision,
@@ -477,7 +482,8 @@ int tn_cholesky_inv(tn_ctx* ctx, int batch, int k, const double* G, double shift
  * tn_clear_cache -- drop the state the context keeps between calls: the
  * start bases of the projector SVDs of ctmrg_iterate / ctmrg_moves (kept per
  * cell geometry so that a converging CTMRG restarts its subspace iterations
- * from the previous projectors).  Results never depend on this state beyond
+ * from the previous projectors), and the device memory energy_grad keeps for
+ * its tapes.  Results never depend on this state beyond
  * the SVD tolerance; clearing it makes a call independent of earlier calls.
  */
 int tn_clear_cache(tn_ctx* ctx);

@@ -541,6 +541,25 @@ int cholqr_passes(tn_ctx* ctx, int n, int k, int batch, double* X, double* Rout,
   return TN_OK;
 }
 
+// X = Src + c_b Z per problem b, with c_b = 1e-10 |Src_b|_F / sqrt(n k): the
+// random directions Z complete a block of lower rank than its column count
+// (one workgroup per problem)
+__global__ __launch_bounds__(256) void fill_deficient_kernel(int n, int k,
+                                                             const double* __restrict__ Src,
+                                                             const double* __restrict__ Z,
+                                                             double* __restrict__ X) {
+  __shared__ double red[4];
+  const long long nk = (long long)n * k, off = (long long)blockIdx.x * nk;
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < nk; i += 256) a += Src[off + i] * Src[off + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const double c = 1e-10 * sqrt((red[0] + red[1] + red[2] + red[3]) / (double)nk);
+  for (long long i = threadIdx.x; i < nk; i += 256) X[off + i] = Src[off + i] + c * Z[off + i];
+}
+
 // Robust orthonormalisation of [batch] blocks: optional column pre-scaling by
 // `scale` (the current Ritz values, which makes a Ritz-ordered block nearly
 // orthonormal), then Cholesky-QR; if any pass of any problem breaks down,
@@ -579,8 +598,32 @@ int orth_robust(tn_ctx* ctx, int n, int k, int batch, double* X, const double* s
     TN_HIP(ctx, hipMemcpyAsync(h.data(), info, ninfo * sizeof(int), hipMemcpyDeviceToHost,
                                ctx->stream));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    bad = false;
+    for (int v : h) bad = bad || v != 0;
+  }
+  if (bad) {
+    // the block has fewer independent directions than columns (a projector
+    // problem of low numerical rank, e.g. a nearly product state): complete
+    // it with random directions at 1e-10 of its scale, orthonormalise, and
+    // take R = Q^T X of the block itself, so that X = Q R still holds
+    double* Z = ws_alloc<double>(ctx, (size_t)tot);
+    if (!Z) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in orth_robust");
+    TN_TRY(fill_random(ctx, Z, tot, 0x5EEDF111ULL + (unsigned long long)tot));
+    hipLaunchKernelGGL(fill_deficient_kernel, dim3(batch), dim3(256), 0, ctx->stream, n, k, save,
+                       Z, X);
+    TN_HIP(ctx, hipGetLastError());
+    TN_HIP(ctx, hipMemsetAsync(info, 0, ninfo * sizeof(int), ctx->stream));
+    TN_TRY(cholqr_passes(ctx, n, k, batch, X, nullptr, tmp, info, 4, 2));
+    TN_HIP(ctx, hipMemcpyAsync(h.data(), info, ninfo * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int v : h)
       if (v) TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown in the projector SVD");
+    if (Rout) {
+      const long long nk = (long long)n * k, kk = (long long)k * k;
+      TN_TRY(gemm(ctx, k, k, n, X, k, true, save, k, false, Rout, k, 1.0, 0.0, batch, nk, nk,
+                  kk));
+    }
   }
   if (scale && Rout) {
     const long long tk = (long long)batch * k * k;
@@ -1234,12 +1277,13 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
   // last three is not below 0.7 times the best before them); then FP64
   // iterations, at least n_polish of them and until delta < tol.  At most
   // max_iter iterations in all (plus n_polish if the reduced phase used them
-  // up).  FP64 throughout: until delta < tol or max_iter.
+  // up).  FP64 throughout: until delta < tol or max_iter.  Either way the
+  // FP64 iterations also stop when they stall (below).
   const double sw = prec == P_F32 ? 1e-6 : (prec == P_BF16 ? 1e-3 : tol);
   const int polish = prec == P_F64 ? 0 : std::max(0, n_polish);
   int it = 0, done_it = 0, fp64_it = 0;
   double hd = INFINITY;
-  std::vector<double> hist;
+  std::vector<double> hist, hist64;
   const int cap = max_iter + polish;
   for (it = 1; it <= cap; ++it) {
     if (g.prec != P_F64) {
@@ -1268,10 +1312,27 @@ int ctmrg_run_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const d
     hd = ctx->host_scratch[0];
     hist.push_back(hd);
     ++done_it;
-    if (g.prec == P_F64) ++fp64_it;
+    if (g.prec == P_F64) {
+      ++fp64_it;
+      hist64.push_back(hd);
+    }
     if (!std::isfinite(hd)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite corner spectra");
     if (g.prec == P_F64 && hd < tol && fp64_it >= polish) break;
     if (prec == P_F64 && it >= max_iter) break;
+    // FP64 stall: after 20 FP64 iterations, the best delta of the last 10
+    // is not below 0.9 times the best before them (progress that slow, a
+    // rate above 0.9895 per iteration, would not reach tol within hundreds
+    // of iterations; a cut through a dense part of the projector spectrum
+    // keeps delta fluctuating without a trend)
+    const int nf = (int)hist64.size();
+    if (g.prec == P_F64 && fp64_it >= polish && nf >= 20) {
+      double recent = INFINITY, before = INFINITY;
+      for (int i = 0; i < nf; ++i) {
+        if (i >= nf - 10) recent = std::min(recent, hist64[i]);
+        else before = std::min(before, hist64[i]);
+      }
+      if (recent > 0.9 * before) break;
+    }
   }
   if (iters) *iters = done_it;
   if (delta) *delta = hd;

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -26,22 +27,24 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// device memory of one tape: 256-byte slices of large chunks, freed together
+// device memory of one tape: 256-byte slices of 256 MiB chunks that the
+// context keeps between calls (keyed by tag and index), so only the first
+// call that needs a chunk allocates it
 // ---------------------------------------------------------------------------
 struct Pool {
-  std::vector<void*> chunks;
-  size_t off = 0, cap = 0;
+  tn_ctx* ctx;
+  const char* tag;
+  size_t nchunk = 0, off = 0, cap = 0;
   char* cur = nullptr;
+  Pool(tn_ctx* c, const char* t) : ctx(c), tag(t) {}
   double* alloc(size_t count) {
     const size_t bytes = ((count * sizeof(double) + 255) / 256) * 256;
     if (off + bytes > cap) {
       const size_t sz = std::max<size_t>(bytes, (size_t)256 << 20);
       void* p = nullptr;
-      if (hipMalloc(&p, sz) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
-      chunks.push_back(p);
+      const std::string key = std::string("energy_grad:") + tag + ":" + std::to_string(nchunk);
+      if (keep_buffer(ctx, key, sz, &p, nullptr) != TN_OK || !p) return nullptr;
+      ++nchunk;
       cur = static_cast<char*>(p);
       off = 0;
       cap = sz;
@@ -49,9 +52,6 @@ struct Pool {
     double* r = reinterpret_cast<double*>(cur + off);
     off += bytes;
     return r;
-  }
-  ~Pool() {
-    for (void* p : chunks) (void)hipFree(p);
   }
 };
 
@@ -246,7 +246,7 @@ struct Tape {
   std::vector<Op> ops;
   std::vector<SvdSave> svd;
 
-  explicit Tape(tn_ctx* c, int p, double e) : ctx(c), prec(p), eps(e) {}
+  explicit Tape(tn_ctx* c, int p, double e) : ctx(c), prec(p), eps(e), pool(c, "tape") {}
 
   int tensor(long long n) {
     double* p = pool.alloc((size_t)n);
@@ -722,7 +722,13 @@ int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double
   if (d != 2) TN_FAIL(ctx, TN_EINVAL, "energy_grad is the TFIM energy: d must be 2");
   if (D < 1 || chi < 1) TN_FAIL(ctx, TN_EINVAL, "bad bond dimensions (D=%d chi=%d)", D, chi);
   if (n_iter < 0 || ckpt < 1) TN_FAIL(ctx, TN_EINVAL, "bad iteration count or checkpoint interval");
-  if (prec != P_F64 && prec != P_F32) TN_FAIL(ctx, TN_EINVAL, "energy_grad precision must be FP64 or FP32");
+  // FP32 bulk contractions make E(A) after a fixed number of iterations from
+  // a random boundary an ill-conditioned function: the rounding of the early
+  // iterations decides which small singular values of the projector problems
+  // come close, and the inverse gaps of the SVD adjoint amplify that, so its
+  // gradient has no bound to state
+  if (prec != P_F64)
+    TN_FAIL(ctx, TN_EINVAL, "energy_grad runs in FP64 only (precision %d given)", prec);
   if (!(eps >= 0.0)) TN_FAIL(ctx, TN_EINVAL, "broadening must be >= 0");
   Shape s;
   s.chi = chi;
@@ -737,7 +743,7 @@ int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double
   // polish iterations of the CTMRG precision form
   const int n_polish = std::min(n_iter, 5);
   auto it_prec = [&](int it) { return it >= n_iter - n_polish ? (int)P_F64 : prec; };
-  Pool keep;
+  Pool keep(ctx, "keep");
   double* ck = keep.alloc((size_t)nck * (ce + te));
   double* cur = keep.alloc((size_t)(ce + te));
   double* gC = keep.alloc((size_t)ce);

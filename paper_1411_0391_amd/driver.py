@@ -30,7 +30,11 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
     environment step whose gauge fix ends below that fidelity (the new state
     is too far from the previous one for its gate to stand in for the
     environment) is not recycled: the evolution continues with the plain
-    step.  ``force_recycle`` takes the recycling branch for n_re = 1 too."""
+    step.  ``force_recycle`` takes the recycling branch for n_re = 1 too.
+    ``callback(step, info)`` gets, per environment step, a dict with the
+    energy, whether it was recycled, the gauge-fix fidelity, the CTMRG
+    iterations and final delta, the block cost over the block norm and the
+    ALS cycles; a true return value ends the evolution there."""
     import torch
     D = sites.shape[2]
     kappa = 2
@@ -46,11 +50,11 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
         _, _, Psu, Qsu, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
                                                        max_iter=canon_max, a_out=False)
         pre = ctx.ipeps_truncate(Lx, Ly, cell, Th, Psu, Qsu)
-        ctx.ctmrg_iterate(Lx, Ly, pre, cell, C, T, ctm_max, ctm_tol)
+        _, ctm_iters, ctm_delta = ctx.ctmrg_iterate(Lx, Ly, pre, cell, C, T, ctm_max, ctm_tol)
         E = ctx.ipeps_energy(Lx, Ly, pre, cell, C, T, J, h)
         P, Q = Psu.clone(), Qsu.clone()
-        ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, Psu, Qsu, P, Q, als_passes, als_sweeps,
-                              als_tol)
+        f, norm, passes, sweeps = ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, Psu, Qsu, P, Q,
+                                                        als_passes, als_sweeps, als_tol)
         new = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
         F = None
         if recycle:
@@ -63,18 +67,25 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
                 recycle = False
         torch.cuda.current_stream().synchronize()
         log.append((step + 1, E, time.perf_counter() - t0, recycle, F))
+        stop = False
         if callback:
-            callback(step, E, recycle, F)
+            stop = bool(callback(step, dict(energy=E, recycled=recycle, fidelity=F,
+                                            ctm_iters=ctm_iters, ctm_delta=ctm_delta,
+                                            als_cost=f / norm, als_passes=passes,
+                                            seconds=log[-1][2])))
         if not recycle:
             sites = new
             step += 1
-            continue
-        Rf, Lf = ctx.fu_renormalized_gate(P, Q, Pc, Qc, U)
-        sites = ctx.ipeps_truncate(Lx, Ly, cell, Th, Rf, Lf)
-        step += 1
-        for _ in range(n_re - 1):
-            if step >= nsteps:
-                break
-            sites = ctx.ipeps_truncate(Lx, Ly, cell, ctx.ipeps_gate(sites, J, h, dt), Rf, Lf)
+        else:
+            Rf, Lf = ctx.fu_renormalized_gate(P, Q, Pc, Qc, U)
+            sites = ctx.ipeps_truncate(Lx, Ly, cell, Th, Rf, Lf)
             step += 1
+            for _ in range(n_re - 1):
+                if step >= nsteps or stop:
+                    break
+                sites = ctx.ipeps_truncate(Lx, Ly, cell, ctx.ipeps_gate(sites, J, h, dt), Rf,
+                                           Lf)
+                step += 1
+        if stop:
+            break
     return sites, log

@@ -142,6 +142,41 @@ def test_headline_move_parity(ctx, headline):
         assert max(errs) < tol, errs
 
 
+def test_low_rank_projector_move_parity(ctx):
+    """A nearly product state (seeded product tensors in D = 4 plus 1e-3 of
+    N(0,1)): the projector problem at n = chi D^2 = 512 has far fewer
+    independent directions than the subspace block (k = 48), so its
+    Cholesky-QR must complete the block with random directions.  One left
+    move against the oracle's.  Kept singular values reach down to ~2e-14
+    s_1, where their vectors are rounding noise in any FP64 SVD and S^-1/2
+    gives them unit weight in the new C and T: the tensors (and their
+    spectra) are not fixed by the problem, the observables, which weight
+    each direction by its singular value, are."""
+    D, chi = 4, 32
+    prod = tninputs.ipeps_sites(0, 2, 1)
+    noise = tninputs.ipeps_sites(1, 2, D)
+    sites = []
+    for a, z in zip(prod, noise):
+        t = 1e-3 * z
+        t[:, 0, 0, 0, 0] += a[:, 0, 0, 0, 0]
+        sites.append(t / np.linalg.norm(t))
+    Lx, Ly, cell = tninputs.CHECKERBOARD
+    cell = list(cell)
+    C, T = tninputs.ctm_env(1, 4, chi, D, positive=True)
+    ocell = octm.Cell(Lx, Ly, cell)
+    Cr, Tr, spectra = octm.left_move(ocell, sites, C, T, 0, chi)
+    assert max(s[1] / s[0] for s in spectra) < 1e-5      # one dominant direction
+    Cg, Tg = dev(C), dev(T)
+    sd = dev(np.stack(sites))
+    ctx.clear_cache()
+    ctx.ctmrg_moves(Lx, Ly, sd, cell, Cg, Tg, 1, 0)
+    assert np.isfinite(host(Cg)).all() and np.isfinite(host(Tg)).all()
+    r1g, rhg, _ = ctx.ipeps_rdms(Lx, Ly, sd, cell, Cg, Tg)
+    np.testing.assert_allclose(host(r1g)[0], opeps.rdm_one(Cr, Tr, 0, sites[cell[0]]), atol=1e-10)
+    np.testing.assert_allclose(host(rhg)[0], opeps.rdm_two_h(ocell, sites, Cr, Tr, 0, 0),
+                               atol=1e-10)
+
+
 def test_eight_row_cell_move_parity(ctx):
     """A left move of a 1 x 8 cell: eight row cuts batched into one projector
     SVD on the subspace path (n = chi D^2 = 288), whose Cholesky status for

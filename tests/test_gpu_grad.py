@@ -144,6 +144,9 @@ def test_bad_arguments(ctx):
         ctx.energy_grad(a, c, t, J, H, n_iter=-1)
     with pytest.raises(tn.TNError):
         ctx.energy_grad(a, c, t, J, H, n_iter=1, precision="bf16")
+    # the FP32-bulk function has no gradient bound to state: rejected
+    with pytest.raises(tn.TNError, match="FP64 only"):
+        ctx.energy_grad(a, c, t, J, H, n_iter=1, precision="fp32")
     A3 = tninputs.ipeps_sites(0, 1, 2, d=3)[0]
     with pytest.raises(tn.TNError):
         ctx.energy_grad(dev(A3), c, t, J, H, n_iter=1)
@@ -157,7 +160,7 @@ def test_bad_arguments(ctx):
 def test_single_site_d4_chi32(ctx):
     # the differentiation workload: D = 4, chi = 32 (n = 512), 20 iterations,
     # checkpoints every 5, against the oracle's energy and central differences
-    # along seeded unit directions; then the FP32-bulk form against FP64
+    # along seeded unit directions
     D, chi, n_iter = 4, 32, 20
     A, C0, T0 = case(D, chi, seed=21)
     t0 = time.perf_counter()
@@ -179,16 +182,3 @@ def test_single_site_d4_chi32(ctx):
     print("directional derivatives gpu", gd)
     print("oracle central differences ", fd)
     np.testing.assert_allclose(gd, fd, rtol=3e-3, atol=0)
-    t0 = time.perf_counter()
-    e32, g32 = ctx.energy_grad(dev(A), dev(C0[0]), dev(T0[0]), J, H, n_iter=n_iter,
-                               ckpt_every=5, precision="fp32")
-    rel = np.linalg.norm(host(g32) - g) / np.linalg.norm(g)
-    print(f"FP32-bulk ({time.perf_counter() - t0:.2f} s): energy error {abs(e32 - e):.2e}, "
-          f"gradient relative error {rel:.2e}")
-    # E after 20 iterations from a random boundary is not a fixed point, and the
-    # FP32 rounding of the first 15 iterations is amplified by the projectors'
-    # S^-1/2: measured relative energy errors range from 1e-8 to 1.3e-3 with the
-    # summation order of the products, and the gradient error is O(1) (stated,
-    # not bounded)
-    assert np.isfinite(e32) and np.isfinite(host(g32)).all()
-    assert abs(e32 - e) < 1e-2 * abs(e)
