@@ -1,0 +1,65 @@
+"""Pins of the classical-partition-function workload of the oracle (Sec. I:
+the power method on the row transfer matrix of the 2D Ising model, with the
+environment recycled)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import tninputs
+from oracle import classical as cl
+from tests import pins
+
+
+def test_row_transfer_matrix_is_the_transverse_field_gate():
+    # brute force on a ring of 4 columns: the row transfer matrix of the
+    # classical model and c^L times the dense second-order gate at
+    # dt J = beta, dt h = K* have the same spectrum
+    beta, L = 0.37, 4
+    confs = list(itertools.product([1, -1], repeat=L))
+    T = np.array([[np.exp(beta * sum(a[i] * b[i] for i in range(L))
+                          + 0.5 * beta * sum(a[i] * a[(i + 1) % L] + b[i] * b[(i + 1) % L]
+                                             for i in range(L)))
+                   for b in confs] for a in confs])
+    J, h, dt = cl.row_gate(beta)
+    bonds = [(i, (i + 1) % L) for i in range(L)]
+    G = pins.trotter_product(L, bonds, h, dt, J)
+    wt = np.sort(np.linalg.eigvals(T).real)
+    wg = np.sort(np.linalg.eigvals(G).real)
+    np.testing.assert_allclose(wt, np.exp(L * cl.log_scale(beta)) * wg, rtol=1e-12)
+
+
+def _start(chi, seed=0):
+    ga, _, gb, _ = tninputs.imps_two_site(seed, chi)
+    return [ga, gb]
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.6])
+def test_power_method_free_energy_is_onsagers(beta):
+    # away from the critical point chi = 8 holds the eigenvector to rounding
+    s = cl.power_method(_start(8), beta, 8, 60)
+    assert abs(cl.log_z(s, beta) - pins.onsager_free_energy(beta)) < 1e-12
+    assert abs(pins.onsager_free_energy(beta) - pins.onsager_free_energy_1d(beta)) < 1e-13
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.6])
+def test_power_method_sigma_x_closed_form(beta):
+    # <sx> in the middle of a vertical bond from Onsager's nearest-neighbour
+    # correlation e: ((1 + e) e^{-2 beta} + (1 - e) e^{2 beta}) / 2
+    s = cl.power_method(_start(8), beta, 8, 60)
+    e = pins.onsager_nn(beta)
+    ref = ((1 + e) * np.exp(-2 * beta) + (1 - e) * np.exp(2 * beta)) / 2
+    assert abs(cl.sigma_x(s) - ref) < 1e-12
+
+
+@pytest.mark.parametrize("n_re", [5, None])
+def test_recycled_power_method_reaches_the_plain_fixed_point(n_re):
+    # recycling the environment (and its limit N_Re -> infinity) changes the
+    # path, not the fixed point; 20 plain steps first (from the random start
+    # the renormalized gate has no simple real dominant eigenvalue, and the
+    # limit does not exist)
+    beta, chi = 0.4, 8
+    plain = cl.power_method(_start(chi, 1), beta, chi, 200)
+    rec = cl.power_method(_start(chi, 1), beta, chi, 180 if n_re else 8, n_re=n_re, n_warm=20)
+    assert abs(cl.log_z(rec, beta) - cl.log_z(plain, beta)) < 1e-11
+    assert abs(cl.log_z(plain, beta) - pins.onsager_free_energy(beta)) < 1e-6
