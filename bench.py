@@ -126,6 +126,147 @@ def run_chain(args):
     print(json.dumps(out), flush=True)
 
 
+def run_classical(args):
+    """The classical workload (Sec. I): the partition function of the 2D
+    Ising model at inverse temperature --cl-beta by the power method on the
+    row transfer matrix with a two-site iMPS, chi = --cl-chi, from seeded
+    N(0,1) tensors.  Plain (environment every step), recycled (N_Re = 20
+    after 20 plain steps) and the limit N_Re -> infinity (20 plain steps,
+    then an environment step and the dominant eigenvector of its
+    renormalized gate, repeated).  ln Z per site is measured every 20 steps
+    (every environment step of the limit run).  The plain run goes on until
+    ln Z changes by less than 1e-13 over 100 steps; its value is the
+    reference, and time-to-1e-10 is the wall time to the first measurement
+    within 1e-10 (relative) of it.  Onsager's exact value is reported
+    beside it (finite chi near the critical point leaves a small bias)."""
+    import numpy as np
+    import torch
+    import paper_1411_0391_amd as tn
+    import tninputs
+    beta, chi, n_re, warm = args.cl_beta, args.cl_chi, 20, 20
+    ga, _, gb, _ = tninputs.imps_two_site(0, chi)
+    A0 = np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)])
+    ctx = tn.Context()
+    out = {"metric": "time to ln Z within 1e-10, 2D classical Ising power method, recycled vs plain",
+           "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"2D classical Ising partition function, iMPS power method on the "
+                                  f"row transfer matrix, beta={beta}, chi={chi}, N_Re={n_re}, "
+                                  f"N_warm={warm}", "beta": beta, "chi": chi},
+           "data": "synthetic", "dtype": "f64", "n_gpus": 1}
+
+    def run(label, kind, ref=None, max_steps=20000):
+        A = torch.from_numpy(A0.copy()).to("cuda")
+        env = ctx.env1d(chi)
+        hist, t_hit, step, envs = [], None, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while step < max_steps:
+            if kind == "limit" and step >= warm:
+                ctx.ising2d_tm_step(A, beta, env, mode=tn.TN_RECYCLE_BUILD)
+                _, lz, rc = ctx.ising2d_tm_step(A, beta, env, mode=tn.TN_RECYCLE_LIMIT, lnz=True)
+                step += n_re
+                envs += 1
+            else:
+                meas = step % n_re == n_re - 1
+                if kind == "plain" or step < warm:
+                    mode = tn.TN_PLAIN
+                else:
+                    mode = tn.TN_RECYCLE_BUILD if (step - warm) % n_re == 0 else \
+                        tn.TN_RECYCLE_APPLY
+                _, lz, _ = ctx.ising2d_tm_step(A, beta, env, mode=mode, lnz=meas)
+                envs += mode != tn.TN_RECYCLE_APPLY
+                step += 1
+                if not meas:
+                    continue
+            t = time.perf_counter() - t0
+            hist.append((step, t, lz))
+            if ref is not None and t_hit is None and abs(lz - ref) <= 1e-10 * abs(ref):
+                t_hit = t
+            if ref is None and len(hist) > 5 and abs(lz - hist[-6][2]) < 1e-13 * abs(lz):
+                break
+            if ref is not None and t_hit is not None and step >= 200:
+                break
+        print(f"[bench] classical {label}: {step} steps, ln Z {hist[-1][2]:.15f}",
+              file=sys.stderr, flush=True)
+        return {"steps": step, "environment_steps": envs, "seconds": round(hist[-1][1], 4),
+                "ln_z": hist[-1][2], "time_to_1e-10": t_hit}
+
+    plain = run("plain", "plain")
+    ref = plain["ln_z"]
+    plain = run("plain", "plain", ref)
+    rec = run("recycled", "recycled", ref)
+    lim = run("limit", "limit", ref)
+    exact = None
+    try:
+        sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+        import pins
+        exact = pins.onsager_free_energy(beta)
+    except ImportError:
+        pass
+    out.update({"ln_z_ref": ref, "ln_z_onsager": exact, "plain": plain, "recycled": rec,
+                "limit": lim, "value": rec["time_to_1e-10"]})
+    if plain["time_to_1e-10"] and rec["time_to_1e-10"]:
+        out["speedup_recycled_over_plain"] = round(plain["time_to_1e-10"] /
+                                                   rec["time_to_1e-10"], 3)
+    if plain["time_to_1e-10"] and lim["time_to_1e-10"]:
+        out["speedup_limit_over_plain"] = round(plain["time_to_1e-10"] / lim["time_to_1e-10"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def run_mz_sweep(args):
+    """Simple update against full update (Sec. VI D, Fig. 26): the
+    magnetisation m_z = |<sz>| of the one-site iPEPS (the paper's cell),
+    D = 2, chi = 16, dt = 0.01, over a range of fields.  Per field: the
+    simple update for --mz-su-steps steps from the seeded near-product
+    state, then the full update with recycling (N_Re = 20 after 20 plain
+    steps) for --mz-fu-steps steps from the simple-update state; m_z and E
+    from the CTMRG environment converged to 1e-10 (chi = 16)."""
+    import numpy as np
+    import torch
+    import paper_1411_0391_amd as tn
+    from paper_1411_0391_amd import driver
+    import tninputs
+    D, chi, dt = 2, 16, 0.01
+    Lx, Ly, cell = tninputs.SINGLE_SITE
+    cell = list(cell)
+    fields = [float(x) for x in args.mz_fields.split(",")]
+    A0 = np.stack([a / np.linalg.norm(a) for a in tninputs.ipeps_near_product(0, 1, D)])
+    C0, T0 = tninputs.ctm_env(1, 1, chi, D, positive=True)
+    ctx = tn.Context()
+    sz = np.diag([1.0, -1.0])
+
+    def measure(sites, h):
+        C = torch.from_numpy(C0.copy()).to("cuda")
+        T = torch.from_numpy(T0.copy()).to("cuda")
+        _, it, delta = ctx.ctmrg_iterate(Lx, Ly, sites, cell, C, T, 200, 1e-10)
+        e = ctx.ipeps_energy(Lx, Ly, sites, cell, C, T, 1.0, h)
+        r1 = ctx.ipeps_rdms(Lx, Ly, sites, cell, C, T)[0].cpu().numpy()
+        return abs(float(np.trace(r1[0] @ sz))), e, delta
+
+    rows = []
+    t0 = time.perf_counter()
+    for h in fields:
+        su = driver.simple_update(ctx, Lx, Ly, cell, torch.from_numpy(A0.copy()).to("cuda"), 1.0,
+                                  h, dt, args.mz_su_steps)
+        m_su, e_su, d_su = measure(su, h)
+        C = torch.from_numpy(C0.copy()).to("cuda")
+        T = torch.from_numpy(T0.copy()).to("cuda")
+        fu, _ = driver.full_update(ctx, Lx, Ly, cell, su.clone(), C, T, 1.0, h, dt,
+                                   args.mz_fu_steps, n_re=20, n_warm=20, min_fidelity=1 - 1e-3)
+        m_fu, e_fu, d_fu = measure(fu, h)
+        rows.append({"h": h, "mz_su": m_su, "mz_fu": m_fu, "E_su": e_su, "E_fu": e_fu,
+                     "ctm_delta": max(d_su, d_fu)})
+        print(f"[bench] mz h={h}: SU m_z {m_su:.6f} E {e_su:.8f} | FU m_z {m_fu:.6f} "
+              f"E {e_fu:.8f} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    out = {"metric": "m_z(h), simple update vs full update (one-site iPEPS)", "unit": "m_z",
+           "config": {"workload": f"TFIM one-site iPEPS, D={D}, chi={chi}, dt={dt}, "
+                                  f"SU {args.mz_su_steps} steps, then FU (N_Re=20) "
+                                  f"{args.mz_fu_steps} steps", "D": D, "chi": chi},
+           "data": "synthetic", "dtype": "f64", "n_gpus": 1, "rows": rows,
+           "seconds": round(time.perf_counter() - t0, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def run_full_update(args):
     """The 2D full-update workload: checkerboard, D = 4, chi = 32, J = 1,
     h = 3.0, dt = 0.01, CTMRG tolerance 1e-10, from seeded N(0,1) sites and
@@ -148,17 +289,7 @@ def run_full_update(args):
         A0 = np.stack(tninputs.ipeps_sites(0, 2, D))
         start = "N(0,1) site tensors of bond D from seed 0"
     else:
-        # the seeded N(0,1) tensors of bond 1 (a random product state) with a
-        # 1e-2 part of N(0,1) bond-D tensors from seed 1: random D-bond
-        # tensors carry closed-loop correlations on their bonds that the
-        # evolution does not remove
-        prod, noise = tninputs.ipeps_sites(0, 2, 1), tninputs.ipeps_sites(1, 2, D)
-        A0 = []
-        for a, z in zip(prod, noise):
-            t = 1e-2 * z
-            t[:, 0, 0, 0, 0] += a[:, 0, 0, 0, 0]
-            A0.append(t)
-        A0 = np.stack(A0)
+        A0 = np.stack(tninputs.ipeps_near_product(0, 2, D))
         start = "seeded N(0,1) product state plus 1e-2 of N(0,1) bond-D tensors"
     C0, T0 = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
     ctx = tn.Context()
@@ -225,16 +356,31 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prep", type=int, default=6,
-                    help="untimed CTMRG iterations that prepare the input boundary")
+    ap.add_argument("--prep", type=int, default=None,
+                    help="untimed CTMRG iterations that prepare the input boundary "
+                         "(default: iterate until delta < --prep-delta)")
+    ap.add_argument("--prep-delta", type=float, default=1e-7,
+                    help="prepare the input boundary to this CTMRG delta (at most 100 "
+                         "iterations)")
     ap.add_argument("--D", type=int, default=6)
     ap.add_argument("--chi", type=int, default=72)
     ap.add_argument("--cpu-moves", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "fp32", "bf16"), default="fp64",
+                    help="bulk precision of the contractions (the factorisations stay FP64)")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--chain", action="store_true", help="run the 1D workload instead")
     ap.add_argument("--chain-steps", type=int, default=2000)
+    ap.add_argument("--mz", action="store_true",
+                    help="m_z(h) of the simple and the full update (one-site iPEPS)")
+    ap.add_argument("--mz-fields", default="2.5,2.8,2.9,3.0,3.05,3.1,3.2,3.3,3.5")
+    ap.add_argument("--mz-su-steps", type=int, default=1000)
+    ap.add_argument("--mz-fu-steps", type=int, default=600)
+    ap.add_argument("--classical", action="store_true",
+                    help="the classical 2D Ising partition function (power method, recycling)")
+    ap.add_argument("--cl-beta", type=float, default=0.42)
+    ap.add_argument("--cl-chi", type=int, default=16)
     ap.add_argument("--fu", action="store_true",
                     help="run the 2D full-update time-to-1e-6 workload instead")
     ap.add_argument("--fu-steps", type=int, default=1500,
@@ -261,6 +407,12 @@ def main():
     if args.fu:
         run_full_update(args)
         return
+    if args.classical:
+        run_classical(args)
+        return
+    if args.mz:
+        run_mz_sweep(args)
+        return
 
     import numpy as np
     import torch
@@ -279,20 +431,31 @@ def main():
     T = torch.from_numpy(T_h).to(dev)
     ctx = tn.Context()
     moves_per_step = 4 * Lx
-    print(f"[bench] D={D} chi={chi} n={chi * D * D} prep {args.prep} warmup {args.warmup} steps",
+    print(f"[bench] D={D} chi={chi} n={chi * D * D} warmup {args.warmup} steps {args.steps}",
           file=sys.stderr, flush=True)
-    for w in range(args.prep):
-        ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0)
-    print(f"[bench] input boundary prepared ({args.prep} iterations)", file=sys.stderr, flush=True)
+    if args.prep is not None:
+        for w in range(args.prep):
+            ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0)
+        prep = f"boundary after {args.prep} CTMRG iterations from a seeded random start"
+    else:
+        # a boundary at a fixed convergence level, so that the timed work (the
+        # subspace iterations per projector follow how much the boundary still
+        # moves) does not depend on how it was prepared
+        _, pit, pdelta = ctx.ctmrg_iterate(Lx, Ly, sites, cell, C, T, 100, args.prep_delta)
+        prep = (f"boundary converged to CTMRG delta {pdelta:.2e} (target {args.prep_delta:g}, "
+                f"{pit} iterations from a seeded random start)")
+    print(f"[bench] input: {prep}", file=sys.stderr, flush=True)
+    prec = args.precision
+    C_prep, T_prep = C.clone(), T.clone()
     for w in range(args.warmup):
-        ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0)
+        ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0, precision=prec)
         print(f"[bench] warmup step {w + 1} done", file=sys.stderr, flush=True)
     C_bench, T_bench = C.detach().cpu().numpy(), T.detach().cpu().numpy()
     ctx.prof_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0)
+        ctx.ctmrg_moves(Lx, Ly, sites, cell, C, T, moves_per_step, 0, precision=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.prof_read()
@@ -323,8 +486,7 @@ def main():
         "config": {"workload": f"TFIM iPEPS CTMRG iteration (8 moves), checkerboard, D={D}, "
                                f"chi={chi}, FP64", "D": D, "chi": chi, "cell": "2x2 checkerboard",
                    "moves_per_step": moves_per_step,
-                   "input": f"boundary after {args.prep} CTMRG iterations from a seeded "
-                            f"random start"},
+                   "input": prep},
         "roofline": {"bound": "mfma", "kernel": "tgemm_f64_kernel",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
@@ -337,6 +499,32 @@ def main():
         "svd_at_cap": prof["svd_unconverged"],
         "jacobi_sweeps": prof["jacobi_sweeps"],
     }
+    if prec != "fp64":
+        # the precision form's energy against the FP64 one: both converge from
+        # the prepared boundary to delta < 1e-10, the reduced form with its
+        # bulk phase first and at least 5 FP64 iterations after it
+        res = {}
+        for pr in ("fp64", prec):
+            Cq, Tq = C_prep.clone(), T_prep.clone()
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            _, it, de = ctx.ctmrg_iterate(Lx, Ly, sites, cell, Cq, Tq, 200, 1e-10, precision=pr,
+                                          n_polish=5)
+            torch.cuda.synchronize()
+            res[pr] = (ctx.ipeps_energy(Lx, Ly, sites, cell, Cq, Tq, 1.0, 3.0), it, de,
+                       time.perf_counter() - tq)
+        e64, ep = res["fp64"][0], res[prec][0]
+        out["precision_form"] = {
+            "bulk": prec, "energy_fp64": e64, "energy": ep,
+            "energy_rel_error": abs(ep - e64) / abs(e64),
+            "iterations_fp64": res["fp64"][1], "iterations": res[prec][1],
+            "seconds_to_1e-10_fp64": round(res["fp64"][3], 3),
+            "seconds_to_1e-10": round(res[prec][3], 3)}
+        out["dtype"] = f"{prec} bulk, f64 factorisations"
+        out["config"]["workload"] += f" ({prec} bulk contractions)"
+        out["roofline"]["kernel"] = f"tgemm_f64_kernel and tgemm_lp_kernel ({prec})"
+        out["roofline"]["note"] = ("averaged over the FP64 and the reduced-precision "
+                                   "contractions against the FP64 peak")
     if not args.no_cpu:
         try:
             from threadpoolctl import threadpool_info

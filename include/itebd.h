@@ -181,7 +181,7 @@ int tm_fixed_point_noalloc(tn_ctx* ctx, int n_sites, int chi, int d, const doubl
 size_t tn_env1d_size(int chi, int d);
 
 /* itebd_step modes */
-enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2 };
+enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2, TN_RECYCLE_LIMIT = 3 };
 
 /*
  * itebd_step -- one imaginary-time step of the transverse-field Ising chain
@@ -202,7 +202,15 @@ enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2 };
  *              env1d; the new state is G A_0.  Needs chi <= 16.
  *              TN_RECYCLE_APPLY: A <- G A with the stored G (no environment);
  *              TN_EINVAL if no build step has stored one; lambda_out is not
- *              written and trunc_err is 0
+ *              written and trunc_err is 0.
+ *              TN_RECYCLE_LIMIT: the limit N_Re -> infinity of applying the
+ *              stored G (Sec. V C): each site becomes the dominant
+ *              eigenvector of its map A_X -> G A_X, unit norm, sign with a
+ *              positive overlap with the site passed in; computed by
+ *              squaring the dense map with normalisation until G v = rho v
+ *              to 1e-10 (relative); TN_NOT_CONVERGED when G has no simple
+ *              real dominant eigenvalue (outputs then hold the last
+ *              iterate); otherwise as TN_RECYCLE_APPLY
  *   env1d      device workspace of tn_env1d_size(chi, d) doubles, owned by
  *              the caller, zero-filled before the first step; carries warm
  *              starts between steps
@@ -218,6 +226,29 @@ enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2 };
 int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
                double* env1d, double* lambda_out, double tol, double* trunc_err,
                double* energy_or_null);
+
+/*
+ * ising2d_tm_step -- one step of the power method for the partition function
+ * of the classical square-lattice Ising model (J = 1, inverse temperature
+ * beta): the two-site iMPS A encodes the dominant eigenvector of the
+ * row-to-row transfer matrix, which takes the place of the imaginary-time
+ * operator (Sec. I), and the environment can be recycled as in Sec. V.
+ * The transfer matrix with the vertical bonds between two rows and half of
+ * each row's horizontal bonds is c^L G, c = sqrt(2 sinh 2 beta), G the
+ * second-order gate of the transverse-field chain at dt J = beta,
+ * dt h = K* (tanh K* = exp(-2 beta)); so this is itebd_step with that gate.
+ *   chi, A, mode, env1d, lambda_out, tol, trunc_err  as for itebd_step
+ *              (d = 2; every mode, TN_RECYCLE_LIMIT included)
+ *   beta       inverse temperature, > 0
+ *   lnz_or_null host out (may be NULL): ln Z per site of the model (minus
+ *              beta times the free energy per site) from the new state:
+ *              ln c + ln mu, mu the per-site Rayleigh quotient of G, i.e.
+ *              the square root of the ratio of the dominant eigenvalues of
+ *              the two-site transfer matrices of (G A, A) and (A, A)
+ * Returns as itebd_step; TN_EINVAL for beta <= 0.
+ */
+int ising2d_tm_step(tn_ctx* ctx, int chi, double* A, double beta, int mode, double* env1d,
+                    double* lambda_out, double tol, double* trunc_err, double* lnz_or_null);
 
 /*
  * ---------------------------------------------------------------------------
@@ -290,19 +321,39 @@ int ipeps_canonicalize(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, 
                        int D_keep, const double* A, double* A_out, double* lambdas, double* P,
                        double* Q, double tol, int max_iter, int* iters);
 
+/* gauge_fix kinds */
+enum { TN_GAUGE_2D = 0, TN_GAUGE_1D = 1, TN_GAUGE_1D_DIRECT = 2 };
+
 /*
- * gauge_fix -- orthogonal U_b per link with a_new ~ U(a_ref) (U_b applied as
- * new = U_b old on both legs of link b), maximising the fidelity of Eq. (25),
- * F = sum_s <a_new_s | U(a_ref_s)> / sum_s |a_ref_s| |a_new_s|, by alternating
- * Procrustes steps (Sec. IV B): each link in turn, the other factors fixed,
- * U_b = W V^T from the SVD of the linear coefficient W S V^T.  Stops when F
- * changes by less than tol in a pass over the links.
- *   a_ref, a_new  device [nsite][d][D]^4 (nsite <= 30)
- *   U             device in/out [nlink][D][D]: start, then result
+ * gauge_fix -- fix the gauge freedom between two tensor networks that
+ * represent one state (Sec. III B for an iMPS, Sec. IV B for an iPEPS),
+ * with one orthogonal U_b per link (real arithmetic: unitary means
+ * orthogonal), U_b applied as new = U_b old on both legs of link b.
+ *   kind = TN_GAUGE_2D: an iPEPS cell (Lx, Ly, nsite, cell as for the
+ *          full-update calls, bond D, a_ref, a_new [nsite][d][D]^4, nsite
+ *          <= 30).  Maximises the fidelity of Eq. (25),
+ *          F = sum_s <a_new_s | U(a_ref_s)> / sum_s |a_ref_s| |a_new_s|, by
+ *          alternating Procrustes steps (Sec. IV B): each link in turn, the
+ *          other factors fixed, U_b = W V^T from the SVD of the linear
+ *          coefficient W S V^T; from the U passed in until F changes by less
+ *          than tol in a pass over the links.
+ *   kind = TN_GAUGE_1D: the two-site iMPS cell (Lx, Ly, nsite, cell ignored;
+ *          D = chi; a_ref, a_new [2][chi][d][chi] in A form, site 0 with
+ *          bond 1 on its left and bond 0 on its right, so a_new_X ~
+ *          U[left] a_ref_X U[right]^T).  The iterative method (Sec. III B 2,
+ *          Eq. (15)) as for 2D, from the U passed in.
+ *   kind = TN_GAUGE_1D_DIRECT: the same cell by the direct method (Sec.
+ *          III B 1, Eq. (iMPSDM1)): per bond the dominant left eigenvector
+ *          X of the mixed transfer matrix (ket a_ref, bra a_new) equals
+ *          w U^T with w the positive fixed point of a_ref, so U is the
+ *          orthogonal polar factor of X^T; the sign of the pair is taken
+ *          with F > 0.  U is output only; tol, max_iter bound the
+ *          fixed-point iterations.  chi <= 32 for both 1D kinds.
+ *   U             device in/out [nlink][D][D] (1D: [2][chi][chi])
  *   fidelity, iters  host out
- * Returns TN_OK or TN_NOT_CONVERGED.
+ * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL, TN_ENUMERIC, TN_EHIP.
  */
-int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+int gauge_fix(tn_ctx* ctx, int kind, int Lx, int Ly, int nsite, const int* cell, int d, int D,
               const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
               double* fidelity, int* iters);
 
@@ -338,8 +389,12 @@ int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, in
  * one P and one Q update per link per cycle.  A link held by two slots (the
  * 1 x 1 cell) gets the mean of their (P, Q).  kappa D^2 <= 140.
  *   Theta        device [nsite][d][Dk]^4, Dk = kappa D
- *   C, T         device, the environment of the pre-truncated state (bond D)
- *   Psu, Qsu     device [nlink][Dk][D], [nlink][D][Dk]: the pre-truncation
+ *   De           bond of the legs facing the environment, 1 <= De <= Dk
+ *   C, T         device, the environment (bond De) of the state those legs
+ *                carry: the pre-truncated state (De = D, the O(chi^3 D^6)
+ *                form the section proposes), or Theta itself (De = Dk, Psu
+ *                and Qsu identities: the O(chi^3 D^6 kappa^6) form)
+ *   Psu, Qsu     device [nlink][Dk][De], [nlink][De][Dk]: the pre-truncation
  *   P, Q         device in/out [nlink][Dk][D], [nlink][D][Dk]: start, result
  *   cost         host out (may be NULL) [2]: final f and <Psi_g|Psi_g>
  *   passes, sweeps  host out (may be NULL): cycles and total ALS sweeps
@@ -347,9 +402,10 @@ int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, in
  * non-finite values, a zero block norm), TN_EHIP.
  */
 int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                      int Dk, const double* Theta, int chi, const double* C, const double* T,
-                      const double* Psu, const double* Qsu, double* P, double* Q, int max_passes,
-                      int max_sweeps, double tol, double* cost, int* passes, int* sweeps);
+                      int Dk, int De, const double* Theta, int chi, const double* C,
+                      const double* T, const double* Psu, const double* Qsu, double* P, double* Q,
+                      int max_passes, int max_sweeps, double tol, double* cost, int* passes,
+                      int* sweeps);
 
 /*
  * bond_environment -- the two environments of one slot of the truncation
@@ -365,9 +421,9 @@ int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, i
  * normalised boundary leaves a common sign free).
  */
 int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                     int Dk, const double* Theta, int chi, const double* C, const double* T,
-                     const double* Psu, const double* Qsu, const double* P, const double* Q,
-                     int slot, double* N, double* M);
+                     int Dk, int De, const double* Theta, int chi, const double* C,
+                     const double* T, const double* Psu, const double* Qsu, const double* P,
+                     const double* Q, int slot, double* N, double* M);
 
 /*
  * fu_gauge_start -- start of the gauge fix inside the recycling step
@@ -451,8 +507,8 @@ int tn_gemm(tn_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, 
 /*
  * tn_svd -- the library's small dense FP64 SVD (one-sided Jacobi, one
  * workgroup per matrix; a single matrix with n > 128 is spread over the
- * whole GPU, one launch per round of column pairs), used for the Rayleigh-Ritz step of the projector
- * SVD, the corner spectra, the canonical-form and gauge-fixing
+ * whole GPU, one launch per round of column pairs), used for the
+ * Rayleigh-Ritz step of the projector SVD, the corner spectra, the canonical-form and gauge-fixing
  * factorisations.  A = U diag(S) V^T for `batch` row-major m x n matrices
  * (m >= n, n <= 512) stored back to back; U [batch][m][n], S [batch][n]
  * (descending), V [batch][n][n]; each column of U sign-fixed so that its

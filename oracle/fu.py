@@ -339,22 +339,50 @@ def fu_truncate(cell, thetas, Psu, Qsu, C, T, tol=1e-12, max_passes=50, max_swee
 # ---------------------------------------------------------------------------
 
 def fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol=1e-10, ctm_max=100, J=1.0, h=3.0,
-                als_tol=1e-12, als_passes=50, als_sweeps=1):
+                als_tol=1e-12, als_passes=50, als_sweeps=1, pretruncate=True):
     """One full-update step with a freshly computed environment: Theta = g A,
     pre-truncation, CTMRG (warm-started from C, T), energy, the ALS cycles
-    over all links, A~ = Q Theta P.  Returns a dict."""
+    over all links, A~ = Q Theta P.  Returns a dict.
+
+    ``pretruncate=False`` is the form without the pre-truncation (Sec. VI B,
+    the cost remark closing the section): the environment is that of Theta
+    itself, bond kappa D (C, T of that bond; cost O(chi^3 D^6 kappa^6)), the
+    block's outer legs stay untruncated, and the energy is Theta's; the ALS
+    still starts from the simple-update truncation."""
     links, _ = cell_links(cell)
     thetas = [gates.apply_ipepo(g, a) for a in sites]
     P, Q = su_truncation(cell, thetas, D)
-    pre = truncate(thetas, links, P, Q)
+    if pretruncate:
+        Pe, Qe = P, Q
+        pre = truncate(thetas, links, P, Q)
+    else:
+        Dk = thetas[0].shape[1]
+        Pe = [np.eye(Dk) for _ in links]
+        Qe = [np.eye(Dk) for _ in links]
+        pre = thetas
     C, T, iters, delta = ctmrg(cell, pre, C, T, chi, ctm_max, ctm_tol)
     E = energy_per_site(cell, pre, C, T, J, h)
-    P, Q, f, passes, sweeps, _ = fu_truncate(cell, thetas, P, Q, C, T, als_tol, als_passes,
-                                             als_sweeps)
+    P, Q, f, passes, sweeps, _ = fu_truncate(cell, thetas, Pe, Qe, C, T, als_tol, als_passes,
+                                             als_sweeps, P0=P, Q0=Q)
     new = truncate(thetas, links, P, Q)
     return dict(sites=new, thetas=thetas, P=P, Q=Q, C=C, T=T, energy=E,
                 ctm_iters=iters, ctm_delta=delta, cost=f, als_passes=passes,
                 als_sweeps=sweeps)
+
+
+def run_su(cell, sites, J, h, dt, D, nsteps, tol=1e-14, max_iter=1000):
+    """The simple update (Sec. VI A, the scheme the section contrasts with
+    the full update): each step applies the iPEPO gate and truncates every
+    link by the canonical form of Theta, keeping its D largest Schmidt
+    values (``su_truncation``); no environment.  Returns the sites."""
+    links, _ = cell_links(cell)
+    g = gates.ipepo(J, h, dt)
+    sites = [s / np.linalg.norm(s) for s in sites]
+    for _ in range(nsteps):
+        thetas = [gates.apply_ipepo(g, a) for a in sites]
+        P, Q = su_truncation(cell, thetas, D, tol, max_iter)
+        sites = [t / np.linalg.norm(t) for t in truncate(thetas, links, P, Q)]
+    return sites
 
 
 def gauge_start(P, Q, Pc, Qc, kappa):
@@ -394,7 +422,7 @@ def recycle_build(cell, a0, out, kappa, gauge_tol=1e-12):
 
 def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=None,
            ctm_tol=1e-10, ctm_max=100, seed_env=0, callback=None, min_fidelity=None,
-           force_recycle=False, als_tol=1e-12, als_passes=50, als_sweeps=1):
+           force_recycle=False, als_tol=1e-12, als_passes=50, als_sweeps=1, pretruncate=True):
     """Imaginary-time evolution of an iPEPS by full update, the environment
     recomputed every ``n_re`` steps after ``n_warm`` plain steps and the
     renormalized gate applied in between (Sec. VI C).  A recycling step
@@ -403,8 +431,10 @@ def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=No
     state is too far from A_0 for G to stand in for the environment).
     ``force_recycle`` takes the recycling branch even for n_re = 1, where it
     must reproduce the plain trajectory (the renormalized gate applied once
-    is the full-update step in another gauge).  Returns (sites, log) with
-    log entries (step, energy_per_site, recycled) at environment steps."""
+    is the full-update step in another gauge).  ``pretruncate=False``
+    computes every environment for Theta itself (``fu_env_step``; C, T then
+    have bond kappa D).  Returns (sites, log) with log entries (step,
+    energy_per_site, recycled) at environment steps."""
     links, _ = cell_links(cell)
     g = gates.ipepo(J, h, dt)
     kappa = g.shape[0]
@@ -412,7 +442,8 @@ def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=No
     npos = cell.Lx * cell.Ly
     if C is None:
         import tninputs
-        C, T = tninputs.ctm_env(seed_env, npos, chi, D, positive=True)
+        C, T = tninputs.ctm_env(seed_env, npos, chi, D if pretruncate else kappa * D,
+                                positive=True)
     log = []
     step = 0
     while step < nsteps:
@@ -420,7 +451,7 @@ def run_fu(cell, sites, J, h, dt, D, chi, nsteps, n_re=1, n_warm=0, C=None, T=No
         if recycle:
             sites = canonicalize_a_form(cell, sites)[0]
         out = fu_env_step(cell, sites, g, D, chi, C, T, ctm_tol, ctm_max, J, h, als_tol,
-                          als_passes, als_sweeps)
+                          als_passes, als_sweeps, pretruncate)
         C, T = out["C"], out["T"]
         F = None
         if recycle:

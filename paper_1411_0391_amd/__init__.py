@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libitebd.so")
 
 TN_OK, TN_NOT_CONVERGED = 0, 1
 TN_FP64, TN_FP32, TN_BF16 = 0, 1, 2
-TN_PLAIN, TN_RECYCLE_BUILD, TN_RECYCLE_APPLY = 0, 1, 2
+TN_PLAIN, TN_RECYCLE_BUILD, TN_RECYCLE_APPLY, TN_RECYCLE_LIMIT = 0, 1, 2, 3
+TN_GAUGE_2D, TN_GAUGE_1D, TN_GAUGE_1D_DIRECT = 0, 1, 2
 _PREC = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -57,6 +58,8 @@ SIGNATURES = {
     "itebd_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                   ctypes.c_double, _c_double_p, _c_double_p]),
+    "ising2d_tm_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
+                                       _vp, _vp, ctypes.c_double, _c_double_p, _c_double_p]),
     "ipeps_cell_links": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
                                         _c_int_p, _c_int_p]),
     "ipeps_gate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -67,16 +70,18 @@ SIGNATURES = {
     "ipeps_canonicalize": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                           _vp, _vp, ctypes.c_double, ctypes.c_int, _c_int_p]),
-    "gauge_fix": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
-                                 ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
-                                 ctypes.c_int, _c_double_p, _c_int_p]),
+    "gauge_fix": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 _c_int_p, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                 ctypes.c_double, ctypes.c_int, _c_double_p, _c_int_p]),
     "bond_env_truncate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
-                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _vp,
                                          ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          _c_double_p, _c_int_p, _c_int_p]),
     "bond_environment": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
-                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        _vp,
                                         ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.c_int, _vp, _vp]),
     "fu_gauge_start": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -274,22 +279,36 @@ class Context:
         nsite, d, D = a_ref.shape[0], a_ref.shape[1], a_ref.shape[2]
         F = ctypes.c_double(0)
         it = ctypes.c_int(0)
-        rc = lib().gauge_fix(self._h, Lx, Ly, nsite, self._cell(cell), d, D, _ptr(a_ref),
-                             _ptr(a_new), _ptr(U), tol, max_iter, ctypes.byref(F),
+        rc = lib().gauge_fix(self._h, TN_GAUGE_2D, Lx, Ly, nsite, self._cell(cell), d, D,
+                             _ptr(a_ref), _ptr(a_new), _ptr(U), tol, max_iter, ctypes.byref(F),
                              ctypes.byref(it))
+        self._check(rc, allow_nc=True)
+        return F.value, it.value, rc
+
+    def gauge_fix_1d(self, a_ref, a_new, U, method="iterative", tol=1e-12, max_iter=1000):
+        """Two-site iMPS gauge fix (device [2][chi][d][chi] A forms); U
+        (device [2][chi][chi]) is the start (iterative) and the result;
+        returns (F, iters, rc)."""
+        chi, d = a_ref.shape[1], a_ref.shape[2]
+        kind = {"iterative": TN_GAUGE_1D, "direct": TN_GAUGE_1D_DIRECT}[method]
+        F = ctypes.c_double(0)
+        it = ctypes.c_int(0)
+        rc = lib().gauge_fix(self._h, kind, 0, 0, 0, None, d, chi, _ptr(a_ref), _ptr(a_new),
+                             _ptr(U), tol, max_iter, ctypes.byref(F), ctypes.byref(it))
         self._check(rc, allow_nc=True)
         return F.value, it.value, rc
 
     def bond_env_truncate(self, Lx, Ly, cell, Theta, C, T, Psu, Qsu, P, Q, max_passes=50,
                           max_sweeps=1, tol=1e-12):
         """P, Q (device, per link) are updated in place from their start;
-        returns (f, <Psi_g|Psi_g>, passes, sweeps)."""
+        the environment bond is the column count of Psu.  Returns
+        (f, <Psi_g|Psi_g>, passes, sweeps)."""
         nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
-        D = P.shape[2]
+        D, De = P.shape[2], Psu.shape[2]
         chi = C.shape[-1]
         cost = (ctypes.c_double * 2)()
         npass, sw = ctypes.c_int(0), ctypes.c_int(0)
-        rc = lib().bond_env_truncate(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
+        rc = lib().bond_env_truncate(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk, De,
                                      _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(Psu), _ptr(Qsu),
                                      _ptr(P), _ptr(Q), max_passes, max_sweeps, tol, cost,
                                      ctypes.byref(npass), ctypes.byref(sw))
@@ -300,11 +319,11 @@ class Context:
         """(N, M) of one slot of the truncation block (device)."""
         import torch
         nsite, d, Dk = Theta.shape[0], Theta.shape[1], Theta.shape[2]
-        D = P.shape[2]
+        D, De = P.shape[2], Psu.shape[2]
         chi = C.shape[-1]
         N = torch.empty((Dk,) * 4, dtype=torch.float64, device=Theta.device)
         M = torch.empty((Dk,) * 4, dtype=torch.float64, device=Theta.device)
-        self._check(lib().bond_environment(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk,
+        self._check(lib().bond_environment(self._h, Lx, Ly, nsite, self._cell(cell), d, D, Dk, De,
                                            _ptr(Theta), chi, _ptr(C), _ptr(T), _ptr(Psu),
                                            _ptr(Qsu), _ptr(P), _ptr(Q), slot, _ptr(N), _ptr(M)))
         return N, M
@@ -368,6 +387,18 @@ class Context:
                               ctypes.byref(e) if energy else None)
         self._check(rc, allow_nc=True)
         return err.value, (e.value if energy else None), rc
+
+    def ising2d_tm_step(self, A, beta, env, mode=0, tol=1e-13, lnz=False, lam=None):
+        """One power-method step on the row transfer matrix of the classical
+        2D Ising model; returns (trunc_err, ln Z per site or None, rc)."""
+        chi = A.shape[1]
+        err = ctypes.c_double(0)
+        z = ctypes.c_double(0)
+        rc = lib().ising2d_tm_step(self._h, chi, _ptr(A), beta, mode, _ptr(env),
+                                   _ptr(lam) if lam is not None else None, tol,
+                                   ctypes.byref(err), ctypes.byref(z) if lnz else None)
+        self._check(rc, allow_nc=True)
+        return err.value, (z.value if lnz else None), rc
 
     def svd(self, A):
         """Batched small SVD of device matrices A [batch][m][n] -> U, S, V."""

@@ -24,6 +24,8 @@ int noalloc_scratch_init(int device);
 int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt, int mode,
                     double* env1d, double* lambda_out, double tol, double* trunc_err,
                     double* energy_or_null);
+int ising2d_tm_step_impl(tn_ctx* ctx, int chi, double* A, double beta, int mode, double* env1d,
+                         double* lambda_out, double tol, double* trunc_err, double* lnz_or_null);
 
 int cell_links_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
                     int* links);
@@ -38,14 +40,19 @@ int ipeps_canonicalize_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* c
 int gauge_fix_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
                    const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
                    double* fidelity, int* iters);
+int gauge_fix_1d(tn_ctx* ctx, int method, int chi, int d, const double* a_ref,
+                 const double* a_new, double* U, double tol, int max_iter, double* fidelity,
+                 int* iters);
 int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                           int Dk, const double* Theta, int chi, const double* C, const double* T,
-                           const double* Psu, const double* Qsu, double* P, double* Q,
+                           int Dk, int De, const double* Theta, int chi, const double* C,
+                           const double* T, const double* Psu, const double* Qsu,
+                           double* P, double* Q,
                            int max_passes, int max_sweeps, double tol, double* cost, int* passes,
                            int* sweeps);
 int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                          int Dk, const double* Theta, int chi, const double* C, const double* T,
-                          const double* Psu, const double* Qsu, const double* P, const double* Q,
+                          int Dk, int De, const double* Theta, int chi, const double* C,
+                          const double* T, const double* Psu, const double* Qsu,
+                          const double* P, const double* Q,
                           int slot, double* N_out, double* M_out);
 int fu_gauge_start_impl(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
                         const double* Q, const double* Pc, const double* Qc, double* U0);
@@ -229,6 +236,14 @@ int itebd_step(tn_ctx* ctx, int chi, int d, double* A, double J, double h, doubl
                          energy_or_null);
 }
 
+int ising2d_tm_step(tn_ctx* ctx, int chi, double* A, double beta, int mode, double* env1d,
+                    double* lambda_out, double tol, double* trunc_err, double* lnz_or_null) {
+  if (!ctx) return TN_EINVAL;
+  ctx->err.clear();
+  return ising2d_tm_step_impl(ctx, chi, A, beta, mode, env1d, lambda_out, tol, trunc_err,
+                              lnz_or_null);
+}
+
 int ipeps_cell_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int* nlink,
                      int* links) {
   if (!ctx) {  // host-only: usable without a context (errors give the code only)
@@ -240,13 +255,14 @@ int ipeps_cell_links(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, in
 }
 
 int bond_environment(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                     int Dk, const double* Theta, int chi, const double* C, const double* T,
-                     const double* Psu, const double* Qsu, const double* P, const double* Q,
+                     int Dk, int De, const double* Theta, int chi, const double* C,
+                     const double* T, const double* Psu, const double* Qsu,
+                     const double* P, const double* Q,
                      int slot, double* N, double* M) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  return bond_environment_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, Psu, Qsu, P,
-                               Q, slot, N, M);
+  return bond_environment_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, De, Theta, chi, C, T, Psu,
+                               Qsu, P, Q, slot, N, M);
 }
 
 int fu_gauge_start(tn_ctx* ctx, int nlink, int Dk, int D, int kappa, const double* P,
@@ -280,23 +296,29 @@ int ipeps_canonicalize(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, 
                                  tol, max_iter, iters);
 }
 
-int gauge_fix(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
+int gauge_fix(tn_ctx* ctx, int kind, int Lx, int Ly, int nsite, const int* cell, int d, int D,
               const double* a_ref, const double* a_new, double* U, double tol, int max_iter,
               double* fidelity, int* iters) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  return gauge_fix_impl(ctx, Lx, Ly, nsite, cell, d, D, a_ref, a_new, U, tol, max_iter, fidelity,
-                        iters);
+  if (kind == TN_GAUGE_2D)
+    return gauge_fix_impl(ctx, Lx, Ly, nsite, cell, d, D, a_ref, a_new, U, tol, max_iter,
+                          fidelity, iters);
+  if (kind == TN_GAUGE_1D || kind == TN_GAUGE_1D_DIRECT)
+    return gauge_fix_1d(ctx, kind == TN_GAUGE_1D ? 0 : 1, D, d, a_ref, a_new, U, tol, max_iter,
+                        fidelity, iters);
+  TN_FAIL(ctx, TN_EINVAL, "unknown gauge_fix kind %d", kind);
 }
 
 int bond_env_truncate(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                      int Dk, const double* Theta, int chi, const double* C, const double* T,
-                      const double* Psu, const double* Qsu, double* P, double* Q, int max_passes,
+                      int Dk, int De, const double* Theta, int chi, const double* C,
+                      const double* T, const double* Psu, const double* Qsu,
+                      double* P, double* Q, int max_passes,
                       int max_sweeps, double tol, double* cost, int* passes, int* sweeps) {
   if (!ctx) return TN_EINVAL;
   ctx->err.clear();
-  return bond_env_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, Theta, chi, C, T, Psu, Qsu, P,
-                                Q, max_passes, max_sweeps, tol, cost, passes, sweeps);
+  return bond_env_truncate_impl(ctx, Lx, Ly, nsite, cell, d, D, Dk, De, Theta, chi, C, T, Psu,
+                                Qsu, P, Q, max_passes, max_sweeps, tol, cost, passes, sweeps);
 }
 
 int fu_renormalized_gate(tn_ctx* ctx, int nlink, int Dk, int D, const double* P, const double* Q,

@@ -256,7 +256,14 @@ constexpr int absorb_threads() {
   return 64 * ((ABS_G * D * D + 15) / 16);
 }
 
-template <int D>
+// Output layouts the store knows: ABS_STRIDED stores each lane's own entries
+// (any strides); ABS_RUN_B and ABS_RUN_D stage the workgroup's tile in LDS
+// and store it in runs of G D^2 consecutive doubles, when the four pairs are
+// consecutive in the output with stride D^2 and (rb, rk) (corner layout) or
+// (db, dk) (edge layout) are the two fastest output indices.
+enum { ABS_STRIDED = 0, ABS_RUN_B = 1, ABS_RUN_D = 2 };
+
+template <int D, int LAYOUT>
 __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
     const double* __restrict__ In, const double* __restrict__ A, double* __restrict__ Out,
     AbsorbDesc g) {
@@ -346,54 +353,101 @@ __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
     }
     __syncthreads();
   }
+  if (LAYOUT == ABS_STRIDED) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * blk + hi + 4 * r;
+      const int ap = row / P, R1 = row % P;
+      const long long pr = p0 + ap;
+      if (row >= ROWS || pr >= npair) continue;
+      const long long c = pr / g.na, a = pr % g.na;
+      const long long base = c * g.out_c + a * g.out_a + (long long)(R1 / D) * g.out_rk +
+                             (long long)(R1 % D) * g.out_dk;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int R2 = 16 * j + lo;
+        if (R2 < P)
+          Out[base + (long long)(R2 / D) * g.out_rb + (long long)(R2 % D) * g.out_db] =
+              acc2[j][r];
+      }
+    }
+    return;
+  }
+  // stage the tile Os[(pair, R1)][R2] in Ts (free after the last barrier of
+  // the loop), then store it in runs: element e = ((y1 D + y0) G + p) D^2 +
+  // x1 D + x0 with (x0, x1) = (rb, rk) or (db, dk) and (y0, y1) the other two
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = 16 * blk + hi + 4 * r;
-    const int ap = row / P, R1 = row % P;
-    const long long pr = p0 + ap;
-    if (row >= ROWS || pr >= npair) continue;
-    const long long c = pr / g.na, a = pr % g.na;
-    const long long base = c * g.out_c + a * g.out_a + (long long)(R1 / D) * g.out_rk +
-                           (long long)(R1 % D) * g.out_dk;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int R2 = 16 * j + lo;
-      if (R2 < P)
-        Out[base + (long long)(R2 / D) * g.out_rb + (long long)(R2 % D) * g.out_db] = acc2[j][r];
+      if (row < ROWS && R2 < P) Ts[row * S + R2] = acc2[j][r];
     }
+  }
+  __syncthreads();
+  // the G pairs are consecutive in the output (checked on the host), so the
+  // tile's base is that of its first pair
+  const long long c0 = p0 / g.na, a0 = p0 % g.na;
+  const long long base0 = c0 * g.out_c + a0 * g.out_a;
+  const long long ystride0 = LAYOUT == ABS_RUN_B ? g.out_db : g.out_rb;
+  const long long ystride1 = LAYOUT == ABS_RUN_B ? g.out_dk : g.out_rk;
+  const int nvalid = (int)min((long long)ABS_G, npair - p0);
+  for (int e = threadIdx.x; e < ROWS * P; e += blockDim.x) {
+    const int x = e % P, q = e / P;  // x = x1 D + x0, contiguous in the output
+    const int p = q % ABS_G, y = q / ABS_G;
+    if (p >= nvalid) continue;
+    const int x0 = x % D, x1 = x / D, y0 = y % D, y1 = y / D;
+    // R1 = (rk, dk), R2 = (rb, db)
+    const int R1 = LAYOUT == ABS_RUN_B ? x1 * D + y1 : y1 * D + x1;
+    const int R2 = LAYOUT == ABS_RUN_B ? x0 * D + y0 : y0 * D + x0;
+    Out[base0 + (long long)p * P + x + y0 * ystride0 + y1 * ystride1] =
+        Ts[(p * P + R1) * S + R2];
   }
 }
 
 // Fused absorption for D = 2..6 in FP64; returns false (nothing launched)
 // for other bond dimensions or precisions, where the caller runs the two
 // products as separate contractions.
+template <int D>
+void absorb_launch(tn_ctx* ctx, int layout, dim3 grid, const double* In, const double* A,
+                   double* Out, const AbsorbDesc& g) {
+  if (layout == ABS_RUN_B)
+    hipLaunchKernelGGL((absorb_kernel<D, ABS_RUN_B>), grid, dim3(absorb_threads<D>()), 0,
+                       ctx->stream, In, A, Out, g);
+  else if (layout == ABS_RUN_D)
+    hipLaunchKernelGGL((absorb_kernel<D, ABS_RUN_D>), grid, dim3(absorb_threads<D>()), 0,
+                       ctx->stream, In, A, Out, g);
+  else
+    hipLaunchKernelGGL((absorb_kernel<D, ABS_STRIDED>), grid, dim3(absorb_threads<D>()), 0,
+                       ctx->stream, In, A, Out, g);
+}
+
 bool absorb_site(tn_ctx* ctx, int D, int prec, const double* In, const double* A, double* Out,
                  const AbsorbDesc& g) {
   if (prec != P_F64 || D < 2 || D > 6) return false;
   const long long npair = (long long)g.nc * g.na;
   if (npair <= 0) return true;
   const dim3 grid((unsigned)((npair + ABS_G - 1) / ABS_G));
+  // runs need the G pairs of a workgroup consecutive in the output: na a
+  // multiple of G (the pairs share c), a-stride D^2, and the two fastest
+  // output indices of one of the two kinds
+  const long long P = (long long)D * D;
+  int layout = ABS_STRIDED;
+  if (g.na % ABS_G == 0 && g.out_a == P) {
+    if (g.out_rb == 1 && g.out_rk == D && g.out_db % (ABS_G * P) == 0 &&
+        g.out_dk % (ABS_G * P) == 0)
+      layout = ABS_RUN_B;
+    else if (g.out_db == 1 && g.out_dk == D && g.out_rb % (ABS_G * P) == 0 &&
+             g.out_rk % (ABS_G * P) == 0)
+      layout = ABS_RUN_D;
+  }
   switch (D) {
-    case 2:
-      hipLaunchKernelGGL(absorb_kernel<2>, grid, dim3(absorb_threads<2>()), 0, ctx->stream, In, A,
-                         Out, g);
-      break;
-    case 3:
-      hipLaunchKernelGGL(absorb_kernel<3>, grid, dim3(absorb_threads<3>()), 0, ctx->stream, In, A,
-                         Out, g);
-      break;
-    case 4:
-      hipLaunchKernelGGL(absorb_kernel<4>, grid, dim3(absorb_threads<4>()), 0, ctx->stream, In, A,
-                         Out, g);
-      break;
-    case 5:
-      hipLaunchKernelGGL(absorb_kernel<5>, grid, dim3(absorb_threads<5>()), 0, ctx->stream, In, A,
-                         Out, g);
-      break;
-    default:
-      hipLaunchKernelGGL(absorb_kernel<6>, grid, dim3(absorb_threads<6>()), 0, ctx->stream, In, A,
-                         Out, g);
-      break;
+    case 2: absorb_launch<2>(ctx, layout, grid, In, A, Out, g); break;
+    case 3: absorb_launch<3>(ctx, layout, grid, In, A, Out, g); break;
+    case 4: absorb_launch<4>(ctx, layout, grid, In, A, Out, g); break;
+    case 5: absorb_launch<5>(ctx, layout, grid, In, A, Out, g); break;
+    default: absorb_launch<6>(ctx, layout, grid, In, A, Out, g); break;
   }
   return true;
 }
@@ -1189,7 +1243,12 @@ int half_left(tn_ctx* ctx, const Geo& g, int f, int p, double* L, double* X1, do
 void set_precision(Geo& g, int prec) {
   g.prec = prec;
   if (prec == P_F64) {
-    g.svd_tol = 1e-13;
+    // the residual's rounding floor grows with the length n of the vectors
+    // (measured 7e-14 to 9e-14 s_1 at n = 2592, about 0.3 n u): the target
+    // is 1e-13 or 0.4 n u, whichever is larger (2.7e-13 at n = 8192, where
+    // 1e-13 lay below the floor and every problem ended on the stagnation
+    // rule)
+    g.svd_tol = std::max(1e-13, 0.4 * (double)g.n * 1.1102230246251565e-16);
     g.svd_maxit = 40;
   } else if (prec == P_F32) {
     g.svd_tol = 2e-5;

@@ -572,11 +572,353 @@ int energy_1d(tn_ctx* ctx, int chi, int d, const double* A /*[2][chi][d][chi]*/,
 
 }  // namespace
 
-int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*/, double J,
-                    double h, double dt, int mode, double* env1d, double* lambda_out,
-                    double tol, double* trunc_err, double* energy_or_null) {
+namespace {
+
+// The map A_X -> G A_X of both sites as dense matrices (Sec. V B (iii)):
+// G_X[(i s j)][(a t b)] = sum_{k k'} Lf_X[i][(a k)] g[k][k'][s][t] Rf_X[(b k')][j],
+// site 0 with Lf[1], Rf[0], site 1 with Lf[0], Rf[1]; Gm [2][N][N], N = chi d chi.
+__global__ void gate_matrix_kernel(int chi, int d, int kap, const double* __restrict__ Lf,
+                                   const double* __restrict__ Rf, const double* __restrict__ g,
+                                   double* __restrict__ Gm) {
+  const long long N = (long long)chi * d * chi, n = (long long)kap * chi;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * N * N) return;
+  const int X = (int)(t / (N * N));
+  const long long e = t % (N * N), row = e / N, col = e % N;
+  const int i = (int)(row / (d * chi)), s = (int)((row / chi) % d), j = (int)(row % chi);
+  const int a = (int)(col / (d * chi)), tt = (int)((col / chi) % d), b = (int)(col % chi);
+  const double* lf = Lf + (X == 0 ? 1 : 0) * chi * n;
+  const double* rf = Rf + (X == 0 ? 0 : 1) * n * chi;
+  double acc = 0.0;
+  for (int k = 0; k < kap; ++k)
+    for (int k2 = 0; k2 < kap; ++k2)
+      acc += lf[(long long)i * n + a * kap + k] * g[((k * kap + k2) * d + s) * d + tt] *
+             rf[(long long)(b * kap + k2) * chi + j];
+  Gm[t] = acc;
+}
+
+// Per site: rho = v.Gv, r = |Gv - rho v| / |Gv| (v of unit norm), and the
+// sign that gives v a positive overlap with the current site a; one block
+// per site.
+__global__ __launch_bounds__(256) void eig_residual_kernel(int N, const double* __restrict__ v,
+                                                           const double* __restrict__ Gv,
+                                                           const double* __restrict__ a,
+                                                           double* __restrict__ out) {
+  __shared__ double red[4][3];
+  const int X = blockIdx.x;
+  const double* vx = v + (long long)X * N;
+  const double* gx = Gv + (long long)X * N;
+  const double* ax = a + (long long)X * N;
+  double p = 0.0, q = 0.0, o = 0.0;
+  for (int e = threadIdx.x; e < N; e += 256) {
+    p += vx[e] * gx[e];
+    q += gx[e] * gx[e];
+    o += vx[e] * ax[e];
+  }
+  for (int k = 32; k > 0; k >>= 1) {
+    p += __shfl_xor(p, k, 64);
+    q += __shfl_xor(q, k, 64);
+    o += __shfl_xor(o, k, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = p;
+    red[threadIdx.x >> 6][1] = q;
+    red[threadIdx.x >> 6][2] = o;
+  }
+  __syncthreads();
+  const double rho = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+  const double gg = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+  const double ov = red[0][2] + red[1][2] + red[2][2] + red[3][2];
+  double r = 0.0;
+  for (int e = threadIdx.x; e < N; e += 256) {
+    const double z = gx[e] - rho * vx[e];
+    r += z * z;
+  }
+  for (int k = 32; k > 0; k >>= 1) r += __shfl_xor(r, k, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][0] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double rr = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    out[3 * X] = rho;
+    out[3 * X + 1] = gg > 0.0 ? sqrt(rr / gg) : INFINITY;
+    out[3 * X + 2] = ov < 0.0 ? -1.0 : 1.0;
+  }
+}
+
+// x[X] *= sgn[3 X + 2]
+__global__ void apply_sign_kernel(int N, double* __restrict__ x, const double* __restrict__ info) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2LL * N) return;
+  x[t] *= info[3 * (t / N) + 2];
+}
+
+}  // namespace
+
+namespace {
+
+// Normalised fidelity of a two-site cell with one orthogonal U per bond,
+// a_new_X ~ U[left] a_ref_X U[right]^T (site 0 has bond 1 on its left and
+// bond 0 on its right): out = sum_X <a_new_X, U a_ref_X U^T> /
+// sum_X |a_ref_X| |a_new_X| (one workgroup).
+__global__ __launch_bounds__(256) void fidelity_1d_kernel(int chi, int d,
+                                                          const double* __restrict__ a_ref,
+                                                          const double* __restrict__ a_new,
+                                                          const double* __restrict__ U,
+                                                          double* __restrict__ out) {
+  __shared__ double red[4][5];
+  const long long cdc = (long long)chi * d * chi, cc = (long long)chi * chi;
+  double f = 0.0, r0 = 0.0, r1 = 0.0, n0 = 0.0, n1 = 0.0;
+  for (long long t = threadIdx.x; t < 2 * cdc; t += 256) {
+    const int X = (int)(t / cdc);
+    const long long e = t % cdc;
+    const int i = (int)(e / (d * chi)), sph = (int)((e / chi) % d), j = (int)(e % chi);
+    const double* Ul = U + (X == 0 ? 1 : 0) * cc;
+    const double* Ur = U + (X == 0 ? 0 : 1) * cc;
+    const double* ar = a_ref + X * cdc;
+    double v = 0.0;
+    for (int a = 0; a < chi; ++a) {
+      double w = 0.0;
+      for (int b = 0; b < chi; ++b) w += ar[((long long)a * d + sph) * chi + b] * Ur[j * chi + b];
+      v += Ul[i * chi + a] * w;
+    }
+    const double an = a_new[X * cdc + e], rr = ar[e];
+    f += an * v;
+    if (X == 0) {
+      r0 += rr * rr;
+      n0 += an * an;
+    } else {
+      r1 += rr * rr;
+      n1 += an * an;
+    }
+  }
+  double vals[5] = {f, r0, r1, n0, n1};
+  for (int q = 0; q < 5; ++q) {
+    for (int o = 32; o > 0; o >>= 1) vals[q] += __shfl_xor(vals[q], o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = vals[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[5];
+    for (int q = 0; q < 5; ++q) t[q] = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+    out[0] = t[0] / (sqrt(t[1]) * sqrt(t[3]) + sqrt(t[2]) * sqrt(t[4]));
+  }
+}
+
+// U <- -U (the second bond's factor)
+__global__ void negate_kernel(double* __restrict__ x, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = -x[t];
+}
+
+}  // namespace
+
+// Gauge fixing of a two-site iMPS (Sec. III B): a_new ~ U a_ref U^T per
+// site with one orthogonal U per bond (U [2][chi][chi], bond 0 after site
+// 0).  method 0: the iterative method (Sec. III B 2, Eq. (15)), alternating
+// Procrustes steps from the U passed in until F changes by less than tol;
+// method 1: the direct method (Sec. III B 1, Eq. (iMPSDM1)): per bond the
+// dominant left eigenvector X of the mixed transfer matrix of a_ref (ket)
+// and a_new (bra) is w U^T for a positive w, so U is the orthogonal polar
+// factor of X^T; the overall sign of the pair (U0, U1) is taken with F > 0.
+int gauge_fix_1d(tn_ctx* ctx, int method, int chi, int d, const double* a_ref,
+                 const double* a_new, double* U, double tol, int max_iter, double* fidelity,
+                 int* iters) {
+  if (chi < 1 || d < 1 || !a_ref || !a_new || !U || max_iter < 1)
+    TN_FAIL(ctx, TN_EINVAL, "bad 1D gauge_fix arguments");
+  if (chi > 32) TN_FAIL(ctx, TN_EINVAL, "1D gauge fixing supports chi <= 32 (chi=%d)", chi);
+  const BondNet net = bondnet_chain2(d);
+  const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
+  const size_t tmw = tm_work_in_global(2, chi, d) ? 2 * tm_work_per_side(2, chi, d) : 0;
+  TN_TRY(ws_reserve(ctx, bondnet_gauge_bytes(net, chi) + (4 * cdc + 12 * cc + tmw + 64) * 8 +
+                             (1 << 20)));
+  ws_reset(ctx);
+  if (method == 0)
+    return bondnet_gauge_fix(ctx, net, chi, a_ref, a_new, U, tol, max_iter, fidelity, iters);
+  if (method != 1) TN_FAIL(ctx, TN_EINVAL, "unknown 1D gauge-fix method %d", method);
+  double* kets = ws_alloc<double>(ctx, 2 * cdc);
+  double* bras = ws_alloc<double>(ctx, 2 * cdc);
+  double* v2 = ws_alloc<double>(ctx, 2 * cc);
+  double* W = ws_alloc<double>(ctx, cc);
+  double* V = ws_alloc<double>(ctx, cc);
+  double* S = ws_alloc<double>(ctx, chi);
+  double* ed = ws_alloc<double>(ctx, 4);
+  int* itd = ws_alloc<int>(ctx, 4);
+  double* fd = ws_alloc<double>(ctx, 2);
+  if (!fd) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (1D gauge fix)");
+  int itmax = 0;
+  for (int b = 0; b < 2; ++b) {
+    // the cell ends with the site left of bond b: (c, a) = (1, 0) for bond 0
+    const int a = b == 0 ? 0 : 1, c = 1 - a;
+    TN_HIP(ctx, hipMemcpyAsync(kets, a_ref + c * cdc, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(kets + cdc, a_ref + a * cdc, cdc * 8, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(bras, a_new + c * cdc, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(bras + cdc, a_new + a * cdc, cdc * 8, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    const size_t mark = ctx->arena_off;
+    TN_TRY(tm_pair(ctx, 2, chi, d, kets, bras, v2, ed, itd, tol > 0 ? tol : 1e-14, max_iter, 0));
+    ctx->arena_off = mark;
+    // the polar factor of X^T: with X = W S V^T (X^T = V S W^T), U = V W^T
+    TN_TRY(jacobi_svd(ctx, 1, chi, chi, v2, chi, 0, W, chi, 0, S, 0, V, chi, 0));
+    TN_TRY(gemm(ctx, chi, chi, chi, V, chi, false, W, chi, true, U + b * cc, chi, 1.0, 0.0));
+    int hi[2];
+    TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    itmax = std::max(itmax, std::max(hi[0], hi[1]));
+  }
+  hipLaunchKernelGGL(fidelity_1d_kernel, dim3(1), dim3(256), 0, ctx->stream, chi, d, a_ref, a_new,
+                     U, fd);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, fd, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double F = ctx->host_scratch[0];
+  if (F < 0) {
+    hipLaunchKernelGGL(negate_kernel, dim3((unsigned)((cc + 255) / 256)), dim3(256), 0,
+                       ctx->stream, U + cc, (long long)cc);
+    TN_HIP(ctx, hipGetLastError());
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    F = -F;
+  }
+  if (!std::isfinite(F)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite fidelity");
+  if (fidelity) *fidelity = F;
+  if (iters) *iters = itmax;
+  return itmax >= max_iter ? TN_NOT_CONVERGED : TN_OK;
+}
+
+// N_Re -> infinity (Sec. V C): each site becomes the dominant eigenvector of
+// its renormalized gate.  The dense map G_X is squared with normalisation,
+// M <- M M / |M M|_F, which converges to the projector on the dominant
+// eigenvector (a power method that doubles the power per step); after each
+// squaring v = M a / |M a| is tested for G v = rho v.  Returns TN_OK,
+// TN_NOT_CONVERGED (no simple real dominant eigenvalue within 2^60 powers).
+int recycle_limit(tn_ctx* ctx, int chi, int d, int kap, const double* Lf, const double* Rf,
+                  const double* g, double* A, double* rho_out) {
+  const int N = chi * d * chi;
+  const size_t NN = (size_t)N * N;
+  double* Gm = ws_alloc<double>(ctx, 2 * NN);
+  double* M = ws_alloc<double>(ctx, 2 * NN);
+  double* M2 = ws_alloc<double>(ctx, 2 * NN);
+  double* v = ws_alloc<double>(ctx, 2 * (size_t)N);
+  double* Gv = ws_alloc<double>(ctx, 2 * (size_t)N);
+  double* info = ws_alloc<double>(ctx, 8);
+  if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (recycling limit)");
+  hipLaunchKernelGGL(gate_matrix_kernel, dim3((unsigned)((2 * NN + 255) / 256)), dim3(256), 0,
+                     ctx->stream, chi, d, kap, Lf, Rf, g, Gm);
+  TN_HIP(ctx, hipGetLastError());
+  for (int X = 0; X < 2; ++X) TN_TRY(frob_normalize_to(ctx, Gm + X * NN, M + X * NN, NN, nullptr));
+  double res = INFINITY, prev = INFINITY;
+  int sq = 0;
+  for (sq = 1; sq <= 60; ++sq) {
+    TN_TRY(gemm(ctx, N, N, N, M, N, false, M, N, false, M2, N, 1.0, 0.0, 2, (long long)NN,
+                (long long)NN, (long long)NN));
+    for (int X = 0; X < 2; ++X) TN_TRY(frob_normalize_to(ctx, M2 + X * NN, M + X * NN, NN, nullptr));
+    // v = M a / |M a|, then G v and the residual
+    TN_TRY(gemm(ctx, N, 1, N, M, N, false, A, 1, false, v, 1, 1.0, 0.0, 2, (long long)NN,
+                (long long)N, (long long)N));
+    for (int X = 0; X < 2; ++X) TN_TRY(frob_normalize(ctx, v + X * N, N, nullptr));
+    TN_TRY(gemm(ctx, N, 1, N, Gm, N, false, v, 1, false, Gv, 1, 1.0, 0.0, 2, (long long)NN,
+                (long long)N, (long long)N));
+    hipLaunchKernelGGL(eig_residual_kernel, dim3(2), dim3(256), 0, ctx->stream, N, v, Gv, A,
+                       info);
+    TN_HIP(ctx, hipGetLastError());
+    TN_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, info, 6 * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    prev = res;
+    res = std::max(ctx->host_scratch[1], ctx->host_scratch[4]);
+    if (!std::isfinite(res)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite renormalized-gate eigenvector");
+    // converged, or at the rounding floor
+    if (res < 1e-13 || (res < 1e-10 && res > 0.5 * prev)) break;
+  }
+  if (rho_out) {
+    rho_out[0] = ctx->host_scratch[0];
+    rho_out[1] = ctx->host_scratch[3];
+  }
+  hipLaunchKernelGGL(apply_sign_kernel, dim3((unsigned)((2LL * N + 255) / 256)), dim3(256), 0,
+                     ctx->stream, N, v, info);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipMemcpyAsync(A, v, 2 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  return res < 1e-10 ? TN_OK : TN_NOT_CONVERGED;
+}
+
+namespace {
+
+// The scalar a step reports for its new state: the TFIM energy per site, or
+// ln Z per site of the classical model whose row transfer matrix the gate is.
+struct StepMeasure {
+  int kind;  // 0: TFIM energy (J, h), 1: classical ln Z (beta)
+  double J, h, beta;
+};
+
+__global__ void pad_bra_kernel(const double* __restrict__ A, double* __restrict__ B, int chi,
+                               int d, int kap) {
+  // B[(i, a)][s][(j, b)] = A[i][s][j] for a = b = 0, else 0 (two sites)
+  const int n = chi * kap;
+  const long long tot = 2LL * n * d * n;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  long long r = t;
+  const int jb = r % n; r /= n;
+  const int s = r % d; r /= d;
+  const int ia = r % n; r /= n;
+  const int site = (int)r;
+  B[t] = (ia % kap == 0 && jb % kap == 0)
+             ? A[(((long long)site * chi + ia / kap) * d + s) * chi + jb / kap]
+             : 0.0;
+}
+
+__global__ void log_z_kernel(const double* __restrict__ eta1, const double* __restrict__ eta0,
+                             double log_scale, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    out[0] = log_scale + 0.5 * (log(eta1[0]) - log(eta0[0]));
+}
+
+// ln Z per site of the classical Ising model from the two-site iMPS A:
+// ln c + ln mu, mu the per-site Rayleigh quotient of the gate g, i.e. the
+// square root of the ratio of the dominant eigenvalues of the mixed
+// transfer matrix of (g A, A) (A zero-padded to the bond kappa chi) and of
+// (A, A) over the cell.
+int log_z_1d(tn_ctx* ctx, int chi, int d, int kap, const double* A, const double* g,
+             double log_scale, double* out_dev) {
+  const int n = kap * chi;
+  const size_t ndn = (size_t)n * d * n, cdc = (size_t)chi * d * chi;
+  double* th = ws_alloc<double>(ctx, 2 * ndn);
+  double* bp = ws_alloc<double>(ctx, 2 * ndn);
+  double* v2 = ws_alloc<double>(ctx, 2 * (size_t)n * n);
+  double* ed = ws_alloc<double>(ctx, 4);
+  int* itd = ws_alloc<int>(ctx, 4);
+  if (!itd) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (ln Z)");
+  for (int s = 0; s < 2; ++s)
+    hipLaunchKernelGGL(impo_apply_kernel, dim3((unsigned)((ndn + 255) / 256)), dim3(256), 0,
+                       ctx->stream, g, A + s * cdc, th + s * ndn, chi, d, kap);
+  hipLaunchKernelGGL(pad_bra_kernel, dim3((unsigned)((2 * ndn + 255) / 256)), dim3(256), 0,
+                     ctx->stream, A, bp, chi, d, kap);
+  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(tm_pair(ctx, 2, n, d, th, bp, v2, ed, itd, 1e-14, 200000, 0));
+  TN_TRY(tm_pair(ctx, 2, chi, d, A, A, v2, ed + 2, itd + 2, 1e-14, 200000, 0));
+  hipLaunchKernelGGL(log_z_kernel, dim3(1), dim3(64), 0, ctx->stream, ed, ed + 2, log_scale,
+                     out_dev);
+  TN_HIP(ctx, hipGetLastError());
+  return TN_OK;
+}
+
+int step_measure(tn_ctx* ctx, int chi, int d, const double* A, const double* g,
+                 const StepMeasure& m, double* out_dev) {
+  if (m.kind == 0) return energy_1d(ctx, chi, d, A, m.J, m.h, out_dev);
+  return log_z_1d(ctx, chi, d, 2, A, g, 0.5 * log(2.0 * sinh(2.0 * m.beta)), out_dev);
+}
+
+// One step of the power method with the two-site iMPO hg (iTEBD, Sec. V):
+// the modes of itebd_step, and the measurement m of the new state into
+// *meas_or_null.
+int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*/,
+               const double hg[2][2][2][2], const StepMeasure& meas, int mode, double* env1d,
+               double* lambda_out, double tol, double* trunc_err, double* energy_or_null) {
   if (chi < 1 || d != 2 || !A || !env1d) TN_FAIL(ctx, TN_EINVAL, "bad itebd_step arguments");
-  if (mode < 0 || mode > 2) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
+  if (mode < 0 || mode > 3) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
   const int kap = 2, n = kap * chi;
   if (mode != 0 && n > 32)
     TN_FAIL(ctx, TN_EINVAL, "recycling supports chi <= 16 (chi=%d)", chi);
@@ -586,10 +928,11 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
   size_t extra = 0;
   if (mode == 1)
     extra = bondnet_canon_bytes(net, chi) + bondnet_gauge_bytes(net, chi) + (12 * cc + 4 * cdc) * 8;
+  if (mode == 3) extra = (6 * cdc * cdc + 4 * cdc + 64) * 8;
+  if (energy_or_null && meas.kind == 1)
+    extra += (4 * ndn + 2 * nn + 8) * 8 + 2 * tm_work_per_side(2, n, d) * 8;
   TN_TRY(ws_reserve(ctx, (40 * nn + 8 * ndn + 16 * cdc) * 8 + extra + (8 << 20)));
   ws_reset(ctx);
-  double hg[2][2][2][2];
-  tfim_impo(J, h, dt, hg);
   double* g = ws_alloc<double>(ctx, 16);
   double* th = ws_alloc<double>(ctx, 2 * ndn);
   double* P = ws_alloc<double>(ctx, 2 * (size_t)n * chi);
@@ -627,14 +970,21 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
     TN_TRY(frob_normalize(ctx, dst + cdc, cdc, nullptr));
     return TN_OK;
   };
-  if (mode == 2) {
-    // recycled step: A <- G A with the stored factors (Sec. V B)
+  if (mode == 2 || mode == 3) {
+    // recycled step: A <- G A with the stored factors (Sec. V B), or its
+    // limit N_Re -> infinity, the dominant eigenvector of G (Sec. V C)
     if (hflag[1] != 1.0)
       TN_FAIL(ctx, TN_EINVAL, "no renormalized gate in env1d: run a TN_RECYCLE_BUILD step first");
-    TN_TRY(gate(A));
-    TN_TRY(truncate2(Lf, Rf, A));
+    int rc = TN_OK;
+    if (mode == 2) {
+      TN_TRY(gate(A));
+      TN_TRY(truncate2(Lf, Rf, A));
+    } else {
+      rc = recycle_limit(ctx, chi, d, kap, Lf, Rf, g, A, nullptr);
+      if (rc < 0) return rc;
+    }
     if (energy_or_null) {
-      TN_TRY(energy_1d(ctx, chi, d, A, J, h, edev));
+      TN_TRY(step_measure(ctx, chi, d, A, g, meas, edev));
       double he = 0.0;
       TN_HIP(ctx, hipMemcpyAsync(&he, edev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
       TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -643,7 +993,7 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
       TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
     if (trunc_err) *trunc_err = 0.0;
-    return TN_OK;
+    return rc;
   }
   double* a0 = A;  // the state the environment is computed for
   double *a0c = nullptr, *tr = nullptr, *Pc = nullptr, *Qc = nullptr, *U = nullptr,
@@ -702,7 +1052,7 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
       TN_HIP(ctx, hipMemcpyAsync(lambda_out, l1, 2 * chi * sizeof(double),
                                  hipMemcpyDeviceToDevice, ctx->stream));
   }
-  if (energy_or_null) TN_TRY(energy_1d(ctx, chi, d, A, J, h, edev));
+  if (energy_or_null) TN_TRY(step_measure(ctx, chi, d, A, g, meas, edev));
   double he = 0.0, herr = 0.0;
   TN_HIP(ctx, hipMemcpyAsync(&herr, errd, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   if (energy_or_null)
@@ -712,4 +1062,30 @@ int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in
   if (energy_or_null) *energy_or_null = he;
   if (!std::isfinite(herr)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite truncation");
   return tmi >= 100000 ? TN_NOT_CONVERGED : TN_OK;
+}
+
+}  // namespace
+
+int itebd_step_impl(tn_ctx* ctx, int chi, int d, double* A, double J, double h, double dt,
+                    int mode, double* env1d, double* lambda_out, double tol, double* trunc_err,
+                    double* energy_or_null) {
+  double hg[2][2][2][2];
+  tfim_impo(J, h, dt, hg);
+  return itebd_core(ctx, chi, d, A, hg, StepMeasure{0, J, h, 0.0}, mode, env1d, lambda_out, tol,
+                    trunc_err, energy_or_null);
+}
+
+// The row transfer matrix of the square-lattice Ising model (J = 1, inverse
+// temperature beta) is c^L times the second-order TFIM gate at dt J = beta,
+// dt h = K* (tanh K* = exp(-2 beta)), c = sqrt(2 sinh 2 beta): one power-
+// method step on it is an iTEBD step with that gate (Sec. I).
+int ising2d_tm_step_impl(tn_ctx* ctx, int chi, double* A, double beta, int mode, double* env1d,
+                         double* lambda_out, double tol, double* trunc_err, double* lnz_or_null) {
+  if (!(beta > 0.0) || !std::isfinite(beta))
+    TN_FAIL(ctx, TN_EINVAL, "inverse temperature %g must be positive", beta);
+  const double kstar = atanh(exp(-2.0 * beta));
+  double hg[2][2][2][2];
+  tfim_impo(beta, kstar, 1.0, hg);
+  return itebd_core(ctx, chi, 2, A, hg, StepMeasure{1, 0.0, 0.0, beta}, mode, env1d,
+                    lambda_out, tol, trunc_err, lnz_or_null);
 }

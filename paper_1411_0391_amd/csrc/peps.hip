@@ -1381,30 +1381,31 @@ enum { L_ZETA = 0, L_FULL = 1 };
 
 struct Block {
   const CellLinks* L;
-  int d, D, n, chi;
+  int d, D, n, chi;  // D: the slots' truncated bond, n: the full bond kappa D
   int pos[4], site[4], slot_link[4];
   Env env;
   const double* Theta;  // [nsite][d][n]^4
-  const double *Psu, *Qsu;  // [nlink][n][D], [nlink][D][n]: legs facing the environment
+  const double *Psu, *Qsu;  // [nlink][n][De], [nlink][De][n]: legs facing the environment
   double *Pz, *Qz;          // [4][n][D], [4][D][n]: the slots' current truncation
   size_t big;               // doubles of the largest corner or ring intermediate
   double *ket[4], *bra[4], *sc1, *sc2;
   TDims kd[4], bd[4];
   double *E[4], *X1, *X2, *X3, *R1, *R2;
+  int De = 0;  // bond of the legs facing the environment (the environment's bond)
 
-  static size_t big_of(int d, int D, int n, int chi) {
+  static size_t big_of(int d, int De, int n, int chi) {
     const size_t c2 = (size_t)chi * chi, n2 = (size_t)n * n;
-    return std::max(c2 * n2 * n2, c2 * (size_t)D * D * d * n2);
+    return std::max(c2 * n2 * n2, c2 * (size_t)De * De * d * n2);
   }
-  static size_t bytes(int d, int D, int n, int chi) {
-    const size_t tsz = (size_t)d * n * n * n * n, big = big_of(d, D, n, chi);
+  static size_t bytes(int d, int D, int De, int n, int chi) {
+    const size_t tsz = (size_t)d * n * n * n * n, big = big_of(d, De, n, chi);
     size_t need = 0;
     auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
     for (int k = 0; k < 8; ++k) add(tsz);   // ket, bra per position
     add(tsz);
     add(tsz);                                // apply_legs scratch
     for (int k = 0; k < 4; ++k) add(big);    // corners
-    add((size_t)chi * chi * D * D);          // X1
+    add((size_t)chi * chi * De * De);        // X1
     add(big);                                // X2 (chi^2 D^4 fits)
     add(big);                                // X3
     add(big);
@@ -1416,7 +1417,7 @@ struct Block {
 
   int alloc(tn_ctx* ctx) {
     const size_t tsz = (size_t)d * n * n * n * n;
-    big = big_of(d, D, n, chi);
+    big = big_of(d, De, n, chi);
     for (int k = 0; k < 4; ++k) {
       ket[k] = ws_alloc<double>(ctx, tsz);
       bra[k] = ws_alloc<double>(ctx, tsz);
@@ -1424,7 +1425,7 @@ struct Block {
     sc1 = ws_alloc<double>(ctx, tsz);
     sc2 = ws_alloc<double>(ctx, tsz);
     for (int k = 0; k < 4; ++k) E[k] = ws_alloc<double>(ctx, big);
-    X1 = ws_alloc<double>(ctx, (size_t)chi * chi * D * D);
+    X1 = ws_alloc<double>(ctx, (size_t)chi * chi * De * De);
     X2 = ws_alloc<double>(ctx, big);
     X3 = ws_alloc<double>(ctx, big);
     R1 = ws_alloc<double>(ctx, big);
@@ -1446,9 +1447,9 @@ struct Block {
       if (k < 0) {
         const int b = L->leg_link[s][ax];
         const bool first = (L->s1[b] == s && L->l1[b] == ax);
-        lm.m[ax] = (first ? Psu : Qsu) + (long long)b * n * D;
+        lm.m[ax] = (first ? Psu : Qsu) + (long long)b * n * De;
         lm.trans[ax] = first ? 1 : 0;
-        lm.nnew[ax] = D;
+        lm.nnew[ax] = De;
       } else if (k != open && mode == L_ZETA) {
         const bool first = SLOT[k].e1 == X;
         lm.m[ax] = (first ? Pz : Qz) + (long long)k * n * D;
@@ -1468,7 +1469,7 @@ struct Block {
       TN_TRY(layer(ctx, X, kmode, open, ket[X], &kd[X]));
       TN_TRY(layer(ctx, X, bmode, open, bra[X], &bd[X]));
     }
-    const int c = chi, e = D, dd = d;
+    const int c = chi, e = De, dd = d;
     auto K = [&](int X, int ax) { return kd[X].n[ax]; };
     auto Bd = [&](int X, int ax) { return bd[X].n[ax]; };
     // top-left: C1 of TL, T1 of TL, T4 of TL
@@ -1597,13 +1598,15 @@ int block_setup(tn_ctx* ctx, const CellLinks& L, int Lx, int Ly, const int* cell
   return TN_OK;
 }
 
-int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int chi, const void* Theta, const void* C,
-                   const void* T, const void* Psu, const void* Qsu) {
+int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int De, int chi, const void* Theta,
+                   const void* C, const void* T, const void* Psu, const void* Qsu) {
   TN_TRY(check_bond(ctx, Dk, "theta bond"));
   if (D < 1 || D > Dk) TN_FAIL(ctx, TN_EINVAL, "truncated bond %d outside [1, %d]", D, Dk);
+  if (De < 1 || De > Dk)
+    TN_FAIL(ctx, TN_EINVAL, "environment bond %d outside [1, %d]", De, Dk);
   if (d < 1 || chi < 1 || !Theta || !C || !T || !Psu || !Qsu)
     TN_FAIL(ctx, TN_EINVAL, "bad bond environment arguments");
-  const double big = (double)Block::big_of(d, D, Dk, chi);
+  const double big = (double)Block::big_of(d, De, Dk, chi);
   if (big > 2.0e9) TN_FAIL(ctx, TN_EINVAL, "truncation block too large (chi %d, bond %d)", chi, Dk);
   return TN_OK;
 }
@@ -1611,19 +1614,21 @@ int bond_env_check(tn_ctx* ctx, int d, int D, int Dk, int chi, const void* Theta
 }  // namespace
 
 int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                          int Dk, const double* Theta, int chi, const double* C, const double* T,
-                          const double* Psu, const double* Qsu, const double* P, const double* Q,
+                          int Dk, int De, const double* Theta, int chi, const double* C,
+                          const double* T, const double* Psu, const double* Qsu,
+                          const double* P, const double* Q,
                           int slot, double* N_out, double* M_out) {
   CellLinks L;
   TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
-  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, Psu, Qsu));
+  TN_TRY(bond_env_check(ctx, d, D, Dk, De, chi, Theta, C, T, Psu, Qsu));
   if (!P || !Q) TN_FAIL(ctx, TN_EINVAL, "null truncation");
   if (slot < 0 || slot > 3) TN_FAIL(ctx, TN_EINVAL, "slot %d outside [0, 4)", slot);
   if (!N_out || !M_out) TN_FAIL(ctx, TN_EINVAL, "null output");
   const size_t n4 = (size_t)Dk * Dk * Dk * Dk;
-  TN_TRY(ws_reserve(ctx, Block::bytes(d, D, Dk, chi) + n4 * 8 + (1 << 20)));
+  TN_TRY(ws_reserve(ctx, Block::bytes(d, D, De, Dk, chi) + n4 * 8 + (1 << 20)));
   ws_reset(ctx);
-  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, D, C, T}, Theta, Psu, Qsu};
+  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, De, C, T}, Theta, Psu, Qsu};
+  B.De = De;
   TN_TRY(block_setup(ctx, L, Lx, Ly, cell, B));
   TN_TRY(B.alloc(ctx));
   double* Nraw = ws_alloc<double>(ctx, n4);
@@ -1641,13 +1646,14 @@ int bond_environment_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cel
 }
 
 int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* cell, int d, int D,
-                           int Dk, const double* Theta, int chi, const double* C, const double* T,
-                           const double* Psu, const double* Qsu, double* P, double* Q,
+                           int Dk, int De, const double* Theta, int chi, const double* C,
+                           const double* T, const double* Psu, const double* Qsu,
+                           double* P, double* Q,
                            int max_passes, int max_sweeps, double tol, double* cost, int* passes,
                            int* sweeps) {
   CellLinks L;
   TN_TRY(build_links(ctx, Lx, Ly, nsite, cell, L));
-  TN_TRY(bond_env_check(ctx, d, D, Dk, chi, Theta, C, T, Psu, Qsu));
+  TN_TRY(bond_env_check(ctx, d, D, Dk, De, chi, Theta, C, T, Psu, Qsu));
   if (!P || !Q) TN_FAIL(ctx, TN_EINVAL, "null truncation");
   if (max_passes < 1 || max_sweeps < 1)
     TN_FAIL(ctx, TN_EINVAL, "max_passes and max_sweeps must be >= 1");
@@ -1655,7 +1661,7 @@ int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* ce
   // the augmented k x (k + 1) system of the solve lives in LDS
   if (k > 140) TN_FAIL(ctx, TN_EINVAL, "kappa*D*D = %d too large for the ALS solve", k);
   const size_t n_ = n, n4 = n_ * n_ * n_ * n_;
-  size_t need = Block::bytes(d, D, Dk, chi);
+  size_t need = Block::bytes(d, D, De, Dk, chi);
   auto add = [&](size_t c) { need += ((c * 8 + 255) / 256) * 256; };
   add(3 * n4);                          // N raw, N symmetrised, M
   add(n_ * n_ + 4);                     // tb, T, scratch
@@ -1664,7 +1670,8 @@ int bond_env_truncate_impl(tn_ctx* ctx, int Lx, int Ly, int nsite, const int* ce
   add(64);                              // info
   TN_TRY(ws_reserve(ctx, need + (1 << 20)));
   ws_reset(ctx);
-  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, D, C, T}, Theta, Psu, Qsu};
+  Block B{&L, d, D, Dk, chi, {}, {}, {}, Env{chi, De, C, T}, Theta, Psu, Qsu};
+  B.De = De;
   TN_TRY(block_setup(ctx, L, Lx, Ly, cell, B));
   TN_TRY(B.alloc(ctx));
   double* Nraw = ws_alloc<double>(ctx, 3 * n4);

@@ -19,7 +19,7 @@ import time
 def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm=0,
                 ctm_tol=1e-10, ctm_max=100, als_tol=1e-12, als_passes=50, als_sweeps=1,
                 canon_tol=1e-14, canon_max=1000, gauge_tol=1e-12, gauge_max=1000,
-                min_fidelity=None, force_recycle=False, callback=None):
+                min_fidelity=None, force_recycle=False, callback=None, pretruncate=True):
     """Evolve the iPEPS ``sites`` (device [nsite][d][D]^4) for ``nsteps``
     steps of size dt.  C, T (device) are the start environment and are
     updated in place.  Returns (sites, log) with log entries (step,
@@ -34,10 +34,19 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
     ``callback(step, info)`` gets, per environment step, a dict with the
     energy, whether it was recycled, the gauge-fix fidelity, the CTMRG
     iterations and final delta, the block cost over the block norm and the
-    ALS cycles; a true return value ends the evolution there."""
+    ALS cycles; a true return value ends the evolution there.
+    ``pretruncate=False`` computes each environment for Theta itself, bond
+    kappa D (C, T of that bond; the O(chi^3 D^6 kappa^6) form that the
+    pre-truncation avoids, Sec. VI B): the truncation block's outer legs
+    then carry identities, and the energy is Theta's."""
     import torch
     D = sites.shape[2]
     kappa = 2
+    eye = None
+    if not pretruncate:
+        nlink = len(ctx.cell_links(Lx, Ly, sites.shape[0], cell))
+        eye = torch.eye(kappa * D, dtype=torch.float64, device=sites.device)
+        eye = eye.expand(nlink, kappa * D, kappa * D).contiguous()
     log = []
     t0 = time.perf_counter()
     step = 0
@@ -49,11 +58,14 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
         Th = ctx.ipeps_gate(sites, J, h, dt)
         _, _, Psu, Qsu, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
                                                        max_iter=canon_max, a_out=False)
-        pre = ctx.ipeps_truncate(Lx, Ly, cell, Th, Psu, Qsu)
+        if pretruncate:
+            pre, Pe, Qe = ctx.ipeps_truncate(Lx, Ly, cell, Th, Psu, Qsu), Psu, Qsu
+        else:
+            pre, Pe, Qe = Th, eye, eye
         _, ctm_iters, ctm_delta = ctx.ctmrg_iterate(Lx, Ly, pre, cell, C, T, ctm_max, ctm_tol)
         E = ctx.ipeps_energy(Lx, Ly, pre, cell, C, T, J, h)
         P, Q = Psu.clone(), Qsu.clone()
-        f, norm, passes, sweeps = ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, Psu, Qsu, P, Q,
+        f, norm, passes, sweeps = ctx.bond_env_truncate(Lx, Ly, cell, Th, C, T, Pe, Qe, P, Q,
                                                         als_passes, als_sweeps, als_tol)
         new = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
         F = None
@@ -89,3 +101,16 @@ def full_update(ctx, Lx, Ly, cell, sites, C, T, J, h, dt, nsteps, n_re=1, n_warm
         if stop:
             break
     return sites, log
+
+
+def simple_update(ctx, Lx, Ly, cell, sites, J, h, dt, nsteps, canon_tol=1e-14, canon_max=1000):
+    """The simple update (Sec. VI A): per step the iPEPO gate, then every
+    link truncated to its D largest Schmidt values through the canonical
+    form of Theta; no environment.  Returns the sites (device)."""
+    D = sites.shape[2]
+    for _ in range(nsteps):
+        Th = ctx.ipeps_gate(sites, J, h, dt)
+        _, _, P, Q, _, _ = ctx.ipeps_canonicalize(Lx, Ly, cell, Th, D_keep=D, tol=canon_tol,
+                                                   max_iter=canon_max, a_out=False)
+        sites = ctx.ipeps_truncate(Lx, Ly, cell, Th, P, Q)
+    return sites

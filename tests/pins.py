@@ -118,3 +118,29 @@ def onsager_free_energy_1d(beta: float) -> float:
     val, _ = integrate.quad(lambda p: np.log(0.5 * (1 + np.sqrt(1 - (k * np.sin(p)) ** 2))),
                             0, np.pi / 2, epsabs=1e-14, epsrel=1e-13, limit=200)
     return float(np.log(2 * np.cosh(2 * beta)) + val / np.pi)
+
+
+def tfim2d_torus_ed(Lx: int, Ly: int, h: float, J: float = 1.0) -> float:
+    """Ground-state energy per site of H = -J sum_<ij> sz sz - h sum sx on an
+    Lx x Ly torus (each nearest-neighbour bond once), by sparse Lanczos."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import eigsh
+    n = Lx * Ly
+    dim = 2 ** n
+    idx = np.arange(dim)
+    bits = (idx[:, None] >> np.arange(n)[None, :]) & 1      # bit i of state: site i
+    z = 1 - 2 * bits                                           # sz eigenvalue per site
+    site = lambda x, y: (y % Ly) * Lx + (x % Lx)
+    bonds = [(site(x, y), site(x + 1, y)) for y in range(Ly) for x in range(Lx)]
+    bonds += [(site(x, y), site(x, y + 1)) for y in range(Ly) for x in range(Lx)]
+    diag = -J * sum(z[:, i] * z[:, j] for i, j in bonds).astype(np.float64)
+    rows, cols = [idx], [idx]
+    vals = [diag]
+    for i in range(n):
+        rows.append(idx)
+        cols.append(idx ^ (1 << i))
+        vals.append(np.full(dim, -h))
+    H = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(dim, dim))
+    w = eigsh(H, k=1, which="SA", tol=1e-12, return_eigenvectors=False)
+    return float(w[0]) / n

@@ -348,3 +348,122 @@ def test_full_update_driver_parity(ctx, n_re, n_warm, nsteps, force):
         if Fr is not None:
             assert abs(F - Fr) < 1e-9
     assert rel(host(sites), np.stack(ref_sites)) < 1e-6
+
+
+def test_untruncated_environment_truncate_parity(ctx):
+    """The form without pre-truncation (Sec. VI B, closing cost remark) on
+    the one-site cell: the environment of Theta itself (bond kappa D) and
+    identities on the block's outer legs (De = kappa D); a fixed number of
+    cycles, then the links' (P, Q) means over their two slots each."""
+    Lx, Ly, cell, oc, nsite = _cell(tninputs.SINGLE_SITE)
+    D, chi = 2, 6
+    a = tninputs.ipeps_sites(7, 1, D)[0]
+    th = [gates.apply_ipepo(gates.ipepo(1.0, 3.0, 0.01), a / np.linalg.norm(a))]
+    Dk = th[0].shape[1]
+    links, _ = opeps.cell_links(oc)
+    P, Q = ofu.su_truncation(oc, th, D)
+    C, T = tninputs.ctm_env(1, 1, chi, Dk, positive=True)
+    C, T, _, _ = octm.ctmrg(oc, th, C, T, chi, 200, 1e-12)
+    eye = [np.eye(Dk) for _ in links]
+    Pr, Qr, fr, _, _, _ = ofu.fu_truncate(oc, th, eye, eye, C, T, 0.0, 2, 1, P0=P, Q0=Q)
+    tn_ = abs(ofu.block_norm(oc, th, eye, eye, C, T))
+    gP, gQ = dev(np.stack(P)), dev(np.stack(Q))
+    f, t, gp, _ = ctx.bond_env_truncate(Lx, Ly, cell, dev(np.stack(th)), dev(C), dev(T),
+                                        dev(np.stack(eye)), dev(np.stack(eye)), gP, gQ, 2, 1, 0.0)
+    assert gp == 2
+    assert abs(t - tn_) < 1e-12 * tn_
+    assert abs(f - fr) < 1e-11 * tn_
+    for b in range(len(links)):
+        assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-9, b
+    assert rel(host(gP), np.stack(Pr)) < 1e-8
+    assert rel(host(gQ), np.stack(Qr)) < 1e-8
+
+
+@pytest.fixture(scope="module")
+def one_site_start():
+    """A one-site D = 2 state 300 simple-update steps (oracle) from the
+    seeded near-product state, E = -3.1931 at h = 3.0: entangled, smoothly
+    evolving, and well conditioned (in the oracle a 1e-13 perturbation of it
+    moves the sites after three full-update steps by 5e-10).  From a
+    near-product state itself the block's environment has directions of
+    weight ~1e-14 along which R^-1 S fixes (P, Q) only through the
+    regularisation, and the sites move by 2e-7 under the same perturbation."""
+    oc = octm.Cell(1, 1, [0])
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_near_product(0, 1, 2)]
+    return ofu.run_su(oc, A, 1.0, 3.0, 0.01, 2, 300)
+
+
+@pytest.mark.parametrize("n_re,nsteps,pretruncate", [(1, 3, True), (2, 5, True), (1, 3, False)])
+def test_one_site_full_update_driver_parity(ctx, one_site_start, n_re, nsteps, pretruncate):
+    """The paper's own scheme (Sec. VI B): one-site cell, the links' (P, Q)
+    the means over their slots; plain and recycled, and the form without
+    pre-truncation.  A fixed number of ALS cycles per step on both sides (20;
+    3 without pre-truncation, its oracle block being slow)."""
+    from paper_1411_0391_amd import driver
+    Lx, Ly, cell, oc, nsite = _cell(tninputs.SINGLE_SITE)
+    D, chi, kappa = 2, 8, 2
+    A = one_site_start
+    C, T = tninputs.ctm_env(3, 1, chi, D if pretruncate else kappa * D, positive=True)
+    passes, tol = (20, 0.0) if pretruncate else (3, 0.0)
+    fids = []
+    ref_sites, ref_log = ofu.run_fu(oc, A, 1.0, 3.0, 0.01, D, chi, nsteps, n_re=n_re, C=C, T=T,
+                                    als_tol=tol, als_passes=passes, pretruncate=pretruncate,
+                                    callback=lambda st, out: fids.append(out["fidelity"]))
+    sites, log = driver.full_update(ctx, Lx, Ly, cell, dev(np.stack(A)), dev(C), dev(T), 1.0,
+                                    3.0, 0.01, nsteps, n_re=n_re, als_tol=tol, als_passes=passes,
+                                    pretruncate=pretruncate)
+    assert [s for s, *_ in log] == [s for s, *_ in ref_log]
+    assert [r for _, _, _, r, _ in log] == [r for _, _, r in ref_log]
+    for (_, e, _, _, F), (_, er, _), Fr in zip(log, ref_log, fids):
+        assert abs(e - er) < 1e-9 * abs(er)
+        if Fr is not None:
+            assert abs(F - Fr) < 1e-9
+    assert rel(host(sites), np.stack(ref_sites)) < 1e-6
+
+
+def test_full_update_energy_within_the_ed_bracket(ctx):
+    """The D = 2 full update from a near-product start at h = 3.0 (300 steps
+    of dt = 0.01): its energy per site must lie below the mean-field value
+    -2 - h^2/8 (the D = 2 state carries correlations a product state cannot)
+    and above the 4x4 torus ED value less 1% (finite-size bias of the torus
+    is downward and below 1% here)."""
+    from paper_1411_0391_amd import driver
+    from tests import pins
+    Lx, Ly, cell, oc, nsite = _cell(tninputs.CHECKERBOARD)
+    D, chi, h = 2, 16, 3.0
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_near_product(0, nsite, D)]
+    C, T = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
+    _, log = driver.full_update(ctx, Lx, Ly, cell, dev(np.stack(A)), dev(C), dev(T), 1.0, h, 0.01,
+                                300)
+    e = log[-1][1]
+    e_ed = pins.tfim2d_torus_ed(4, 4, h)
+    assert e < -2 - h * h / 8 - 0.05, e
+    assert e > 1.01 * e_ed, e
+
+
+@pytest.mark.parametrize("spec", [tninputs.SINGLE_SITE, tninputs.CHECKERBOARD])
+def test_simple_update_parity(ctx, spec):
+    """The simple update (Sec. VI A): 100 steps of gate and canonical-form
+    truncation against the oracle's, the sites entry by entry and the energy
+    and magnetisation of the result with its converged environment (chi = 4
+    converges to 1e-12 here; a larger chi leaves noise directions on which
+    delta stalls near 1e-9)."""
+    from paper_1411_0391_amd import driver
+    Lx, Ly, cell, oc, nsite = _cell(spec)
+    D, chi, h = 2, 4, 3.0
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_near_product(0, nsite, D)]
+    ref = ofu.run_su(oc, A, 1.0, h, 0.01, D, 100)
+    got = driver.simple_update(ctx, Lx, Ly, cell, dev(np.stack(A)), 1.0, h, 0.01, 100)
+    assert rel(host(got), np.stack(ref)) < 1e-8
+    C, T = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
+    Cr, Tr, _, dr = octm.ctmrg(oc, ref, C, T, chi, 100, 1e-11)
+    er = opeps.energy_per_site(oc, ref, Cr, Tr, 1.0, h)
+    mr = opeps.magnetization_z(oc, ref, Cr, Tr)
+    Cg, Tg = dev(C), dev(T)
+    _, _, dg = ctx.ctmrg_iterate(Lx, Ly, got, cell, Cg, Tg, 100, 1e-11)
+    eg = ctx.ipeps_energy(Lx, Ly, got, cell, Cg, Tg, 1.0, h)
+    r1 = host(ctx.ipeps_rdms(Lx, Ly, got, cell, Cg, Tg)[0])
+    mg = float(np.mean([np.trace(r @ np.diag([1.0, -1.0])) for r in r1]))
+    assert dr < 1e-10 and dg < 1e-10
+    assert abs(eg - er) < 1e-9 * abs(er)
+    assert abs(mg - mr) < 1e-8

@@ -182,3 +182,56 @@ def test_single_site_d4_chi32(ctx):
     print("directional derivatives gpu", gd)
     print("oracle central differences ", fd)
     np.testing.assert_allclose(gd, fd, rtol=3e-3, atol=0)
+
+
+def _richardson(A, C0, T0, chi, n_iter, dirs, h):
+    # central differences at h and 2h combined to cancel the h^2 term: the
+    # error is O(h^4) plus rounding ~1e-16 |E| / h
+    d1 = ograd.fd_directional(A, C0, T0, chi, n_iter, J, H, dirs, step=h)
+    d2 = ograd.fd_directional(A, C0, T0, chi, n_iter, J, H, dirs, step=2 * h)
+    return (4 * d1 - d2) / 3
+
+
+def _smooth_case(D, chi):
+    # a near-product state (bond-D part 0.3) and the positive seeded
+    # boundary: E(A) is smooth on the scale of 1e-2 here, unlike the N(0,1)
+    # states above, so Richardson-extrapolated differences at h = 1e-3 reach
+    # ~1e-10 (measured: estimates from h = 2e-3, 1e-3, 5e-4 agree to 1e-10
+    # relative, 2e-11 absolute on the smallest component)
+    A = tninputs.ipeps_near_product(3, 1, D, eps=0.3)[0]
+    C0, T0 = tninputs.ctm_env(4, 1, chi, D, positive=True)
+    return A, C0, T0
+
+
+@pytest.mark.timeout(600)
+def test_gradient_along_64_directions(ctx):
+    """64 seeded unit directions (D = 3, chi = 12, 6 iterations, n = 108):
+    the adjoint's directional derivatives against Richardson-extrapolated
+    central differences of the oracle's E, to 1e-7 relative."""
+    D, chi, n_iter = 3, 12, 6
+    A, C0, T0 = _smooth_case(D, chi)
+    e, g = ctx.energy_grad(dev(A), dev(C0[0]), dev(T0[0]), J, H, n_iter=n_iter, ckpt_every=2)
+    assert abs(e - ograd.energy_after(A, C0, T0, chi, n_iter, J, H)) < 1e-10 * abs(e)
+    dirs = tninputs.unit_directions(11, 64, A.shape)
+    fd = _richardson(A, C0, T0, chi, n_iter, dirs, 1e-3)
+    gd = np.tensordot(dirs, host(g), axes=A.ndim)
+    err = np.abs(gd - fd)
+    print("max relative deviation", float(np.max(err / np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max()))))
+    np.testing.assert_allclose(gd, fd, rtol=1e-7, atol=1e-9 * np.abs(fd).max())
+
+
+@pytest.mark.timeout(900)
+def test_d4_chi32_gradient_richardson(ctx):
+    """The differentiation workload's size (D = 4, chi = 32, n = 512, 20
+    iterations, checkpoints every 5) on a state where E is smooth: four
+    seeded directions against Richardson-extrapolated central differences
+    (each oracle evaluation takes ~8 s), to 1e-7 relative."""
+    D, chi, n_iter = 4, 32, 20
+    A, C0, T0 = _smooth_case(D, chi)
+    e, g = ctx.energy_grad(dev(A), dev(C0[0]), dev(T0[0]), J, H, n_iter=n_iter, ckpt_every=5)
+    assert abs(e - ograd.energy_after(A, C0, T0, chi, n_iter, J, H)) < 1e-10 * abs(e)
+    dirs = tninputs.unit_directions(5, 4, A.shape)
+    fd = _richardson(A, C0, T0, chi, n_iter, dirs, 1e-3)
+    gd = np.tensordot(dirs, host(g), axes=A.ndim)
+    print("gpu", gd, "richardson", fd)
+    np.testing.assert_allclose(gd, fd, rtol=1e-7, atol=1e-9 * np.abs(fd).max())

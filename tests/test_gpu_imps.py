@@ -196,3 +196,103 @@ def test_recycle_apply_needs_a_build(ctx):
     A = dev(np.stack(_state(1, 4)))
     with pytest.raises(tn.TNError):
         ctx.itebd_step(A, 1.0, 1.0, 0.01, ctx.env1d(4), mode=tn.TN_RECYCLE_APPLY)
+
+
+@pytest.mark.parametrize("chi,h,seed,steps", [(8, 2.0, 0, 20), (12, 2.0, 1, 50), (4, 2.0, 3, 50)])
+def test_recycle_limit_parity(ctx, chi, h, seed, steps):
+    """N_Re -> infinity (Sec. V C): an environment step, then the limit step
+    (each site the dominant eigenvector of its renormalized gate) against
+    the oracle.  The build step's factors agree to ~1e-7 (the gauge fix
+    stops at |1 - F| < 1e-12), and an eigenvector moves with its matrix by
+    that over the gap 1 - |l2 / l1|.  The limit must also be a fixed point
+    of the library's own recycled step.  The cases have a separated real
+    dominant eigenvalue (|l2 / l1| 0.98, 0.98, 0.90): where the chain is
+    near critical, or chi exceeds what the state needs, the map's leading
+    eigenvalues come within 1e-6 of each other or form a complex pair, and
+    the limit is not defined (both sides report it)."""
+    dt = 0.05
+    sites = _state(seed, chi, steps=steps, h=h)
+    g = gates.impo(1.0, h, dt)
+    new, (Lf, Rf), _, _, _ = imps.recycle_build(sites, g, chi)
+    lim, lams, ratios = imps.recycle_limit(Lf, Rf, g, new)
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    _, _, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_BUILD)
+    assert rc == tn.TN_OK
+    _, e, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_LIMIT, energy=True)
+    assert rc == tn.TN_OK
+    tol = 2e-7 / (1 - max(ratios))
+    np.testing.assert_allclose(host(A), np.stack(lim), atol=tol * np.abs(np.stack(lim)).max())
+    er = imps.energy_per_site(lim, 1.0, h)
+    assert abs(e - er) < 10 * tol * abs(er)
+    B = A.clone()
+    _, _, rc = ctx.itebd_step(B, 1.0, h, dt, env, mode=tn.TN_RECYCLE_APPLY)
+    assert rc == tn.TN_OK
+    np.testing.assert_allclose(host(B), host(A), atol=1e-10)
+
+
+def test_recycle_limit_trajectory_parity(ctx):
+    """The N_Re -> infinity scheme (a build and a limit step per environment
+    computation) reaches the fixed point of plain iTEBD in a few environment
+    steps; its final energy against the oracle's plain fixed point."""
+    chi, h, dt = 4, 2.0, 0.05
+    ref = _state(0, chi, steps=600, h=h)
+    e_ref = imps.energy_per_site(ref, 1.0, h)
+    A = dev(np.stack(_state(0, chi, steps=3, h=h)))
+    env = ctx.env1d(chi)
+    es = []
+    for _ in range(12):
+        _, _, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_BUILD)
+        assert rc >= 0
+        _, e, rc = ctx.itebd_step(A, 1.0, h, dt, env, mode=tn.TN_RECYCLE_LIMIT, energy=True)
+        assert rc == tn.TN_OK
+        es.append(e)
+    assert abs(es[0] - e_ref) > 1e-4
+    assert abs(es[-1] - e_ref) < 1e-9
+
+
+def _rand_orth(rng, n):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))
+
+
+def _gauged(a, V):
+    # site 0 sits between bond 1 (left) and bond 0 (right)
+    return [np.einsum("ia,asb,jb->isj", V[1], a[0], V[0]),
+            np.einsum("ia,asb,jb->isj", V[0], a[1], V[1])]
+
+
+@pytest.mark.parametrize("chi", [8, 16])
+def test_gauge_fix_1d_parity(ctx, chi):
+    """gauge_fix of the two-site iMPS cell, both methods of Sec. III B, on a
+    planted orthogonal gauge of a canonical state: against the oracle, and
+    the planted gauge recovered."""
+    rng = np.random.default_rng(chi)
+    a, _, _, _ = imps.canonicalize_a_form(_state(4, chi, h=1.5))
+    V = [_rand_orth(rng, chi), _rand_orth(rng, chi)]
+    new = _gauged(a, V)
+    # direct method (Eq. (iMPSDM1))
+    Ur, Fr = imps.gauge_fix_direct(a, new)
+    U = torch.zeros((2, chi, chi), dtype=torch.float64, device="cuda")
+    F, _, rc = ctx.gauge_fix_1d(dev(np.stack(a)), dev(np.stack(new)), U, method="direct",
+                                tol=1e-14, max_iter=200000)
+    assert rc == tn.TN_OK
+    assert abs(F - Fr) < 1e-12 and abs(F - 1) < 1e-10
+    np.testing.assert_allclose(host(U), np.stack(Ur), atol=1e-9)
+    sgn = np.sign(np.sum(host(U)[0] * V[0]))
+    np.testing.assert_allclose(sgn * host(U), np.stack(V), atol=1e-9)
+    # iterative method (Eq. (15)) from a perturbed start
+    start = [imps.polar_orthogonal(v + 0.2 * rng.standard_normal(v.shape)) for v in V]
+    Ui, Fi, _ = imps.gauge_fix(a, new, U0=start, tol=1e-14)
+    U = dev(np.stack(start))
+    F, _, rc = ctx.gauge_fix_1d(dev(np.stack(a)), dev(np.stack(new)), U, tol=1e-14)
+    assert rc == tn.TN_OK
+    assert abs(F - Fi) < 1e-12 and abs(F - 1) < 1e-12
+    # the iteration stops when F changes by less than 1e-14 over a pass; F is
+    # stationary at its maximum, and a rotation among the directions of the
+    # smallest Schmidt values changes it least: at 1 - F = 4e-13 the
+    # oracle's U is 8e-6 (chi = 8) and 3e-6 (chi = 16) from the planted
+    # gauge, so U is compared to 2e-5 (GPU and oracle measured 2e-7 apart)
+    np.testing.assert_allclose(host(U), np.stack(Ui), atol=2e-5)
+    sgn = np.sign(np.sum(host(U)[0] * V[0]))
+    np.testing.assert_allclose(sgn * host(U), np.stack(V), atol=2e-5)

@@ -404,3 +404,108 @@ def test_energy_is_scale_invariant():
     d = grad.fd_directional(A, C0, T0, 6, 4, 1.0, 3.0, [A / np.linalg.norm(A)])
     # rounding through the SVDs of the iterations sets the difference floor
     assert abs(d[0]) < 1e-6
+
+
+def test_one_site_truncation_is_the_slot_mean_of_the_checkerboard():
+    # The one-site cell (Sec. VI B): its block holds the horizontal link in
+    # the top and bottom slots and the vertical link in the left and right
+    # ones, and each link gets the mean of its two slots' (P, Q).  The
+    # checkerboard with B = A and the one-site environment on every position
+    # is the same block with one link per slot, so its four results, averaged
+    # over the slots of each one-site link, must give the one-site result.
+    c1 = ctmrg.Cell(1, 1, [0])
+    cb = ctmrg.Cell(2, 2, [0, 1, 1, 0])
+    g = gates.ipepo(1.0, 3.0, 0.01)
+    D, chi = 2, 6
+    a = tninputs.ipeps_sites(7, 1, D)[0]
+    th = [gates.apply_ipepo(g, a / np.linalg.norm(a))]
+    P, Q = fu.su_truncation(c1, th, D)
+    links1, _ = peps.cell_links(c1)
+    C, T = _env(c1, chi, D, seed=1)
+    C, T, _, _ = ctmrg.ctmrg(c1, peps.truncate(th, links1, P, Q), C, T, chi, 100, 1e-10)
+    P1, Q1, f1, _, _, _ = fu.fu_truncate(c1, th, P, Q, C, T, 0.0, 3, 1)
+    linksb, _ = peps.cell_links(cb)
+    onesite = [0 if leg == "r" else 1 for _, leg, _, _ in linksb]
+    Pb, Qb, fb, _, _, _ = fu.fu_truncate(cb, [th[0], th[0]], [P[m] for m in onesite],
+                                         [Q[m] for m in onesite], np.repeat(C, 4, axis=0),
+                                         np.repeat(T, 4, axis=0), 0.0, 3, 1)
+    assert abs(fb - f1) < 1e-12 * abs(fu.block_norm(c1, th, P, Q, C, T))
+    for link in (0, 1):
+        ks = [b for b in range(4) if onesite[b] == link]
+        assert len(ks) == 2
+        np.testing.assert_allclose(sum(Pb[b] for b in ks) / 2, P1[link], atol=1e-12)
+        np.testing.assert_allclose(sum(Qb[b] for b in ks) / 2, Q1[link], atol=1e-12)
+
+
+def test_untruncated_environment_equals_an_orthogonal_pretruncation():
+    # The form without pre-truncation (Sec. VI B, closing cost remark): the
+    # environment of Theta itself and identities on the block's outer legs.
+    # An orthogonal gauge O per link (O on the first end, O^T on the second)
+    # is a pre-truncation that keeps the state; CTMRG is covariant under it,
+    # so the truncation from the environment of the gauged Theta with
+    # (O, O^T) on the outer legs must equal the untruncated form, while the
+    # wrong orientation (O on both ends) must not.
+    c1 = ctmrg.Cell(1, 1, [0])
+    g = gates.ipepo(1.0, 3.0, 0.01)
+    D, chi = 2, 6
+    a = tninputs.ipeps_sites(7, 1, D)[0]
+    th = [gates.apply_ipepo(g, a / np.linalg.norm(a))]
+    Dk = th[0].shape[1]
+    links, _ = peps.cell_links(c1)
+    P0, Q0 = fu.su_truncation(c1, th, D)
+    rng = np.random.default_rng(3)
+    O = []
+    for _ in links:
+        q, r = np.linalg.qr(rng.standard_normal((Dk, Dk)))
+        O.append(q * np.sign(np.diag(r)))
+    Ot = [o.T for o in O]
+    eye = [np.eye(Dk) for _ in links]
+    Ca, Ta = _env(c1, chi, Dk, seed=1)
+    C1, T1, _, d1 = ctmrg.ctmrg(c1, th, Ca, Ta, chi, 200, 1e-12)
+    C2, T2, _, d2 = ctmrg.ctmrg(c1, peps.truncate(th, links, O, Ot), Ca, Ta, chi, 200, 1e-12)
+    assert d1 < 1e-12 and d2 < 1e-12
+    r1 = fu.fu_truncate(c1, th, eye, eye, C1, T1, 0.0, 2, 1, P0=P0, Q0=Q0)
+    r2 = fu.fu_truncate(c1, th, O, Ot, C2, T2, 0.0, 2, 1, P0=P0, Q0=Q0)
+    t1 = abs(fu.block_norm(c1, th, eye, eye, C1, T1))
+    t2 = abs(fu.block_norm(c1, th, O, Ot, C2, T2))
+    # the two environments agree to the CTMRG tolerance
+    assert abs(r1[2] / t1 - r2[2] / t2) < 1e-9 * r1[2] / t1
+    for b in range(len(links)):
+        assert np.abs(r1[0][b] @ r1[1][b] - r2[0][b] @ r2[1][b]).max() < 1e-9
+    r3 = fu.fu_truncate(c1, th, O, O, C2, T2, 0.0, 1, 1, P0=P0, Q0=Q0)
+    assert max(np.abs(r1[0][b] @ r1[1][b] - r3[0][b] @ r3[1][b]).max() for b in (0, 1)) > 0.1
+
+
+def test_torus_ed_brackets():
+    # the 4x4 torus ED that brackets 2D energies loosely (finite size): its
+    # own limits (h = 0: -2 exactly; h >> J: -h - J^2 / (2 h) from second-order
+    # perturbation, two bonds per site, the next order J^4 / h^3 coming from
+    # the plaquettes: 5e-6 at h = 50), the 4x4 values at h = 3.0, 3.05, and
+    # the variational bound it sets for product states (mean field -2 - h^2/8)
+    assert abs(pins.tfim2d_torus_ed(3, 3, 0.0) + 2.0) < 1e-12
+    h = 50.0
+    assert abs(pins.tfim2d_torus_ed(4, 4, h) - (-h - 1.0 / (2 * h))) < 1e-5
+    e3 = pins.tfim2d_torus_ed(4, 4, 3.0)
+    assert abs(e3 + 3.215508) < 1e-6
+    assert abs(pins.tfim2d_torus_ed(4, 4, 3.05) + 3.259021) < 1e-6
+    assert e3 < -2 - 3.0 ** 2 / 8
+
+
+def test_simple_update_limits():
+    # no interaction: the gate is a product of one-site gates, the state
+    # goes to the x-polarised product state, E = -h
+    oc = ctmrg.Cell(1, 1, [0])
+    A = [a / np.linalg.norm(a) for a in tninputs.ipeps_near_product(0, 1, 1)]
+    s = fu.run_su(oc, A, 0.0, 3.0, 0.05, 1, 200)
+    C, T = _env(oc, 1, 1, seed=1)
+    C, T, _, _ = ctmrg.ctmrg(oc, s, C, T, 1, 10, 1e-12)
+    assert abs(peps.energy_per_site(oc, s, C, T, 0.0, 3.0) + 3.0) < 1e-12
+    # D = 1: the simple update tends to the mean-field product state,
+    # E = -2 - h^2 / 8, with a Trotter error that falls as dt^2
+    errs = []
+    for dt in (0.02, 0.01):
+        s = fu.run_su(oc, A, 1.0, 3.0, dt, 1, int(4 / dt))
+        C, T = _env(oc, 1, 1, seed=1)
+        C, T, _, _ = ctmrg.ctmrg(oc, s, C, T, 1, 10, 1e-12)
+        errs.append(peps.energy_per_site(oc, s, C, T, 1.0, 3.0) - (-2 - 3.0 ** 2 / 8))
+    assert 0 < errs[1] < 1e-4 and errs[0] / errs[1] > 3

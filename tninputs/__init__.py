@@ -59,6 +59,22 @@ def ipeps_sites(seed: int, nsite: int, D: int, d: int = 2):
     return [rng.standard_normal((d, D, D, D, D)) for _ in range(nsite)]
 
 
+def ipeps_near_product(seed: int, nsite: int, D: int, eps: float = 1e-2, d: int = 2):
+    """A random product state with a small bond-D part: the N(0,1) tensors
+    of bond 1 from ``seed`` (``ipeps_sites(seed, nsite, 1)``) on the index-0
+    corner of each bond, plus ``eps`` times the N(0,1) bond-D tensors from
+    ``seed + 1``.  Random bond-D tensors alone carry closed-loop
+    correlations on their bonds that imaginary-time evolution does not
+    remove; this start has none."""
+    prod, noise = ipeps_sites(seed, nsite, 1, d), ipeps_sites(seed + 1, nsite, D, d)
+    out = []
+    for a, z in zip(prod, noise):
+        t = eps * z
+        t[:, 0, 0, 0, 0] += a[:, 0, 0, 0, 0]
+        out.append(t)
+    return out
+
+
 def ctm_env(seed: int, npos: int, chi: int, D: int, positive: bool = False):
     """Random CTM environment for ``npos`` cell positions.
 
