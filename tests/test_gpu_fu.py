@@ -104,10 +104,12 @@ def test_su_pretruncation_parity(ctx):
     _, _, gP, gQ, _, rc = ctx.ipeps_canonicalize(Lx, Ly, cell, Thg, D_keep=D, tol=1e-13,
                                                  a_out=False)
     assert rc == 0
+    # both sides stop the canonical-form iteration when the spectra move by
+    # less than 1e-13; measured deviations 1e-13 to 4e-13 in P, Q and P Q
     for b in range(len(P)):
-        assert rel(host(gP)[b] @ host(gQ)[b], P[b] @ Q[b]) < 1e-8
-    assert rel(host(gP), np.stack(P)) < 1e-7
-    assert rel(host(gQ), np.stack(Q)) < 1e-7
+        assert rel(host(gP)[b] @ host(gQ)[b], P[b] @ Q[b]) < 1e-11
+    assert rel(host(gP), np.stack(P)) < 1e-11
+    assert rel(host(gQ), np.stack(Q)) < 1e-11
 
 
 def _fu_state(spec, D, chi, converged, seed=0):
@@ -206,7 +208,7 @@ def test_full_update_chain_d4_chi32(ctx, c2_state):
     assert rc == 0
     Pt, Qt = ofu.su_truncation(oc, th, D, tol=1e-13)
     for b in range(len(P)):
-        assert rel(host(gPs)[b] @ host(gQs)[b], Pt[b] @ Qt[b]) < 1e-8
+        assert rel(host(gPs)[b] @ host(gQs)[b], Pt[b] @ Qt[b]) < 1e-11
     # environments of the top and bottom slots
     for k in (0, 2):
         N, M = ofu.bond_environment(oc, th, P, Q, P, Q, C, T, k)
