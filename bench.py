@@ -130,8 +130,8 @@ def run_classical(args):
     """The classical workload (Sec. I): the partition function of the 2D
     Ising model at inverse temperature --cl-beta by the power method on the
     row transfer matrix with a two-site iMPS, chi = --cl-chi, from seeded
-    N(0,1) tensors.  Plain (environment every step), recycled (N_Re = 20
-    after 20 plain steps) and the limit N_Re -> infinity (20 plain steps,
+    N(0,1) tensors.  Plain (environment every step), recycled (N_Re =
+    --cl-nre after 20 plain steps) and the limit N_Re -> infinity (20 plain steps,
     then an environment step and the dominant eigenvector of its
     renormalized gate, repeated).  ln Z per site is measured every 20 steps
     (every environment step of the limit run).  The plain run goes on until
@@ -143,7 +143,7 @@ def run_classical(args):
     import torch
     import paper_1411_0391_amd as tn
     import tninputs
-    beta, chi, n_re, warm = args.cl_beta, args.cl_chi, 20, 20
+    beta, chi, n_re, warm = args.cl_beta, args.cl_chi, args.cl_nre, 20
     ga, _, gb, _ = tninputs.imps_two_site(0, chi)
     A0 = np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)])
     ctx = tn.Context()
@@ -180,11 +180,13 @@ def run_classical(args):
                     continue
             t = time.perf_counter() - t0
             hist.append((step, t, lz))
+            print(f"[bench] classical {label} step {step} ln Z {lz:.15f} t {t:.2f}s",
+                  file=sys.stderr, flush=True)
             if ref is not None and t_hit is None and abs(lz - ref) <= 1e-10 * abs(ref):
                 t_hit = t
             if ref is None and len(hist) > 5 and abs(lz - hist[-6][2]) < 1e-13 * abs(lz):
                 break
-            if ref is not None and t_hit is not None and step >= 200:
+            if ref is not None and t_hit is not None and step >= 100:
                 break
         print(f"[bench] classical {label}: {step} steps, ln Z {hist[-1][2]:.15f}",
               file=sys.stderr, flush=True)
@@ -193,9 +195,10 @@ def run_classical(args):
 
     plain = run("plain", "plain")
     ref = plain["ln_z"]
-    plain = run("plain", "plain", ref)
-    rec = run("recycled", "recycled", ref)
-    lim = run("limit", "limit", ref)
+    cap = 4 * plain["steps"]
+    plain = run("plain", "plain", ref, cap)
+    rec = run("recycled", "recycled", ref, cap)
+    lim = run("limit", "limit", ref, cap)
     exact = None
     try:
         sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
@@ -381,6 +384,9 @@ def main():
                     help="the classical 2D Ising partition function (power method, recycling)")
     ap.add_argument("--cl-beta", type=float, default=0.42)
     ap.add_argument("--cl-chi", type=int, default=16)
+    ap.add_argument("--cl-nre", type=int, default=5,
+                    help="N_Re of the recycled power method (the transfer matrix changes the "
+                         "state much more per step than a small imaginary-time step)")
     ap.add_argument("--fu", action="store_true",
                     help="run the 2D full-update time-to-1e-6 workload instead")
     ap.add_argument("--fu-steps", type=int, default=1500,
