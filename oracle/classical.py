@@ -80,14 +80,15 @@ def sigma_x(sites):
     return -imps.energy_per_site(sites, 0.0, 1.0)
 
 
-def power_method(sites, beta, chi, nsteps, n_re=1, n_warm=0):
+def power_method(sites, beta, chi, nsteps, n_re=1, n_warm=0, gauge="iterative"):
     """``n_warm`` plain applications of the transfer matrix with the
     truncation of iTEBD, then ``nsteps`` more: plain with n_re = 1, the
     environment recycled otherwise, the limit N_Re -> infinity with
-    n_re = None (nsteps then counts environment steps).  Returns the
-    sites."""
+    n_re = None (nsteps then counts environment steps); ``gauge`` is the
+    gauge fix of the recycling's environment steps ("iterative" or
+    "direct").  Returns the sites."""
     J, h, dt = row_gate(beta)
     if n_warm:
         sites, _ = imps.run_itebd(sites, J, h, dt, chi, n_warm)
-    out, _ = imps.run_itebd(sites, J, h, dt, chi, nsteps, n_re=n_re)
+    out, _ = imps.run_itebd(sites, J, h, dt, chi, nsteps, n_re=n_re, gauge=gauge)
     return out

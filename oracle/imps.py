@@ -459,17 +459,23 @@ def apply_renormalized(Lf, Rf, g, sites):
     return [t / np.linalg.norm(t) for t in new]
 
 
-def recycle_build(sites, g, chi):
+def recycle_build(sites, g, chi, gauge="iterative"):
     """Environment step of the recycling scheme (Sec. V B (i)-(iii)):
     truncate g A_0 with a fresh environment, canonicalize, gauge-fix against
-    A_0, and build the renormalized gate.  Returns (new_sites, (Lf, Rf),
-    spectra, trunc_err, fidelity)."""
+    A_0 (``gauge``: "iterative", Sec. III B 2, or "direct", Sec. III B 1),
+    and build the renormalized gate.  Returns (new_sites, (Lf, Rf), spectra,
+    trunc_err, fidelity)."""
     # the scheme starts from a canonical A_0
     sites, _, _, _ = canonicalize_a_form(sites)
     trunc, P, Q, spec, err = itebd_plain_step(sites, g, chi)
     a1, l1, Qc, Pc = canonicalize_a_form(trunc, spec)
     kappa = g.shape[0]
-    U, F, _ = gauge_fix(sites, a1, U0=gauge_start(P, Pc, Q, Qc, kappa))
+    if gauge == "direct":
+        U, F = gauge_fix_direct(sites, a1)
+    elif gauge == "iterative":
+        U, F, _ = gauge_fix(sites, a1, U0=gauge_start(P, Pc, Q, Qc, kappa))
+    else:
+        raise ValueError(f"unknown gauge-fix method {gauge!r}")
     Lf, Rf = renormalized_gate(P, Q, Qc, Pc, U)
     new = apply_renormalized(Lf, Rf, g, sites)
     return new, (Lf, Rf), l1, err, F
@@ -515,21 +521,22 @@ def recycle_limit(Lf, Rf, g, sites):
     return out, lams, ratios
 
 
-def run_itebd(sites, J, h, dt, chi, nsteps, n_re=1, energy_every=None):
+def run_itebd(sites, J, h, dt, chi, nsteps, n_re=1, energy_every=None, gauge="iterative"):
     """Imaginary-time iTEBD (Eq. (eq), power method on the iMPO) with the
     environment recomputed every ``n_re`` steps and the renormalized gate
     applied in between.  ``n_re=1`` is the plain algorithm; ``n_re=None`` is
     the limit N_Re -> infinity (each environment step jumps to the dominant
     eigenvector of its renormalized gate; ``nsteps`` then counts environment
-    steps).  Returns the final sites and a list of (step, energy) taken at
-    environment steps."""
+    steps).  ``gauge`` picks the gauge fix of the environment steps (see
+    recycle_build).  Returns the final sites and a list of (step, energy)
+    taken at environment steps."""
     g = gates.impo(J, h, dt)
     sites = [s / np.linalg.norm(s) for s in sites]
     log = []
     fac = None
     if n_re is None:
         for step in range(nsteps):
-            sites, fac, _, _, _ = recycle_build(sites, g, chi)
+            sites, fac, _, _, _ = recycle_build(sites, g, chi, gauge)
             sites, _, _ = recycle_limit(fac[0], fac[1], g, sites)
             if energy_every and step % energy_every == 0:
                 log.append((step + 1, energy_per_site(sites, J, h)))
@@ -539,7 +546,7 @@ def run_itebd(sites, J, h, dt, chi, nsteps, n_re=1, energy_every=None):
             if n_re == 1:
                 sites, _, _, _, _ = itebd_plain_step(sites, g, chi)
             else:
-                sites, fac, _, _, _ = recycle_build(sites, g, chi)
+                sites, fac, _, _, _ = recycle_build(sites, g, chi, gauge)
             if energy_every and (step // n_re) % energy_every == 0:
                 log.append((step + 1, energy_per_site(sites, J, h)))
         else:
