@@ -133,7 +133,8 @@ def run_classical(args):
     N(0,1) tensors.  Plain (environment every step), recycled (N_Re =
     --cl-nre after 20 plain steps) and the limit N_Re -> infinity (20 plain steps,
     then an environment step and the dominant eigenvector of its
-    renormalized gate, repeated).  ln Z per site is measured every 20 steps
+    renormalized gate, repeated); the environment steps fix the gauge by
+    --cl-gauge (direct, Sec. III B 1, or iterative, Sec. III B 2).  ln Z per site is measured every 20 steps
     (every environment step of the limit run).  The plain run goes on until
     ln Z changes by less than 1e-13 over 100 steps; its value is the
     reference, and time-to-1e-10 is the wall time to the first measurement
@@ -144,6 +145,7 @@ def run_classical(args):
     import paper_1411_0391_amd as tn
     import tninputs
     beta, chi, n_re, warm = args.cl_beta, args.cl_chi, args.cl_nre, 20
+    build = tn.TN_RECYCLE_BUILD_DIRECT if args.cl_gauge == "direct" else tn.TN_RECYCLE_BUILD
     ga, _, gb, _ = tninputs.imps_two_site(0, chi)
     A0 = np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)])
     ctx = tn.Context()
@@ -151,7 +153,8 @@ def run_classical(args):
            "unit": "s", "higher_is_better": False,
            "config": {"workload": f"2D classical Ising partition function, iMPS power method on the "
                                   f"row transfer matrix, beta={beta}, chi={chi}, N_Re={n_re}, "
-                                  f"N_warm={warm}", "beta": beta, "chi": chi},
+                                  f"N_warm={warm}, {args.cl_gauge} gauge fix", "beta": beta,
+                      "chi": chi},
            "data": "synthetic", "dtype": "f64", "n_gpus": 1}
 
     def run(label, kind, ref=None, max_steps=20000):
@@ -162,7 +165,7 @@ def run_classical(args):
         t0 = time.perf_counter()
         while step < max_steps:
             if kind == "limit" and step >= warm:
-                ctx.ising2d_tm_step(A, beta, env, mode=tn.TN_RECYCLE_BUILD)
+                ctx.ising2d_tm_step(A, beta, env, mode=build)
                 _, lz, rc = ctx.ising2d_tm_step(A, beta, env, mode=tn.TN_RECYCLE_LIMIT, lnz=True)
                 step += n_re
                 envs += 1
@@ -171,8 +174,7 @@ def run_classical(args):
                 if kind == "plain" or step < warm:
                     mode = tn.TN_PLAIN
                 else:
-                    mode = tn.TN_RECYCLE_BUILD if (step - warm) % n_re == 0 else \
-                        tn.TN_RECYCLE_APPLY
+                    mode = build if (step - warm) % n_re == 0 else tn.TN_RECYCLE_APPLY
                 _, lz, _ = ctx.ising2d_tm_step(A, beta, env, mode=mode, lnz=meas)
                 envs += mode != tn.TN_RECYCLE_APPLY
                 step += 1
@@ -384,9 +386,10 @@ def main():
                     help="the classical 2D Ising partition function (power method, recycling)")
     ap.add_argument("--cl-beta", type=float, default=0.42)
     ap.add_argument("--cl-chi", type=int, default=16)
-    ap.add_argument("--cl-nre", type=int, default=5,
-                    help="N_Re of the recycled power method (the transfer matrix changes the "
-                         "state much more per step than a small imaginary-time step)")
+    ap.add_argument("--cl-gauge", choices=["direct", "iterative"], default="direct",
+                    help="gauge fix of the recycling's environment steps")
+    ap.add_argument("--cl-nre", type=int, default=20,
+                    help="N_Re of the recycled power method")
     ap.add_argument("--fu", action="store_true",
                     help="run the 2D full-update time-to-1e-6 workload instead")
     ap.add_argument("--fu-steps", type=int, default=1500,

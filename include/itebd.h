@@ -181,7 +181,13 @@ int tm_fixed_point_noalloc(tn_ctx* ctx, int n_sites, int chi, int d, const doubl
 size_t tn_env1d_size(int chi, int d);
 
 /* itebd_step modes */
-enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2, TN_RECYCLE_LIMIT = 3 };
+enum {
+  TN_PLAIN = 0,
+  TN_RECYCLE_BUILD = 1,
+  TN_RECYCLE_APPLY = 2,
+  TN_RECYCLE_LIMIT = 3,
+  TN_RECYCLE_BUILD_DIRECT = 4
+};
 
 /*
  * itebd_step -- one imaginary-time step of the transverse-field Ising chain
@@ -199,7 +205,15 @@ enum { TN_PLAIN = 0, TN_RECYCLE_BUILD = 1, TN_RECYCLE_APPLY = 2, TN_RECYCLE_LIMI
  *              against A_0 by the alternating Procrustes maximisation of the
  *              fidelity (start: kappa = 0 blocks of P Pc and Qc Q), and the
  *              renormalized gate G = U^T (Qc Q) g (P Pc) U is stored in
- *              env1d; the new state is G A_0.  Needs chi <= 16.
+ *              env1d; the new state is G A_0.  Needs chi <= 64.
+ *              TN_RECYCLE_BUILD_DIRECT: the same environment step with the
+ *              gauge fixed by the direct method (Sec. III B 1, Eq.
+ *              (iMPSDM1)): per bond U is the orthogonal polar factor of the
+ *              transposed dominant left eigenvector of the mixed transfer
+ *              matrix of (A_0, canonical truncated state), the pair's sign
+ *              taken with a positive fidelity.  Stays at the fixed point
+ *              where the Procrustes iteration stalls (a Schmidt spectrum
+ *              with near-degenerate pairs, a gate far from the identity).
  *              TN_RECYCLE_APPLY: A <- G A with the stored G (no environment);
  *              TN_EINVAL if no build step has stored one; lambda_out is not
  *              written and trunc_err is 0.
@@ -348,7 +362,7 @@ enum { TN_GAUGE_2D = 0, TN_GAUGE_1D = 1, TN_GAUGE_1D_DIRECT = 2 };
  *          w U^T with w the positive fixed point of a_ref, so U is the
  *          orthogonal polar factor of X^T; the sign of the pair is taken
  *          with F > 0.  U is output only; tol, max_iter bound the
- *          fixed-point iterations.  chi <= 32 for both 1D kinds.
+ *          fixed-point iterations.  chi <= 64 for both 1D kinds.
  *   U             device in/out [nlink][D][D] (1D: [2][chi][chi])
  *   fidelity, iters  host out
  * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL, TN_ENUMERIC, TN_EHIP.

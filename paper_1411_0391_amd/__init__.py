@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libitebd.so")
 TN_OK, TN_NOT_CONVERGED = 0, 1
 TN_FP64, TN_FP32, TN_BF16 = 0, 1, 2
 TN_PLAIN, TN_RECYCLE_BUILD, TN_RECYCLE_APPLY, TN_RECYCLE_LIMIT = 0, 1, 2, 3
+TN_RECYCLE_BUILD_DIRECT = 4
 TN_GAUGE_2D, TN_GAUGE_1D, TN_GAUGE_1D_DIRECT = 0, 1, 2
 _PREC = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16}
 

@@ -28,6 +28,10 @@ struct BondNet {
   }
 };
 
+// Largest bond of the small per-leg kernels (canonical form, gauge fixing,
+// ALS cost), whose n x n tiles live in LDS.
+constexpr int TN_SMALL_BOND = 64;
+
 // The two-site iMPS cell [chi][d][chi] (left, physical, right): link 0 joins
 // the right leg of site 0 to the left leg of site 1, link 1 the right leg of
 // site 1 to the left leg of site 0.
@@ -51,7 +55,7 @@ int bondnet_canonicalize(tn_ctx* ctx, const BondNet& net, int n, const double* A
 // bondnet_canonicalize leaves them): P [nl][n][n] acts on the first ends and
 // Q, its inverse up to a factor, on the second.  The sign rule goes on the
 // columns of P (the rows of Q flip with them); then P Q = I through its
-// trace and |P|_F = |Q|_F.  n <= 32.
+// trace and |P|_F = |Q|_F.  n <= TN_SMALL_BOND.
 int canonical_pq(tn_ctx* ctx, int nl, int n, const double* P, const double* Q, double* Pc,
                  double* Qc);
 

@@ -31,48 +31,66 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+typedef double tm_dv4 __attribute__((ext_vector_type(4)));
+
+// C = A B for small matrices given by element accessors, on FP64 MFMA
+// 16x16x4 tiles: each wave of the workgroup takes 16 x 16 output tiles in
+// turn; lane (hi, lo) = (lane / 16, lane % 16) supplies A[row lo][k hi] and
+// B[k hi][col lo] of each k-step and holds C[row hi + 4 r][col lo].  Rows,
+// columns and k past the sizes read as zero and are not written.
+template <class FA, class FB, class FC>
+__device__ void small_gemm(int Mr, int Nc, int Kd, FA a, FB b, FC c) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int hi = lane >> 4, lo = lane & 15;
+  const int tn = (Nc + 15) / 16, nt = ((Mr + 15) / 16) * tn, nk = (Kd + 3) / 4;
+  for (int tile = wv; tile < nt; tile += nw) {
+    const int r0 = (tile / tn) * 16, c0 = (tile % tn) * 16;
+    const int ra = r0 + lo, cb = c0 + lo;
+    tm_dv4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < nk; ++q) {
+      const int k = 4 * q + hi;
+      const double av = (ra < Mr && k < Kd) ? a(ra, k) : 0.0;
+      const double bv = (k < Kd && cb < Nc) ? b(k, cb) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + hi + 4 * r;
+      if (row < Mr && cb < Nc) c(row, cb, acc[r]);
+    }
+  }
+}
+
 // v <- one application of the cell transfer matrix (left: v -> sum K^T v B
-// site by site in cell order; right: v -> sum K v B^T, last site first)
+// site by site in cell order; right: v -> sum K v B^T, last site first),
+// each site as two small products on MFMA
 __device__ void tm_apply(const double* K, const double* B, int nsite, int chi, int d, int left,
                          double* v, double* x) {
-  const int tid = threadIdx.x;
-  const int cdc = chi * d * chi;
+  const int cdc = chi * d * chi, dn = d * chi;
   for (int q = 0; q < nsite; ++q) {
     const int site = left ? q : nsite - 1 - q;
     const double* k = K + (long long)site * cdc;
     const double* bb = B + (long long)site * cdc;
     if (left) {
-      // x[b][s][c] = sum_a v[a][b] k[a][s][c]
-      for (int t = tid; t < cdc; t += TM_THREADS) {
-        const int b = t / (d * chi), sc = t % (d * chi);
-        double acc = 0.0;
-        for (int a = 0; a < chi; ++a) acc += v[a * chi + b] * k[a * d * chi + sc];
-        x[t] = acc;
-      }
+      // x[b][(s c)] = sum_a v[a][b] k[a][(s c)]
+      small_gemm(chi, dn, chi, [&](int r, int kk) { return v[kk * chi + r]; },
+                 [&](int kk, int c) { return k[kk * dn + c]; },
+                 [&](int r, int c, double val) { x[r * dn + c] = val; });
       __syncthreads();
-      // v[c][e] = sum_{b,s} x[b][s][c] bb[b][s][e]
-      for (int t = tid; t < chi * chi; t += TM_THREADS) {
-        const int c = t / chi, e = t % chi;
-        double acc = 0.0;
-        for (int bs = 0; bs < chi * d; ++bs) acc += x[bs * chi + c] * bb[bs * chi + e];
-        v[t] = acc;
-      }
+      // v[c][e] = sum_{(b s)} x[(b s)][c] bb[(b s)][e]
+      small_gemm(chi, chi, dn, [&](int r, int kk) { return x[kk * chi + r]; },
+                 [&](int kk, int c) { return bb[kk * chi + c]; },
+                 [&](int r, int c, double val) { v[r * chi + c] = val; });
     } else {
-      // x[a][s][e] = sum_c k[a][s][c] v[c][e]
-      for (int t = tid; t < cdc; t += TM_THREADS) {
-        const int as = t / chi, e = t % chi;
-        double acc = 0.0;
-        for (int c = 0; c < chi; ++c) acc += k[as * chi + c] * v[c * chi + e];
-        x[t] = acc;
-      }
+      // x[(a s)][e] = sum_c k[(a s)][c] v[c][e]
+      small_gemm(dn, chi, chi, [&](int r, int kk) { return k[r * chi + kk]; },
+                 [&](int kk, int c) { return v[kk * chi + c]; },
+                 [&](int r, int c, double val) { x[r * chi + c] = val; });
       __syncthreads();
-      // v[a][b] = sum_{s,e} x[a][s][e] bb[b][s][e]
-      for (int t = tid; t < chi * chi; t += TM_THREADS) {
-        const int a = t / chi, b = t % chi;
-        double acc = 0.0;
-        for (int se = 0; se < d * chi; ++se) acc += x[a * d * chi + se] * bb[b * d * chi + se];
-        v[t] = acc;
-      }
+      // v[a][b] = sum_{(s e)} x[a][(s e)] bb[b][(s e)]
+      small_gemm(chi, chi, dn, [&](int r, int kk) { return x[r * dn + kk]; },
+                 [&](int kk, int c) { return bb[c * dn + kk]; },
+                 [&](int r, int c, double val) { v[r * chi + c] = val; });
     }
     __syncthreads();
   }
@@ -152,6 +170,225 @@ __global__ __launch_bounds__(TM_THREADS) void tm_power_kernel(
   if (tid == 0) {
     eta[blockIdx.x] = ev;
     iters[blockIdx.x] = it;
+  }
+}
+
+// Restarted Arnoldi for the same fixed point: per restart an m-step Krylov
+// basis V_0 = v, V_{j+1} ~ (TM - h) V_j, orthogonalised by two passes of
+// classical Gram-Schmidt, the Hessenberg matrix H of TM on the basis, and
+// the dominant Ritz pair (theta, y) of H by repeated squaring of H applied
+// to e_0 (normalised); v <- V y with unit norm and positive trace.  The
+// Arnoldi relation gives the residual |TM v - theta v| = |H[m][m-1] y[m-1]|;
+// the restarts end when it is below tol |theta|.  Near the critical field,
+// where the transfer matrix's gap is small, this takes an order of magnitude
+// fewer applications than the power iteration.  kry: (TM_KRYLOV + 1) chi^2
+// doubles per side.  iters counts applications (>= max_iter when not
+// converged).
+constexpr int TM_KRYLOV = 12;
+
+// Orders the LDS accesses of one wave among themselves (a wave's LDS
+// instructions complete in order; this keeps the compiler from moving them
+// across the point).  Only for code that a single wave runs: a workgroup
+// barrier there would pair with the other waves' barriers.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(TM_THREADS) void tm_krylov_kernel(
+    const double* __restrict__ kets, const double* __restrict__ bras, int nsite, int chi, int d,
+    double* __restrict__ vout, double* __restrict__ eta, int* __restrict__ iters, double tol,
+    int max_iter, int warm, double* __restrict__ gwork, double* __restrict__ kry) {
+  constexpr int M = TM_KRYLOV;
+  constexpr int NW = TM_THREADS / 64;
+  extern __shared__ double lds[];
+  __shared__ double red[NW];
+  __shared__ double part[NW][M];
+  __shared__ double H[(M + 1) * M];
+  __shared__ double Hp[M * M], Hq[M * M];
+  __shared__ double hcol[M + 1], y[M], sc[4];
+  const int left = blockIdx.x == 0 ? 1 : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cdc = chi * d * chi, cc = chi * chi;
+  const long long per = 2LL * nsite * cdc + 2LL * cc + cdc;
+  double* base;
+  if constexpr (GLOBAL)
+    base = gwork + blockIdx.x * per;
+  else
+    base = lds;
+  double* K = base;
+  double* B = K + (long long)nsite * cdc;
+  double* v = B + (long long)nsite * cdc;
+  double* w = v + cc;
+  double* x = w + cc;
+  double* V = kry + (long long)blockIdx.x * (M + 1) * cc;
+  for (long long t = tid; t < (long long)nsite * cdc; t += TM_THREADS) {
+    K[t] = kets[t];
+    B[t] = bras[t];
+  }
+  double* vo = vout + blockIdx.x * cc;
+  for (int t = tid; t < cc; t += TM_THREADS)
+    v[t] = warm ? vo[t] : ((t / chi == t % chi) ? 1.0 : 0.0);
+  __syncthreads();
+  int mv = 0;
+  double theta = 0.0;
+  bool conv = false;
+  while (!conv && mv < max_iter) {
+    // V_0 = v / |v|
+    {
+      double a = 0.0;
+      for (int t = tid; t < cc; t += TM_THREADS) a += v[t] * v[t];
+      const double nrm = sqrt(block_sum(a, red));
+      const double f = nrm > 0.0 ? 1.0 / nrm : 1.0;
+      for (int t = tid; t < cc; t += TM_THREADS) V[t] = v[t] * f;
+    }
+    __syncthreads();
+    int m = 0;
+    for (int j = 0; j < M; ++j) {
+      for (int t = tid; t < cc; t += TM_THREADS) w[t] = V[(long long)j * cc + t];
+      __syncthreads();
+      tm_apply(K, B, nsite, chi, d, left, w, x);
+      ++mv;
+      if (tid <= j) hcol[tid] = 0.0;
+      // two passes of classical Gram-Schmidt against V_0..V_j
+      for (int pass = 0; pass < 2; ++pass) {
+        double hp[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) hp[i] = 0.0;
+        for (int t = tid; t < cc; t += TM_THREADS) {
+          const double wt = w[t];
+#pragma unroll
+          for (int i = 0; i < M; ++i)
+            if (i <= j) hp[i] += V[(long long)i * cc + t] * wt;
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          if (i <= j) {  // uniform over the wave
+            double a = hp[i];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+            if (lane == 0) part[wv][i] = a;
+          }
+        }
+        __syncthreads();
+        if (tid <= j) {
+          double a = 0.0;
+          for (int q = 0; q < NW; ++q) a += part[q][tid];
+          hcol[tid] += a;
+          y[tid] = a;  // this pass's coefficients
+        }
+        __syncthreads();
+        for (int t = tid; t < cc; t += TM_THREADS) {
+          double a = w[t];
+          for (int i = 0; i <= j; ++i) a -= y[i] * V[(long long)i * cc + t];
+          w[t] = a;
+        }
+        __syncthreads();
+      }
+      double a = 0.0;
+      for (int t = tid; t < cc; t += TM_THREADS) a += w[t] * w[t];
+      const double hn = sqrt(block_sum(a, red));
+      if (tid <= j) H[tid * M + j] = hcol[tid];
+      if (tid == 0) H[(j + 1) * M + j] = hn;
+      for (int i = j + 2 + tid; i <= M; i += TM_THREADS) H[i * M + j] = 0.0;
+      m = j + 1;
+      // an invariant subspace (or a zero map): the Ritz pair is exact
+      const bool breakdown = !(hn > 1e-14 * fabs(hcol[0]) + 1e-300);
+      if (breakdown || j == M - 1) {
+        __syncthreads();
+        break;
+      }
+      const double f = 1.0 / hn;
+      for (int t = tid; t < cc; t += TM_THREADS) V[(long long)(j + 1) * cc + t] = w[t] * f;
+      __syncthreads();
+    }
+    // dominant Ritz pair of the m x m leading block of H (wave 0): y is the
+    // normalised first column of H^(2^k), squaring until it stops changing
+    if (wv == 0) {
+      for (int e = lane; e < M * M; e += 64) {
+        const int r = e / M, c = e % M;
+        Hp[e] = (r < m && c < m) ? H[r * M + c] : 0.0;
+      }
+      wave_sync();
+      double yprev[M];
+      for (int q = 0; q < M; ++q) yprev[q] = q == 0 ? 1.0 : 0.0;
+      for (int sq = 0; sq < 60; ++sq) {
+        // Hq = Hp Hp, scaled to unit max norm
+        for (int e = lane; e < M * M; e += 64) {
+          const int r = e / M, c = e % M;
+          double acc = 0.0;
+          for (int q = 0; q < M; ++q) acc += Hp[r * M + q] * Hp[q * M + c];
+          Hq[e] = acc;
+        }
+        wave_sync();
+        double mx = 0.0;
+        for (int e = lane; e < M * M; e += 64) mx = fmax(mx, fabs(Hq[e]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        const double f = mx > 0.0 ? 1.0 / mx : 1.0;
+        for (int e = lane; e < M * M; e += 64) Hp[e] = Hq[e] * f;
+        wave_sync();
+        // candidate y: the first column, unit norm, positive first nonzero
+        double nrm = 0.0;
+        for (int q = 0; q < m; ++q) nrm += Hp[q * M] * Hp[q * M];
+        nrm = sqrt(nrm);
+        double sgn = 1.0;
+        for (int q = 0; q < m; ++q)
+          if (fabs(Hp[q * M]) > 1e-8 * nrm) {
+            sgn = Hp[q * M] < 0.0 ? -1.0 : 1.0;
+            break;
+          }
+        double dmax = 0.0;
+        for (int q = 0; q < M; ++q) {
+          const double yq = (q < m && nrm > 0.0) ? sgn * Hp[q * M] / nrm : 0.0;
+          dmax = fmax(dmax, fabs(yq - yprev[q]));
+          yprev[q] = yq;
+        }
+        if (dmax < 1e-15) break;
+      }
+      if (lane < M) y[lane] = yprev[lane];
+      wave_sync();
+      if (lane == 0) {
+        // theta from the Rayleigh quotient of H on y; residual from the
+        // Arnoldi relation
+        double num = 0.0, den = 0.0;
+        for (int r = 0; r < m; ++r) {
+          double hy = 0.0;
+          for (int c = 0; c < m; ++c) hy += H[r * M + c] * y[c];
+          num += y[r] * hy;
+          den += y[r] * y[r];
+        }
+        sc[1] = den > 0.0 ? num / den : 0.0;
+        sc[2] = fabs(H[m * M + (m - 1)] * y[m - 1]);
+      }
+    }
+    __syncthreads();
+    theta = sc[1];
+    const double res = sc[2];
+    // v = V y, unit norm and positive trace
+    for (int t = tid; t < cc; t += TM_THREADS) {
+      double a = 0.0;
+      for (int i = 0; i < m; ++i) a += y[i] * V[(long long)i * cc + t];
+      v[t] = a;
+    }
+    __syncthreads();
+    {
+      double a = 0.0, tr = 0.0;
+      for (int t = tid; t < cc; t += TM_THREADS) a += v[t] * v[t];
+      for (int i = tid; i < chi; i += TM_THREADS) tr += v[i * chi + i];
+      const double nrm = sqrt(block_sum(a, red));
+      tr = block_sum(tr, red);
+      const double f = (tr < 0.0 ? -1.0 : 1.0) / (nrm > 0.0 ? nrm : 1.0);
+      for (int t = tid; t < cc; t += TM_THREADS) v[t] *= f;
+      __syncthreads();
+    }
+    conv = res <= tol * fabs(theta);  // also false on NaN
+  }
+  for (int t = tid; t < cc; t += TM_THREADS) vo[t] = v[t];
+  if (tid == 0) {
+    eta[blockIdx.x] = theta;
+    iters[blockIdx.x] = conv ? mv : (mv > max_iter ? mv : max_iter);
   }
 }
 
@@ -264,7 +501,7 @@ bool tm_work_in_global(int nsite, int chi, int d) {
 // set exceeds LDS (null: taken from the arena).
 int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const double* bras,
             double* v2 /*[2][chi][chi]*/, double* eta_d, int* it_d, double tol, int max_iter,
-            int warm, double* gwork = nullptr) {
+            int warm, double* gwork = nullptr, bool krylov = false) {
   const size_t per = tm_work_per_side(nsite, chi, d);
   size_t dyn = per * sizeof(double);
   if (!tm_work_in_global(nsite, chi, d)) {
@@ -274,7 +511,18 @@ int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const do
     if (!gwork) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (transfer matrix)");
     dyn = 0;
   }
-  if (gwork)
+  if (krylov) {
+    double* kry = ws_alloc<double>(ctx, 2 * (size_t)(TM_KRYLOV + 1) * chi * chi);
+    if (!kry) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (Krylov basis)");
+    if (gwork)
+      hipLaunchKernelGGL(tm_krylov_kernel<true>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream,
+                         kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork,
+                         kry);
+    else
+      hipLaunchKernelGGL(tm_krylov_kernel<false>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream,
+                         kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork,
+                         kry);
+  } else if (gwork)
     hipLaunchKernelGGL(tm_power_kernel<true>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets,
                        bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
   else
@@ -451,7 +699,7 @@ int bond_truncation(tn_ctx* ctx, int n, int chi, int d, const double* th /*[2][n
   TN_HIP(ctx, hipMemcpyAsync(cell, th + o * ndn, ndn * 8, hipMemcpyDeviceToDevice, ctx->stream));
   TN_HIP(ctx, hipMemcpyAsync(cell + ndn, th + a * ndn, ndn * 8, hipMemcpyDeviceToDevice,
                              ctx->stream));
-  TN_TRY(tm_pair(ctx, 2, n, d, cell, cell, vwarm, ed, itd, tol, 100000, warm));
+  TN_TRY(tm_pair(ctx, 2, n, d, cell, cell, vwarm, ed, itd, tol, 100000, warm, nullptr, true));
   int hi[2];
   TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   // vl = Yt Yt^T (Y = Yt^T), vr = X X^T
@@ -711,31 +959,14 @@ __global__ void negate_kernel(double* __restrict__ x, long long n) {
   if (t < n) x[t] = -x[t];
 }
 
-}  // namespace
-
-// Gauge fixing of a two-site iMPS (Sec. III B): a_new ~ U a_ref U^T per
-// site with one orthogonal U per bond (U [2][chi][chi], bond 0 after site
-// 0).  method 0: the iterative method (Sec. III B 2, Eq. (15)), alternating
-// Procrustes steps from the U passed in until F changes by less than tol;
-// method 1: the direct method (Sec. III B 1, Eq. (iMPSDM1)): per bond the
-// dominant left eigenvector X of the mixed transfer matrix of a_ref (ket)
-// and a_new (bra) is w U^T for a positive w, so U is the orthogonal polar
-// factor of X^T; the overall sign of the pair (U0, U1) is taken with F > 0.
-int gauge_fix_1d(tn_ctx* ctx, int method, int chi, int d, const double* a_ref,
-                 const double* a_new, double* U, double tol, int max_iter, double* fidelity,
-                 int* iters) {
-  if (chi < 1 || d < 1 || !a_ref || !a_new || !U || max_iter < 1)
-    TN_FAIL(ctx, TN_EINVAL, "bad 1D gauge_fix arguments");
-  if (chi > 32) TN_FAIL(ctx, TN_EINVAL, "1D gauge fixing supports chi <= 32 (chi=%d)", chi);
-  const BondNet net = bondnet_chain2(d);
+// The direct method (Sec. III B 1, Eq. (iMPSDM1)) on arena memory: per bond
+// the dominant left eigenvector X of the mixed transfer matrix of a_ref
+// (ket) and a_new (bra) is w U^T for a positive w, so U is the orthogonal
+// polar factor of X^T; the overall sign of the pair (U0, U1) is taken with
+// F > 0.  *itmax: the larger fixed-point iteration count of the two bonds.
+int gauge_direct_1d(tn_ctx* ctx, int chi, int d, const double* a_ref, const double* a_new,
+                    double* U, double tol, int max_iter, double* fidelity, int* itmax_out) {
   const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
-  const size_t tmw = tm_work_in_global(2, chi, d) ? 2 * tm_work_per_side(2, chi, d) : 0;
-  TN_TRY(ws_reserve(ctx, bondnet_gauge_bytes(net, chi) + (4 * cdc + 12 * cc + tmw + 64) * 8 +
-                             (1 << 20)));
-  ws_reset(ctx);
-  if (method == 0)
-    return bondnet_gauge_fix(ctx, net, chi, a_ref, a_new, U, tol, max_iter, fidelity, iters);
-  if (method != 1) TN_FAIL(ctx, TN_EINVAL, "unknown 1D gauge-fix method %d", method);
   double* kets = ws_alloc<double>(ctx, 2 * cdc);
   double* bras = ws_alloc<double>(ctx, 2 * cdc);
   double* v2 = ws_alloc<double>(ctx, 2 * cc);
@@ -783,6 +1014,39 @@ int gauge_fix_1d(tn_ctx* ctx, int method, int chi, int d, const double* a_ref,
   }
   if (!std::isfinite(F)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite fidelity");
   if (fidelity) *fidelity = F;
+  if (itmax_out) *itmax_out = itmax;
+  return TN_OK;
+}
+
+// Arena bytes gauge_direct_1d needs beyond the caller's.
+size_t gauge_direct_bytes(int chi, int d) {
+  const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
+  const size_t tmw = tm_work_in_global(2, chi, d) ? 2 * tm_work_per_side(2, chi, d) : 0;
+  return (4 * cdc + 12 * cc + tmw + 64) * 8 + (1 << 20);
+}
+
+}  // namespace
+
+// Gauge fixing of a two-site iMPS (Sec. III B): a_new ~ U a_ref U^T per
+// site with one orthogonal U per bond (U [2][chi][chi], bond 0 after site
+// 0).  method 0: the iterative method (Sec. III B 2, Eq. (15)), alternating
+// Procrustes steps from the U passed in until F changes by less than tol;
+// method 1: the direct method (gauge_direct_1d).
+int gauge_fix_1d(tn_ctx* ctx, int method, int chi, int d, const double* a_ref,
+                 const double* a_new, double* U, double tol, int max_iter, double* fidelity,
+                 int* iters) {
+  if (chi < 1 || d < 1 || !a_ref || !a_new || !U || max_iter < 1)
+    TN_FAIL(ctx, TN_EINVAL, "bad 1D gauge_fix arguments");
+  if (chi > TN_SMALL_BOND)
+    TN_FAIL(ctx, TN_EINVAL, "1D gauge fixing supports chi <= %d (chi=%d)", TN_SMALL_BOND, chi);
+  const BondNet net = bondnet_chain2(d);
+  TN_TRY(ws_reserve(ctx, bondnet_gauge_bytes(net, chi) + gauge_direct_bytes(chi, d)));
+  ws_reset(ctx);
+  if (method == 0)
+    return bondnet_gauge_fix(ctx, net, chi, a_ref, a_new, U, tol, max_iter, fidelity, iters);
+  if (method != 1) TN_FAIL(ctx, TN_EINVAL, "unknown 1D gauge-fix method %d", method);
+  int itmax = 0;
+  TN_TRY(gauge_direct_1d(ctx, chi, d, a_ref, a_new, U, tol, max_iter, fidelity, &itmax));
   if (iters) *iters = itmax;
   return itmax >= max_iter ? TN_NOT_CONVERGED : TN_OK;
 }
@@ -918,16 +1182,20 @@ int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*
                const double hg[2][2][2][2], const StepMeasure& meas, int mode, double* env1d,
                double* lambda_out, double tol, double* trunc_err, double* energy_or_null) {
   if (chi < 1 || d != 2 || !A || !env1d) TN_FAIL(ctx, TN_EINVAL, "bad itebd_step arguments");
-  if (mode < 0 || mode > 3) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
+  if (mode < 0 || mode > 4) TN_FAIL(ctx, TN_EINVAL, "itebd_step mode %d not available", mode);
+  // mode 4 is the environment step of mode 1 with the direct gauge fix
+  const bool direct = mode == 4;
+  if (direct) mode = 1;
   const int kap = 2, n = kap * chi;
-  if (mode != 0 && n > 32)
-    TN_FAIL(ctx, TN_EINVAL, "recycling supports chi <= 16 (chi=%d)", chi);
+  if (mode != 0 && chi > TN_SMALL_BOND)
+    TN_FAIL(ctx, TN_EINVAL, "recycling supports chi <= %d (chi=%d)", TN_SMALL_BOND, chi);
   const size_t nn = (size_t)n * n, ndn = (size_t)n * d * n, cdc = (size_t)chi * d * chi;
   const size_t cc = (size_t)chi * chi;
   const BondNet net = bondnet_chain2(d);
   size_t extra = 0;
   if (mode == 1)
-    extra = bondnet_canon_bytes(net, chi) + bondnet_gauge_bytes(net, chi) + (12 * cc + 4 * cdc) * 8;
+    extra = bondnet_canon_bytes(net, chi) + bondnet_gauge_bytes(net, chi) +
+            (direct ? gauge_direct_bytes(chi, d) : 0) + (12 * cc + 4 * cdc) * 8;
   if (mode == 3) extra = (6 * cdc * cdc + 4 * cdc + 64) * 8;
   if (energy_or_null && meas.kind == 1)
     extra += (4 * ndn + 2 * nn + 8) * 8 + 2 * tm_work_per_side(2, n, d) * 8;
@@ -1038,10 +1306,16 @@ int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*
     size_t mark = ctx->arena_off;
     TN_TRY(canonical_1d(ctx, net, chi, d, tr, tol, Pc, Qc, l1, a1));
     ctx->arena_off = mark;
-    TN_TRY(recycle_gauge_start(ctx, 2, n, chi, kap, P, Q, Pc, Qc, U));
     double F = 0.0;
-    const int rc = bondnet_gauge_fix(ctx, net, chi, a0c, a1, U, 1e-12, 1000, &F, nullptr);
-    if (rc < 0) return rc;
+    if (direct) {
+      int it = 0;
+      TN_TRY(gauge_direct_1d(ctx, chi, d, a0c, a1, U, 1e-14, 100000, &F, &it));
+      tmi = it > tmi ? it : tmi;
+    } else {
+      TN_TRY(recycle_gauge_start(ctx, 2, n, chi, kap, P, Q, Pc, Qc, U));
+      const int rc = bondnet_gauge_fix(ctx, net, chi, a0c, a1, U, 1e-12, 1000, &F, nullptr);
+      if (rc < 0) return rc;
+    }
     ctx->arena_off = mark;
     TN_TRY(recycle_factors(ctx, 2, n, chi, P, Q, Pc, Qc, U, Rf, Lf));
     TN_HIP(ctx, hipMemcpyAsync(flagp + 1, &one, sizeof(double), hipMemcpyHostToDevice,

@@ -31,7 +31,9 @@ int ipeps_rdms_impl(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const 
 namespace {
 
 constexpr int MAXL = 64;        // links of a cell
-constexpr int MAXN = 32;        // largest bond handled by the small per-leg kernels
+constexpr int MAXN = TN_SMALL_BOND;  // largest bond handled by the small per-leg kernels
+// entries of an n x n result per thread of a 256-thread workgroup (n <= MAXN)
+constexpr int EPT = (MAXN * MAXN + 255) / 256;
 constexpr double CUT = 1e-14;   // relative cutoff of pseudo-inverse square roots
 enum { AX_S = 0, AX_L = 1, AX_R = 2, AX_D = 3, AX_U = 4 };
 
@@ -239,7 +241,9 @@ __global__ __launch_bounds__(256) void leg_gram_kernel(GramBatch batch) {
   st[4] = 1;
   for (int k = 3; k >= 0; --k) st[k] = st[k + 1] * J.dims.n[k + 1];
   const long long rest = tsize(J.dims) / n;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) acc[q] = 0.0;
   const int tid = threadIdx.x;
   for (int term = 0; term < J.nterm; ++term) {
     const double* A = J.A[term];
@@ -272,7 +276,7 @@ __global__ __launch_bounds__(256) void leg_gram_kernel(GramBatch batch) {
       }
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * 256;
         if (e < n * n) {
           const int i = e / n, j = e % n;
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(256) void leg_gram_kernel(GramBatch batch) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = tid + q * 256;
     if (e < n * n) J.out[e] = acc[q];
   }
@@ -421,10 +425,10 @@ __global__ __launch_bounds__(256) void canon_update_kernel(
     Lout[b * nn + e] = l[e];
   }
   // TR <- TR r, TL <- l TL (in registers: each thread owns up to 4 entries)
-  double nr[4], nlv[4];
+  double nr[EPT], nlv[EPT];
   double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = threadIdx.x + q * 256;
     nr[q] = nlv[q] = 0.0;
     if (e < n * n) {
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(256) void canon_update_kernel(
   const double n1 = sqrt(block_sum256(s1, red));
   const double n2 = sqrt(block_sum256(s2, red));
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = threadIdx.x + q * 256;
     if (e < n * n) {
       TR[b * nn + e] = nr[q] / n1;
@@ -1845,10 +1849,10 @@ __global__ __launch_bounds__(256) void gauge_start_kernel(int Dk, int D, int kap
   const double* Qb = Q + b * per;
   const double* Pcb = Pc + b * dd;
   const double* Qcb = Qc + b * dd;
-  double a[4], c[4];
+  double a[EPT], c[EPT];
   double na = 0.0, nc = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = threadIdx.x + q * 256;
     a[q] = c[q] = 0.0;
     if (e < D * D) {
@@ -1868,7 +1872,7 @@ __global__ __launch_bounds__(256) void gauge_start_kernel(int Dk, int D, int kap
   na = sqrt(block_sum256(na, red));
   nc = sqrt(block_sum256(nc, red));
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = threadIdx.x + q * 256;
     if (e < D * D) K[b * dd + e] = a[q] / na + c[q] / nc;
   }

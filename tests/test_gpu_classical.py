@@ -89,6 +89,65 @@ def test_recycled_and_limit_power_method(ctx):
         assert abs(lz - ref) < 1e-10, n_re
 
 
+def _factors(env, chi, Lf_ref, Rf_ref):
+    """The stored factors of the renormalized gate, with the sign of their
+    kappa = 1 index aligned to the oracle's.  The gate's bond split
+    g = sum_k L_k (x) R_k is fixed up to (L_1, R_1) -> (-L_1, -R_1); the
+    oracle takes the sign from the larger entry of a singular vector whose
+    two entries tie in magnitude for sz (x) sz, the library from the closed
+    form.  Gate and factors flip together, so the new sites do not depend
+    on it."""
+    n = 2 * chi
+    e = host(env)
+    Lf = e[4 * n * n:4 * n * n + 2 * chi * n].reshape(2, chi, n).copy()
+    Rf = e[4 * n * n + 2 * chi * n:4 * n * n + 4 * chi * n].reshape(2, n, chi).copy()
+    Lr, Rr = np.stack(Lf_ref), np.stack(Rf_ref)
+    if np.abs(Lf[:, :, 1::2] + Lr[:, :, 1::2]).max() < np.abs(Lf[:, :, 1::2] - Lr[:, :, 1::2]).max():
+        Lf[:, :, 1::2] *= -1
+        Rf[:, 1::2, :] *= -1
+    return Lf, Rf
+
+
+def test_direct_build_parity(ctx):
+    # an environment step with the direct gauge fix (Sec. III B 1) at
+    # beta = 0.42, chi = 12, from the plain fixed point (near-degenerate
+    # Schmidt pairs): factors, new sites and ln Z against the oracle
+    beta, chi = 0.42, 12
+    sites = cl.power_method(_start(chi, 1), beta, chi, 40)
+    J, h, dt = cl.row_gate(beta)
+    new, (Lf, Rf), l1, err, F = imps.recycle_build(sites, gates.impo(J, h, dt), chi,
+                                                   gauge="direct")
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    lam = torch.empty((2, chi), dtype=torch.float64, device="cuda")
+    gerr, lz, rc = ctx.ising2d_tm_step(A, beta, env, mode=tn.TN_RECYCLE_BUILD_DIRECT, lnz=True,
+                                       lam=lam)
+    assert rc == tn.TN_OK
+    assert abs(gerr - err) < 1e-9 * max(err, 1e-30) + 1e-15
+    np.testing.assert_allclose(host(lam), np.stack(l1), atol=1e-10)
+    gLf, gRf = _factors(env, chi, Lf, Rf)
+    assert np.abs(gLf - np.stack(Lf)).max() < 1e-7 * np.abs(Lf).max()
+    assert np.abs(gRf - np.stack(Rf)).max() < 1e-7 * np.abs(Rf).max()
+    np.testing.assert_allclose(host(A), np.stack(new), atol=2e-7 * np.abs(np.stack(new)).max())
+    assert abs(lz - cl.log_z(new, beta)) < 1e-11
+
+
+def test_direct_recycling_near_the_critical_point(ctx):
+    # 20 plain steps, then N_Re = 5 with the direct gauge fix: ln Z reaches
+    # the oracle's plain fixed point to 1e-10 at beta = 0.42, chi = 12
+    beta, chi = 0.42, 12
+    ref = cl.log_z(cl.power_method(_start(chi, 1), beta, chi, 150), beta)
+    A = dev(np.stack(_start(chi, 1)))
+    env = ctx.env1d(chi)
+    for _ in range(20):
+        ctx.ising2d_tm_step(A, beta, env)
+    for step in range(100):
+        mode = tn.TN_RECYCLE_BUILD_DIRECT if step % 5 == 0 else tn.TN_RECYCLE_APPLY
+        _, lz, rc = ctx.ising2d_tm_step(A, beta, env, mode=mode, lnz=(step == 99))
+        assert rc == tn.TN_OK
+    assert abs(lz - ref) < 1e-10
+
+
 def test_rejects_bad_beta(ctx):
     A = dev(np.stack(_start(4)))
     with pytest.raises(tn.TNError):

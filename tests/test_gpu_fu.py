@@ -173,11 +173,15 @@ def test_bond_env_truncate_parity(ctx, spec, D, chi):
         # f = T - 2c + q cancels down from T: its rounding is relative to T
         assert abs(f - fr) < 1e-11 * tn, (passes, f, fr)
         if tol == 0.0:
+            # the same cycles on both sides: measured deviations 7e-14 to
+            # 4e-13 in P Q and 1e-12 to 5e-12 in P, Q (these carry the
+            # balancing SVD's basis, which near-degenerate singular values
+            # of P Q fix less well than the product)
             assert gp == pr == passes and gsw == swr
             for b in range(len(P)):
-                assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-9, b
-            assert rel(host(gP), np.stack(Pr)) < 1e-8
-            assert rel(host(gQ), np.stack(Qr)) < 1e-8
+                assert rel(host(gP)[b] @ host(gQ)[b], Pr[b] @ Qr[b]) < 1e-11, b
+            assert rel(host(gP), np.stack(Pr)) < 1e-10
+            assert rel(host(gQ), np.stack(Qr)) < 1e-10
         else:
             assert abs(gp - pr) <= 1
 

@@ -132,14 +132,15 @@ def test_critical_chain_full_config(ctx):
     assert abs(e + 4 / np.pi) < 2e-4
 
 
-@pytest.mark.parametrize("chi,h", [(8, 1.0), (16, 1.2)])
+@pytest.mark.parametrize("chi,h", [(8, 1.0), (16, 1.2), (32, 1.2), (50, 1.05)])
 def test_recycle_build_and_apply_parity(ctx, chi, h):
     """An environment step of the recycling scheme (canonical A_0, truncation,
     canonical form, gauge fix, renormalized gate) and one recycled step.
     (A short run from a random start can leave a cat-like state whose
     dominant transfer-matrix eigenvalue is nearly degenerate; the local
     canonical iteration then does not converge in 1000 steps.  These seeds
-    converge in 65 and 187.)"""
+    converge in 65 and 187.)  chi = 50 at h = 1.05 is the setting of the
+    paper's Fig. 19."""
     sites = _state(6, chi, h=h)
     g = gates.impo(1.0, h, 0.01)
     new, (Lf, Rf), l1, err, F = imps.recycle_build(sites, g, chi)
@@ -166,6 +167,30 @@ def test_recycle_build_and_apply_parity(ctx, chi, h):
     # the factors once more, on sites that already carry their deviation
     np.testing.assert_allclose(host(A), np.stack(nxt), atol=4e-7 * np.abs(np.stack(nxt)).max())
     er = imps.energy_per_site(nxt, 1.0, h)
+    assert abs(ge - er) < 1e-9 * abs(er)
+
+
+def test_recycle_build_direct_gauge_parity(ctx):
+    """The environment step with the direct gauge fix (Sec. III B 1) on the
+    TFIM chain: factors and new sites against the oracle."""
+    chi, h = 16, 1.2
+    sites = _state(6, chi, h=h)
+    g = gates.impo(1.0, h, 0.01)
+    new, (Lf, Rf), l1, err, F = imps.recycle_build(sites, g, chi, gauge="direct")
+    A = dev(np.stack(sites))
+    env = ctx.env1d(chi)
+    gerr, ge, rc = ctx.itebd_step(A, 1.0, h, 0.01, env, mode=tn.TN_RECYCLE_BUILD_DIRECT,
+                                  energy=True)
+    assert rc == tn.TN_OK
+    assert abs(gerr - err) < 1e-9 * max(err, 1e-30) + 1e-15
+    n = 2 * chi
+    e = host(env)
+    gLf = e[4 * n * n:4 * n * n + 2 * chi * n].reshape(2, chi, n)
+    gRf = e[4 * n * n + 2 * chi * n:4 * n * n + 4 * chi * n].reshape(2, n, chi)
+    assert np.abs(gLf - np.stack(Lf)).max() < 1e-7 * np.abs(Lf).max()
+    assert np.abs(gRf - np.stack(Rf)).max() < 1e-7 * np.abs(Rf).max()
+    np.testing.assert_allclose(host(A), np.stack(new), atol=2e-7 * np.abs(np.stack(new)).max())
+    er = imps.energy_per_site(new, 1.0, h)
     assert abs(ge - er) < 1e-9 * abs(er)
 
 
