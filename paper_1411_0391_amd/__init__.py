@@ -111,6 +111,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     """Load libitebd.so and attach the C signatures; raise if it is absent."""
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} is not built; run paper_1411_0391_amd/build.py")
+    # torch first: it brings its own HIP runtime, and the library must bind
+    # to that one (loaded first, the library would bind to the system copy,
+    # and torch's streams would be foreign to it)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -256,6 +256,13 @@ constexpr int absorb_threads() {
   return 64 * ((ABS_G * D * D + 15) / 16);
 }
 
+// D = 6: three 9-wave workgroups per CU need 7 waves per SIMD (at most 72
+// VGPRs) and at most 53 KB of LDS each
+template <int D>
+constexpr int absorb_min_waves() {
+  return D == 6 ? 7 : 1;
+}
+
 // Output layouts the store knows: ABS_STRIDED stores each lane's own entries
 // (any strides); ABS_RUN_B and ABS_RUN_D stage the workgroup's tile in LDS
 // and store it in runs of G D^2 consecutive doubles, when the four pairs are
@@ -264,14 +271,14 @@ constexpr int absorb_threads() {
 enum { ABS_STRIDED = 0, ABS_RUN_B = 1, ABS_RUN_D = 2 };
 
 template <int D, int LAYOUT>
-__global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
+__global__ __launch_bounds__(absorb_threads<D>(), absorb_min_waves<D>()) void absorb_kernel(
     const double* __restrict__ In, const double* __restrict__ A, double* __restrict__ Out,
     AbsorbDesc g) {
   constexpr int P = D * D;
   constexpr int ROWS = ABS_G * P;
   constexpr int NJ = (P + 15) / 16;  // 16-column blocks over P
   constexpr int NQ = (P + 3) / 4;    // k-steps of 4 over P
-  constexpr int S = NJ * 16 + 1;     // LDS row stride (odd)
+  constexpr int S = P % 2 == 0 ? P + 1 : P + 2;  // LDS row stride (odd)
   __shared__ double Ts[ROWS * S];
   __shared__ double Bs[NQ * 4 * S];
   const int lane = threadIdx.x & 63, blk = threadIdx.x >> 6;
@@ -310,35 +317,32 @@ __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc2[j] = dv4{0.0, 0.0, 0.0, 0.0};
   for (int s = 0; s < g.d; ++s) {
-    // Am[s] into LDS, zero-padded to NQ*4 rows and NJ*16 columns: the B
-    // operand of both products, Bs[4q + lane/16][16j + lane%16]
-    for (int t = threadIdx.x; t < NQ * 4 * NJ * 16; t += blockDim.x) {
-      const int row = t / (NJ * 16), col = t % (NJ * 16);
-      Bs[row * S + col] = (row < P && col < P)
-                              ? A[(long long)s * P * P + (row / D) * D * P + (col / D) * P +
-                                  (col % D) * D + (row % D)]
-                              : 0.0;
+    // Am[s] into LDS, zero-padded to NQ*4 rows: the B operand of both
+    // products, Bs[4q + lane/16][16j + lane%16]; the columns past P are
+    // not stored, their operand lanes read zero
+    for (int t = threadIdx.x; t < NQ * 4 * P; t += blockDim.x) {
+      const int row = t / P, col = t % P;
+      Bs[row * S + col] = row < P ? A[(long long)s * P * P + (row / D) * D * P + (col / D) * P +
+                                      (col % D) * D + (row % D)]
+                                  : 0.0;
     }
     __syncthreads();
-    // ket layer: rows (pair, l, u') of this wave, all columns R1 (the
-    // column blocks as independent accumulation chains)
-    {
-      dv4 acc1[NJ];
+    // ket layer: rows (pair, l, u') of this wave, one 16-column block of R1
+    // at a time (one accumulator live beside acc2 and inA keeps the kernel
+    // within the registers of two workgroups per CU)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc1[j] = dv4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) {
+      dv4 acc1 = dv4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
+      for (int q = 0; q < NQ; ++q) {
+        const double b = 16 * j + lo < P ? Bs[(4 * q + hi) * S + 16 * j + lo] : 0.0;
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(inA[q], b, acc1, 0, 0, 0);
+      }
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          acc1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              inA[q], Bs[(4 * q + hi) * S + 16 * j + lo], acc1[j], 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * blk + hi + 4 * r;
-          if (row < ROWS) Ts[row * S + 16 * j + lo] = acc1[j][r];
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * blk + hi + 4 * r;
+        if (row < ROWS && 16 * j + lo < P) Ts[row * S + 16 * j + lo] = acc1[r];
+      }
     }
     __syncthreads();
     // bra layer: rows (pair, R1) of this wave, k over (l, u') of the same pair
@@ -347,9 +351,10 @@ __global__ __launch_bounds__(absorb_threads<D>()) void absorb_kernel(
       const int L = 4 * q + hi;
       const double a2 = (rowA && L < P) ? Ts[(aA * P + L) * S + LA] : 0.0;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        acc2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, Bs[(4 * q + hi) * S + 16 * j + lo],
-                                                       acc2[j], 0, 0, 0);
+      for (int j = 0; j < NJ; ++j) {
+        const double b = 16 * j + lo < P ? Bs[(4 * q + hi) * S + 16 * j + lo] : 0.0;
+        acc2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b, acc2[j], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
