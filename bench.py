@@ -81,19 +81,23 @@ def cpu_baseline(sites, C, T, chi, cell, moves):
 def run_chain(args):
     """The 1D workload: two-site iMPS, chi = 16, J = h = 1, dt = 0.01, 2000
     steps from seeded N(0,1) tensors, plain (environment every step) and
-    recycled (every 20 steps after gauge fixing); energy against -4/pi."""
+    recycled (an environment step every 20 steps, its gauge fixed by
+    --chain-gauge: direct, Sec. III B 1, or iterative, Sec. III B 2);
+    energy against -4/pi."""
     import math
     import numpy as np
     import torch
     import paper_1411_0391_amd as tn
     import tninputs
     chi, nsteps, n_re = 16, args.chain_steps, 20
+    build = tn.TN_RECYCLE_BUILD_DIRECT if args.chain_gauge == "direct" else tn.TN_RECYCLE_BUILD
     ga, _, gb, _ = tninputs.imps_two_site(0, chi)
     A0 = np.stack([ga / np.linalg.norm(ga), gb / np.linalg.norm(gb)])
     ctx = tn.Context()
     out = {"metric": "1D iTEBD step time and energy, recycled vs plain", "unit": "ms/step",
            "config": {"workload": f"TFIM chain, two-site iMPS, chi={chi}, J=h=1, dt=0.01, "
-                                  f"{nsteps} steps, N_Re={n_re}", "chi": chi, "steps": nsteps},
+                                  f"{nsteps} steps, N_Re={n_re}, {args.chain_gauge} gauge fix",
+                      "chi": chi, "steps": nsteps},
            "data": "synthetic", "dtype": "f64", "n_gpus": 1}
     exact = -4.0 / math.pi
     for label, recyc in (("plain", False), ("recycled", True)):
@@ -107,8 +111,7 @@ def run_chain(args):
             if not recyc:
                 _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, energy=last)
             elif step % n_re == 0:
-                _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, mode=tn.TN_RECYCLE_BUILD,
-                                          energy=last)
+                _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, mode=build, energy=last)
             else:
                 _, e1, _ = ctx.itebd_step(A, 1.0, 1.0, 0.01, env, mode=tn.TN_RECYCLE_APPLY,
                                           energy=last)
@@ -377,6 +380,8 @@ def main():
                     help="only run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--chain", action="store_true", help="run the 1D workload instead")
     ap.add_argument("--chain-steps", type=int, default=2000)
+    ap.add_argument("--chain-gauge", choices=["direct", "iterative"], default="direct",
+                    help="gauge fix of the chain's recycling builds")
     ap.add_argument("--mz", action="store_true",
                     help="m_z(h) of the simple and the full update (one-site iPEPS)")
     ap.add_argument("--mz-fields", default="2.5,2.8,2.9,3.0,3.05,3.1,3.2,3.3,3.5")

@@ -361,8 +361,11 @@ enum { TN_GAUGE_2D = 0, TN_GAUGE_1D = 1, TN_GAUGE_1D_DIRECT = 2 };
  *          X of the mixed transfer matrix (ket a_ref, bra a_new) equals
  *          w U^T with w the positive fixed point of a_ref, so U is the
  *          orthogonal polar factor of X^T; the sign of the pair is taken
- *          with F > 0.  U is output only; tol, max_iter bound the
- *          fixed-point iterations.  chi <= 64 for both 1D kinds.
+ *          with F > 0.  U is output only.  The eigenvectors of both
+ *          bonds come from one restarted-Arnoldi launch: it stops when
+ *          the Arnoldi residual is below tol times the Ritz value
+ *          (tol <= 0: 1e-14), max_iter bounds the transfer-matrix
+ *          applications.  chi <= 64 for both 1D kinds.
  *   U             device in/out [nlink][D][D] (1D: [2][chi][chi])
  *   fidelity, iters  host out
  * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL, TN_ENUMERIC, TN_EHIP.

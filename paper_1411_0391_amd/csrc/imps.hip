@@ -107,7 +107,10 @@ __global__ __launch_bounds__(TM_THREADS) void tm_power_kernel(
     int max_iter, int warm, double* __restrict__ gwork) {
   extern __shared__ double lds[];
   __shared__ double red[TM_THREADS / 64];
-  const int left = blockIdx.x == 0 ? 1 : 0;
+  // blocks 2p and 2p + 1: the left and right fixed points of problem p
+  const int left = (blockIdx.x & 1) == 0 ? 1 : 0;
+  kets += (long long)(blockIdx.x >> 1) * nsite * chi * d * chi;
+  bras += (long long)(blockIdx.x >> 1) * nsite * chi * d * chi;
   const int tid = threadIdx.x;
   const int cdc = chi * d * chi, cc = chi * chi;
   const long long per = 2LL * nsite * cdc + 2LL * cc + cdc;
@@ -208,7 +211,10 @@ __global__ __launch_bounds__(TM_THREADS) void tm_krylov_kernel(
   __shared__ double H[(M + 1) * M];
   __shared__ double Hp[M * M], Hq[M * M];
   __shared__ double hcol[M + 1], y[M], sc[4];
-  const int left = blockIdx.x == 0 ? 1 : 0;
+  // blocks 2p and 2p + 1: the left and right fixed points of problem p
+  const int left = (blockIdx.x & 1) == 0 ? 1 : 0;
+  kets += (long long)(blockIdx.x >> 1) * nsite * chi * d * chi;
+  bras += (long long)(blockIdx.x >> 1) * nsite * chi * d * chi;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int cdc = chi * d * chi, cc = chi * chi;
   const long long per = 2LL * nsite * cdc + 2LL * cc + cdc;
@@ -232,7 +238,7 @@ __global__ __launch_bounds__(TM_THREADS) void tm_krylov_kernel(
     v[t] = warm ? vo[t] : ((t / chi == t % chi) ? 1.0 : 0.0);
   __syncthreads();
   int mv = 0;
-  double theta = 0.0;
+  double theta = 0.0, res_prev = INFINITY;
   bool conv = false;
   while (!conv && mv < max_iter) {
     // V_0 = v / |v|
@@ -383,7 +389,10 @@ __global__ __launch_bounds__(TM_THREADS) void tm_krylov_kernel(
       for (int t = tid; t < cc; t += TM_THREADS) v[t] *= f;
       __syncthreads();
     }
-    conv = res <= tol * fabs(theta);  // also false on NaN
+    // converged, or within 100x of the target with the residual no longer
+    // halving per restart (its rounding floor); both false on NaN
+    conv = res <= tol * fabs(theta) || (res <= 100.0 * tol * fabs(theta) && res > 0.5 * res_prev);
+    res_prev = res;
   }
   for (int t = tid; t < cc; t += TM_THREADS) vo[t] = v[t];
   if (tid == 0) {
@@ -499,38 +508,47 @@ bool tm_work_in_global(int nsite, int chi, int d) {
 
 // Both fixed points: gwork holds 2 tm_work_per_side doubles when the working
 // set exceeds LDS (null: taken from the arena).
+// nprob independent problems in one launch: problem p's cell at
+// kets/bras + p nsite chi d chi, its fixed points at v2 + 2 p chi^2, its
+// eta and iteration counts at index 2 p (left) and 2 p + 1 (right).
 int tm_pair(tn_ctx* ctx, int nsite, int chi, int d, const double* kets, const double* bras,
-            double* v2 /*[2][chi][chi]*/, double* eta_d, int* it_d, double tol, int max_iter,
-            int warm, double* gwork = nullptr, bool krylov = false) {
+            double* v2 /*[nprob][2][chi][chi]*/, double* eta_d, int* it_d, double tol,
+            int max_iter, int warm, double* gwork = nullptr, bool krylov = false,
+            int nprob = 1) {
   const size_t per = tm_work_per_side(nsite, chi, d);
+  const unsigned blocks = 2u * (unsigned)nprob;
   size_t dyn = per * sizeof(double);
   if (!tm_work_in_global(nsite, chi, d)) {
     gwork = nullptr;
   } else {
-    if (!gwork) gwork = ws_alloc<double>(ctx, 2 * per);
+    // a caller's gwork holds the two sides of one problem
+    if (gwork && nprob != 1) TN_FAIL(ctx, TN_EINVAL, "caller workspace for one problem only");
+    if (!gwork) gwork = ws_alloc<double>(ctx, blocks * per);
     if (!gwork) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (transfer matrix)");
     dyn = 0;
   }
   if (krylov) {
-    double* kry = ws_alloc<double>(ctx, 2 * (size_t)(TM_KRYLOV + 1) * chi * chi);
+    double* kry = ws_alloc<double>(ctx, blocks * (size_t)(TM_KRYLOV + 1) * chi * chi);
     if (!kry) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (Krylov basis)");
     if (gwork)
-      hipLaunchKernelGGL(tm_krylov_kernel<true>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream,
-                         kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork,
-                         kry);
+      hipLaunchKernelGGL(tm_krylov_kernel<true>, dim3(blocks), dim3(TM_THREADS), dyn,
+                         ctx->stream, kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter,
+                         warm, gwork, kry);
     else
-      hipLaunchKernelGGL(tm_krylov_kernel<false>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream,
-                         kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork,
-                         kry);
+      hipLaunchKernelGGL(tm_krylov_kernel<false>, dim3(blocks), dim3(TM_THREADS), dyn,
+                         ctx->stream, kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter,
+                         warm, gwork, kry);
   } else if (gwork)
-    hipLaunchKernelGGL(tm_power_kernel<true>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets,
-                       bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
+    hipLaunchKernelGGL(tm_power_kernel<true>, dim3(blocks), dim3(TM_THREADS), dyn, ctx->stream,
+                       kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
   else
-    hipLaunchKernelGGL(tm_power_kernel<false>, dim3(2), dim3(TM_THREADS), dyn, ctx->stream, kets,
-                       bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
+    hipLaunchKernelGGL(tm_power_kernel<false>, dim3(blocks), dim3(TM_THREADS), dyn, ctx->stream,
+                       kets, bras, nsite, chi, d, v2, eta_d, it_d, tol, max_iter, warm, gwork);
   TN_HIP(ctx, hipGetLastError());
-  hipLaunchKernelGGL(pair_normalize_kernel, dim3(1), dim3(256), 0, ctx->stream, v2,
-                     v2 + (size_t)chi * chi, chi * chi);
+  const size_t cc = (size_t)chi * chi;
+  for (int p = 0; p < nprob; ++p)
+    hipLaunchKernelGGL(pair_normalize_kernel, dim3(1), dim3(256), 0, ctx->stream, v2 + 2 * p * cc,
+                       v2 + (2 * p + 1) * cc, chi * chi);
   TN_HIP(ctx, hipGetLastError());
   return TN_OK;
 }
@@ -672,58 +690,71 @@ int tm_fixed_point_noalloc_impl(tn_ctx* ctx, int n_sites, int chi, int d, const 
 
 namespace {
 
-// Truncation of bond b of the two-site Theta chain (bond 0 after site 0):
-// fixed points of the cell ending with the left site, factors, SVD of Y X,
-// P (n x chi) and Q (chi x n).
-int bond_truncation(tn_ctx* ctx, int n, int chi, int d, const double* th /*[2][n][d][n]*/, int b,
-                    double* vwarm /*[2][n][n] in/out*/, int warm, double tol, double* P, double* Q,
-                    double* lam, double* err, int* tm_iters) {
+// Truncation of both bonds of the two-site Theta chain (bond 0 after site
+// 0), the two bonds batched in every launch: fixed points of the cell
+// ending with the left site of the bond, factors, SVD of Y X, P (n x chi)
+// and Q (chi x n) per bond.
+int bond_truncations(tn_ctx* ctx, int n, int chi, int d, const double* th /*[2][n][d][n]*/,
+                     double* vwarm /*[2 bonds][2][n][n] in/out*/, int warm, double tol,
+                     double* P /*[2][n][chi]*/, double* Q /*[2][chi][n]*/, double* lam /*[2][chi]*/,
+                     double* err, int* tm_iters) {
   const size_t nn = (size_t)n * n, ndn = (size_t)n * d * n;
-  double* cell = ws_alloc<double>(ctx, 2 * ndn);
-  double* ed = ws_alloc<double>(ctx, 2);
-  int* itd = ws_alloc<int>(ctx, 2);
-  double* U = ws_alloc<double>(ctx, nn);
-  double* S = ws_alloc<double>(ctx, n);
-  double* Yt = ws_alloc<double>(ctx, nn);
-  double* Ytinv = ws_alloc<double>(ctx, nn);
-  double* X = ws_alloc<double>(ctx, nn);
-  double* Xinv = ws_alloc<double>(ctx, nn);
-  double* M = ws_alloc<double>(ctx, nn);
-  double* Um = ws_alloc<double>(ctx, nn);
-  double* Vm = ws_alloc<double>(ctx, nn);
-  double* Sm = ws_alloc<double>(ctx, n);
+  double* cell = ws_alloc<double>(ctx, 4 * ndn);
+  double* ed = ws_alloc<double>(ctx, 4);
+  int* itd = ws_alloc<int>(ctx, 4);
+  double* U = ws_alloc<double>(ctx, 4 * nn);
+  double* S = ws_alloc<double>(ctx, 4 * (size_t)n);
+  double* Yt = ws_alloc<double>(ctx, 2 * nn);
+  double* Ytinv = ws_alloc<double>(ctx, 2 * nn);
+  double* X = ws_alloc<double>(ctx, 2 * nn);
+  double* Xinv = ws_alloc<double>(ctx, 2 * nn);
+  double* M = ws_alloc<double>(ctx, 2 * nn);
+  double* Um = ws_alloc<double>(ctx, 2 * nn);
+  double* Vm = ws_alloc<double>(ctx, 2 * nn);
+  double* Sm = ws_alloc<double>(ctx, 2 * (size_t)n);
   if (!Sm) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (truncation)");
-  // cell [other, b]: its left fixed point ends with site b, its right one
-  // starts with the other site
-  const int a = b, o = 1 - b;
-  TN_HIP(ctx, hipMemcpyAsync(cell, th + o * ndn, ndn * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  TN_HIP(ctx, hipMemcpyAsync(cell + ndn, th + a * ndn, ndn * 8, hipMemcpyDeviceToDevice,
-                             ctx->stream));
-  TN_TRY(tm_pair(ctx, 2, n, d, cell, cell, vwarm, ed, itd, tol, 100000, warm, nullptr, true));
-  int hi[2];
-  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  // vl = Yt Yt^T (Y = Yt^T), vr = X X^T
-  TN_TRY(jacobi_svd(ctx, 1, n, n, vwarm, n, 0, U, n, 0, S, 0, nullptr, 0, 0));
-  hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, U,
-                     S, n, Yt, Ytinv);
-  TN_TRY(jacobi_svd(ctx, 1, n, n, vwarm + nn, n, 0, U, n, 0, S, 0, nullptr, 0, 0));
-  hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, U,
-                     S, n, X, Xinv);
+  // cell of bond b = [other site, site b]: its left fixed point ends with
+  // site b, its right one starts with the other site
+  for (int b = 0; b < 2; ++b) {
+    TN_HIP(ctx, hipMemcpyAsync(cell + 2 * b * ndn, th + (1 - b) * ndn, ndn * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(cell + (2 * b + 1) * ndn, th + b * ndn, ndn * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  TN_TRY(tm_pair(ctx, 2, n, d, cell, cell, vwarm, ed, itd, tol, 100000, warm, nullptr, true, 2));
+  int hi[4];
+  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  // per bond vl = Yt Yt^T (Y = Yt^T), vr = X X^T: the four SVDs at once
+  TN_TRY(jacobi_svd(ctx, 4, n, n, vwarm, n, (long long)nn, U, n, (long long)nn, S, n, nullptr, 0,
+                    0));
+  for (int b = 0; b < 2; ++b) {
+    hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream,
+                       U + 2 * b * nn, S + 2 * b * n, n, Yt + b * nn, Ytinv + b * nn);
+    hipLaunchKernelGGL(sqrt_factors_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream,
+                       U + (2 * b + 1) * nn, S + (2 * b + 1) * n, n, X + b * nn, Xinv + b * nn);
+  }
   TN_HIP(ctx, hipGetLastError());
   // M = Y X = Yt^T X ; SVD M = Um Sm Vm^T (sign-fixed)
-  TN_TRY(gemm(ctx, n, n, n, Yt, n, true, X, n, false, M, n, 1.0, 0.0));
-  TN_TRY(jacobi_svd(ctx, 1, n, n, M, n, 0, Um, n, 0, Sm, 0, Vm, n, 0));
+  TN_TRY(gemm(ctx, n, n, n, Yt, n, true, X, n, false, M, n, 1.0, 0.0, 2, (long long)nn,
+              (long long)nn, (long long)nn));
+  TN_TRY(jacobi_svd(ctx, 2, n, n, M, n, (long long)nn, Um, n, (long long)nn, Sm, n, Vm, n,
+                    (long long)nn));
   // P = Y^+ Um[:, :chi] sqrt(S) with Y^+ = Ytinv^T ; Q = sqrt(S) Vm[:, :chi]^T X^+
-  TN_TRY(gemm(ctx, n, chi, n, Ytinv, n, true, Um, n, false, P, chi, 1.0, 0.0));
-  hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream, P,
-                     n, chi, chi, Sm, 0);
-  TN_TRY(gemm(ctx, chi, n, n, Vm, n, true, Xinv, n, false, Q, n, 1.0, 0.0));
-  hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream, Q,
-                     chi, n, n, Sm, 1);
-  hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1), 0, ctx->stream, Sm, n, chi, lam, err);
+  TN_TRY(gemm(ctx, n, chi, n, Ytinv, n, true, Um, n, false, P, chi, 1.0, 0.0, 2, (long long)nn,
+              (long long)nn, (long long)n * chi));
+  TN_TRY(gemm(ctx, chi, n, n, Vm, n, true, Xinv, n, false, Q, n, 1.0, 0.0, 2, (long long)nn,
+              (long long)nn, (long long)chi * n));
+  for (int b = 0; b < 2; ++b) {
+    hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream,
+                       P + b * n * chi, n, chi, chi, Sm + b * n, 0);
+    hipLaunchKernelGGL(scale_sqrt_kernel, dim3((n * chi + 255) / 256), dim3(256), 0, ctx->stream,
+                       Q + b * chi * n, chi, n, n, Sm + b * n, 1);
+    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1), 0, ctx->stream, Sm + b * n, n, chi,
+                       lam + b * chi, err);
+  }
   TN_HIP(ctx, hipGetLastError());
   TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  *tm_iters = hi[0] > hi[1] ? hi[0] : hi[1];
+  *tm_iters = std::max(std::max(hi[0], hi[1]), std::max(hi[2], hi[3]));
   return TN_OK;
 }
 
@@ -749,11 +780,10 @@ int canonical_1d(tn_ctx* ctx, const BondNet& net, int chi, int d, const double* 
   double* sc = ws_alloc<double>(ctx, 2 * cdc);
   if (!sc) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (canonical form)");
   TN_HIP(ctx, hipMemsetAsync(err, 0, sizeof(double), ctx->stream));
-  for (int b = 0; b < 2; ++b) {
+  {
     const size_t m2 = ctx->arena_off;
     int it = 0;
-    TN_TRY(bond_truncation(ctx, chi, chi, d, A, b, vw + 2 * b * cc, 0, tol, P + b * cc,
-                           Q + b * cc, lam + b * chi, err, &it));
+    TN_TRY(bond_truncations(ctx, chi, chi, d, A, vw, 0, tol, P, Q, lam, err, &it));
     ctx->arena_off = m2;
   }
   TN_TRY(canonical_pq(ctx, 2, chi, P, Q, Pc, Qc));
@@ -967,37 +997,45 @@ __global__ void negate_kernel(double* __restrict__ x, long long n) {
 int gauge_direct_1d(tn_ctx* ctx, int chi, int d, const double* a_ref, const double* a_new,
                     double* U, double tol, int max_iter, double* fidelity, int* itmax_out) {
   const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
-  double* kets = ws_alloc<double>(ctx, 2 * cdc);
-  double* bras = ws_alloc<double>(ctx, 2 * cdc);
-  double* v2 = ws_alloc<double>(ctx, 2 * cc);
-  double* W = ws_alloc<double>(ctx, cc);
-  double* V = ws_alloc<double>(ctx, cc);
-  double* S = ws_alloc<double>(ctx, chi);
+  double* kets = ws_alloc<double>(ctx, 4 * cdc);
+  double* bras = ws_alloc<double>(ctx, 4 * cdc);
+  double* v4 = ws_alloc<double>(ctx, 4 * cc);
+  double* W = ws_alloc<double>(ctx, 2 * cc);
+  double* V = ws_alloc<double>(ctx, 2 * cc);
+  double* S = ws_alloc<double>(ctx, 2 * (size_t)chi);
   double* ed = ws_alloc<double>(ctx, 4);
   int* itd = ws_alloc<int>(ctx, 4);
   double* fd = ws_alloc<double>(ctx, 2);
   if (!fd) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted (1D gauge fix)");
-  int itmax = 0;
+  // the cell of bond b ends with the site left of it: [ref 1, ref 0] for
+  // bond 0, [ref 0, ref 1] for bond 1 (bras likewise); both bonds in one
+  // launch, their left fixed points at v4[0] and v4[2]
   for (int b = 0; b < 2; ++b) {
-    // the cell ends with the site left of bond b: (c, a) = (1, 0) for bond 0
     const int a = b == 0 ? 0 : 1, c = 1 - a;
-    TN_HIP(ctx, hipMemcpyAsync(kets, a_ref + c * cdc, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(kets + cdc, a_ref + a * cdc, cdc * 8, hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(bras, a_new + c * cdc, cdc * 8, hipMemcpyDeviceToDevice, ctx->stream));
-    TN_HIP(ctx, hipMemcpyAsync(bras + cdc, a_new + a * cdc, cdc * 8, hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    const size_t mark = ctx->arena_off;
-    TN_TRY(tm_pair(ctx, 2, chi, d, kets, bras, v2, ed, itd, tol > 0 ? tol : 1e-14, max_iter, 0));
-    ctx->arena_off = mark;
-    // the polar factor of X^T: with X = W S V^T (X^T = V S W^T), U = V W^T
-    TN_TRY(jacobi_svd(ctx, 1, chi, chi, v2, chi, 0, W, chi, 0, S, 0, V, chi, 0));
-    TN_TRY(gemm(ctx, chi, chi, chi, V, chi, false, W, chi, true, U + b * cc, chi, 1.0, 0.0));
-    int hi[2];
-    TN_HIP(ctx, hipMemcpyAsync(hi, itd, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    itmax = std::max(itmax, std::max(hi[0], hi[1]));
+    TN_HIP(ctx, hipMemcpyAsync(kets + 2 * b * cdc, a_ref + c * cdc, cdc * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(kets + (2 * b + 1) * cdc, a_ref + a * cdc, cdc * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(bras + 2 * b * cdc, a_new + c * cdc, cdc * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    TN_HIP(ctx, hipMemcpyAsync(bras + (2 * b + 1) * cdc, a_new + a * cdc, cdc * 8,
+                               hipMemcpyDeviceToDevice, ctx->stream));
   }
+  {
+    const size_t mark = ctx->arena_off;
+    TN_TRY(tm_pair(ctx, 2, chi, d, kets, bras, v4, ed, itd, tol > 0 ? tol : 1e-14, max_iter, 0,
+                   nullptr, true, 2));
+    ctx->arena_off = mark;
+  }
+  // the polar factor of X^T: with X = W S V^T (X^T = V S W^T), U = V W^T
+  TN_TRY(jacobi_svd(ctx, 2, chi, chi, v4, chi, 2 * (long long)cc, W, chi, (long long)cc, S, chi,
+                    V, chi, (long long)cc));
+  TN_TRY(gemm(ctx, chi, chi, chi, V, chi, false, W, chi, true, U, chi, 1.0, 0.0, 2, (long long)cc,
+              (long long)cc, (long long)cc));
+  int hi[4];
+  TN_HIP(ctx, hipMemcpyAsync(hi, itd, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int itmax = std::max(std::max(hi[0], hi[1]), std::max(hi[2], hi[3]));
   hipLaunchKernelGGL(fidelity_1d_kernel, dim3(1), dim3(256), 0, ctx->stream, chi, d, a_ref, a_new,
                      U, fd);
   TN_HIP(ctx, hipGetLastError());
@@ -1021,8 +1059,9 @@ int gauge_direct_1d(tn_ctx* ctx, int chi, int d, const double* a_ref, const doub
 // Arena bytes gauge_direct_1d needs beyond the caller's.
 size_t gauge_direct_bytes(int chi, int d) {
   const size_t cdc = (size_t)chi * d * chi, cc = (size_t)chi * chi;
-  const size_t tmw = tm_work_in_global(2, chi, d) ? 2 * tm_work_per_side(2, chi, d) : 0;
-  return (4 * cdc + 12 * cc + tmw + 64) * 8 + (1 << 20);
+  const size_t tmw = tm_work_in_global(2, chi, d) ? 4 * tm_work_per_side(2, chi, d) : 0;
+  // cells, fixed points, SVD factors, the four sides' Krylov bases
+  return (8 * cdc + 10 * cc + 4 * (TM_KRYLOV + 1) * cc + tmw + 64) * 8 + (1 << 20);
 }
 
 }  // namespace
@@ -1199,7 +1238,10 @@ int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*
   if (mode == 3) extra = (6 * cdc * cdc + 4 * cdc + 64) * 8;
   if (energy_or_null && meas.kind == 1)
     extra += (4 * ndn + 2 * nn + 8) * 8 + 2 * tm_work_per_side(2, n, d) * 8;
-  TN_TRY(ws_reserve(ctx, (40 * nn + 8 * ndn + 16 * cdc) * 8 + extra + (8 << 20)));
+  // the batched truncation: Krylov bases and fixed-point workspaces of four
+  // sides, four factor SVDs and two bond SVDs
+  const size_t tmw = tm_work_in_global(2, n, d) ? 4 * tm_work_per_side(2, n, d) : 0;
+  TN_TRY(ws_reserve(ctx, (96 * nn + 12 * ndn + 16 * cdc + tmw) * 8 + extra + (8 << 20)));
   ws_reset(ctx);
   double* g = ws_alloc<double>(ctx, 16);
   double* th = ws_alloc<double>(ctx, 2 * ndn);
@@ -1284,12 +1326,9 @@ int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*
   TN_TRY(gate(a0));
   const int warm = hflag[0] == 1.0 ? 1 : 0;
   int tmi = 0;
-  for (int b = 0; b < 2; ++b) {
+  {
     const size_t mark = ctx->arena_off;
-    int it = 0;
-    TN_TRY(bond_truncation(ctx, n, chi, d, th, b, env1d + 2 * b * nn, warm, tol, P + b * n * chi,
-                           Q + b * n * chi, lam + b * chi, errd, &it));
-    tmi = it > tmi ? it : tmi;
+    TN_TRY(bond_truncations(ctx, n, chi, d, th, env1d, warm, tol, P, Q, lam, errd, &tmi));
     ctx->arena_off = mark;
   }
   const double one = 1.0;
@@ -1309,7 +1348,7 @@ int itebd_core(tn_ctx* ctx, int chi, int d, double* A /*[2][chi][d][chi] in/out*
     double F = 0.0;
     if (direct) {
       int it = 0;
-      TN_TRY(gauge_direct_1d(ctx, chi, d, a0c, a1, U, 1e-14, 100000, &F, &it));
+      TN_TRY(gauge_direct_1d(ctx, chi, d, a0c, a1, U, tol, 100000, &F, &it));
       tmi = it > tmi ? it : tmi;
     } else {
       TN_TRY(recycle_gauge_start(ctx, 2, n, chi, kap, P, Q, Pc, Qc, U));
