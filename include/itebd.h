@@ -490,7 +490,9 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
  * (s_i^2 + s_j^2)^2), g = s_j^2 - s_i^2 (0 broadens nothing; exactly
  * degenerate pairs then contribute nothing).  The
  * iterations are checkpointed every ckpt_every iterations and recomputed
- * segment by segment in the reverse pass.
+ * segment by segment in the reverse pass; the projector factorisations
+ * (U, S, V of each move) are kept from the forward pass and reused there,
+ * the recomputation being bitwise the forward pass.
  *   A      device [d][D][D][D][D] (s, l, r, d, u); d must be 2
  *   C0, T0 device [4][chi][chi], [4][chi][D][D][chi] (the slots of the one
  *          position, as for ctmrg_iterate)
@@ -503,8 +505,11 @@ int ipeps_energy(tn_ctx* ctx, int Lx, int Ly, int D, int d, int nsite, const dou
  *   energy host out; dEdA device out, shape of A
  * TN_EINVAL for d != 2, n > 512, n_iter < 0, ckpt_every < 1, a precision
  * other than TN_FP64 or a negative broadening.  Device memory: about 2 GB
- * per checkpoint segment at D = 4, chi = 32, in 256 MiB chunks that the
- * context keeps for later calls (tn_clear_cache releases them).
+ * per checkpoint segment at D = 4, chi = 32, plus 4 n_iter (2 n^2 + n)
+ * doubles of kept factorisations (336 MB at n = 512, 20 iterations; when
+ * they cannot be allocated the segments recompute them), in chunks of at
+ * least 256 MiB that the context keeps for later calls (tn_clear_cache
+ * releases them).
  */
 int energy_grad(tn_ctx* ctx, int D, int d, double J, double h, const double* A, int chi,
                 const double* C0, const double* T0, int n_iter, int ckpt_every, int precision,

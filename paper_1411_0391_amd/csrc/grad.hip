@@ -245,6 +245,13 @@ struct Tape {
   std::vector<long long> len;
   std::vector<Op> ops;
   std::vector<SvdSave> svd;
+  // factorisations of the forward pass, reused when a checkpoint segment is
+  // recomputed: slot svd_slot holds U, V (n x n) and S (n) of one projector
+  // problem; with svd_replay the slot is read instead of recomputed (the
+  // recomputation is bitwise the forward pass: same inputs, same kernels)
+  double* svd_cache = nullptr;
+  int svd_slot = -1;
+  bool svd_replay = false;
 
   explicit Tape(tn_ctx* c, int p, double e) : ctx(c), prec(p), eps(e), pool(c, "tape") {}
 
@@ -353,11 +360,21 @@ int t_svdproj(Tape& tp, const int e[4], int n, int chi, int* P, int* PtT) {
   sv.n = n;
   sv.chi = chi;
   const long long nn = (long long)n * n;
+  const bool cached = tp.svd_cache && tp.svd_slot >= 0;
+  const int slot_id = tp.svd_slot;
+  tp.svd_slot = -1;  // one factorisation per slot
   sv.Lft = tp.scratch(nn);
   sv.Rgt = tp.scratch(nn);
-  sv.U = tp.scratch(nn);
-  sv.V = tp.scratch(nn);
-  sv.S = tp.scratch(n);
+  if (cached) {
+    double* slot = tp.svd_cache + (size_t)slot_id * (size_t)(2 * nn + n);
+    sv.U = slot;
+    sv.V = slot + nn;
+    sv.S = slot + 2 * nn;
+  } else {
+    sv.U = tp.scratch(nn);
+    sv.V = tp.scratch(nn);
+    sv.S = tp.scratch(n);
+  }
   sv.isq = tp.scratch(chi);
   double* K = tp.scratch(nn);
   double* X = tp.scratch((long long)n * chi);
@@ -366,12 +383,14 @@ int t_svdproj(Tape& tp, const int e[4], int n, int chi, int* P, int* PtT) {
               0, 0, tp.prec));
   TN_TRY(gemm(ctx, n, n, n, tp.v[e[0]], n, false, tp.v[e[1]], n, false, sv.Rgt, n, 1.0, 0.0, 1, 0,
               0, 0, tp.prec));
-  TN_TRY(gemm(ctx, n, n, n, sv.Lft, n, false, sv.Rgt, n, false, K, n, 1.0, 0.0, 1, 0, 0, 0,
-              tp.prec));
-  if (n > 128)
-    TN_TRY(jacobi_svd_large(ctx, n, n, K, n, sv.U, n, sv.S, sv.V, n));
-  else
-    TN_TRY(jacobi_svd(ctx, 1, n, n, K, n, 0, sv.U, n, 0, sv.S, 0, sv.V, n, 0));
+  if (!(cached && tp.svd_replay)) {
+    TN_TRY(gemm(ctx, n, n, n, sv.Lft, n, false, sv.Rgt, n, false, K, n, 1.0, 0.0, 1, 0, 0, 0,
+                tp.prec));
+    if (n > 128)
+      TN_TRY(jacobi_svd_large(ctx, n, n, K, n, sv.U, n, sv.S, sv.V, n));
+    else
+      TN_TRY(jacobi_svd(ctx, 1, n, n, K, n, 0, sv.U, n, 0, sv.S, 0, sv.V, n, 0));
+  }
   hipLaunchKernelGGL(isq_kernel, dim3((chi + 63) / 64), dim3(64), 0, ctx->stream, sv.S, sv.isq,
                      chi, n);
   TP_NEW(p, tp, (long long)n * chi);
@@ -751,6 +770,13 @@ int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double
   double* gC2 = keep.alloc((size_t)ce);
   double* gT2 = keep.alloc((size_t)te);
   if (!ck || !cur || !gC2 || !gT2) TN_FAIL(ctx, TN_ENOMEM, "out of device memory in energy_grad");
+  // the forward pass's projector factorisations (one per move), reused by
+  // the recomputation of the checkpoint segments; without the memory the
+  // segments recompute them
+  Pool svd_pool(ctx, "svd");
+  const size_t svd_per = 2 * (size_t)s.n * s.n + s.n;
+  double* svd_cache = n_iter > 0 ? svd_pool.alloc((size_t)n_iter * 4 * svd_per) : nullptr;
+  if (!svd_cache) ctx->err.clear();
   TN_HIP(ctx, hipMemcpyAsync(cur, C0, ce * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   TN_HIP(ctx, hipMemcpyAsync(cur + ce, T0, te * sizeof(double), hipMemcpyDeviceToDevice,
                              ctx->stream));
@@ -761,10 +787,14 @@ int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double
       TN_HIP(ctx, hipMemcpyAsync(ck + (size_t)(it / ckpt) * (ce + te), cur,
                                  (ce + te) * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     Tape tp(ctx, it_prec(it), eps);
+    tp.svd_cache = svd_cache;
     int a_id, arot[4];
     Env env;
     TN_TRY(t_inputs(tp, s, A, cur, cur + ce, &a_id, arot, env));
-    for (int f = 0; f < 4; ++f) TN_TRY(t_move(tp, s, env, arot, f));
+    for (int f = 0; f < 4; ++f) {
+      tp.svd_slot = 4 * it + f;
+      TN_TRY(t_move(tp, s, env, arot, f));
+    }
     TN_TRY(copy_env_out(tp, s, env, cur, cur + ce));
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
   }
@@ -822,9 +852,14 @@ int energy_grad_impl(tn_ctx* ctx, int D, int d, double J, double h, const double
     const double* cs = ck + (size_t)sg * (ce + te);
     TN_TRY(t_inputs(tp, s, A, cs, cs + ce, &a_id, arot, env0));
     env = env0;
+    tp.svd_cache = svd_cache;
+    tp.svd_replay = true;
     for (int it = i0; it < i1; ++it) {
       tp.prec = it_prec(it);
-      for (int f = 0; f < 4; ++f) TN_TRY(t_move(tp, s, env, arot, f));
+      for (int f = 0; f < 4; ++f) {
+        tp.svd_slot = 4 * it + f;
+        TN_TRY(t_move(tp, s, env, arot, f));
+      }
     }
     TN_TRY(seed_env(tp, s, env, gC, gT));
     TN_TRY(backward(tp));
