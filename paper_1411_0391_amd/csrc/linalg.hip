@@ -385,14 +385,6 @@ jacobi_fast_fn jacobi_fast_kernel(int me, int ne) {
 // off-diagonal of a sweep is collected with an atomic maximum on the bit
 // pattern (order-preserving for non-negative doubles).
 // ---------------------------------------------------------------------------
-__device__ inline double block_sum256(double v, double* red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
-}
-
 __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ X, int ldx,
                                                            double* __restrict__ W, int ldw, int m,
                                                            int n, int N, int r, double tol,
@@ -405,16 +397,45 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   const int p = min(p0, p1), qq = max(p0, p1);
   double* xp = X + (long long)p * ldx;
   double* xq = X + (long long)qq * ldx;
+  // columns of up to 512 rows stay in registers between the dot products
+  // and the rotation (two entries per thread)
+  const bool held = m <= 512;
+  double us[2] = {0.0, 0.0}, vs[2] = {0.0, 0.0};
   double a = 0.0, bb = 0.0, g = 0.0;
-  for (int i = threadIdx.x; i < m; i += 256) {
-    const double u = xp[i], v = xq[i];
-    a += u * u;
-    bb += v * v;
-    g += u * v;
+  if (held) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < m) {
+        us[k] = xp[i];
+        vs[k] = xq[i];
+        a += us[k] * us[k];
+        bb += vs[k] * vs[k];
+        g += us[k] * vs[k];
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const double u = xp[i], v = xq[i];
+      a += u * u;
+      bb += v * v;
+      g += u * v;
+    }
   }
-  a = block_sum256(a, red[0]);
-  bb = block_sum256(bb, red[1]);
-  g = block_sum256(g, red[2]);
+  // the three sums in one exchange: each a wave sum, then the four wave
+  // partials in order
+  a = wave_sum(a);
+  bb = wave_sum(bb);
+  g = wave_sum(g);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = bb;
+    red[2][threadIdx.x >> 6] = g;
+  }
+  __syncthreads();
+  a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  bb = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  g = red[2][0] + red[2][1] + red[2][2] + red[2][3];
   const double scale = sqrt(a * bb);
   if (scale == 0.0 || fabs(g) <= tol * scale) return;
   if (threadIdx.x == 0)
@@ -422,10 +443,21 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   const double z = (bb - a) / (2.0 * g);
   const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
   const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-  for (int i = threadIdx.x; i < m; i += 256) {
-    const double u = xp[i], v = xq[i];
-    xp[i] = c * u - sn * v;
-    xq[i] = sn * u + c * v;
+  if (held) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < m) {
+        xp[i] = c * us[k] - sn * vs[k];
+        xq[i] = sn * us[k] + c * vs[k];
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const double u = xp[i], v = xq[i];
+      xp[i] = c * u - sn * v;
+      xq[i] = sn * u + c * v;
+    }
   }
   double* wp = W + (long long)p * ldw;
   double* wq = W + (long long)qq * ldw;
