@@ -3,6 +3,7 @@
 // one (small) matrix; batches run as a grid of workgroups.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 
@@ -388,6 +389,7 @@ jacobi_fast_fn jacobi_fast_kernel(int me, int ne) {
 __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ X, int ldx,
                                                            double* __restrict__ W, int ldw, int m,
                                                            int n, int N, int r, double tol,
+                                                           const double* __restrict__ null2,
                                                            unsigned long long* __restrict__ offbits) {
   __shared__ double red[3][4];
   const int q = blockIdx.x;
@@ -436,6 +438,9 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
   bb = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   g = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  // a numerically null column (squared norm at most null2) is left alone:
+  // its direction is rounding noise, and rotating it never settles
+  if (a <= null2[0] || bb <= null2[0]) return;
   const double scale = sqrt(a * bb);
   if (scale == 0.0 || fabs(g) <= tol * scale) return;
   if (threadIdx.x == 0)
@@ -466,6 +471,31 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
     wp[i] = c * u - sn * v;
     wq[i] = sn * u + c * v;
   }
+}
+
+// out[0] = scale2 * sum x^2 over n entries, in one workgroup (a fixed order)
+__global__ __launch_bounds__(1024) void sumsq_kernel(const double* __restrict__ x, long long n,
+                                                     double scale2, double* __restrict__ out) {
+  __shared__ double red[16];
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 1024) a += x[i] * x[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[0] = scale2 * t;
+  }
+}
+
+// dst[i][c0 + j] = src[i][j] for an m x nc block (row-major, leading dims)
+__global__ void copy_cols_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst,
+                                 int ldd, int m, int nc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m * nc) return;
+  const int i = (int)(t / nc), j = (int)(t % nc);
+  dst[(long long)i * ldd + j] = src[(long long)i * lds + j];
 }
 
 // X[j][i] = A[i][j] (columns contiguous), W = I
@@ -898,12 +928,52 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
   return TN_OK;
 }
 
+// Columns m x nc of Z orthonormal and orthogonal to the first r columns of
+// U (m x r, orthonormal, leading dimension ldu): a seeded random start,
+// projected off U_r twice, then two Cholesky-QR passes; written into
+// U[:, r : r + nc].
+static int complete_left_basis(tn_ctx* ctx, int m, int r, int nc, double* U, int ldu) {
+  if (nc <= 0) return TN_OK;
+  const size_t mark = ctx->arena_off;
+  double* Z = ws_alloc<double>(ctx, (size_t)m * nc);
+  double* Z2 = ws_alloc<double>(ctx, (size_t)m * nc);
+  double* T = ws_alloc<double>(ctx, (size_t)std::max(r, 1) * nc);
+  double* G = ws_alloc<double>(ctx, (size_t)nc * nc);
+  double* R = ws_alloc<double>(ctx, (size_t)nc * nc);
+  double* Ri = ws_alloc<double>(ctx, (size_t)nc * nc);
+  int* info = ws_alloc<int>(ctx, 2);
+  if (!info) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted completing the left basis");
+  TN_TRY(fill_random(ctx, Z, (long long)m * nc, 0x6a09e667f3bcc909ULL));
+  for (int pass = 0; pass < 2 && r > 0; ++pass) {
+    TN_TRY(gemm(ctx, r, nc, m, U, ldu, true, Z, nc, false, T, nc, 1.0, 0.0));
+    TN_TRY(gemm(ctx, m, nc, r, U, ldu, false, T, nc, false, Z, nc, -1.0, 1.0));
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    TN_TRY(gemm(ctx, nc, nc, m, Z, nc, true, Z, nc, false, G, nc, 1.0, 0.0));
+    TN_TRY(cholesky_inv(ctx, nc, G, 0.0, R, Ri, info + pass, 1));
+    TN_TRY(gemm(ctx, m, nc, nc, Z, nc, false, Ri, nc, false, Z2, nc, 1.0, 0.0));
+    std::swap(Z, Z2);
+  }
+  int hinfo[2] = {0, 0};
+  TN_HIP(ctx, hipMemcpyAsync(hinfo, info, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  const long long tot = (long long)m * nc;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, Z, nc, U + r, ldu, m, nc);
+  TN_HIP(ctx, hipGetLastError());
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->arena_off = mark;
+  if (hinfo[0] != 0 || hinfo[1] != 0)
+    TN_FAIL(ctx, TN_ENUMERIC, "Cholesky-QR breakdown completing the left basis");
+  return TN_OK;
+}
+
 int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
                      double* S, double* V, int ldv) {
   if (m < n || n < 1 || n > 512) TN_FAIL(ctx, TN_EINVAL, "jacobi_svd_large needs 1 <= n <= m, n <= 512");
   const size_t mark = ctx->arena_off;
   double* X = ws_alloc<double>(ctx, (size_t)m * n);
   double* W = ws_alloc<double>(ctx, (size_t)n * n);
+  double* null2 = ws_alloc<double>(ctx, 1);
   unsigned long long* off = ws_alloc<unsigned long long>(ctx, 1);
   if (!off) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in jacobi_svd_large");
   const long long tot = (long long)std::max(m, n) * n;
@@ -911,13 +981,17 @@ int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double
                      ctx->stream, A, lda, m, n, X, W);
   TN_HIP(ctx, hipGetLastError());
   const double tol = 8.0 * 1.1102230246251565e-16 * (double)m;
+  // columns with |x|^2 <= tol^2 |A|_F^2 count as numerically null
+  hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(1024), 0, ctx->stream, X, (long long)m * n,
+                     tol * tol, null2);
+  TN_HIP(ctx, hipGetLastError());
   const int N = (n + 1) & ~1;
   unsigned long long* hoff = reinterpret_cast<unsigned long long*>(ctx->host_scratch + 40);
   for (int sweep = 0; sweep < 80 && n > 1; ++sweep) {
     TN_HIP(ctx, hipMemsetAsync(off, 0, sizeof(unsigned long long), ctx->stream));
     for (int r = 0; r < N - 1; ++r)
       hipLaunchKernelGGL(jacobi_round_kernel, dim3(N / 2), dim3(256), 0, ctx->stream, X, m, W, n,
-                         m, n, N, r, tol, off);
+                         m, n, N, r, tol, null2, off);
     TN_HIP(ctx, hipGetLastError());
     TN_HIP(ctx, hipMemcpyAsync(hoff, off, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                ctx->stream));
@@ -927,6 +1001,20 @@ int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double
   hipLaunchKernelGGL(jacobi_emit_kernel, dim3(1), dim3(1024), 0, ctx->stream, X, m, W, n, m, n, U,
                      ldu, S, V, ldv);
   TN_HIP(ctx, hipGetLastError());
+  // the left vectors of the null columns (the trailing ones: S is sorted)
+  // are rounding noise; replace them by an orthonormal basis of the
+  // complement of the others (the right vectors, accumulated rotations,
+  // are orthonormal already)
+  std::vector<double> hs(n + 1);
+  TN_HIP(ctx, hipMemcpyAsync(hs.data(), S, n * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  TN_HIP(ctx, hipMemcpyAsync(hs.data() + n, null2, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const double thr = sqrt(hs[n]);
+  int r = 0;
+  while (r < n && hs[r] > thr) ++r;
+  TN_TRY(complete_left_basis(ctx, m, r, n - r, U, ldu));
   ctx->arena_off = mark;
   return TN_OK;
 }
