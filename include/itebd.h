@@ -231,7 +231,10 @@ enum {
  *   lambda_out device out [2][chi] (may be NULL): kept spectra of bonds 0
  *              (after site 0) and 1, unit l2 norm (after a build step: the
  *              canonical spectra of the truncated state)
- *   tol        fixed-point tolerance
+ *   tol        fixed-point tolerance (the bond environments come from
+ *              restarted Arnoldi: Arnoldi residual below tol times the
+ *              Ritz value, or below 100 tol while no longer halving per
+ *              restart)
  *   trunc_err  host out: discarded weight summed over the two bonds
  *   energy_or_null host out (may be NULL): energy per site of the new state
  * Returns TN_OK, TN_NOT_CONVERGED (a fixed point hit its iteration cap),
@@ -363,9 +366,10 @@ enum { TN_GAUGE_2D = 0, TN_GAUGE_1D = 1, TN_GAUGE_1D_DIRECT = 2 };
  *          orthogonal polar factor of X^T; the sign of the pair is taken
  *          with F > 0.  U is output only.  The eigenvectors of both
  *          bonds come from one restarted-Arnoldi launch: it stops when
- *          the Arnoldi residual is below tol times the Ritz value
- *          (tol <= 0: 1e-14), max_iter bounds the transfer-matrix
- *          applications.  chi <= 64 for both 1D kinds.
+ *          the Arnoldi residual is below tol times the Ritz value, or
+ *          below 100 tol times it while no longer halving per restart
+ *          (its rounding floor) (tol <= 0: 1e-14); max_iter bounds the
+ *          transfer-matrix applications.  chi <= 64 for both 1D kinds.
  *   U             device in/out [nlink][D][D] (1D: [2][chi][chi])
  *   fidelity, iters  host out
  * Returns TN_OK, TN_NOT_CONVERGED, TN_EINVAL, TN_ENUMERIC, TN_EHIP.
