@@ -276,9 +276,10 @@ def run_mz_sweep(args):
 
 
 def run_full_update(args):
-    """The 2D full-update workload: checkerboard, D = 4, chi = 32, J = 1,
-    h = 3.0, dt = 0.01, CTMRG tolerance 1e-10, from seeded N(0,1) sites and
-    the positive seeded boundary.  The plain run (environment every step)
+    """The 2D full-update workload: checkerboard (or --fu-cell one-site, the
+    paper's scheme with averaged links), D = --fu-D (4), chi = --fu-chi (32),
+    J = 1, h = 3.0, dt = 0.01, CTMRG tolerance 1e-10, from seeded N(0,1)
+    sites and the positive seeded boundary.  The plain run (environment every step)
     goes on until its energy changes by less than --fu-conv (relative) over
     100 steps, or --fu-steps steps; its last energy is E_ref.  The recycled
     run (N_Re = --fu-nre after --fu-warm plain steps; an environment step is
@@ -290,14 +291,16 @@ def run_full_update(args):
     import paper_1411_0391_amd as tn
     from paper_1411_0391_amd import driver
     import tninputs
-    D, chi = 4, 32
-    Lx, Ly, cell = tninputs.CHECKERBOARD
+    D, chi = args.fu_D, args.fu_chi
+    one_site = args.fu_cell == "one-site"
+    Lx, Ly, cell = tninputs.SINGLE_SITE if one_site else tninputs.CHECKERBOARD
     cell = list(cell)
+    nsite = 1 if one_site else 2
     if args.fu_start == "random":
-        A0 = np.stack(tninputs.ipeps_sites(0, 2, D))
+        A0 = np.stack(tninputs.ipeps_sites(0, nsite, D))
         start = "N(0,1) site tensors of bond D from seed 0"
     else:
-        A0 = np.stack(tninputs.ipeps_near_product(0, 2, D))
+        A0 = np.stack(tninputs.ipeps_near_product(0, nsite, D))
         start = "seeded N(0,1) product state plus 1e-2 of N(0,1) bond-D tensors"
     C0, T0 = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
     ctx = tn.Context()
@@ -335,8 +338,9 @@ def run_full_update(args):
         plain_conv = abs(runs["plain"][-1][1] - runs["plain"][-101][1]) < args.fu_conv * abs(e_ref)
     out = {"metric": "time-to-1e-6 energy, recycled vs plain (2D full update)", "unit": "s",
            "higher_is_better": False,
-           "config": {"workload": f"TFIM iPEPS full update, checkerboard, D={D}, chi={chi}, "
-                                  f"h=3.0, dt=0.01, CTMRG tol 1e-10", "D": D, "chi": chi,
+           "config": {"workload": f"TFIM iPEPS full update, {args.fu_cell} cell, D={D}, "
+                                  f"chi={chi}, h=3.0, dt=0.01, CTMRG tol 1e-10", "D": D,
+                      "chi": chi, "cell": args.fu_cell,
                       "steps": nsteps, "N_Re": args.fu_nre, "N_warm": args.fu_warm,
                       "min_fidelity": 1 - 1e-3, "start": start},
            "data": "synthetic", "dtype": "f64", "n_gpus": 1,
@@ -401,6 +405,10 @@ def main():
                     help="step cap of the plain full-update run")
     ap.add_argument("--fu-warm", type=int, default=20)
     ap.add_argument("--fu-nre", type=int, default=20)
+    ap.add_argument("--fu-cell", choices=("checkerboard", "one-site"), default="checkerboard",
+                    help="unit cell of the full-update workload (one-site: the paper's scheme)")
+    ap.add_argument("--fu-D", type=int, default=4)
+    ap.add_argument("--fu-chi", type=int, default=32)
     ap.add_argument("--fu-start", choices=("random", "product"), default="random",
                     help="start of the full update: N(0,1) bond-D tensors, or a random "
                          "product state with a 1e-2 bond-D part")

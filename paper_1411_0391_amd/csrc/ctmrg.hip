@@ -898,8 +898,11 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       --it;
       continue;
     }
+    // after a breakdown the block stays on the robust path for the rest of
+    // this problem: a nearly rank-deficient K (a product-like state) breaks
+    // every fast orthonormalisation, and falling back to it would spend the
+    // retries
     q_pending = false;
-    robust = false;
     const double hprev = hres;
     hres = ctx->host_scratch[0];
     if (!std::isfinite(hres)) TN_FAIL(ctx, TN_ENUMERIC, "non-finite residual in the projector SVD");
@@ -921,8 +924,15 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
     std::swap(Y, Ysave);
     std::swap(S, Sprev);
     s_current = false;
-    TN_TRY(orth_fast(ctx, n, k, B, Q, Sprev, nullptr, tmp, info_q, Ysave));
-    q_pending = true;
+    if (robust) {
+      TN_HIP(ctx, hipMemcpyAsync(Q, Ysave, bnk * sizeof(double), hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+      TN_TRY(orth_robust(ctx, n, k, B, Q, Sprev, nullptr, tmp, save, info));
+      q_pending = false;
+    } else {
+      TN_TRY(orth_fast(ctx, n, k, B, Q, Sprev, nullptr, tmp, info_q, Ysave));
+      q_pending = true;
+    }
     have_s = true;
   }
   if (!s_current) std::swap(S, Sprev);  // the last Ritz values
