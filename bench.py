@@ -304,6 +304,11 @@ def run_full_update(args):
         start = "seeded N(0,1) product state plus 1e-2 of N(0,1) bond-D tensors"
     C0, T0 = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
     ctx = tn.Context()
+    if args.fu_start == "su":
+        # the product start evolved by the simple update (untimed)
+        A0 = driver.simple_update(ctx, Lx, Ly, cell, torch.from_numpy(A0.copy()).to("cuda"),
+                                  1.0, 3.0, 0.01, args.fu_su_steps).cpu().numpy()
+        start += f", then {args.fu_su_steps} simple-update steps (untimed)"
     runs, info_all = {}, {}
     nsteps = args.fu_steps
     for label, n_re, n_warm in (("plain", 1, 0), ("recycled", args.fu_nre, args.fu_warm)):
@@ -409,9 +414,12 @@ def main():
                     help="unit cell of the full-update workload (one-site: the paper's scheme)")
     ap.add_argument("--fu-D", type=int, default=4)
     ap.add_argument("--fu-chi", type=int, default=32)
-    ap.add_argument("--fu-start", choices=("random", "product"), default="random",
-                    help="start of the full update: N(0,1) bond-D tensors, or a random "
-                         "product state with a 1e-2 bond-D part")
+    ap.add_argument("--fu-su-steps", type=int, default=300,
+                    help="simple-update steps before the full update with --fu-start su")
+    ap.add_argument("--fu-start", choices=("random", "product", "su"), default="random",
+                    help="start of the full update: N(0,1) bond-D tensors, a random "
+                         "product state with a 1e-2 bond-D part, or that state after "
+                         "--fu-su-steps simple-update steps")
     ap.add_argument("--fu-conv", type=float, default=1e-9,
                     help="plain run ends when E changes by less than this over 100 steps")
     args = ap.parse_args()
