@@ -161,6 +161,9 @@ int side_stream_ready(tn_ctx* ctx);
 // modified; U m x n, S n, V n x n as for jacobi_svd.
 int jacobi_svd_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
                      double* S, double* V, int ldv);
+// the same factorisation with a Householder QR preconditioner (Jacobi on R^T)
+int svd_qr_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
+                 double* S, double* V, int ldv);
 
 // Upper Cholesky factor of (G + shift*I) and its inverse, k x k row-major, for
 // `batch` matrices stored back to back (info: one int per matrix, 0 or the

@@ -387,7 +387,7 @@ int t_svdproj(Tape& tp, const int e[4], int n, int chi, int* P, int* PtT) {
     TN_TRY(gemm(ctx, n, n, n, sv.Lft, n, false, sv.Rgt, n, false, K, n, 1.0, 0.0, 1, 0, 0, 0,
                 tp.prec));
     if (n > 128)
-      TN_TRY(jacobi_svd_large(ctx, n, n, K, n, sv.U, n, sv.S, sv.V, n));
+      TN_TRY(svd_qr_large(ctx, n, n, K, n, sv.U, n, sv.S, sv.V, n));
     else
       TN_TRY(jacobi_svd(ctx, 1, n, n, K, n, 0, sv.U, n, 0, sv.S, 0, sv.V, n, 0));
   }

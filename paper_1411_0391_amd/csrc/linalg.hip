@@ -498,6 +498,75 @@ __global__ void copy_cols_kernel(const double* __restrict__ src, int lds, double
   dst[(long long)i * ldd + j] = src[(long long)i * lds + j];
 }
 
+// Householder QR on column-contiguous storage Xq[c][r] (row c of Xq is
+// column c of the matrix, length m).  Reflector j: from x = Xq[j][j..m),
+// beta = -sign(x_j) |x|, v = (1, x_{j+1..} / (x_j - beta)), tau = (beta -
+// x_j) / beta; on exit Xq[j][j] = beta (the diagonal of R), Xq[j][r > j] the
+// tail of v, tau[j] (0 when the tail is zero: H = I).
+__global__ __launch_bounds__(256) void hh_vec_kernel(double* __restrict__ Xq, int ld, int m,
+                                                     int j, double* __restrict__ tau) {
+  __shared__ double red[4];
+  double* x = Xq + (long long)j * ld;
+  const double alpha = x[j];  // read by every thread before thread 0 rewrites it
+  double a = 0.0;
+  for (int r = j + 1 + threadIdx.x; r < m; r += 256) a += x[r] * x[r];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const double xn2 = red[0] + red[1] + red[2] + red[3];
+  if (xn2 == 0.0) {
+    if (threadIdx.x == 0) tau[j] = 0.0;
+    return;
+  }
+  const double beta = alpha >= 0.0 ? -sqrt(alpha * alpha + xn2) : sqrt(alpha * alpha + xn2);
+  const double sc = 1.0 / (alpha - beta);
+  for (int r = j + 1 + threadIdx.x; r < m; r += 256) x[r] *= sc;
+  if (threadIdx.x == 0) {
+    x[j] = beta;
+    tau[j] = (beta - alpha) / beta;
+  }
+}
+
+// y <- (I - tau v v^T) y for the columns c = c0 + blockIdx.x of Y (column-
+// contiguous, rows j..m of each touched), v = (1, Xq[j][j+1..m)).
+__global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict__ Xq, int ldq,
+                                                       double* __restrict__ Y, int ldy, int m,
+                                                       int j, const double* __restrict__ tau,
+                                                       int c0) {
+  __shared__ double red[4];
+  const double t = tau[j];
+  if (t == 0.0) return;
+  const double* v = Xq + (long long)j * ldq;
+  double* y = Y + (long long)(c0 + blockIdx.x) * ldy;
+  double a = threadIdx.x == 0 ? y[j] : 0.0;
+  for (int r = j + 1 + threadIdx.x; r < m; r += 256) a += v[r] * y[r];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const double sdot = t * (red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) y[j] -= sdot;
+  for (int r = j + 1 + threadIdx.x; r < m; r += 256) y[r] -= sdot * v[r];
+}
+
+// dst[r][c] = src[c][r] for a rows x cols destination (leading dimensions
+// ldd, lds)
+__global__ void transpose_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst,
+                                 int ldd, int rows, int cols) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)rows * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);
+  dst[(long long)r * ldd + c] = src[(long long)c * lds + r];
+}
+
+// dst[r][c] = src[r][c] for c <= r, 0 above (n x n)
+__global__ void lower_copy_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst,
+                                  int ldd, int n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int r = (int)(t / n), c = (int)(t % n);
+  dst[(long long)r * ldd + c] = c <= r ? src[(long long)r * lds + c] : 0.0;
+}
+
 // X[j][i] = A[i][j] (columns contiguous), W = I
 __global__ void jacobi_setup_kernel(const double* __restrict__ A, int lda, int m, int n,
                                     double* __restrict__ X, double* __restrict__ W) {
@@ -932,6 +1001,58 @@ int jacobi_svd(tn_ctx* ctx, int batch, int m, int n, double* A, int lda, long lo
 // U (m x r, orthonormal, leading dimension ldu): a seeded random start,
 // projected off U_r twice, then two Cholesky-QR passes; written into
 // U[:, r : r + nc].
+// SVD of one m x n matrix (m >= n, n <= 512) with a QR preconditioner:
+// A = Q R by Householder reflections (on column-contiguous storage), then
+// the one-sided Jacobi SVD of R^T = U' S W^T (jacobi_svd_large), so that
+// A = (Q W) S U'^T.  On a graded matrix the Jacobi sweeps on R^T are far
+// fewer than on A itself.
+int svd_qr_large(tn_ctx* ctx, int m, int n, const double* A, int lda, double* U, int ldu,
+                 double* S, double* V, int ldv) {
+  if (m < n || n < 1 || n > 512) TN_FAIL(ctx, TN_EINVAL, "svd_qr_large needs 1 <= n <= m, n <= 512");
+  const size_t mark = ctx->arena_off;
+  double* Xq = ws_alloc<double>(ctx, (size_t)n * m);   // [n][m]: column c of A
+  double* Rt = ws_alloc<double>(ctx, (size_t)n * n);   // R^T, row-major
+  double* Ue = ws_alloc<double>(ctx, (size_t)n * n);
+  double* We = ws_alloc<double>(ctx, (size_t)n * n);
+  double* Y = ws_alloc<double>(ctx, (size_t)n * m);    // [n][m]: columns of Q W
+  double* tau = ws_alloc<double>(ctx, (size_t)n);
+  if (!tau) TN_FAIL(ctx, TN_ENOMEM, "workspace exhausted in svd_qr_large");
+  const long long nm = (long long)n * m, nn = (long long)n * n;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0,
+                     ctx->stream, A, lda, Xq, m, n, m);
+  TN_HIP(ctx, hipGetLastError());
+  for (int j = 0; j < n; ++j) {
+    hipLaunchKernelGGL(hh_vec_kernel, dim3(1), dim3(256), 0, ctx->stream, Xq, m, m, j, tau);
+    if (j + 1 < n)
+      hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)(n - j - 1)), dim3(256), 0, ctx->stream,
+                         Xq, m, Xq, m, m, j, tau, j + 1);
+  }
+  TN_HIP(ctx, hipGetLastError());
+  // R^T[i][c] = R[c][i] = Xq[i][c] for c <= i, zero above
+  hipLaunchKernelGGL(lower_copy_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
+                     ctx->stream, Xq, m, Rt, n, n);
+  TN_HIP(ctx, hipGetLastError());
+  TN_TRY(jacobi_svd_large(ctx, n, n, Rt, n, Ue, n, S, We, n));
+  // Q W: the columns of W (length n) padded to m, the reflectors applied
+  // in reverse order
+  TN_HIP(ctx, hipMemsetAsync(Y, 0, (size_t)nm * sizeof(double), ctx->stream));
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
+                     ctx->stream, We, n, Y, m, n, n);
+  TN_HIP(ctx, hipGetLastError());
+  for (int j = n - 1; j >= 0; --j)
+    hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, Xq, m, Y, m,
+                       m, j, tau, 0);
+  TN_HIP(ctx, hipGetLastError());
+  // U[r][i] = (Q W)[r][i] = Y[i][r]; V = U'
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0,
+                     ctx->stream, Y, m, U, ldu, m, n);
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
+                     ctx->stream, Ue, n, V, ldv, n, n);
+  TN_HIP(ctx, hipGetLastError());
+  ctx->arena_off = mark;
+  return TN_OK;
+}
+
 static int complete_left_basis(tn_ctx* ctx, int m, int r, int nc, double* U, int ldu) {
   if (nc <= 0) return TN_OK;
   const size_t mark = ctx->arena_off;
