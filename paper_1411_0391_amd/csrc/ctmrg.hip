@@ -93,6 +93,17 @@ __global__ void max_over_kernel(const double* __restrict__ colres, int chi, int 
   *out = r;
 }
 
+// At[b] = A[b]^T for a batch of k x k row-major matrices
+__global__ __launch_bounds__(256) void transpose_sq_kernel(int k, long long total,
+                                                           const double* __restrict__ A,
+                                                           double* __restrict__ At) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const long long kk = (long long)k * k, b = t / kk;
+  const int r = (int)(t - b * kk), i = r / k, j = r - i * k;
+  At[b * kk + (long long)j * k + i] = A[t];
+}
+
 // sign convention on the kept left singular vectors of M (= W): the first
 // entry within a relative 1e-8 of the largest magnitude is made positive; the
 // matching columns of V flip with them
@@ -772,6 +783,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
   double* tmp = ws_alloc<double>(ctx, bnk);
   double* save = ws_alloc<double>(ctx, bnk);
   double* R = ws_alloc<double>(ctx, bkk);
+  double* Rt = ws_alloc<double>(ctx, bkk);
   double* UR = ws_alloc<double>(ctx, bkk);
   double* VR = ws_alloc<double>(ctx, bkk);
   double* S = ws_alloc<double>(ctx, (size_t)B * k);
@@ -837,6 +849,16 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       TN_TRY(orth_fast(ctx, n, k, B, Bm, Sprev, R, tmp, info_b));
     else
       TN_TRY(orth_robust(ctx, n, k, B, Bm, have_s ? Sprev : nullptr, R, tmp, save, info));
+    // R = UR S VR^T by the one-sided Jacobi SVD of R^T = VR S UR^T (its
+    // normalised columns are VR, its accumulated rotations UR).  From a warm
+    // start R is diag(S) plus entries eps s_j above the diagonal: in the
+    // columns of R every pair starts at cosine eps, in its rows pair (i, j)
+    // at eps s_j / s_i, so only pairs of close Ritz values need rotating
+    // (fewer sweeps, the QR preconditioning of one-sided Jacobi).
+    const long long bkk_l = (long long)bkk;
+    hipLaunchKernelGGL(transpose_sq_kernel, dim3((unsigned)((bkk_l + 255) / 256)), dim3(256), 0,
+                       ctx->stream, k, bkk_l, R, Rt);
+    TN_HIP(ctx, hipGetLastError());
     // The Ritz rotation UR only turns the basis inside span(Bm), so K Bm can
     // be formed while the SVD of R (a few workgroups) runs on the side
     // stream; then K Wb = (K Bm) UR.
@@ -846,7 +868,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       TN_HIP(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
       hipStream_t main_stream = ctx->stream;
       ctx->stream = ctx->side;
-      const int rc = jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk);
+      const int rc = jacobi_svd(ctx, B, k, k, Rt, k, kk, VR, k, kk, S, k, UR, k, kk);
       ctx->stream = main_stream;
       if (rc != TN_OK) return rc;
       TN_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->side));
@@ -856,7 +878,7 @@ int topk_svd(tn_ctx* ctx, TopK& t, double* warmQ, double* warmS, bool warm_valid
       TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
       TN_TRY(gemm(ctx, n, k, k, Zk, k, false, UR, k, false, Y, k, 1.0, 0.0, B, snk, kk, snk));
     } else {
-      TN_TRY(jacobi_svd(ctx, B, k, k, R, k, kk, UR, k, kk, S, k, VR, k, kk));
+      TN_TRY(jacobi_svd(ctx, B, k, k, Rt, k, kk, VR, k, kk, S, k, UR, k, kk));
       TN_TRY(gemm(ctx, n, k, k, Bm, k, false, UR, k, false, Wb, k, 1.0, 0.0, B, snk, kk, snk));
       TN_TRY(gemm(ctx, n, k, k, Q, k, false, VR, k, false, Vr, k, 1.0, 0.0, B, snk, kk, snk));
       TN_TRY(applyK(ctx, t, Wb, Y));
@@ -1159,7 +1181,7 @@ size_t move_bytes(const Geo& g, int k, bool warm) {
   add(Lm * (16 * n * k + 64 * (size_t)k * k));  // split-K partials of the n x n x k products
   // topk_svd scratch (explicit path for n <= 256, subspace path otherwise)
   add(std::max(Lm * 9 * n * k, 4 * n * n + n));
-  add(Lm * 3 * k * k);
+  add(Lm * 4 * k * k);  // R, R^T, UR, VR
   add(Lm * (4 * k + chi) + 64);
   add(Lm * 16 + 64);
   add(64);                                        // status of the plain steps
