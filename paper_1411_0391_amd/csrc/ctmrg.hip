@@ -14,7 +14,7 @@
 // forming K (four n x n x k products per application, n = chi D^2): block
 // subspace iteration on K K^T with k = chi + oversampling columns,
 // orthonormalised by shifted Cholesky-QR (three passes), Rayleigh-Ritz by a
-// one-sided Jacobi SVD of the k x k factor, stopped when the residual
+// one-sided Jacobi SVD of the transposed k x k factor, stopped when the residual
 // |K w_i - s_i v_i| of every kept triplet is below tol * s_1.
 #include <algorithm>
 #include <cmath>
