@@ -142,6 +142,29 @@ def test_headline_move_parity(ctx, headline):
         assert max(errs) < tol, errs
 
 
+def test_headline_boundary_converges_below_1e_12(ctx):
+    """The measured workload's boundary (the bench's seeded sites and positive
+    seeded boundary, D = 6, chi = 72), converged by the library to CTMRG
+    delta < 1e-7 and then advanced one iteration per call: the change of the
+    corner spectra must fall below 1e-12 and stay there.  The projector
+    triplets are accurate to 1e-13 s_1; when the Rayleigh-Ritz basis was
+    orthonormal only to the Jacobi tolerance (8 k u = 1.7e-13), delta stalled
+    near 3e-10."""
+    D, chi = 6, 72
+    Lx, Ly, cell = tninputs.CHECKERBOARD
+    cell = list(cell)
+    sd = dev(np.stack(tninputs.ipeps_sites(0, 2, D)))
+    C_h, T_h = tninputs.ctm_env(1, Lx * Ly, chi, D, positive=True)
+    Cg, Tg = dev(C_h), dev(T_h)
+    ctx.clear_cache()
+    _, it, de = ctx.ctmrg_iterate(Lx, Ly, sd, cell, Cg, Tg, 100, 1e-7)
+    assert de < 1e-7
+    ds = [ctx.ctmrg_iterate(Lx, Ly, sd, cell, Cg, Tg, 1, 0.0)[2] for _ in range(24)]
+    print(f"prepared in {it} iterations (delta {de:.1e}); then " +
+          " ".join(f"{d:.1e}" for d in ds))
+    assert max(ds[-10:]) < 1e-12, ds
+
+
 def test_low_rank_projector_move_parity(ctx):
     """A nearly product state (seeded product tensors in D = 4 plus 1e-3 of
     N(0,1)): the projector problem at n = chi D^2 = 512 has far fewer
