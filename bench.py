@@ -52,6 +52,21 @@ def measured_traffic():
     return float(vals["hbm_bytes_per_launch"])
 
 
+def settled_time(points, ref, rtol):
+    """(settled, first) for a run's measurements `points` = [(t, value), ...]
+    in time order: `settled` is the time of the first measurement from which
+    every later one lies within rtol |ref| of ref, `first` the time of the
+    first one within it; None where there is none."""
+    near = [abs(v - ref) <= rtol * abs(ref) for _, v in points]
+    first = next((t for (t, _), ok in zip(points, near) if ok), None)
+    settled = None
+    for (t, _), ok in zip(reversed(points), reversed(near)):
+        if not ok:
+            break
+        settled = t
+    return settled, first
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, run under the HBM byte
     counters to scale them."""
@@ -200,10 +215,7 @@ def run_classical(args):
               file=sys.stderr, flush=True)
         settled = None
         if ref is not None:
-            for _, t, v in reversed(hist):
-                if abs(v - ref) > 1e-10 * abs(ref):
-                    break
-                settled = t
+            settled, _ = settled_time([(t, v) for _, t, v in hist], ref, 1e-10)
         return {"steps": step, "environment_steps": envs, "seconds": round(hist[-1][1], 4),
                 "ln_z": hist[-1][2], "time_to_1e-10": settled, "first_within_1e-10": t_hit}
 
@@ -365,13 +377,7 @@ def run_full_update(args):
                                f"{args.fu_conv:g} (relative) over 100 steps "
                                f"(or after {args.fu_steps} steps)"}
     for label, log in runs.items():
-        near = [abs(e - e_ref) <= 1e-6 * abs(e_ref) for _, e, *_ in log]
-        first = next((rec[2] for rec, ok in zip(log, near) if ok), None)
-        hit = None
-        for rec, ok in zip(reversed(log), reversed(near)):
-            if not ok:
-                break
-            hit = rec[2]
+        hit, first = settled_time([(t, e) for _, e, t, *_ in log], e_ref, 1e-6)
         recycled = [i for i in info_all[label] if i["recycled"]]
         fids = [i["fidelity"] for i in info_all[label] if i["fidelity"] is not None]
         out[label] = {"seconds": round(log[-1][2], 3), "env_steps": len(log),
